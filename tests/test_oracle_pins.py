@@ -1,0 +1,467 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows.  None of them re-types the oracle's
+own formulas: they use brute force, closed forms, theorems and an independent
+LP solver (HiGHS via scipy) so that a dropped term, a wrong sign or index, or a
+transposed operand in the oracle fails at least one of them.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.optimize as so
+
+import workloads
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# ------------------------------------------------------------ helpers
+def monomials(q):
+    """Exponents (a, b) with 1 <= a + b <= q in the oracle's row order."""
+    out = [(1, 0), (0, 1), (2, 0), (1, 1), (0, 2)]
+    if q >= 3:
+        out += [(3, 0), (2, 1), (1, 2), (0, 3)]
+    return out
+
+
+def vandermonde(rx, ry, q):
+    return np.array([rx ** a * ry ** b for a, b in monomials(q)])
+
+
+def rhs(q):
+    # Sec. 2, eq. (cond_two): 2 at alpha = (2,0) and (0,2), zero for every other alpha
+    return np.array([2.0 if (a, b) in ((2, 0), (0, 2)) else 0.0 for a, b in monomials(q)])
+
+
+def canonical_cost(rx, ry, ids, q):
+    rank = np.argsort(np.argsort(ids))
+    return np.hypot(rx, ry) ** (q + 1) + 2.0 ** -10 * rank
+
+
+def enumerate_vertices(A, b, c):
+    """Brute force: every m-subset of columns, solve, keep feasible, return min cost."""
+    m, k = A.shape
+    best = None
+    for S in itertools.combinations(range(k), m):
+        B = A[:, S]
+        if abs(np.linalg.det(B)) < 1e-12:
+            continue
+        x = np.linalg.solve(B, b)
+        if x.min() < -1e-10:
+            continue
+        if np.abs(B @ x - b).max() > 1e-9:
+            continue
+        f = np.zeros(k)
+        f[list(S)] = np.maximum(x, 0)
+        cost = c @ f
+        if best is None or cost < best[0] - 1e-12:
+            best = (cost, f)
+    return best
+
+
+def random_annulus(rng, k, rmin=0.5, rmax=2.0, spread=0.45):
+    """k points in the annulus, angles spread around the circle like a neighbourhood."""
+    rad = np.sqrt(rng.uniform(rmin ** 2, rmax ** 2, k))
+    ang = 2 * np.pi * (np.arange(k) + rng.uniform(-spread, spread, k)) / k + rng.uniform(0, 2 * np.pi)
+    return rad * np.cos(ang), rad * np.sin(ang)
+
+
+def dyadic_lattice(half=16, e=-4):
+    h = 2.0 ** e
+    g = np.arange(-half, half + 1) * h
+    X, Y = np.meshgrid(g, g)
+    return X.ravel().copy(), Y.ravel().copy(), h
+
+
+# ------------------------------------------------------------- P2 / P3
+@pytest.mark.parametrize("q,k", [(2, 6), (2, 8), (2, 10), (3, 10), (3, 12)])
+def test_lp_matches_vertex_enumeration(orc, q, k):
+    """Sec. 4.1: an LP optimum sits on a basic solution; brute force over all bases."""
+    rng = np.random.default_rng(100 + 7 * k + q)
+    n_feasible = 0
+    for trial in range(25):
+        rx, ry = random_annulus(rng, k)
+        ids = rng.permutation(1000)[:k]
+        A = vandermonde(rx, ry, q)
+        b = rhs(q)
+        c = canonical_cost(rx, ry, ids, q)
+        st, f, _ = orc.lp(A, b, c)
+        bf = enumerate_vertices(A, b, c)
+        if bf is None:
+            assert st == 1, f"trial {trial}: oracle found a solution where none exists"
+            continue
+        n_feasible += 1
+        assert st == 0, f"trial {trial}: oracle reports infeasible, brute force has cost {bf[0]}"
+        assert abs(c @ f - bf[0]) <= 1e-10 * max(1.0, bf[0])
+        np.testing.assert_allclose(f, bf[1], atol=1e-10)
+    assert n_feasible >= 5
+
+
+@pytest.mark.parametrize("q,kmax", [(2, 20), (3, 40)])
+def test_lp_against_independent_solver(orc, q, kmax):
+    """Optimal value and feasibility agree with HiGHS on larger neighbourhoods (Sec. 4.1)."""
+    rng = np.random.default_rng(7 + q)
+    for trial in range(40):
+        k = int(rng.integers(m := (5 if q == 2 else 9), kmax + 1))
+        rmax = 2.0 if q == 2 else 3.0
+        rx, ry = random_annulus(rng, k, 0.5, rmax)
+        ids = rng.permutation(10000)[:k]
+        A, b, c = vandermonde(rx, ry, q), rhs(q), canonical_cost(rx, ry, ids, q)
+        st, f, _ = orc.lp(A, b, c)
+        ref = so.linprog(c, A_eq=A, b_eq=b, bounds=(0, None), method="highs")
+        if ref.status == 2:
+            assert st == 1
+            continue
+        assert ref.status == 0 and st == 0
+        assert abs(c @ f - ref.fun) <= 1e-8 * max(1.0, abs(ref.fun))
+        # KKT: primal feasibility; dual from the support of f
+        assert f.min() >= 0
+        assert np.abs(A @ f - b).max() <= 1e-12 * 2
+
+
+def test_lp_kkt_certificate(orc):
+    """Reduced costs of the optimal basis are non-negative (optimality certificate)."""
+    rng = np.random.default_rng(3)
+    q = 3
+    for trial in range(30):
+        rx, ry = random_annulus(rng, 30, 0.5, 3.0)
+        ids = np.arange(30)
+        A, b, c = vandermonde(rx, ry, q), rhs(q), canonical_cost(rx, ry, ids, q)
+        st, f, _ = orc.lp(A, b, c)
+        assert st == 0
+        S = np.flatnonzero(f > 0)
+        # dual y solves the support columns in the least-squares sense (exact when non-degenerate)
+        y, *_ = np.linalg.lstsq(A[:, S].T, c[S], rcond=None)
+        red = c - y @ A
+        assert red.min() >= -1e-8 * np.abs(c).max(), red.min()
+
+
+# ------------------------------------------------------------------ P1
+@pytest.mark.parametrize("q", [2, 3])
+def test_lattice_gives_five_point_stencil(orc, q):
+    """On a lattice the method reduces to the five-point stencil (Sec. 3.3 remark on
+    the a-priori bound; Sec. 1): f = 1 on the four axis neighbours, f_ii = -4."""
+    x, y, h = dyadic_lattice()
+    n = x.size
+    ids = np.arange(n, dtype=np.int32)
+    mask = (np.hypot(x, y) < 0.7).astype(np.uint8)
+    st = orc.stencils(x, y, ids, mask, orc.params(h, q=q))
+    sel = np.flatnonzero(mask)
+    assert (st.status[sel] == (0 if q == 2 else 1)).all()
+    golden = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "five_point_stencil.txt"))
+    expect = {(gx, gy): gf for gx, gy, gf in golden}
+    for i in sel:
+        cols, f, fii = orc.stencil_matrix_row(st, i)
+        got = {(0.0, 0.0): fii}
+        for c, v in zip(cols, f):
+            if v != 0:
+                got[((x[c] - x[i]) / h, (y[c] - y[i]) / h)] = v
+        assert got == expect
+
+
+def test_lattice_run_equals_textbook_fd(orc):
+    """One SSP-RK3 step on a lattice equals the five-point finite-difference Laplacian
+    applied to the diffused circulations, advanced by SSP-RK3 (independent numpy)."""
+    x, y, h = dyadic_lattice(half=24, e=-4)
+    nu = 0.01
+    g = workloads.lamb_oseen_omega(x, y, 1.0, nu) * h * h
+    wl = workloads.Workload("lattice", x.astype(np.float32), y.astype(np.float32), g.astype(np.float32),
+                            h=h, nu=nu, q=2, dt=0.1 * h * h / nu, steps=1, t0=1.0)
+    s0 = orc.initial_state(wl)
+    mask, _, _ = orc.diffused(s0.gamma, s0.ids, h, 2)
+    s1 = orc.step(s0, wl)
+    assert s1.x.shape[0] == x.size  # no holes on a lattice interior
+    m = 49
+    D = mask.reshape(m, m).astype(float)
+
+    def lap(G):  # scatter of the five-point stencil from diffused particles
+        S = D * G
+        out = -4.0 * S
+        out[:, 1:] += S[:, :-1]
+        out[:, :-1] += S[:, 1:]
+        out[1:, :] += S[:-1, :]
+        out[:-1, :] += S[1:, :]
+        return nu / (h * h) * out
+
+    G0 = s0.gamma.reshape(m, m)
+    dt = wl.dt
+    G1 = G0 + dt * lap(G0)
+    G2 = 0.75 * G0 + 0.25 * (G1 + dt * lap(G1))
+    G3 = G0 / 3.0 + 2.0 / 3.0 * (G2 + dt * lap(G2))
+    np.testing.assert_allclose(s1.gamma.reshape(m, m), G3, rtol=0, atol=1e-13 * np.abs(G0).max())
+
+
+# ------------------------------------------------------------- P4 / P5
+@pytest.fixture(scope="module")
+def jittered_stencils():
+    import oracle
+    out = {}
+    for q in (2, 3):
+        wl = workloads.config_jittered(h=0.04, q=q, seed=11)
+        P = oracle.params_of(wl)
+        mask, _, _ = oracle.diffused(wl.gamma, wl.ids, wl.h, q)
+        x, y, g, ids, _ = oracle.insert(wl.x.astype(float), wl.y.astype(float), wl.gamma.astype(float),
+                                        wl.ids, mask, P)
+        mask = np.concatenate([mask, np.zeros(x.size - mask.size, np.uint8)])
+        out[q] = (wl, x, y, ids, mask, oracle.stencils(x, y, ids, mask, P))
+    return out
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_polynomial_exactness(jittered_stencils, q):
+    """Sec. 3.2 Theorem (Consistency): the moment conditions make sum_j f_ij p(x_j)
+    equal to the Laplacian of p at x_i for every polynomial of degree <= q."""
+    wl, x, y, ids, mask, st = jittered_stencils[q]
+    h = wl.h
+    polys = [(lambda X, Y: np.ones_like(X), lambda X, Y: 0 * X),
+             (lambda X, Y: X, lambda X, Y: 0 * X), (lambda X, Y: Y, lambda X, Y: 0 * X),
+             (lambda X, Y: X * X, lambda X, Y: 2 + 0 * X), (lambda X, Y: X * Y, lambda X, Y: 0 * X),
+             (lambda X, Y: Y * Y - 3 * X, lambda X, Y: 2 + 0 * X)]
+    if q >= 3:
+        polys += [(lambda X, Y: X ** 3, lambda X, Y: 6 * X), (lambda X, Y: X * X * Y, lambda X, Y: 2 * Y),
+                  (lambda X, Y: X * Y * Y, lambda X, Y: 2 * X), (lambda X, Y: Y ** 3, lambda X, Y: 6 * Y)]
+    ok = np.flatnonzero(st.status <= 1)
+    assert ok.size > 100
+    for i in ok[:: max(1, ok.size // 300)]:
+        cols, f, fii = st.cols[i, :st.kcol[i]], st.f[i, :st.kcol[i]] / h ** 2, st.fii[i] / h ** 2
+        xc, yc = x[i], y[i]
+        for p, lp in polys:
+            # evaluate in coordinates centred at x_i (the operator is translation invariant)
+            val = f @ p(x[cols] - xc, y[cols] - yc) + fii * p(np.zeros(1), np.zeros(1))[0]
+            exact = lp(np.zeros(1), np.zeros(1))[0]
+            assert abs(val - exact) <= 1e-9 * (1 + abs(exact)) / 1.0, (i, val, exact)
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_lemma_bounds(jittered_stencils, q):
+    """Sec. 3.2 Lemma: f_ii <= 0 and 4 (Rh)^-2 <= sum_{j != i} f_ij <= 4 (rh)^-2;
+    the (2,0) + (0,2) rows give sum_j f |r|^2 = 4 exactly."""
+    wl, x, y, ids, mask, st = jittered_stencils[q]
+    h, r = wl.h, wl.r
+    R = wl.R_full
+    for i in np.flatnonzero(st.status <= 1):
+        k = st.kcol[i]
+        cols, f = st.cols[i, :k], st.f[i, :k]
+        assert f.min() >= 0
+        r2 = ((x[cols] - x[i]) ** 2 + (y[cols] - y[i]) ** 2) / h ** 2
+        assert abs(f @ r2 - 4.0) <= 1e-11
+        s = f.sum()
+        assert st.fii[i] == pytest.approx(-s, abs=1e-13)
+        assert 4.0 / (R * R) * (1 - 1e-6) <= s <= 4.0 / (r * r) * (1 + 1e-6)
+
+
+def test_fourth_order_is_infeasible(orc):
+    """Sec. 3.6: no non-negative stencil satisfies the |alpha| = 4 conditions as well."""
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        rx, ry = random_annulus(rng, 30, 0.5, 3.0)
+        rows = monomials(3) + [(4, 0), (3, 1), (2, 2), (1, 3), (0, 4)]
+        A = np.array([rx ** a * ry ** b for a, b in rows])
+        b = np.array([2.0 if (a, bb) in ((2, 0), (0, 2)) else 0.0 for a, bb in rows])
+        # plain feasibility problem; the oracle's LP handles any m <= 9 only, so use HiGHS
+        res = so.linprog(np.zeros(30), A_eq=A, b_eq=b, bounds=(0, None), method="highs")
+        assert res.status == 2
+        # and the oracle on 9 rows of the same cloud is feasible (the limit is exactly |alpha| = 4)
+        st, f, _ = orc.lp(vandermonde(rx, ry, 3), rhs(3), canonical_cost(rx, ry, np.arange(30), 3))
+        assert st == 0
+
+
+# ------------------------------------------------------------------ P7
+@pytest.mark.parametrize("q", [2, 3])
+def test_conservation_per_euler_stage(orc, jittered_stencils, q):
+    """Sec. 3.4 Theorem (Conservation): with the fractions of one stage, one Euler step
+    keeps I0 and I1 and changes I2 by exactly 4 nu dt sum_{j diffused} Gamma_j."""
+    wl, x, y, ids, mask, st = jittered_stencils[q]
+    rng = np.random.default_rng(q)
+    g = rng.normal(size=x.size)
+    P = orc.params_of(wl)
+    dg = orc.apply(st, g, P)
+    dt = wl.dt
+    g1 = g + dt * dg
+    i0a, i1a, i2a = orc.invariants(x, y, g)
+    i0b, i1b, i2b = orc.invariants(x, y, g1)
+    scale = np.abs(g).sum()
+    assert abs(i0b - i0a) <= 1e-13 * scale
+    assert abs(i1b[0] - i1a[0]) <= 1e-13 * scale and abs(i1b[1] - i1a[1]) <= 1e-13 * scale
+    active = st.status <= 1
+    expect = 4 * wl.nu * dt * g[active].sum()
+    assert abs((i2b - i2a) - expect) <= 1e-11 * scale
+
+
+def test_run_conserves_circulation(orc):
+    """Sec. 5.1: with the reduced operator, I0 and I1 are kept to machine precision
+    in the heat equation, and I2 grows by the diffused share of 4 nu I0 per unit time."""
+    wl = workloads.config_jittered(h=0.04, q=2, seed=3)
+    s = orc.run(wl, steps=5)
+    i0, i1, i2 = orc.invariants(wl.x, wl.y, wl.gamma)
+    j0, j1, j2 = orc.invariants(s.x, s.y, s.gamma)
+    assert abs(j0 - i0) <= 1e-13
+    assert abs(j1[0] - i1[0]) <= 1e-13 and abs(j1[1] - i1[1]) <= 1e-13
+    expect = 4 * wl.nu * i0 * 5 * wl.dt
+    # circulation that reaches left-out particles stops feeding dI2/dt = 4 nu I0 (Sec. 3.5)
+    assert 0.98 * expect <= j2 - i2 <= expect * (1 + 1e-12)
+
+
+# ------------------------------------------------------------------ P8
+def test_stability_positive_stencil(orc):
+    """Sec. 3.3 Theorem (Stability): positive stencils with nu dt <= -1/f_ii keep
+    ||Gamma||_1 constant and Gamma >= 0 for Gamma >= 0."""
+    wl = workloads.config_jittered(h=0.04, q=2, seed=4)
+    s = orc.initial_state(wl)
+    P = orc.params_of(wl)
+    mask, _, _ = orc.diffused(s.gamma, s.ids, wl.h, 2)
+    st = orc.stencils(s.x, s.y, s.ids, mask, P)
+    lam = wl.nu * wl.dt / wl.h ** 2
+    assert lam * (-st.fii).max() <= 1.0     # a-posteriori bound holds for this dt
+    g = s.gamma
+    g1 = g + wl.dt * orc.apply(st, g, P)
+    assert g1.min() >= 0
+    assert abs(np.abs(g1).sum() - np.abs(g).sum()) <= 1e-13 * np.abs(g).sum()
+    # beyond the bound the l1 norm grows (the "only if" part)
+    big = 1.5 / (wl.nu / wl.h ** 2 * (-st.fii).max())
+    i = int(np.argmax(-st.fii))
+    e = np.zeros_like(g)
+    e[i] = 1.0
+    g2 = e + big * orc.apply(st, e, P)
+    assert np.abs(g2).sum() > 1.0 + 1e-6
+
+
+# ------------------------------------------------------------------ P10
+def test_lone_particle_insertion(orc):
+    """Sec. 4.2 / 5: a lone particle gets eight new particles at 1.5 h on the
+    segments' centre lines (the Dirac start)."""
+    h = 0.0625
+    x = np.zeros(1)
+    y = np.zeros(1)
+    g = np.ones(1)
+    ids = np.zeros(1, np.int32)
+    X, Y, G, I, nc = orc.insert(x, y, g, ids, np.ones(1, np.uint8), orc.params(h))
+    assert nc == 8 and X.size == 9
+    ang = np.arctan2(Y[1:], X[1:])
+    np.testing.assert_allclose(np.hypot(X[1:], Y[1:]), 1.5 * h, rtol=1e-6)
+    np.testing.assert_allclose(np.sort(np.mod(ang, 2 * np.pi)), np.arange(8) * np.pi / 4, atol=1e-6)
+    assert (G[1:] == 0).all() and list(I[1:]) == list(range(1, 9))
+
+
+def test_insertion_fills_every_segment(orc):
+    """Sec. 4.2 figure caption: after one insertion round no diffused particle has an
+    empty segment, and no inserted particle is closer than 0.5 h to any other."""
+    wl = workloads.config_vortices(h=0.02, lo=-1.0, hi=1.0)
+    P = orc.params_of(wl)
+    mask, _, _ = orc.diffused(wl.gamma, wl.ids, wl.h, 2)
+    x, y, g, ids, nc = orc.insert(wl.x.astype(float), wl.y.astype(float), wl.gamma.astype(float),
+                                  wl.ids, mask, P)
+    n0 = wl.n
+    assert x.size > n0
+    mask2 = np.concatenate([mask, np.zeros(x.size - n0, np.uint8)])
+    st = orc.stencils(x, y, ids, mask2, P)
+    assert (st.small[mask2 > 0] >= 0).all()
+    # exclusion radius of the new particles against everyone (brute force)
+    new = np.arange(n0, x.size)
+    for i in new[:: max(1, new.size // 400)]:
+        d = np.hypot(x - x[i], y - y[i])
+        d[i] = np.inf
+        assert d.min() >= 0.5 * wl.h * (1 - 1e-5)
+
+
+# ------------------------------------------------------------------ P11
+def _jittered_dyadic(seed=1, half=20, e=-5):
+    rng = np.random.default_rng(seed)
+    h = 2.0 ** e
+    g = np.arange(-half, half + 1) * h
+    X, Y = np.meshgrid(g, g)
+    # jitter on a 2^-12 h grid keeps every transform below exact in FP32 and FP64
+    jx = np.round(rng.uniform(-0.3, 0.3, X.shape) * 4096) / 4096 * h
+    jy = np.round(rng.uniform(-0.3, 0.3, X.shape) * 4096) / 4096 * h
+    return (X + jx).ravel(), (Y + jy).ravel(), h
+
+
+def _stencil_dict(st, ids, i):
+    k = st.kcol[i]
+    return {int(ids[c]): v for c, v in zip(st.cols[i, :k], st.f[i, :k])}
+
+
+@pytest.mark.parametrize("transform", ["translate", "rot90", "reflect_x", "scale"])
+def test_invariance(orc, transform):
+    """Sec. 4.2: results do not depend on the frame; exact for the symmetries that map
+    segments onto segments (translation, 90-degree rotation, reflection, scaling by 2^k)."""
+    x, y, h = _jittered_dyadic()
+    n = x.size
+    ids = np.arange(n, dtype=np.int32)
+    mask = (np.hypot(x, y) < 0.4).astype(np.uint8)
+    h2 = h
+    if transform == "translate":
+        x2, y2 = x + 0.75, y - 0.5
+    elif transform == "rot90":
+        x2, y2 = -y, x.copy()
+    elif transform == "reflect_x":
+        x2, y2 = -x, y.copy()
+    else:
+        x2, y2, h2 = x * 4.0, y * 4.0, h * 4.0
+    a = orc.stencils(x, y, ids, mask, orc.params(h, q=2))
+    b = orc.stencils(x2, y2, ids, mask, orc.params(h2, q=2))
+    np.testing.assert_array_equal(a.status, b.status)
+    for i in np.flatnonzero(mask):
+        da, db = _stencil_dict(a, ids, i), _stencil_dict(b, ids, i)
+        assert da.keys() == db.keys()
+        for key in da:
+            assert abs(da[key] - db[key]) <= 1e-12, (transform, i, key)
+
+
+# ------------------------------------------------------------------ P12
+def test_reduced_operator_brute_force(orc):
+    """Sec. 3.5 eq. (reduced_bound): the left-out set is the largest set of smallest
+    |Gamma| (whole groups of equal |Gamma|) whose l1 norm is <= C_diff h^(q+1) ||Gamma||_1."""
+    rng = np.random.default_rng(9)
+    for trial in range(200):
+        n = int(rng.integers(1, 12))
+        g = rng.choice([0.0, 1e-4, 2e-4, 5e-3, 0.1, -0.1, 1.0, -2.0], size=n) * rng.choice([1, 1, 1.5], size=n)
+        h = float(rng.choice([0.05, 0.1, 0.3, 0.6]))
+        q = int(rng.choice([2, 3]))
+        ids = rng.permutation(n).astype(np.int32)
+        mask, n1, bound = orc.diffused(g, ids, h, q)
+        assert n1 == pytest.approx(np.abs(g).sum())
+        assert bound == pytest.approx(h ** (q + 1) * np.abs(g).sum())
+        # brute force: thresholds over the distinct |Gamma| values
+        best_t = -1.0
+        for t in sorted(set(np.abs(g))):
+            if np.abs(g)[np.abs(g) <= t].sum() <= bound:
+                best_t = t
+        expect = (np.abs(g) > best_t).astype(np.uint8)
+        np.testing.assert_array_equal(mask, expect)
+
+
+def test_lattice_initial_circulation():
+    """Sec. 5 Lamb-Oseen: a lattice-sampled Gaussian integrates to the total circulation."""
+    wl = workloads.config_lattice_small()
+    assert abs(wl.gamma.astype(np.float64).sum() - 1.0) <= 1e-7
+
+
+# ------------------------------------------------------------------ P9
+def _weak_error(x, y, g, t, nu, s=0.1):
+    """max over Gaussian test functions of |<omega_h, phi_c> - <omega, phi_c>| with the
+    Lamb-Oseen closed form <omega(t), phi_c> = s^2/(s^2 + 4 nu t) exp(-|c|^2/(s^2 + 4 nu t))."""
+    a = 4 * nu * t
+    err = 0.0
+    for cx in np.linspace(-0.4, 0.4, 9):
+        for cy in np.linspace(-0.4, 0.4, 9):
+            num = (g * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / s ** 2)).sum()
+            ex = s * s / (a + s * s) * np.exp(-(cx * cx + cy * cy) / (a + s * s))
+            err = max(err, abs(num - ex))
+    return err
+
+
+def test_lamb_oseen_second_order(orc):
+    """Sec. 5.1: the Lamb-Oseen solution is reproduced with second-order convergence in h
+    (one order above the proven bound); lattice start, SSP-RK3, dt = 0.1 h^2 / nu, T = 0.256."""
+    T = 0.256
+    errs = []
+    for h in (0.08, 0.04, 0.02):
+        wl = workloads.config_jittered(h=h, q=2, seed=2, jitter=0.0)
+        s = orc.run(wl, steps=int(round(T / wl.dt)))
+        errs.append(_weak_error(s.x, s.y, s.gamma, wl.t0 + T, wl.nu))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert ((orders > 1.8) & (orders < 2.3)).all(), (errs, orders)
