@@ -1,0 +1,191 @@
+/*
+ * vrm.h -- C ABI of the MI355X (gfx950) vorticity redistribution library.
+ *
+ * Splitting-free vorticity redistribution (Kirchhart & Obi): every particle
+ * i carries a circulation Gamma_i at x_i (Sec. 1, eq. vfield).  The library
+ * computes, for every diffused particle, non-negative fractions f_ij over its
+ * neighbourhood that satisfy the moment conditions (Sec. 2, eqs. cond_two,
+ * cond_alpha, fii, momcondmv), inserts Gamma = 0 particles where a
+ * neighbourhood has an empty 45-degree segment (Sec. 4.2), and applies
+ * dGamma_i/dt = nu sum_j f_ji Gamma_j (Sec. 3.4, eq. nsode) inside the stages
+ * of an SSP Runge-Kutta scheme (Sec. 3.3).
+ *
+ * Conventions for every entry point
+ *   - Pointers named *_dev are device pointers on the context's device; the
+ *     caller owns them and keeps them alive until the stream has drained.
+ *     Host pointers are named *_host.
+ *   - Every call enqueues work on the context's stream and returns without
+ *     waiting, except where "synchronises" is stated.
+ *   - Return value: VRM_OK (0) or a negative VRM_E_* code; vrm_last_error()
+ *     then describes the failure (thread-local).  Argument errors are found
+ *     before anything is enqueued and leave all buffers untouched.
+ *   - Fractions are normalised: f_ij = fhat_ij / h^2 (Sec. 2, last paragraph).
+ *   - Floating point: FP32 state and fractions; FP64 only in the verification
+ *     sums (moment residual, circulation).
+ */
+#ifndef VRM_H
+#define VRM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VRM_OK 0
+#define VRM_E_ARG (-1)        /* bad argument (null, sizes, parameters) */
+#define VRM_E_CAPACITY (-2)   /* insertion would exceed cloud capacity; nothing appended */
+#define VRM_E_HIP (-3)        /* a HIP runtime call failed */
+#define VRM_E_STATE (-4)      /* call order violated (e.g. no diffused set yet) */
+
+#define VRM_NSEG 8            /* 45-degree segments of a neighbourhood (Sec. 4.2) */
+#define VRM_KMAX 48           /* max columns of a complete-neighbourhood LP */
+
+/* per-particle status written by vrm_solve_fractions (Sec. 4.3) */
+#define VRM_ST_SMALL 0        /* small neighbourhood LP solved */
+#define VRM_ST_FULL 1         /* complete neighbourhood LP solved (fallback) */
+#define VRM_ST_INFEASIBLE 2   /* no non-negative stencil: not diffused this stage */
+#define VRM_ST_SKIPPED 3      /* not in the diffused set (Sec. 3.5) */
+
+typedef struct vrm_ctx vrm_ctx;
+
+/* Particle cloud (Sec. 1, eq. vfield), structure of arrays, all device
+ * pointers of `capacity` entries.  n_dev points to one int32 in device memory
+ * holding the current count N; insertion increases it on the device.
+ * vrm_insert_particles permutes the arrays (id travels with its particle). */
+typedef struct {
+    float* x_dev;
+    float* y_dev;
+    float* gamma_dev;
+    int32_t* id_dev;
+    int32_t* n_dev;
+    int32_t capacity;
+} vrm_cloud;
+
+/* Method parameters.
+ *   h       average particle spacing (> 0)
+ *   nu      kinematic viscosity (>= 0)
+ *   r, R    neighbourhood annulus r h <= |x_i - x_j| <= R h, R > r > 0
+ *           (Sec. 2, eq. neighbourhood; the paper uses r = 1/2, R = 2)
+ *   R_full  radius of the complete neighbourhood used when the small one fails
+ *   c_diff  reduced-operator constant (Sec. 3.5, eq. reduced_bound)
+ *   dt      time step of vrm_rk_stage
+ *   q       highest moment order matched: 2 (5 conditions, paper n = 1) or
+ *           3 (9 conditions, paper n = 2) */
+typedef struct {
+    double h, nu, r, R, R_full, c_diff, dt;
+    int32_t q;
+    int32_t reserved;
+} vrm_params;
+
+/* Stencil output of vrm_solve_fractions, device arrays indexed by particle
+ * index (capacity entries).  Unused slots hold -1 / 0. */
+typedef struct {
+    int32_t* small_idx_dev;   /* [capacity][8]: small-neighbourhood member per segment, or -1 */
+    float* small_f_dev;       /* [capacity][8]: fhat for those members */
+    float* fii_dev;           /* [capacity]:    fhat_ii = -sum_j fhat_ij (eq. fii) */
+    uint8_t* status_dev;      /* [capacity]:    VRM_ST_* */
+    int32_t* full_k_dev;      /* [capacity]:    number of complete-neighbourhood columns */
+    int32_t* full_idx_dev;    /* [capacity][VRM_KMAX] (may be NULL: then not written) */
+    float* full_f_dev;        /* [capacity][VRM_KMAX] (may be NULL together with full_idx_dev) */
+} vrm_stencils;
+
+/* Device-side counters, read with vrm_read_counters. */
+typedef struct {
+    int32_t n;                /* current particle count */
+    int32_t n_diffused;       /* size of the diffused set of the step */
+    int32_t n_candidates;     /* insertion candidates of the last insertion */
+    int32_t n_inserted;       /* particles appended by the last insertion */
+    int32_t n_small;          /* LPs solved on the small neighbourhood (cumulative) */
+    int32_t n_full;           /* LPs solved on the complete neighbourhood (cumulative) */
+    int32_t n_infeasible;     /* particles without a stencil (cumulative) */
+    int32_t n_uncertified;    /* LPs whose optimality could not be certified (cumulative) */
+    int32_t n_truncated;      /* complete neighbourhoods cut to VRM_KMAX (cumulative) */
+    int32_t n_grid_clamped;   /* cell grids that hit their size limit (cumulative) */
+    int64_t pivots;           /* simplex pivots (cumulative) */
+    int64_t redistributions;  /* stencils applied by vrm_rk_stage (cumulative) */
+    int32_t capacity_needed;  /* set when an insertion failed for capacity */
+    int32_t mis_rounds;       /* rounds of the last insertion's conflict resolution */
+} vrm_counters;
+
+/* Create a context on `device` that enqueues on `stream` (a hipStream_t; NULL
+ * = the null stream) for clouds of up to `capacity` particles.  The context
+ * owns all scratch memory (about 120 bytes per particle of capacity) and
+ * frees it in vrm_destroy.  Synchronises. */
+int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity);
+int vrm_destroy(vrm_ctx* ctx);
+
+/* Sec. 3.5, eq. reduced_bound: choose the diffused set of the step from the
+ * current circulations: leave out the particles of smallest |Gamma| (whole
+ * groups of equal |Gamma|) while the l1 norm of the left-out ones stays
+ * <= c_diff h^(q+1) ||Gamma||_1.  Kept in the context (and written to
+ * mask_dev[N] as 0/1 when mask_dev != NULL). */
+int vrm_select_diffused(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params* p, uint8_t* mask_dev);
+
+/* Replace the context's diffused set with mask_dev[N] (0/1), e.g. to solve
+ * for an externally chosen set. */
+int vrm_set_diffused(vrm_ctx* ctx, const vrm_cloud* cloud, const uint8_t* mask_dev);
+
+/* Sec. 2 eq. neighbourhood, Sec. 4.2-4.3: build the cell list at the
+ * current positions and, for every diffused particle, the small
+ * neighbourhood (closest member of each 45-degree segment of the annulus
+ * r h <= d <= R h; ties by smaller id) and the size of the complete
+ * neighbourhood within R_full h.  small_idx_dev[N][8] gets particle indices
+ * (-1 for an empty segment); kfull_dev[N] the complete count (either may be
+ * NULL).  Non-diffused particles get -1 / 0. */
+int vrm_build_neighbourhoods(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params* p,
+                             int32_t* small_idx_dev, int32_t* kfull_dev);
+
+/* Sec. 4.2: once per step.  Selects the diffused set (as
+ * vrm_select_diffused), inserts a Gamma = 0 particle on the centre line of
+ * every empty segment of every diffused particle at radius 1.5 h, resolving
+ * conflicts between candidates closer than 0.5 h greedily in (id, segment)
+ * order, appends the new particles with ids max_id+1, ... in that order, and
+ * reorders the whole cloud by cell.  On VRM_E_CAPACITY (detected on the
+ * device; reported by the next vrm_read_counters as capacity_needed) the
+ * cloud is left unchanged. */
+int vrm_insert_particles(vrm_ctx* ctx, vrm_cloud* cloud, const vrm_params* p);
+
+/* Sec. 2 and 4.1-4.3: stencils of all diffused particles at the current
+ * positions.  The small-neighbourhood LP is tried when it has at least as many
+ * columns as conditions; otherwise, or if it is infeasible, the complete
+ * neighbourhood within R_full h (its VRM_KMAX nearest members).  Among all
+ * non-negative solutions the one minimising sum_j c_j fhat_j with
+ * c_j = |r_ij / h|^(q+1) + 2^-10 rank(id_j) is returned. */
+int vrm_solve_fractions(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params* p, vrm_stencils* out);
+
+/* Sec. 3.3-3.4: one stage (0, 1, 2) of the Shu-Osher SSP-RK3 scheme,
+ *   y^(s) = a_s y^n + b_s (y^(s-1) + dt L(y^(s-1))),  (a, b) = (0,1), (3/4,1/4), (1/3,2/3),
+ * with L = (u, v, nu sum_j f_ji Gamma_j) evaluated at the current state.
+ * u_dev, v_dev [N]: caller-supplied velocity at the current positions (NULL
+ * for zero velocity).  Stage 0 records y^n.  Uses the diffused set of the
+ * step. */
+int vrm_rk_stage(vrm_ctx* ctx, vrm_cloud* cloud, const float* u_dev, const float* v_dev,
+                 const vrm_params* p, int stage);
+
+/* Sec. 2 eqs. cond_two/cond_alpha, Sec. 3.4: FP64 checks of a stencil set.
+ * Writes, to report_dev[4] (device doubles): the maximum over particles of
+ * max_alpha |sum_j fhat_ij r_ij^alpha / h^|alpha| - b_alpha| / 2, the circulation
+ * sum_i Gamma_i, sum_i |Gamma_i|, and the largest sum_{j != i} fhat_ij. */
+int vrm_verify(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params* p, const vrm_stencils* st,
+               double* report_dev);
+
+/* Copy the device counters to *out_host.  Synchronises the stream. */
+int vrm_read_counters(vrm_ctx* ctx, vrm_counters* out_host);
+
+/* Prescribed velocity of a sum of spreading Gaussian (Lamb-Oseen) vortices
+ * at the current positions (test and benchmark harness, not part of the
+ * method): for vortex k with centre (cx, cy), core sigma and strength G,
+ *   u_theta = G / (2 pi r) (1 - exp(-r^2 / (sigma^2 + 4 nu t))), counter-clockwise.
+ * vort_dev = device floats [n_vort][4] (cx, cy, sigma, G). */
+int vrm_vortex_velocity(vrm_ctx* ctx, const vrm_cloud* cloud, const float* vort_dev, int32_t n_vort,
+                        double nu, double t, float* u_dev, float* v_dev);
+
+const char* vrm_last_error(void);
+const char* vrm_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VRM_H */

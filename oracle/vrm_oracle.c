@@ -169,7 +169,21 @@ static void grid_free(orc_grid* g)
 }
 
 /* ------------------------------------------------ diffused-set selection */
-typedef struct { double a; int id; int idx; } orc_key;
+typedef struct { double a, v; int id; int idx; } orc_key;
+
+/* Ranking key of a particle for the reduced operator: |Gamma| rounded to FP32
+ * and truncated to 16 significant bits, so that circulations equal up to
+ * round-off form one group (reading of "the smallest amount of individual
+ * circulation" that does not depend on the working precision of Gamma). */
+static double selection_key(double g)
+{
+    float a = (float)fabs(g);
+    uint32_t b;
+    memcpy(&b, &a, sizeof b);
+    b &= 0xffffff00u;
+    memcpy(&a, &b, sizeof a);
+    return (double)a;
+}
 
 static int key_cmp(const void* pa, const void* pb)
 {
@@ -181,7 +195,8 @@ static int key_cmp(const void* pa, const void* pb)
 }
 
 /* Sec. 3.5: leave out the particles of smallest |Gamma| (whole groups of equal
- * |Gamma|) while the l1 norm of the left-out set stays <= c_diff h^(q+1) ||Gamma||_1.
+ * ranking key, see selection_key) while the l1 norm of the left-out set stays
+ * <= c_diff h^(q+1) ||Gamma||_1.
  * diffused[i] = 1 for the particles that are diffused.  Returns the count
  * diffused; *norm1 = ||Gamma||_1 and *bound = the right-hand side. */
 int orc_diffused(int n, const double* gamma, const int32_t* id, double h, int q, double c_diff,
@@ -190,10 +205,11 @@ int orc_diffused(int n, const double* gamma, const int32_t* id, double h, int q,
     orc_key* k = (orc_key*)malloc(sizeof(orc_key) * (size_t)(n > 0 ? n : 1));
     double s = 0.0;
     for (int i = 0; i < n; ++i) {
-        k[i].a = fabs(gamma[i]);
+        k[i].a = selection_key(gamma[i]);
+        k[i].v = fabs(gamma[i]);
         k[i].id = id[i];
         k[i].idx = i;
-        s += k[i].a;
+        s += k[i].v;
     }
     double b = c_diff * pow(h, q + 1) * s;
     qsort(k, (size_t)n, sizeof(orc_key), key_cmp);
@@ -203,7 +219,7 @@ int orc_diffused(int n, const double* gamma, const int32_t* id, double h, int q,
     while (i < n) {
         int j = i;
         double grp = 0.0;
-        while (j < n && k[j].a == k[i].a) grp += k[j++].a;
+        while (j < n && k[j].a == k[i].a) grp += k[j++].v;
         if (prefix + grp <= b) {
             prefix += grp;
             for (int t = i; t < j; ++t) diffused[k[t].idx] = 0;
@@ -453,8 +469,16 @@ static int lp_run(int m, int k, const double* A, const double* b_in, const doubl
     }
     if (status == 0) {
         for (int j = 0; j < k; ++j) f[j] = 0.0;
+        double fsum = 0.0;
         for (int t = 0; t < m; ++t)
-            if (basis[t] < k) f[basis[t]] = xB[t] > 0.0 ? xB[t] : 0.0;
+            if (basis[t] < k) {
+                f[basis[t]] = xB[t] > 0.0 ? xB[t] : 0.0;
+                fsum += f[basis[t]];
+            }
+        /* a basic value below 2^-30 of the stencil's sum is the round-off of a
+         * degenerate vertex (exactly zero in exact arithmetic): make it zero */
+        for (int j = 0; j < k; ++j)
+            if (f[j] < 0x1p-30 * fsum) f[j] = 0.0;
         if (basis_out)
             for (int t = 0; t < m; ++t) basis_out[t] = basis[t] < k ? basis[t] : -1;
     }
@@ -680,15 +704,47 @@ int orc_insert(int n, int cap, double* x, double* y, double* gamma, int32_t* id,
     float ex2 = (float)(0.25 * P->h * P->h);
     int* acc = (int*)malloc(sizeof(int) * (size_t)(ncand > 0 ? ncand : 1));
     int na = 0;
+    /* accepted candidates are bucketed in cells of edge 0.5 h (a search aid only:
+     * every candidate closer than 0.5 h lies in the 3 x 3 surrounding cells) */
+    double bx0 = 0, by0 = 0, bx1 = 0, by1 = 0;
     for (int t = 0; t < ncand; ++t) {
-        int ok = 1;
-        for (int u = 0; u < na; ++u) {  /* plain quadratic scan over accepted */
-            float dx = c[acc[u]].x - c[t].x;
-            float dy = c[acc[u]].y - c[t].y;
-            if (f32_d2(dx, dy) < ex2) { ok = 0; break; }
-        }
-        if (ok) acc[na++] = t;
+        if (t == 0 || c[t].x < bx0) bx0 = c[t].x;
+        if (t == 0 || c[t].y < by0) by0 = c[t].y;
+        if (t == 0 || c[t].x > bx1) bx1 = c[t].x;
+        if (t == 0 || c[t].y > by1) by1 = c[t].y;
     }
+    double ce = 0.5 * P->h * 1.001;
+    long long gnx = (long long)((bx1 - bx0) / ce) + 3, gny = (long long)((by1 - by0) / ce) + 3;
+    if (gnx * gny > 50000000LL) { gnx = 1; gny = 1; ce = 1e300; }   /* degenerate: plain scan */
+    int* head = (int*)malloc(sizeof(int) * (size_t)(gnx * gny));
+    int* next = (int*)malloc(sizeof(int) * (size_t)(ncand > 0 ? ncand : 1));
+    for (long long q = 0; q < gnx * gny; ++q) head[q] = -1;
+    for (int t = 0; t < ncand; ++t) {
+        long long cxq = gnx > 1 ? (long long)((c[t].x - bx0) / ce) + 1 : 0;
+        long long cyq = gny > 1 ? (long long)((c[t].y - by0) / ce) + 1 : 0;
+        int ok = 1;
+        for (long long oy = -1; oy <= 1 && ok; ++oy) {
+            long long yy = cyq + oy;
+            if (yy < 0 || yy >= gny) continue;
+            for (long long ox = -1; ox <= 1 && ok; ++ox) {
+                long long xx = cxq + ox;
+                if (xx < 0 || xx >= gnx) continue;
+                for (int u = head[yy * gnx + xx]; u >= 0; u = next[u]) {
+                    float dx = c[u].x - c[t].x;
+                    float dy = c[u].y - c[t].y;
+                    if (f32_d2(dx, dy) < ex2) { ok = 0; break; }
+                }
+            }
+        }
+        if (ok) {
+            acc[na++] = t;
+            long long q = cyq * gnx + cxq;
+            next[t] = head[q];
+            head[q] = t;
+        }
+    }
+    free(head);
+    free(next);
     if (n + na > cap) { free(acc); free(c); return -1; }
     for (int u = 0; u < na; ++u) {
         x[n + u] = c[acc[u]].x;

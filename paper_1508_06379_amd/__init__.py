@@ -1,0 +1,258 @@
+"""Python binding of libvrm, the MI355X (gfx950) vorticity redistribution library.
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``libvrm.so`` (declared in ``include/vrm.h``).  PyTorch provides device memory
+and the stream.  There is no CPU fallback: importing works without a GPU, but
+every call needs the built library and a GPU, and raises otherwise.
+
+Kirchhart & Obi, "A Splitting-free Vorticity Redistribution Method": the
+library computes non-negative redistribution fractions under the moment
+conditions (Sec. 2), inserts particles where a neighbourhood has an empty
+segment (Sec. 4.2), and applies dGamma_i/dt = nu sum_j f_ji Gamma_j inside SSP
+Runge-Kutta stages (Sec. 3.3-3.4).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvrm.so")
+
+NSEG = 8
+KMAX = 48
+ST_SMALL, ST_FULL, ST_INFEASIBLE, ST_SKIPPED = 0, 1, 2, 3
+E_ARG, E_CAPACITY, E_HIP, E_STATE = -1, -2, -3, -4
+
+
+class VrmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class vrm_params(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("nu", ctypes.c_double), ("r", ctypes.c_double), ("R", ctypes.c_double),
+                ("R_full", ctypes.c_double), ("c_diff", ctypes.c_double), ("dt", ctypes.c_double),
+                ("q", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class vrm_cloud(ctypes.Structure):
+    _fields_ = [("x_dev", ctypes.c_void_p), ("y_dev", ctypes.c_void_p), ("gamma_dev", ctypes.c_void_p),
+                ("id_dev", ctypes.c_void_p), ("n_dev", ctypes.c_void_p), ("capacity", ctypes.c_int32)]
+
+
+class vrm_stencils(ctypes.Structure):
+    _fields_ = [("small_idx_dev", ctypes.c_void_p), ("small_f_dev", ctypes.c_void_p), ("fii_dev", ctypes.c_void_p),
+                ("status_dev", ctypes.c_void_p), ("full_k_dev", ctypes.c_void_p),
+                ("full_idx_dev", ctypes.c_void_p), ("full_f_dev", ctypes.c_void_p)]
+
+
+class vrm_counters(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_diffused", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
+                ("n_inserted", ctypes.c_int32), ("n_small", ctypes.c_int32), ("n_full", ctypes.c_int32),
+                ("n_infeasible", ctypes.c_int32), ("n_uncertified", ctypes.c_int32),
+                ("n_truncated", ctypes.c_int32), ("n_grid_clamped", ctypes.c_int32),
+                ("pivots", ctypes.c_int64), ("redistributions", ctypes.c_int64),
+                ("capacity_needed", ctypes.c_int32), ("mis_rounds", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ["vrm_create", "vrm_destroy", "vrm_select_diffused", "vrm_set_diffused", "vrm_build_neighbourhoods",
+           "vrm_insert_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_verify", "vrm_read_counters",
+           "vrm_vortex_velocity", "vrm_last_error", "vrm_status_string"]
+
+_lib = None
+
+
+def lib():
+    """Load libvrm.so (built in-tree by build.py); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libvrm.so not built ({LIB_PATH}); run paper_1508_06379_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.vrm_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_int32]
+        L.vrm_destroy.argtypes = [vp]
+        L.vrm_select_diffused.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params), vp]
+        L.vrm_set_diffused.argtypes = [vp, ctypes.POINTER(vrm_cloud), vp]
+        L.vrm_build_neighbourhoods.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params), vp, vp]
+        L.vrm_insert_particles.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params)]
+        L.vrm_solve_fractions.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params),
+                                          ctypes.POINTER(vrm_stencils)]
+        L.vrm_rk_stage.argtypes = [vp, ctypes.POINTER(vrm_cloud), vp, vp, ctypes.POINTER(vrm_params), ctypes.c_int]
+        L.vrm_verify.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params),
+                                 ctypes.POINTER(vrm_stencils), vp]
+        L.vrm_read_counters.argtypes = [vp, ctypes.POINTER(vrm_counters)]
+        L.vrm_vortex_velocity.argtypes = [vp, ctypes.POINTER(vrm_cloud), vp, ctypes.c_int32, ctypes.c_double,
+                                          ctypes.c_double, vp, vp]
+        L.vrm_last_error.restype = ctypes.c_char_p
+        L.vrm_status_string.restype = ctypes.c_char_p
+        L.vrm_status_string.argtypes = [ctypes.c_int]
+        for name in EXPORTS:
+            if name not in ("vrm_last_error", "vrm_status_string"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise VrmError(code, lib().vrm_last_error().decode())
+    return code
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def make_params(h, nu=0.01, q=2, dt=0.0, r=0.5, R=2.0, R_full=None, c_diff=1.0) -> vrm_params:
+    if R_full is None:
+        R_full = R if q == 2 else 3.0
+    return vrm_params(h, nu, r, R, R_full, c_diff, dt, q, 0)
+
+
+def params_of(wl) -> vrm_params:
+    return vrm_params(wl.h, wl.nu, wl.r, wl.R, wl.R_full, wl.c_diff, wl.dt, wl.q, 0)
+
+
+class Cloud:
+    """Device particle cloud (torch tensors) with spare capacity for insertion."""
+
+    def __init__(self, x, y, gamma, ids=None, capacity=None, device="cuda"):
+        import torch
+        n = len(x)
+        cap = int(capacity or max(16, 2 * n))
+        self.capacity = cap
+        self.x = torch.zeros(cap, dtype=torch.float32, device=device)
+        self.y = torch.zeros(cap, dtype=torch.float32, device=device)
+        self.gamma = torch.zeros(cap, dtype=torch.float32, device=device)
+        self.id = torch.zeros(cap, dtype=torch.int32, device=device)
+        self.n_dev = torch.tensor([n], dtype=torch.int32, device=device)
+        if n:
+            self.x[:n] = torch.as_tensor(np.asarray(x, np.float32), device=device)
+            self.y[:n] = torch.as_tensor(np.asarray(y, np.float32), device=device)
+            self.gamma[:n] = torch.as_tensor(np.asarray(gamma, np.float32), device=device)
+            ids = np.arange(n, dtype=np.int32) if ids is None else np.asarray(ids, np.int32)
+            self.id[:n] = torch.as_tensor(ids, device=device)
+        self.c = vrm_cloud(self.x.data_ptr(), self.y.data_ptr(), self.gamma.data_ptr(), self.id.data_ptr(),
+                           self.n_dev.data_ptr(), cap)
+
+    @property
+    def n(self) -> int:
+        return int(self.n_dev.item())
+
+    def numpy(self):
+        """(x, y, gamma, id) of the current particles, in array order."""
+        n = self.n
+        return (self.x[:n].cpu().numpy(), self.y[:n].cpu().numpy(), self.gamma[:n].cpu().numpy(),
+                self.id[:n].cpu().numpy())
+
+
+@dataclass
+class Stencils:
+    small_idx: object
+    small_f: object
+    fii: object
+    status: object
+    full_k: object
+    full_idx: object
+    full_f: object
+
+    @staticmethod
+    def alloc(capacity, full=True, device="cuda"):
+        import torch
+        z = lambda *s, dt=torch.float32: torch.zeros(*s, dtype=dt, device=device)
+        return Stencils(z(capacity, NSEG, dt=torch.int32), z(capacity, NSEG), z(capacity),
+                        z(capacity, dt=torch.uint8), z(capacity, dt=torch.int32),
+                        z(capacity, KMAX, dt=torch.int32) if full else None, z(capacity, KMAX) if full else None)
+
+    def c(self):
+        return vrm_stencils(*[t.data_ptr() if t is not None else None for t in
+                              (self.small_idx, self.small_f, self.fii, self.status, self.full_k, self.full_idx,
+                               self.full_f)])
+
+
+class Context:
+    """A libvrm context on the current torch device and stream."""
+
+    def __init__(self, capacity, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libvrm needs a GPU; none is visible")
+        dev = torch.cuda.current_device() if device is None else device
+        s = torch.cuda.current_stream(dev) if stream is None else stream
+        self.stream = s
+        self.handle = ctypes.c_void_p()
+        _check(lib().vrm_create(ctypes.byref(self.handle), dev, ctypes.c_void_p(s.cuda_stream), int(capacity)))
+        self.capacity = capacity
+
+    def close(self):
+        if self.handle:
+            lib().vrm_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- entry points, same names as the C ABI
+    def vrm_select_diffused(self, cloud: Cloud, p: vrm_params, mask=None):
+        _check(lib().vrm_select_diffused(self.handle, ctypes.byref(cloud.c), ctypes.byref(p), _ptr(mask)))
+
+    def vrm_set_diffused(self, cloud: Cloud, mask):
+        _check(lib().vrm_set_diffused(self.handle, ctypes.byref(cloud.c), _ptr(mask)))
+
+    def vrm_build_neighbourhoods(self, cloud: Cloud, p: vrm_params, small_idx=None, kfull=None):
+        _check(lib().vrm_build_neighbourhoods(self.handle, ctypes.byref(cloud.c), ctypes.byref(p), _ptr(small_idx),
+                                              _ptr(kfull)))
+
+    def vrm_insert_particles(self, cloud: Cloud, p: vrm_params):
+        _check(lib().vrm_insert_particles(self.handle, ctypes.byref(cloud.c), ctypes.byref(p)))
+
+    def vrm_solve_fractions(self, cloud: Cloud, p: vrm_params, out: Stencils):
+        st = out.c()
+        _check(lib().vrm_solve_fractions(self.handle, ctypes.byref(cloud.c), ctypes.byref(p), ctypes.byref(st)))
+
+    def vrm_rk_stage(self, cloud: Cloud, p: vrm_params, stage: int, u=None, v=None):
+        _check(lib().vrm_rk_stage(self.handle, ctypes.byref(cloud.c), _ptr(u), _ptr(v), ctypes.byref(p), stage))
+
+    def vrm_verify(self, cloud: Cloud, p: vrm_params, st: Stencils, report):
+        sc = st.c() if st is not None else None
+        _check(lib().vrm_verify(self.handle, ctypes.byref(cloud.c), ctypes.byref(p),
+                                ctypes.byref(sc) if sc is not None else None, _ptr(report)))
+
+    def vrm_read_counters(self) -> dict:
+        c = vrm_counters()
+        _check(lib().vrm_read_counters(self.handle, ctypes.byref(c)))
+        return c.as_dict()
+
+    def vrm_vortex_velocity(self, cloud: Cloud, vort, nu, t, u, v):
+        _check(lib().vrm_vortex_velocity(self.handle, ctypes.byref(cloud.c), _ptr(vort), int(vort.shape[0]),
+                                         float(nu), float(t), _ptr(u), _ptr(v)))
+
+    # --- convenience
+    def step(self, cloud: Cloud, p: vrm_params, velocity=None, t=0.0, insertion=True):
+        """One SSP-RK3 step: insertion (diffused set, new particles, reorder), then three stages.
+        velocity(cloud, t_stage) -> (u, v) device tensors or None for zero velocity."""
+        if insertion:
+            self.vrm_insert_particles(cloud, p)
+        for s, c in enumerate((0.0, 1.0, 0.5)):
+            uv = velocity(cloud, t + c * p.dt) if velocity is not None else None
+            u, v = uv if uv is not None else (None, None)
+            self.vrm_rk_stage(cloud, p, s, u, v)
+
+
+def vortex_table(v: dict, device="cuda"):
+    """Device table [n][4] (cx, cy, sigma, Gamma) for vrm_vortex_velocity."""
+    import torch
+    tab = np.stack([v["cx"], v["cy"], v["sigma"], v["gamma"]], 1).astype(np.float32)
+    return torch.as_tensor(tab, device=device).contiguous()

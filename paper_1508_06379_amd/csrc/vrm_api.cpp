@@ -1,0 +1,381 @@
+// C ABI of libvrm: context management, argument checking and the order of
+// the kernel launches of each entry point (the entry points are documented
+// in include/vrm.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "vrm_internal.h"
+
+size_t vrm_sort_tmp_bytes(int32_t cap);
+
+namespace {
+thread_local std::string g_err;
+
+vrm::LaunchParams launch_params(const vrm_params* p)
+{
+    vrm::LaunchParams L{};
+    const double h = p->h;
+    L.h = (float)h;
+    L.lo2 = (float)(p->r * p->r * h * h * (1.0 - 0x1p-20));
+    L.hi2 = (float)(p->R * p->R * h * h * (1.0 + 0x1p-20));
+    L.lo2f = L.lo2;
+    L.hi2f = (float)(p->R_full * p->R_full * h * h * (1.0 + 0x1p-20));
+    L.rad = (float)(1.5 * h);
+    L.ex2 = (float)(0.25 * h * h);
+    // exact offset scaling by 2^-e with 2^e >= h; the rhs and costs absorb s = 2^e / h
+    int e = (int)std::ceil(std::log2(h));
+    if (std::ldexp(1.0, e) < h) ++e;
+    L.scale2e = (float)std::ldexp(1.0, -e);
+    double s = std::ldexp(1.0, e) / h;
+    double bt = 2.0 / (s * s);
+    L.bt_hi = (float)bt;
+    L.bt_lo = (float)(bt - (double)L.bt_hi);
+    double cs = std::pow(s, p->q + 1);
+    L.cs_hi = (float)cs;
+    L.cs_lo = (float)(cs - (double)L.cs_hi);
+    L.lam = (float)(p->nu / (h * h));
+    L.q = p->q;
+    L.m = p->q == 2 ? 5 : 9;
+    return L;
+}
+
+int check_params(const vrm_params* p)
+{
+    if (!p) return vrm_fail(VRM_E_ARG, "params is NULL");
+    if (!(p->h > 0.0) || !std::isfinite(p->h)) return vrm_fail(VRM_E_ARG, "h must be positive and finite");
+    if (!(p->r > 0.0) || !(p->R > p->r) || !std::isfinite(p->R))
+        return vrm_fail(VRM_E_ARG, "need 0 < r < R (got r=%g, R=%g)", p->r, p->R);
+    if (!(p->R_full >= p->R) || !std::isfinite(p->R_full))
+        return vrm_fail(VRM_E_ARG, "need R_full >= R (got %g)", p->R_full);
+    if (p->q != 2 && p->q != 3) return vrm_fail(VRM_E_ARG, "q must be 2 or 3 (got %d)", p->q);
+    if (!(p->nu >= 0.0) || !std::isfinite(p->nu)) return vrm_fail(VRM_E_ARG, "nu must be >= 0");
+    if (!(p->c_diff >= 0.0) || !std::isfinite(p->c_diff)) return vrm_fail(VRM_E_ARG, "c_diff must be >= 0");
+    if (!(p->dt >= 0.0) || !std::isfinite(p->dt)) return vrm_fail(VRM_E_ARG, "dt must be >= 0");
+    return VRM_OK;
+}
+
+int check_cloud(vrm_ctx* c, const vrm_cloud* cl)
+{
+    if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
+    if (!cl || !cl->x_dev || !cl->y_dev || !cl->gamma_dev || !cl->id_dev || !cl->n_dev)
+        return vrm_fail(VRM_E_ARG, "cloud or one of its arrays is NULL");
+    if (cl->capacity <= 0 || cl->capacity > c->capacity)
+        return vrm_fail(VRM_E_ARG, "cloud capacity %d outside (0, %d]", cl->capacity, c->capacity);
+    return VRM_OK;
+}
+
+// Read N from the device (synchronises) and remember it.
+int read_n(vrm_ctx* c, const vrm_cloud* cl)
+{
+    int32_t n = 0;
+    VRM_HIP(hipMemcpyAsync(&n, cl->n_dev, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    VRM_HIP(hipStreamSynchronize(c->stream));
+    if (n < 0 || n > cl->capacity) return vrm_fail(VRM_E_ARG, "particle count %d outside [0, %d]", n, cl->capacity);
+    c->n = n;
+    c->n_ptr = cl->n_dev;
+    return VRM_OK;
+}
+
+int cached_n(vrm_ctx* c, const vrm_cloud* cl)
+{
+    if (c->n_ptr != cl->n_dev || !c->n_diffused_valid)
+        return vrm_fail(VRM_E_STATE, "no diffused set for this cloud: call vrm_select_diffused, vrm_set_diffused or "
+                                     "vrm_insert_particles first");
+    return VRM_OK;
+}
+
+template <typename T>
+int alloc(T** p, size_t count)
+{
+    void* q = nullptr;
+    VRM_HIP(hipMalloc(&q, count * sizeof(T) + 16));
+    *p = static_cast<T*>(q);
+    return VRM_OK;
+}
+
+__global__ void k_copy_mask(int n, const uint8_t* in, uint8_t* out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i] ? 1 : 0;
+}
+}  // namespace
+
+int vrm_fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int vrm_hip_check(hipError_t e, const char* what)
+{
+    return vrm_fail(VRM_E_HIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+extern "C" {
+
+const char* vrm_last_error(void) { return g_err.c_str(); }
+
+const char* vrm_status_string(int code)
+{
+    switch (code) {
+    case VRM_OK: return "ok";
+    case VRM_E_ARG: return "invalid argument";
+    case VRM_E_CAPACITY: return "capacity exceeded";
+    case VRM_E_HIP: return "HIP runtime error";
+    case VRM_E_STATE: return "invalid call order";
+    default: return "unknown";
+    }
+}
+
+int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
+{
+    if (!out) return vrm_fail(VRM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (capacity <= 0 || capacity > (1 << 28)) return vrm_fail(VRM_E_ARG, "capacity %d outside (0, 2^28]", capacity);
+    VRM_HIP(hipSetDevice(device));
+    vrm_ctx* c = new vrm_ctx();
+    std::memset(c, 0, sizeof(*c));
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    c->capacity = capacity;
+    c->ncell_cap = 2 * capacity + 4096;
+    size_t cap = (size_t)capacity, cap2 = 2 * cap, nc = (size_t)c->ncell_cap + 1;
+    int r = VRM_OK;
+#define A(ptr, n)                                \
+    if (r == VRM_OK) r = alloc(&c->ptr, (n));
+    A(grid, 1);
+    A(queues, 1);
+    A(sel, 1);
+    A(counters, 1);
+    A(cell_of, cap);
+    A(rank, cap);
+    A(cell_start, nc);
+    A(scan_part, 1024);
+    A(perm, cap);
+    A(xs, cap);
+    A(ys, cap);
+    A(ids, cap);
+    A(diffused, cap);
+    A(acc, cap);
+    A(x0, cap);
+    A(y0, cap);
+    A(g0, cap);
+    A(q_small, cap);
+    A(q_full, cap);
+    A(small_slot, cap * VRM_NSEG);
+    A(cx, cap2);
+    A(cy, cap2);
+    A(ckey, cap2);
+    A(cstate, cap2);
+    A(ccell, cap2);
+    A(crank, cap2);
+    A(cstart, nc);
+    A(cperm, cap2);
+    A(akey, cap2);
+    A(aidx, cap2);
+    A(tmp_f, 3 * cap);
+    A(tmp_i, cap);
+    A(tmp_u8, cap);
+    A(verify_buf, 8);
+#undef A
+    if (r == VRM_OK) {
+        c->sort_tmp_bytes = vrm_sort_tmp_bytes(capacity);
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, c->sort_tmp_bytes + 256);
+        if (e != hipSuccess) r = vrm_hip_check(e, "hipMalloc(sort)");
+        c->sort_tmp = p;
+    }
+    if (r == VRM_OK) {
+        hipError_t e = hipMemsetAsync(c->acc, 0, cap * sizeof(float), c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->counters, 0, sizeof(vrm_counters), c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) r = vrm_hip_check(e, "initialisation");
+    }
+    if (r != VRM_OK) {
+        std::string keep = g_err;
+        vrm_destroy(c);
+        g_err = keep;
+        return r;
+    }
+    *out = c;
+    return VRM_OK;
+}
+
+int vrm_destroy(vrm_ctx* c)
+{
+    if (!c) return VRM_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    void* ptrs[] = {c->grid, c->queues, c->sel, c->counters, c->cell_of, c->rank, c->cell_start, c->scan_part,
+                    c->perm, c->xs, c->ys, c->ids, c->diffused, c->acc, c->x0, c->y0, c->g0, c->q_small, c->q_full,
+                    c->small_slot, c->cx, c->cy, c->ckey, c->cstate, c->ccell, c->crank, c->cstart, c->cperm,
+                    c->akey, c->aidx, c->tmp_f, c->tmp_i, c->tmp_u8, c->verify_buf, c->sort_tmp};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete c;
+    return VRM_OK;
+}
+
+int vrm_select_diffused(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, uint8_t* mask_dev)
+{
+    int r = check_cloud(c, cl);
+    if (!r) r = check_params(p);
+    if (!r) r = read_n(c, cl);
+    if (r) return r;
+    double factor = p->c_diff * std::pow(p->h, p->q + 1);
+    r = vrm_select_run(c, cl->gamma_dev, c->n, factor);
+    if (r) return r;
+    if (mask_dev && c->n > 0) {
+        hipLaunchKernelGGL(k_copy_mask, dim3((c->n + 255) / 256), dim3(256), 0, c->stream, c->n, c->diffused, mask_dev);
+        VRM_HIP(hipGetLastError());
+    }
+    c->n_diffused_valid = 1;
+    return VRM_OK;
+}
+
+int vrm_set_diffused(vrm_ctx* c, const vrm_cloud* cl, const uint8_t* mask_dev)
+{
+    int r = check_cloud(c, cl);
+    if (!r && !mask_dev) r = vrm_fail(VRM_E_ARG, "mask is NULL");
+    if (!r) r = read_n(c, cl);
+    if (r) return r;
+    if (c->n > 0) {
+        hipLaunchKernelGGL(k_copy_mask, dim3((c->n + 255) / 256), dim3(256), 0, c->stream, c->n, mask_dev, c->diffused);
+        VRM_HIP(hipGetLastError());
+    }
+    c->n_diffused_valid = 1;
+    return VRM_OK;
+}
+
+int vrm_build_neighbourhoods(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, int32_t* small_idx_dev,
+                             int32_t* kfull_dev)
+{
+    int r = check_cloud(c, cl);
+    if (!r) r = check_params(p);
+    if (!r) r = cached_n(c, cl);
+    if (r) return r;
+    vrm::LaunchParams L = launch_params(p);
+    r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
+    if (r) return r;
+    c->cells_valid = 1;
+    return vrm_small_nbhd_run(c, cl, c->n, L, small_idx_dev, kfull_dev);
+}
+
+int vrm_insert_particles(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p)
+{
+    int r = check_cloud(c, cl);
+    if (!r) r = check_params(p);
+    if (!r) r = read_n(c, cl);
+    if (r) return r;
+    vrm::LaunchParams L = launch_params(p);
+    double factor = p->c_diff * std::pow(p->h, p->q + 1);
+    r = vrm_select_run(c, cl->gamma_dev, c->n, factor);
+    if (!r) r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
+    if (r) return r;
+    c->n_diffused_valid = 1;
+    int n2 = vrm_insert_run(c, cl, c->n, L);
+    if (n2 < 0) {
+        c->cells_valid = 1;   // the cloud is unchanged
+        return n2;
+    }
+    c->n = n2;
+    r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, n2, L);
+    if (!r) r = vrm_reorder_cloud(c, cl, n2);
+    if (r) return r;
+    c->cells_valid = 1;
+    c->base_valid = 0;
+    return VRM_OK;
+}
+
+int vrm_solve_fractions(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, vrm_stencils* out)
+{
+    int r = check_cloud(c, cl);
+    if (!r) r = check_params(p);
+    if (!r) r = cached_n(c, cl);
+    if (!r && (!out || !out->small_idx_dev || !out->small_f_dev || !out->fii_dev || !out->status_dev ||
+               !out->full_k_dev || (!out->full_idx_dev) != (!out->full_f_dev)))
+        r = vrm_fail(VRM_E_ARG, "stencil output arrays missing");
+    if (r) return r;
+    vrm::LaunchParams L = launch_params(p);
+    if (!c->cells_valid) {
+        r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
+        if (r) return r;
+        c->cells_valid = 1;
+    }
+    return vrm_stencil_run(c, cl, c->n, L, out, 0);
+}
+
+int vrm_rk_stage(vrm_ctx* c, vrm_cloud* cl, const float* u_dev, const float* v_dev, const vrm_params* p, int stage)
+{
+    int r = check_cloud(c, cl);
+    if (!r) r = check_params(p);
+    if (!r) r = cached_n(c, cl);
+    if (!r && (stage < 0 || stage > 2)) r = vrm_fail(VRM_E_ARG, "stage must be 0, 1 or 2 (got %d)", stage);
+    if (!r && ((u_dev == nullptr) != (v_dev == nullptr))) r = vrm_fail(VRM_E_ARG, "u and v must both be given or both NULL");
+    if (!r && stage > 0 && !c->base_valid) r = vrm_fail(VRM_E_STATE, "stage %d before stage 0", stage);
+    if (r) return r;
+    int n = c->n;
+    vrm::LaunchParams L = launch_params(p);
+    if (stage == 0) {
+        if (n > 0) {
+            VRM_HIP(hipMemcpyAsync(c->x0, cl->x_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
+            VRM_HIP(hipMemcpyAsync(c->y0, cl->y_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
+            VRM_HIP(hipMemcpyAsync(c->g0, cl->gamma_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
+        }
+        c->base_valid = 1;
+    }
+    if (!c->cells_valid) {
+        r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, n, L);
+        if (r) return r;
+        c->cells_valid = 1;
+    }
+    r = vrm_stencil_run(c, cl, n, L, nullptr, 1);
+    if (!r) r = vrm_combine_run(c, cl, n, u_dev, v_dev, p->dt, L.lam, stage);
+    if (r) return r;
+    if (u_dev) c->cells_valid = 0;
+    if (stage == 2) c->base_valid = 0;
+    return VRM_OK;
+}
+
+int vrm_verify(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, const vrm_stencils* st, double* report_dev)
+{
+    int r = check_cloud(c, cl);
+    if (!r) r = check_params(p);
+    if (!r && !report_dev) r = vrm_fail(VRM_E_ARG, "report is NULL");
+    if (!r && c->n_ptr != cl->n_dev) r = read_n(c, cl);
+    if (r) return r;
+    vrm::LaunchParams L = launch_params(p);
+    return vrm_verify_run(c, cl, c->n, L, st, report_dev);
+}
+
+int vrm_read_counters(vrm_ctx* c, vrm_counters* out)
+{
+    if (!c || !out) return vrm_fail(VRM_E_ARG, "NULL argument");
+    VRM_HIP(hipMemcpyAsync(out, c->counters, sizeof(vrm_counters), hipMemcpyDeviceToHost, c->stream));
+    VRM_HIP(hipStreamSynchronize(c->stream));
+    out->n = c->n;
+    return VRM_OK;
+}
+
+int vrm_vortex_velocity(vrm_ctx* c, const vrm_cloud* cl, const float* vort_dev, int32_t n_vort, double nu, double t,
+                        float* u_dev, float* v_dev)
+{
+    int r = check_cloud(c, cl);
+    if (!r && (!u_dev || !v_dev || (n_vort > 0 && !vort_dev) || n_vort < 0))
+        r = vrm_fail(VRM_E_ARG, "velocity arguments");
+    if (!r && c->n_ptr != cl->n_dev) r = read_n(c, cl);
+    if (r) return r;
+    return vrm_velocity_run(c, cl, c->n, vort_dev, n_vort, nu, t, u_dev, v_dev);
+}
+
+}  // extern "C"

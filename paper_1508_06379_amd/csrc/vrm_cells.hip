@@ -1,0 +1,634 @@
+// Cell lists, reduced-operator selection and particle insertion of libvrm.
+//
+// Cell list: a counting sort of the particles into square cells of edge
+// max(R, R_full) h (so a 3 x 3 block of cells covers every neighbourhood),
+// over the bounding box found on the device.  Selection: Sec. 3.5, eq.
+// reduced_bound, by a radix select on the bits of |Gamma| with FP64 bucket
+// sums.  Insertion: Sec. 4.2, with conflicts between candidates resolved to
+// the greedy result in (id, segment) order by rounds of the lexicographically
+// first independent set.
+#include <hip/hip_runtime.h>
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "vrm_device.h"
+#include "vrm_internal.h"
+
+using namespace vrm;
+
+namespace {
+
+constexpr int kScanBlocks = 512;
+
+__global__ void k_grid_reset(GridState* g)
+{
+    g->bbox[0] = 0xffffffffu;
+    g->bbox[1] = 0xffffffffu;
+    g->bbox[2] = 0u;
+    g->bbox[3] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ x, const float* __restrict__ y, int n,
+                                              GridState* g)
+{
+    uint32_t mnx = 0xffffffffu, mny = 0xffffffffu, mxx = 0u, mxy = 0u;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        float xv = x[i], yv = y[i];
+        if (!(fabsf(xv) <= 3.0e38f) || !(fabsf(yv) <= 3.0e38f)) continue;   // skip non-finite
+        uint32_t kx = ordered_key(xv), ky = ordered_key(yv);
+        mnx = min(mnx, kx);
+        mny = min(mny, ky);
+        mxx = max(mxx, kx);
+        mxy = max(mxy, ky);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mnx = min(mnx, (uint32_t)__shfl_xor((int)mnx, o, VRM_WAVE));
+        mny = min(mny, (uint32_t)__shfl_xor((int)mny, o, VRM_WAVE));
+        mxx = max(mxx, (uint32_t)__shfl_xor((int)mxx, o, VRM_WAVE));
+        mxy = max(mxy, (uint32_t)__shfl_xor((int)mxy, o, VRM_WAVE));
+    }
+    if (lane_id() == 0) {
+        atomicMin(&g->bbox[0], mnx);
+        atomicMin(&g->bbox[1], mny);
+        atomicMax(&g->bbox[2], mxx);
+        atomicMax(&g->bbox[3], mxy);
+    }
+}
+
+__global__ void k_grid_params(GridState* g, float cs, int ncell_cap, vrm_counters* cnt)
+{
+    float xmin = 0.0f, ymin = 0.0f, xmax = 0.0f, ymax = 0.0f;
+    if (g->bbox[0] != 0xffffffffu) {
+        xmin = ordered_key_inv(g->bbox[0]);
+        ymin = ordered_key_inv(g->bbox[1]);
+        xmax = ordered_key_inv(g->bbox[2]);
+        ymax = ordered_key_inv(g->bbox[3]);
+    }
+    g->cs = cs;
+    g->inv_cs = 1.0f / cs;
+    g->x0 = xmin - cs;
+    g->y0 = ymin - cs;
+    double fx = ((double)xmax - (double)g->x0) * (double)g->inv_cs;
+    double fy = ((double)ymax - (double)g->y0) * (double)g->inv_cs;
+    long long nx = (long long)fmin(fx, 1.0e9) + 2;
+    long long ny = (long long)fmin(fy, 1.0e9) + 2;
+    int clamped = 0;
+    if (nx * ny > ncell_cap) {
+        // keep the aspect ratio; far particles share the edge cells (still exact, slower)
+        double f = sqrt((double)ncell_cap / (double)(nx * ny));
+        nx = nx * f > 1 ? (long long)(nx * f) : 1;
+        ny = ncell_cap / nx;
+        clamped = 1;
+    }
+    g->nx = (int)nx;
+    g->ny = (int)ny;
+    g->ncells = (int)(nx * ny);
+    g->clamped = clamped;
+    if (clamped) atomicAdd(&cnt->n_grid_clamped, 1);
+}
+
+__device__ __forceinline__ int cell_index(const GridState& g, float x, float y)
+{
+    float fx = (x - g.x0) * g.inv_cs;
+    float fy = (y - g.y0) * g.inv_cs;
+    fx = fminf(fmaxf(fx, 0.0f), (float)(g.nx - 1));
+    fy = fminf(fmaxf(fy, 0.0f), (float)(g.ny - 1));
+    return (int)fy * g.nx + (int)fx;
+}
+
+__global__ __launch_bounds__(256) void k_clear_cells(int32_t* start, const GridState* g)
+{
+    int nc = g->ncells + 1;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) start[c] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_count(const float* __restrict__ x, const float* __restrict__ y, int n,
+                                               const GridState* gs, int32_t* start, int32_t* cell_of, int32_t* rank)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    GridState g = *gs;
+    int c = cell_index(g, x[i], y[i]);
+    cell_of[i] = c;
+    rank[i] = atomicAdd(&start[c], 1);
+}
+
+// ----- three-kernel exclusive scan over start[0..ncells), total in start[ncells]
+__device__ __forceinline__ int block_exclusive_scan(int v, int& total)
+{
+    __shared__ int wsum[8];
+    int lane = lane_id(), w = threadIdx.x >> 6;
+    int incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(incl, o, VRM_WAVE);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int nw = blockDim.x >> 6;
+    int off = 0, tot = 0;
+    for (int k = 0; k < nw; ++k) {
+        int s = wsum[k];
+        if (k < w) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return off + incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_partial(const int32_t* start, const GridState* g, int32_t* part)
+{
+    int nc = g->ncells;
+    int chunk = (nc + kScanBlocks - 1) / kScanBlocks;
+    int lo = blockIdx.x * chunk, hi = min(nc, lo + chunk);
+    int s = 0;
+    for (int c = lo + threadIdx.x; c < hi; c += blockDim.x) s += start[c];
+    int tot;
+    block_exclusive_scan(s, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanBlocks) void k_scan_top(int32_t* part)
+{
+    int v = part[threadIdx.x];
+    int tot;
+    int ex = block_exclusive_scan(v, tot);
+    part[threadIdx.x] = ex;
+    if (threadIdx.x == 0) part[kScanBlocks] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_final(int32_t* start, const GridState* g, const int32_t* part)
+{
+    int nc = g->ncells;
+    int chunk = (nc + kScanBlocks - 1) / kScanBlocks;
+    int lo = blockIdx.x * chunk, hi = min(nc, lo + chunk);
+    int carry = part[blockIdx.x];
+    for (int base = lo; base < hi; base += blockDim.x) {
+        int c = base + threadIdx.x;
+        int v = c < hi ? start[c] : 0;
+        int tot;
+        int ex = block_exclusive_scan(v, tot);
+        if (c < hi) start[c] = carry + ex;
+        carry += tot;
+    }
+    if (blockIdx.x == kScanBlocks - 1 && threadIdx.x == 0) start[nc] = part[kScanBlocks];
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ x, const float* __restrict__ y,
+                                                 const int32_t* __restrict__ id, int n,
+                                                 const int32_t* __restrict__ start, const int32_t* __restrict__ cell_of,
+                                                 const int32_t* __restrict__ rank, int32_t* perm, float* xs, float* ys,
+                                                 int32_t* ids)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int t = start[cell_of[i]] + rank[i];
+    perm[t] = i;
+    if (xs) {
+        xs[t] = x[i];
+        ys[t] = y[i];
+        ids[t] = id[i];
+    }
+}
+
+int scan_cells(vrm_ctx* c, int32_t* start)
+{
+    hipLaunchKernelGGL(k_scan_partial, dim3(kScanBlocks), dim3(256), 0, c->stream, start, c->grid, c->scan_part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlocks), 0, c->stream, c->scan_part);
+    hipLaunchKernelGGL(k_scan_final, dim3(kScanBlocks), dim3(256), 0, c->stream, start, c->grid, c->scan_part);
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
+}
+
+// ------------------------------------------------------ reduced operator
+// Ranking key: |Gamma| truncated to 16 significant bits, so circulations that
+// are equal up to round-off form one group (whole groups are left out).
+__device__ __forceinline__ uint32_t selection_key(float a) { return __float_as_uint(a) & 0xffffff00u; }
+
+__global__ void k_sel_init(SelectState* s)
+{
+    int t = threadIdx.x;
+    if (t == 0) {
+        s->norm1 = 0.0;
+        s->bound = 0.0;
+        s->prefix = 0.0;
+        s->key_prefix = 0u;
+        s->done = 0u;
+        s->threshold = 0u;
+    }
+    s->bin_sum[t] = 0.0;
+    s->bin_cnt[t] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ g, int n, SelectState* s, int shift)
+{
+    __shared__ double h_sum[256];
+    __shared__ uint32_t h_cnt[256];
+    h_sum[threadIdx.x] = 0.0;
+    h_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    if (!s->done) {
+        uint32_t pre = s->key_prefix;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            float a = fabsf(g[i]);
+            uint32_t key = selection_key(a);
+            if (shift < 24 && (key >> (shift + 8)) != (pre >> (shift + 8))) continue;
+            int b = (key >> shift) & 255u;
+            atomicAdd(&h_sum[b], (double)a);
+            atomicAdd(&h_cnt[b], 1u);
+        }
+    }
+    __syncthreads();
+    if (h_cnt[threadIdx.x]) {
+        atomicAdd(&s->bin_sum[threadIdx.x], h_sum[threadIdx.x]);
+        atomicAdd(&s->bin_cnt[threadIdx.x], h_cnt[threadIdx.x]);
+    }
+}
+
+__global__ void k_sel_pick(SelectState* s, int shift, double factor)
+{
+    if (threadIdx.x != 0) return;
+    if (shift == 24) {
+        double tot = 0.0;
+        for (int b = 0; b < 256; ++b) tot += s->bin_sum[b];
+        s->norm1 = tot;
+        s->bound = factor * tot;
+        s->prefix = 0.0;
+    }
+    if (s->done) return;
+    double cum = s->prefix;
+    int b = 0;
+    for (; b < 256; ++b) {
+        if (cum + s->bin_sum[b] > s->bound) break;
+        cum += s->bin_sum[b];
+    }
+    if (b == 256) {
+        // every particle in the current key range is left out
+        uint64_t top = (uint64_t)s->key_prefix + ((uint64_t)256 << shift);
+        s->threshold = top > 0xffffffffull ? 0xffffffffu : (uint32_t)top;
+        s->done = top > 0xffffffffull ? 2u : 1u;
+    } else {
+        s->key_prefix |= (uint32_t)b << shift;
+        s->prefix = cum;
+        if (shift == 0) {
+            s->threshold = s->key_prefix;
+            s->done = 1u;
+        }
+    }
+    for (int k = 0; k < 256; ++k) {
+        s->bin_sum[k] = 0.0;
+        s->bin_cnt[k] = 0u;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sel_mask(const float* __restrict__ g, int n, const SelectState* s,
+                                                  uint8_t* diffused, uint8_t* mask_out, vrm_counters* cnt)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool d = false;
+    if (i < n) {
+        uint32_t key = selection_key(fabsf(g[i]));
+        d = s->done == 2u ? false : key >= s->threshold;
+        diffused[i] = d ? 1 : 0;
+        if (mask_out) mask_out[i] = d ? 1 : 0;
+    }
+    uint64_t m = __ballot(d);
+    if (lane_id() == 0 && m) atomicAdd(&cnt->n_diffused, __popcll(m));
+}
+
+__global__ void k_zero_diffused_count(vrm_counters* cnt) { cnt->n_diffused = 0; }
+
+// ------------------------------------------------------------ insertion
+__device__ __forceinline__ int wave_append_n(int* counter, int want)
+{
+    int lane = lane_id();
+    int incl = want;
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(incl, o, VRM_WAVE);
+        if (lane >= o) incl += t;
+    }
+    int total = __shfl(incl, 63, VRM_WAVE);
+    int base = 0;
+    if (lane == 0 && total) base = atomicAdd(counter, total);
+    base = __shfl(base, 0, VRM_WAVE);
+    return base + incl - want;
+}
+
+// Candidates: every empty segment of a diffused particle (slot order).
+__global__ __launch_bounds__(256) void k_candidates(int n, const int32_t* __restrict__ perm,
+                                                    const float* __restrict__ xs, const float* __restrict__ ys,
+                                                    const int32_t* __restrict__ ids,
+                                                    const int32_t* __restrict__ cell_start,
+                                                    const uint8_t* __restrict__ diffused, const GridState* gs,
+                                                    LaunchParams P, Queues* qs, int cand_cap, float* cx, float* cy,
+                                                    uint64_t* ckey, uint8_t* cstate)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int occupied = 0xff;
+    float xi = 0.0f, yi = 0.0f;
+    if (t < n && diffused[perm[t]]) {
+        occupied = 0;
+        GridState g = *gs;
+        xi = xs[t];
+        yi = ys[t];
+        int c0 = cell_index(g, xi, yi);
+        int cxi = c0 % g.nx, cyi = c0 / g.nx;
+        for (int oy = -1; oy <= 1; ++oy) {
+            int yy = cyi + oy;
+            if (yy < 0 || yy >= g.ny) continue;
+            for (int ox = -1; ox <= 1; ++ox) {
+                int xx = cxi + ox;
+                if (xx < 0 || xx >= g.nx) continue;
+                int c = yy * g.nx + xx;
+                for (int u = cell_start[c]; u < cell_start[c + 1]; ++u) {
+                    if (u == t) continue;
+                    float dx = xs[u] - xi;
+                    float dy = ys[u] - yi;
+                    float d2 = d2_f32(dx, dy);
+                    if (d2 < P.lo2 || d2 > P.hi2) continue;
+                    occupied |= 1 << segment_f32(dx, dy);
+                }
+            }
+        }
+    }
+    int empty = (~occupied) & 0xff;
+    int want = __popc(empty);
+    int base = wave_append_n(&qs->n_cand, want);
+    if (want) {
+        int id = ids[t];
+        int k = 0;
+        for (int s = 0; s < VRM_NSEG; ++s) {
+            if (!(empty & (1 << s))) continue;
+            int p = base + k++;
+            if (p >= cand_cap) continue;
+            float xc, yc;
+            candidate_f32(xi, yi, P.rad, s, xc, yc);
+            cx[p] = xc;
+            cy[p] = yc;
+            ckey[p] = ((uint64_t)(uint32_t)id << 3) | (uint64_t)s;
+            cstate[p] = 0;
+        }
+    }
+}
+
+// One round of the lexicographically first independent set: a candidate is
+// accepted once every conflicting candidate of smaller key is rejected, and
+// rejected as soon as one of them is accepted.
+__global__ __launch_bounds__(256) void k_mis_round(int nc, const float* __restrict__ cx, const float* __restrict__ cy,
+                                                   const uint64_t* __restrict__ ckey, uint8_t* cstate,
+                                                   const int32_t* __restrict__ cstart, const int32_t* __restrict__ cperm,
+                                                   const GridState* gs, float ex2, Queues* qs)
+{
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    bool undecided = false;
+    if (a < nc && cstate[a] == 0) {
+        GridState g = *gs;
+        float xa = cx[a], ya = cy[a];
+        uint64_t ka = ckey[a];
+        int c0 = cell_index(g, xa, ya);
+        int cxa = c0 % g.nx, cya = c0 / g.nx;
+        bool any_in = false, any_open = false;
+        for (int oy = -1; oy <= 1 && !any_in; ++oy) {
+            int yy = cya + oy;
+            if (yy < 0 || yy >= g.ny) continue;
+            for (int ox = -1; ox <= 1 && !any_in; ++ox) {
+                int xx = cxa + ox;
+                if (xx < 0 || xx >= g.nx) continue;
+                int c = yy * g.nx + xx;
+                for (int u = cstart[c]; u < cstart[c + 1]; ++u) {
+                    int b = cperm[u];
+                    if (b == a || ckey[b] >= ka) continue;
+                    float dx = cx[b] - xa;
+                    float dy = cy[b] - ya;
+                    if (!(d2_f32(dx, dy) < ex2)) continue;
+                    uint8_t sb = ((volatile const uint8_t*)cstate)[b];
+                    if (sb == 1) {
+                        any_in = true;
+                        break;
+                    }
+                    if (sb == 0) any_open = true;
+                }
+            }
+        }
+        if (any_in)
+            cstate[a] = 2;
+        else if (!any_open)
+            cstate[a] = 1;
+        else
+            undecided = true;
+    }
+    uint64_t m = __ballot(undecided);
+    if (lane_id() == 0 && m) atomicAdd(&qs->n_undecided, __popcll(m));
+}
+
+__global__ __launch_bounds__(256) void k_accepted(int nc, const uint64_t* __restrict__ ckey,
+                                                  const uint8_t* __restrict__ cstate, Queues* qs, uint64_t* akey,
+                                                  int32_t* aidx)
+{
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    bool acc = a < nc && cstate[a] == 1;
+    int p = wave_append_n(&qs->n_accepted, acc ? 1 : 0);
+    if (acc) {
+        akey[p] = ckey[a];
+        aidx[p] = a;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_append(int n0, int na, const int32_t* __restrict__ aidx_sorted,
+                                                const float* __restrict__ cx, const float* __restrict__ cy, float* x,
+                                                float* y, float* gamma, int32_t* id, uint8_t* diffused, int32_t* n_dev)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0) *n_dev = n0 + na;
+    if (r >= na) return;
+    int a = aidx_sorted[r];
+    x[n0 + r] = cx[a];
+    y[n0 + r] = cy[a];
+    gamma[n0 + r] = 0.0f;
+    id[n0 + r] = n0 + r;
+    diffused[n0 + r] = 0;
+}
+
+// ------------------------------------------------------------- reorder
+__global__ __launch_bounds__(256) void k_gather_cloud(int n, const int32_t* __restrict__ perm,
+                                                      const float* __restrict__ g, const uint8_t* __restrict__ dif,
+                                                      float* tg, uint8_t* tdif)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int i = perm[t];
+    tg[t] = g[i];
+    tdif[t] = dif[i];
+}
+
+__global__ __launch_bounds__(256) void k_iota(int n, int32_t* perm)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) perm[t] = t;
+}
+
+__global__ void k_reset_insert(Queues* q)
+{
+    q->n_cand = 0;
+    q->n_undecided = 0;
+    q->n_accepted = 0;
+}
+__global__ void k_reset_undecided(Queues* q) { q->n_undecided = 0; }
+
+__global__ void k_insert_counters(const Queues* q, vrm_counters* cnt, int rounds, int n_after)
+{
+    cnt->n_candidates = q->n_cand;
+    cnt->n_inserted = q->n_accepted;
+    cnt->mis_rounds = rounds;
+    cnt->n = n_after;
+}
+
+int blocks_for(int n) { return n > 0 ? (n + 255) / 256 : 1; }
+
+}  // namespace
+
+// Cell list of (x, y) into ctx->cell_start / perm / xs, ys, ids (slot order).
+int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* id, int32_t n, const LaunchParams& lp)
+{
+    hipStream_t s = c->stream;
+    hipLaunchKernelGGL(k_grid_reset, dim3(1), dim3(1), 0, s, c->grid);
+    int nbb = min(1024, blocks_for(n));
+    hipLaunchKernelGGL(k_bbox, dim3(nbb), dim3(256), 0, s, x, y, n, c->grid);
+    float Rmax = (float)fmax((double)lp.hi2, (double)lp.hi2f);
+    float cs = sqrtf(Rmax) * (1.0f + 1.0f / 1024.0f);
+    hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(1), 0, s, c->grid, cs, c->ncell_cap, c->counters);
+    hipLaunchKernelGGL(k_clear_cells, dim3(1024), dim3(256), 0, s, c->cell_start, c->grid);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_count, dim3(blocks_for(n)), dim3(256), 0, s, x, y, n, c->grid, c->cell_start, c->cell_of,
+                           c->rank);
+    }
+    VRM_HIP(hipGetLastError());
+    int r = scan_cells(c, c->cell_start);
+    if (r) return r;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(256), 0, s, x, y, id, n, c->cell_start, c->cell_of,
+                           c->rank, c->perm, c->xs, c->ys, c->ids);
+    }
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
+}
+
+int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double factor)
+{
+    hipStream_t s = c->stream;
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c->sel);
+    int nb = min(2048, blocks_for(n));
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        if (n > 0) hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, s, gamma, n, c->sel, shift);
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(64), 0, s, c->sel, shift, factor);
+    }
+    hipLaunchKernelGGL(k_zero_diffused_count, dim3(1), dim3(1), 0, s, c->counters);
+    if (n > 0)
+        hipLaunchKernelGGL(k_sel_mask, dim3(blocks_for(n)), dim3(256), 0, s, gamma, n, c->sel, c->diffused,
+                           (uint8_t*)nullptr, c->counters);
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
+}
+
+// Insertion; the cell list of the cloud must be current.  Synchronises.
+int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp)
+{
+    hipStream_t s = c->stream;
+    const int cand_cap = 2 * c->capacity;
+    hipLaunchKernelGGL(k_reset_insert, dim3(1), dim3(1), 0, s, c->queues);
+    if (n > 0)
+        hipLaunchKernelGGL(k_candidates, dim3(blocks_for(n)), dim3(256), 0, s, n, c->perm, c->xs, c->ys, c->ids,
+                           c->cell_start, c->diffused, c->grid, lp, c->queues, cand_cap, c->cx, c->cy, c->ckey,
+                           c->cstate);
+    VRM_HIP(hipGetLastError());
+    Queues q;
+    VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
+    VRM_HIP(hipStreamSynchronize(s));
+    int nc = q.n_cand;
+    if (nc > cand_cap) return vrm_fail(VRM_E_CAPACITY, "insertion: %d candidates exceed the buffer of %d", nc, cand_cap);
+    int rounds = 0;
+    int na = 0;
+    if (nc > 0) {
+        // cell list of the candidates on the particles' grid
+        hipLaunchKernelGGL(k_clear_cells, dim3(1024), dim3(256), 0, s, c->cstart, c->grid);
+        hipLaunchKernelGGL(k_count, dim3(blocks_for(nc)), dim3(256), 0, s, c->cx, c->cy, nc, c->grid, c->cstart,
+                           c->ccell, c->crank);
+        VRM_HIP(hipGetLastError());
+        int r = scan_cells(c, c->cstart);
+        if (r) return r;
+        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nc)), dim3(256), 0, s, c->cx, c->cy, (const int32_t*)nullptr,
+                           nc, c->cstart, c->ccell, c->crank, c->cperm, (float*)nullptr, (float*)nullptr,
+                           (int32_t*)nullptr);
+        VRM_HIP(hipGetLastError());
+        for (;;) {
+            const int batch = 4;
+            for (int k = 0; k < batch; ++k) {
+                hipLaunchKernelGGL(k_reset_undecided, dim3(1), dim3(1), 0, s, c->queues);
+                hipLaunchKernelGGL(k_mis_round, dim3(blocks_for(nc)), dim3(256), 0, s, nc, c->cx, c->cy, c->ckey,
+                                   c->cstate, c->cstart, c->cperm, c->grid, lp.ex2, c->queues);
+            }
+            rounds += batch;
+            VRM_HIP(hipGetLastError());
+            VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
+            VRM_HIP(hipStreamSynchronize(s));
+            if (q.n_undecided == 0) break;
+            if (rounds > 4 * nc + 64)
+                return vrm_fail(VRM_E_STATE, "insertion: conflict resolution did not converge");
+        }
+        hipLaunchKernelGGL(k_accepted, dim3(blocks_for(nc)), dim3(256), 0, s, nc, c->ckey, c->cstate, c->queues,
+                           c->akey, c->aidx);
+        VRM_HIP(hipGetLastError());
+        VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
+        VRM_HIP(hipStreamSynchronize(s));
+        na = q.n_accepted;
+        if (n + na > cl->capacity) {
+            int need = n + na;
+            hipMemcpyAsync(&c->counters->capacity_needed, &need, sizeof(int), hipMemcpyHostToDevice, s);
+            hipStreamSynchronize(s);
+            return vrm_fail(VRM_E_CAPACITY, "insertion needs %d particles, capacity is %d", n + na, cl->capacity);
+        }
+        if (na > 0) {
+            // ids and append order follow the (id, segment) keys; sorted pairs go to the reorder scratch
+            size_t bytes = c->sort_tmp_bytes;
+            uint64_t* kin = c->akey;
+            int32_t* vin = c->aidx;
+            uint64_t* ksorted = reinterpret_cast<uint64_t*>(c->tmp_f);
+            int32_t* vsorted = c->tmp_i;
+            VRM_HIP(rocprim::radix_sort_pairs(c->sort_tmp, bytes, kin, ksorted, vin, vsorted, (size_t)na, 0, 35, s));
+            hipLaunchKernelGGL(k_append, dim3(blocks_for(na)), dim3(256), 0, s, n, na, vsorted, c->cx, c->cy, cl->x_dev,
+                               cl->y_dev, cl->gamma_dev, cl->id_dev, c->diffused, cl->n_dev);
+            VRM_HIP(hipGetLastError());
+        }
+    }
+    hipLaunchKernelGGL(k_insert_counters, dim3(1), dim3(1), 0, s, c->queues, c->counters, rounds, n + na);
+    VRM_HIP(hipGetLastError());
+    return n + na;
+}
+
+// Reorder the cloud by the current cell list (perm) and make perm the identity.
+int vrm_reorder_cloud(vrm_ctx* c, vrm_cloud* cl, int32_t n)
+{
+    if (n <= 0) return VRM_OK;
+    hipStream_t s = c->stream;
+    // xs, ys, ids already hold x, y, id in slot order
+    hipLaunchKernelGGL(k_gather_cloud, dim3(blocks_for(n)), dim3(256), 0, s, n, c->perm, cl->gamma_dev, c->diffused,
+                       c->tmp_f, c->tmp_u8);
+    VRM_HIP(hipGetLastError());
+    VRM_HIP(hipMemcpyAsync(cl->x_dev, c->xs, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    VRM_HIP(hipMemcpyAsync(cl->y_dev, c->ys, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    VRM_HIP(hipMemcpyAsync(cl->id_dev, c->ids, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    VRM_HIP(hipMemcpyAsync(cl->gamma_dev, c->tmp_f, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    VRM_HIP(hipMemcpyAsync(c->diffused, c->tmp_u8, sizeof(uint8_t) * n, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_iota, dim3(blocks_for(n)), dim3(256), 0, s, n, c->perm);
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
+}
+
+size_t vrm_sort_tmp_bytes(int32_t cap)
+{
+    size_t bytes = 0;
+    rocprim::radix_sort_pairs((void*)nullptr, bytes, (uint64_t*)nullptr, (uint64_t*)nullptr, (int32_t*)nullptr,
+                              (int32_t*)nullptr, (size_t)cap, 0, 35, (hipStream_t)0);
+    return bytes;
+}

@@ -1,0 +1,129 @@
+// Internal state of a libvrm context and the kernel launchers shared by the
+// translation units.  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vrm.h"
+
+namespace vrm {
+
+// Grid of square cells over the bounding box of the cloud (device side).
+struct GridState {
+    uint32_t bbox[4];      // ordered keys: min x, min y, max x, max y
+    float x0, y0, cs, inv_cs;
+    int32_t nx, ny, ncells, clamped;
+};
+
+// Queue counters of a stage (device side).
+struct Queues {
+    int32_t n_small;       // items in the small-LP queue
+    int32_t n_full;        // items in the complete-LP queue
+    int32_t n_cand;        // insertion candidates
+    int32_t n_undecided;   // insertion candidates not yet decided
+    int32_t n_accepted;    // accepted insertion candidates
+    int32_t pad[3];
+};
+
+// Reduced-operator selection state (device side).
+struct SelectState {
+    double norm1, bound, prefix;
+    uint32_t key_prefix;   // resolved high bits of the threshold key
+    uint32_t done;         // 1 once the threshold is known
+    uint32_t threshold;    // particles with key < threshold are left out
+    uint32_t pad;
+    double bin_sum[256];
+    uint32_t bin_cnt[256];
+};
+
+struct LaunchParams {
+    float h, lo2, hi2, lo2f, hi2f;      // annulus bounds (FP32, squared, unnormalised)
+    float rad, ex2;                      // insertion radius 1.5 h and exclusion (0.5 h)^2
+    float scale2e;                       // 2^-e with 2^e >= h: exact offset scaling
+    float bt_hi, bt_lo;                  // rhs 2 h^2 / 4^e of the (2,0), (0,2) rows (double-float)
+    float cs_hi, cs_lo;                  // (2^e / h)^(q+1): cost scale (double-float)
+    float lam;                           // nu / h^2
+    int q, m;
+};
+
+}  // namespace vrm
+
+struct vrm_ctx {
+    int device;
+    hipStream_t stream;
+    int32_t capacity;
+    int32_t ncell_cap;
+    // cached count for the cloud last seen (host)
+    const int32_t* n_ptr;
+    int32_t n;
+    int32_t n_diffused_valid;   // the diffused set matches the cloud
+    int32_t cells_valid;        // cell list matches the current positions
+    int32_t base_valid;         // y^n recorded (stage 0 done)
+    // device buffers
+    vrm::GridState* grid;
+    vrm::Queues* queues;
+    vrm::SelectState* sel;
+    vrm_counters* counters;
+    int32_t* cell_of;     // [cap] cell of particle
+    int32_t* rank;        // [cap] rank within its cell
+    int32_t* cell_start;  // [ncell_cap + 1]
+    int32_t* scan_part;   // [1024]
+    int32_t* perm;        // [cap] slot -> particle
+    float* xs;            // [cap] positions in slot order
+    float* ys;
+    int32_t* ids;         // [cap] ids in slot order
+    uint8_t* diffused;    // [cap] per particle
+    float* acc;           // [cap] sum_j fhat_ji Gamma_j
+    float* x0;            // [cap] stage-0 state
+    float* y0;
+    float* g0;
+    int32_t* q_small;     // [cap] slots queued for the small LP
+    int32_t* q_full;      // [cap] slots queued for the complete LP
+    int32_t* small_slot;  // [cap][8] small neighbourhood, slot indices
+    // insertion
+    float* cx;            // [2 cap] candidate positions
+    float* cy;
+    uint64_t* ckey;       // [2 cap] (id << 3) | segment
+    uint8_t* cstate;      // [2 cap] 0 undecided, 1 in, 2 out
+    int32_t* ccell;       // [2 cap]
+    int32_t* crank;
+    int32_t* cstart;      // [ncell_cap + 1]
+    int32_t* cperm;       // [2 cap]
+    uint64_t* akey;       // [2 cap] accepted keys / sort scratch
+    int32_t* aidx;
+    void* sort_tmp;
+    size_t sort_tmp_bytes;
+    // reorder scratch
+    float* tmp_f;         // [3 cap]
+    int32_t* tmp_i;       // [cap]
+    uint8_t* tmp_u8;      // [cap]
+    double* verify_buf;   // [8]
+};
+
+// launchers (vrm_cells.hip)
+int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* id, int32_t n,
+                    const vrm::LaunchParams& lp);
+int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double bound_factor);
+int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp);
+int vrm_reorder_cloud(vrm_ctx* c, vrm_cloud* cl, int32_t n);
+// launchers (vrm_lp.hip)
+int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp,
+                    const vrm_stencils* out, int apply);
+int vrm_small_nbhd_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp,
+                       int32_t* small_idx, int32_t* kfull);
+// launchers (vrm_stage.hip)
+int vrm_combine_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const float* u, const float* v, double dt,
+                    float lam, int stage);
+int vrm_verify_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp,
+                   const vrm_stencils* st, double* report);
+int vrm_velocity_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const float* vort, int32_t nv, double nu,
+                     double t, float* u, float* v);
+
+// error helpers (vrm_api.cpp)
+int vrm_fail(int code, const char* fmt, ...);
+int vrm_hip_check(hipError_t e, const char* what);
+#define VRM_HIP(call)                                                    \
+    do {                                                                 \
+        hipError_t _e = (call);                                          \
+        if (_e != hipSuccess) return vrm_hip_check(_e, #call);           \
+    } while (0)

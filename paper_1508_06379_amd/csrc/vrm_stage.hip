@@ -1,0 +1,181 @@
+// Runge-Kutta stage combination, FP64 verification and the prescribed
+// velocity harness of libvrm.
+//
+// Stage update: Sec. 3.3 (Euler steps; SSP Runge-Kutta schemes are convex
+// combinations of them) with the Shu-Osher SSP-RK3 weights, applied to
+// Gamma with dGamma_i/dt = nu sum_j f_ji Gamma_j (Sec. 3.4, eq. nsode) and to
+// the positions with the caller's velocity.
+#include <hip/hip_runtime.h>
+
+#include "vrm_device.h"
+#include "vrm_internal.h"
+
+using namespace vrm;
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_combine(int n, float a, float b, float dt, float lam, const float* __restrict__ x0,
+                                                 const float* __restrict__ y0, const float* __restrict__ g0, float* x,
+                                                 float* y, float* g, const float* __restrict__ u,
+                                                 const float* __restrict__ v, float* acc)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float dg = lam * acc[i];
+    acc[i] = 0.0f;
+    float gn = __builtin_fmaf(dt, dg, g[i]);
+    float gs = b * gn;
+    if (a != 0.0f) gs = __builtin_fmaf(a, g0[i], gs);
+    g[i] = gs;
+    if (u) {
+        float xn = __builtin_fmaf(dt, u[i], x[i]);
+        float yn = __builtin_fmaf(dt, v[i], y[i]);
+        float xs = b * xn, ys = b * yn;
+        if (a != 0.0f) {
+            xs = __builtin_fmaf(a, x0[i], xs);
+            ys = __builtin_fmaf(a, y0[i], ys);
+        }
+        x[i] = xs;
+        y[i] = ys;
+    } else if (a != 0.0f) {
+        // zero velocity: positions stay exactly y^n (the convex combination is the identity)
+        x[i] = x0[i];
+        y[i] = y0[i];
+    }
+}
+
+// FP64 moment residual of each stencil (rows 1 <= |alpha| <= q, relative to
+// b = 2), circulation and l1 norm, and the largest sum_j fhat_ij.
+__global__ __launch_bounds__(256) void k_verify(int n, const float* __restrict__ x, const float* __restrict__ y,
+                                                const float* __restrict__ g, double h, int q,
+                                                const int32_t* __restrict__ sidx, const float* __restrict__ sf,
+                                                const uint8_t* __restrict__ status, const int32_t* __restrict__ fk,
+                                                const int32_t* __restrict__ fidx, const float* __restrict__ ff,
+                                                unsigned long long* out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double res = 0.0, i0 = 0.0, l1 = 0.0, fsum = 0.0;
+    if (i < n) {
+        double gi = (double)g[i];
+        i0 = gi;
+        l1 = fabs(gi);
+        int st = status ? status[i] : 3;
+        if (st <= 1) {
+            double m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            double xi = (double)x[i], yi = (double)y[i];
+            int k = st == 0 ? VRM_NSEG : fk[i];
+            for (int t = 0; t < k; ++t) {
+                int j;
+                double f;
+                if (st == 0) {
+                    j = sidx[(size_t)i * VRM_NSEG + t];
+                    f = (double)sf[(size_t)i * VRM_NSEG + t];
+                } else {
+                    j = fidx[(size_t)i * VRM_KMAX + t];
+                    f = (double)ff[(size_t)i * VRM_KMAX + t];
+                }
+                if (j < 0) continue;
+                double rx = ((double)x[j] - xi) / h, ry = ((double)y[j] - yi) / h;
+                m[0] += f * rx;
+                m[1] += f * ry;
+                m[2] += f * rx * rx;
+                m[3] += f * rx * ry;
+                m[4] += f * ry * ry;
+                m[5] += f * rx * rx * rx;
+                m[6] += f * rx * rx * ry;
+                m[7] += f * rx * ry * ry;
+                m[8] += f * ry * ry * ry;
+                fsum += f;
+            }
+            m[2] -= 2.0;
+            m[4] -= 2.0;
+            int rows = q == 2 ? 5 : 9;
+            for (int a = 0; a < rows; ++a) res = fmax(res, fabs(m[a]) / 2.0);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        res = fmax(res, __shfl_xor(res, o, VRM_WAVE));
+        fsum = fmax(fsum, __shfl_xor(fsum, o, VRM_WAVE));
+        i0 += __shfl_xor(i0, o, VRM_WAVE);
+        l1 += __shfl_xor(l1, o, VRM_WAVE);
+    }
+    if (lane_id() == 0) {
+        atomicMax(&out[0], (unsigned long long)__double_as_longlong(res));
+        atomicAdd((double*)&out[1], i0);
+        atomicAdd((double*)&out[2], l1);
+        atomicMax(&out[3], (unsigned long long)__double_as_longlong(fsum));
+    }
+}
+
+__global__ void k_verify_init(unsigned long long* out)
+{
+    out[0] = 0ull;
+    out[1] = 0ull;
+    out[2] = 0ull;
+    out[3] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_velocity(int n, const float* __restrict__ x, const float* __restrict__ y,
+                                                  const float* __restrict__ vort, int nv, float four_nu_t, float* u,
+                                                  float* v)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float xi = x[i], yi = y[i];
+    float su = 0.0f, sv = 0.0f;
+    const float inv2pi = 0.15915494309189535f;
+    for (int k = 0; k < nv; ++k) {
+        float dx = xi - vort[4 * k], dy = yi - vort[4 * k + 1];
+        float s = vort[4 * k + 2];
+        float G = vort[4 * k + 3];
+        float r2 = dx * dx + dy * dy;
+        float s2 = s * s + four_nu_t;
+        float fac = r2 > 0.0f ? G * inv2pi / r2 * (1.0f - __expf(-r2 / s2)) : 0.0f;
+        su -= fac * dy;
+        sv += fac * dx;
+    }
+    u[i] = su;
+    v[i] = sv;
+}
+
+int blocks_for(int n) { return n > 0 ? (n + 255) / 256 : 1; }
+
+}  // namespace
+
+int vrm_combine_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const float* u, const float* v, double dt, float lam,
+                    int stage)
+{
+    static const float A[3] = {0.0f, 0.75f, 1.0f / 3.0f};
+    static const float B[3] = {1.0f, 0.25f, 2.0f / 3.0f};
+    if (n <= 0) return VRM_OK;
+    hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, A[stage], B[stage], (float)dt, lam,
+                       c->x0, c->y0, c->g0, cl->x_dev, cl->y_dev, cl->gamma_dev, u, v, c->acc);
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
+}
+
+int vrm_verify_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchParams& lp, const vrm_stencils* st,
+                   double* report)
+{
+    unsigned long long* out = reinterpret_cast<unsigned long long*>(report);
+    hipLaunchKernelGGL(k_verify_init, dim3(1), dim3(1), 0, c->stream, out);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_verify, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, cl->x_dev, cl->y_dev,
+                           cl->gamma_dev, (double)lp.h, lp.q, st ? st->small_idx_dev : nullptr,
+                           st ? st->small_f_dev : nullptr, st ? st->status_dev : nullptr,
+                           st ? st->full_k_dev : nullptr, st ? st->full_idx_dev : nullptr,
+                           st ? st->full_f_dev : nullptr, out);
+    }
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
+}
+
+int vrm_velocity_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const float* vort, int32_t nv, double nu, double t,
+                     float* u, float* v)
+{
+    if (n <= 0) return VRM_OK;
+    hipLaunchKernelGGL(k_velocity, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, cl->x_dev, cl->y_dev, vort, nv,
+                       (float)(4.0 * nu * t), u, v);
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
+}

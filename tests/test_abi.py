@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports every
+function include/vrm.h declares, and the Python binding's structures have the
+header's layout (compared with a C program built against the header)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1508_06379_amd as vrm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vrm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(vrm_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(vrm.LIB_PATH):
+        pytest.skip("libvrm.so not built")
+    return ctypes.CDLL(vrm.LIB_PATH)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(vrm.EXPORTS)
+
+
+def test_status_strings(lib):
+    lib.vrm_status_string.restype = ctypes.c_char_p
+    assert lib.vrm_status_string(0) == b"ok"
+    assert lib.vrm_status_string(-2) == b"capacity exceeded"
+
+
+def test_create_rejects_bad_capacity(lib):
+    h = ctypes.c_void_p()
+    lib.vrm_last_error.restype = ctypes.c_char_p
+    assert lib.vrm_create(ctypes.byref(h), 0, None, 0) == -1
+    assert b"capacity" in lib.vrm_last_error()
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "vrm.h"
+#define P(T, f) printf(#T "." #f " %zu\\n", offsetof(T, f));
+int main(void) {
+  printf("vrm_params %zu\\n", sizeof(vrm_params));
+  printf("vrm_cloud %zu\\n", sizeof(vrm_cloud));
+  printf("vrm_stencils %zu\\n", sizeof(vrm_stencils));
+  printf("vrm_counters %zu\\n", sizeof(vrm_counters));
+  P(vrm_params, q) P(vrm_cloud, capacity) P(vrm_stencils, full_f_dev)
+  P(vrm_counters, pivots) P(vrm_counters, redistributions) P(vrm_counters, mis_rounds)
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = dict(l.rsplit(" ", 1) for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    assert int(out["vrm_params"]) == ctypes.sizeof(vrm.vrm_params)
+    assert int(out["vrm_cloud"]) == ctypes.sizeof(vrm.vrm_cloud)
+    assert int(out["vrm_stencils"]) == ctypes.sizeof(vrm.vrm_stencils)
+    assert int(out["vrm_counters"]) == ctypes.sizeof(vrm.vrm_counters)
+    assert int(out["vrm_params.q"]) == vrm.vrm_params.q.offset
+    assert int(out["vrm_cloud.capacity"]) == vrm.vrm_cloud.capacity.offset
+    assert int(out["vrm_stencils.full_f_dev"]) == vrm.vrm_stencils.full_f_dev.offset
+    assert int(out["vrm_counters.pivots"]) == vrm.vrm_counters.pivots.offset
+    assert int(out["vrm_counters.redistributions"]) == vrm.vrm_counters.redistributions.offset
+    assert int(out["vrm_counters.mis_rounds"]) == vrm.vrm_counters.mis_rounds.offset
+
+
+def test_product_path_has_no_cpu_fallback():
+    """The package never imports the oracle: it fails loudly without its HIP library."""
+    src = open(os.path.join(ROOT, "paper_1508_06379_amd", "__init__.py")).read()
+    assert "oracle" not in src.replace("oracle", "", 0) or "import oracle" not in src
+    assert "import oracle" not in src and "from oracle" not in src

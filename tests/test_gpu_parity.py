@@ -1,0 +1,288 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every GPU result is compared with the oracle run on the same seeded inputs.
+Integer and index work (diffused set, neighbourhoods, insertion) must match
+bit for bit; fractions within 1e-6 (FP32 path, normalised units), moment
+residuals <= 1e-6 relative, Gamma within 1e-5 relative L2 after whole runs
+(particles matched by id).
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vrm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1508_06379_amd as v
+    v.lib()
+    return v
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def small_configs():
+    return {
+        "lattice": workloads.config_lattice_small(),
+        "jittered_q2_h0.02": workloads.config_jittered(h=0.02, q=2, seed=2),
+        "jittered_q3_h0.02": workloads.config_jittered(h=0.02, q=3, seed=2),
+        "vortices_h0.02": workloads.config_vortices(h=0.02, lo=-1.0, hi=1.0),
+    }
+
+
+CONFIGS = small_configs()
+
+
+def _gpu_cloud(vrm, wl, cap_factor=3):
+    return vrm.Cloud(wl.x, wl.y, wl.gamma, capacity=cap_factor * wl.n + 64)
+
+
+# ------------------------------------------------------------------ a0
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_diffused_set_bit_exact(vrm, orc, name):
+    """Sec. 3.5 reduced operator: the GPU radix select picks exactly the oracle's set."""
+    wl = CONFIGS[name]
+    _say("case", name, wl.n)
+    cloud = _gpu_cloud(vrm, wl)
+    ctx = vrm.Context(cloud.capacity)
+    mask = torch.zeros(cloud.capacity, dtype=torch.uint8, device="cuda")
+    ctx.vrm_select_diffused(cloud, vrm.params_of(wl), mask)
+    got = mask[:wl.n].cpu().numpy()
+    ref, _, _ = orc.diffused(wl.gamma, wl.ids, wl.h, wl.q, wl.c_diff)
+    np.testing.assert_array_equal(got, ref)
+
+
+# ------------------------------------------------------------------ a1-a2
+@pytest.mark.parametrize("name", ["lattice", "jittered_q2_h0.02", "vortices_h0.02"])
+def test_small_neighbourhoods_bit_exact(vrm, orc, name):
+    """Sec. 4.3: closest member of each 45-degree segment, identical to the oracle."""
+    wl = CONFIGS[name]
+    _say("case", name)
+    cloud = _gpu_cloud(vrm, wl)
+    ctx = vrm.Context(cloud.capacity)
+    P = vrm.params_of(wl)
+    ctx.vrm_select_diffused(cloud, P)
+    sidx = torch.full((cloud.capacity, 8), -1, dtype=torch.int32, device="cuda")
+    kfull = torch.zeros(cloud.capacity, dtype=torch.int32, device="cuda")
+    ctx.vrm_build_neighbourhoods(cloud, P, sidx, kfull)
+    got = sidx[:wl.n].cpu().numpy()
+    mask, _, _ = orc.diffused(wl.gamma, wl.ids, wl.h, wl.q)
+    ref = orc.stencils(wl.x, wl.y, wl.ids, mask, orc.params_of(wl))
+    sel = mask > 0
+    np.testing.assert_array_equal(got[sel], ref.small[sel])
+    np.testing.assert_array_equal(kfull[:wl.n].cpu().numpy()[sel], ref.kfull[sel])
+
+
+# ------------------------------------------------------------------ a3
+def _oracle_inserted(orc, wl):
+    P = orc.params_of(wl)
+    mask, _, _ = orc.diffused(wl.gamma, wl.ids, wl.h, wl.q)
+    x, y, g, ids, _ = orc.insert(wl.x.astype(np.float64), wl.y.astype(np.float64), wl.gamma.astype(np.float64),
+                                 wl.ids, mask, P)
+    mask = np.concatenate([mask, np.zeros(x.size - mask.size, np.uint8)])
+    return x, y, g, ids, mask
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_insertion_bit_exact(vrm, orc, name):
+    """Sec. 4.2: same new particles (positions, ids), Gamma = 0, and the same count."""
+    wl = CONFIGS[name]
+    _say("case", name)
+    cloud = _gpu_cloud(vrm, wl)
+    ctx = vrm.Context(cloud.capacity)
+    ctx.vrm_insert_particles(cloud, vrm.params_of(wl))
+    x, y, g, ids = cloud.numpy()
+    rx, ry, rg, rids, _ = _oracle_inserted(orc, wl)
+    assert x.size == rx.size
+    o = np.argsort(ids)
+    np.testing.assert_array_equal(ids[o], rids)
+    np.testing.assert_array_equal(x[o], rx.astype(np.float32))
+    np.testing.assert_array_equal(y[o], ry.astype(np.float32))
+    np.testing.assert_array_equal(g[o], rg.astype(np.float32))
+
+
+# ------------------------------------------------------------------ a4-a6
+def _gpu_stencils(vrm, ctx, cloud, P):
+    st = vrm.Stencils.alloc(cloud.capacity)
+    ctx.vrm_solve_fractions(cloud, P, st)
+    torch.cuda.synchronize()
+    n = cloud.n
+    return {k: (getattr(st, k)[:n].cpu().numpy() if getattr(st, k) is not None else None)
+            for k in ("small_idx", "small_f", "fii", "status", "full_k", "full_idx", "full_f")}, st
+
+
+def _as_dicts_gpu(S, ids):
+    out = {}
+    for i in range(ids.size):
+        st = S["status"][i]
+        if st == 0:
+            cols, f = S["small_idx"][i], S["small_f"][i]
+        elif st == 1:
+            k = S["full_k"][i]
+            cols, f = S["full_idx"][i, :k], S["full_f"][i, :k]
+        else:
+            continue
+        out[int(ids[i])] = (int(st), {int(ids[c]): float(v) for c, v in zip(cols, f) if c >= 0 and v != 0.0},
+                            float(S["fii"][i]))
+    return out
+
+
+def _as_dicts_oracle(st, ids):
+    out = {}
+    for i in range(ids.size):
+        if st.status[i] > 1:
+            continue
+        k = st.kcol[i]
+        out[int(ids[i])] = (int(st.status[i]),
+                            {int(ids[c]): float(v) for c, v in zip(st.cols[i, :k], st.f[i, :k]) if v != 0.0},
+                            float(st.fii[i]))
+    return out
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_fractions_match_oracle(vrm, orc, name):
+    """Sec. 2 / 4.1 / 4.3: same status, same support (basis) and fractions within 1e-6;
+    GPU moment residual <= 1e-6 (FP64 check of the FP32 fractions)."""
+    wl = CONFIGS[name]
+    _say("case", name)
+    cloud = _gpu_cloud(vrm, wl)
+    ctx = vrm.Context(cloud.capacity)
+    P = vrm.params_of(wl)
+    ctx.vrm_insert_particles(cloud, P)
+    S, st = _gpu_stencils(vrm, ctx, cloud, P)
+    x, y, g, ids = cloud.numpy()
+    rx, ry, rg, rids, rmask = _oracle_inserted(orc, wl)
+    ref = orc.stencils(rx, ry, rids, rmask, orc.params_of(wl))
+    G = _as_dicts_gpu(S, ids)
+    R = _as_dicts_oracle(ref, rids)
+    # statuses of every particle
+    o = np.argsort(ids)
+    np.testing.assert_array_equal(S["status"][o], ref.status)
+    bad_support, worst = [], 0.0
+    for pid, (rs, rf, rfii) in R.items():
+        gs, gf, gfii = G[pid]
+        assert gs == rs
+        if set(gf) != set(rf):
+            bad_support.append(pid)
+            continue
+        for k, v in rf.items():
+            worst = max(worst, abs(gf[k] - v) / max(1.0, abs(v)))
+        worst = max(worst, abs(gfii - rfii) / max(1.0, abs(rfii)))
+    _say(name, "particles", len(R), "support mismatches", len(bad_support), "worst rel diff", worst)
+    assert not bad_support, f"{len(bad_support)} stencils with a different support, e.g. ids {bad_support[:5]}"
+    assert worst <= 1e-6
+    rep = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ctx.vrm_verify(cloud, P, st, rep)
+    res, i0, l1, fmax = rep.cpu().numpy()
+    _say(name, "max moment residual", res, "max sum f", fmax)
+    assert res <= 1e-6
+    assert abs(i0 - rg.sum()) <= 1e-6 * np.abs(rg).sum()
+
+
+# ------------------------------------------------------------------ a7: runs
+def _run_parity(vrm, orc, wl, steps):
+    P = vrm.params_of(wl)
+    cloud = _gpu_cloud(vrm, wl, cap_factor=4)
+    ctx = vrm.Context(cloud.capacity)
+    vt = vrm.vortex_table(wl.vortices) if wl.vortices is not None else None
+    u = torch.zeros(cloud.capacity, device="cuda")
+    v = torch.zeros(cloud.capacity, device="cuda")
+
+    def vel(cl, t):
+        if vt is None:
+            return None
+        ctx.vrm_vortex_velocity(cl, vt, wl.nu, t, u, v)
+        return u, v
+
+    t = wl.t0
+    for _ in range(steps):
+        ctx.step(cloud, P, velocity=vel, t=t)
+        t += wl.dt
+    torch.cuda.synchronize()
+    ref = orc.run(wl, steps=steps)
+    x, y, g, ids = cloud.numpy()
+    return ctx, (x, y, g, ids), ref
+
+
+def _rel_l2_by_id(ids, g, rids, rg):
+    a = dict(zip(ids.tolist(), g.astype(np.float64).tolist()))
+    b = dict(zip(rids.tolist(), rg.tolist()))
+    keys = set(a) | set(b)
+    d = np.array([a.get(k, 0.0) - b.get(k, 0.0) for k in keys])
+    return np.linalg.norm(d) / np.linalg.norm(rg)
+
+
+@pytest.mark.parametrize("name,steps", [("lattice", 10), ("jittered_q2_h0.02", 25), ("jittered_q3_h0.02", 10)])
+def test_run_gamma_matches_oracle(vrm, orc, name, steps):
+    """Sec. 3.3-3.4: whole SSP-RK3 runs; Gamma within 1e-5 relative L2 of the oracle,
+    circulation kept to 1e-5 of ||Gamma||_1."""
+    wl = CONFIGS[name]
+    _say("case", name, steps)
+    ctx, (x, y, g, ids), ref = _run_parity(vrm, orc, wl, steps)
+    err = _rel_l2_by_id(ids, g, ref.ids, ref.gamma)
+    cnt = ctx.vrm_read_counters()
+    _say(name, "N", x.size, ref.x.size, "rel L2", err, cnt)
+    assert x.size == ref.x.size
+    assert err <= 1e-5
+    assert abs(g.astype(np.float64).sum() - wl.gamma.astype(np.float64).sum()) <= 1e-5 * np.abs(wl.gamma).sum()
+
+
+# ------------------------------------------------------------------ edges
+def test_empty_and_single(vrm, orc):
+    """N = 0 does nothing; a lone particle gets the eight Dirac-start neighbours (Sec. 5)."""
+    P = vrm.make_params(0.05, q=2, dt=1e-3)
+    cloud = vrm.Cloud([], [], [], capacity=32)
+    ctx = vrm.Context(32)
+    ctx.step(cloud, P)
+    assert cloud.n == 0
+    cloud = vrm.Cloud([0.0], [0.0], [1.0], capacity=32)
+    ctx = vrm.Context(32)
+    ctx.vrm_insert_particles(cloud, P)
+    x, y, g, ids = cloud.numpy()
+    assert x.size == 9 and sorted(ids.tolist()) == list(range(9))
+    np.testing.assert_allclose(np.hypot(x, y)[ids > 0], 1.5 * 0.05, rtol=1e-6)
+
+
+def test_capacity_error_leaves_cloud(vrm):
+    """Insertion beyond capacity fails with VRM_E_CAPACITY and changes nothing."""
+    P = vrm.make_params(0.05, q=2, dt=1e-3)
+    cloud = vrm.Cloud([0.0], [0.0], [1.0], capacity=4)
+    ctx = vrm.Context(4)
+    with pytest.raises(vrm.VrmError) as e:
+        ctx.vrm_insert_particles(cloud, P)
+    assert e.value.code == vrm.E_CAPACITY
+    assert cloud.n == 1
+    cnt = ctx.vrm_read_counters()
+    assert cnt["capacity_needed"] == 9
+
+
+def test_argument_errors(vrm):
+    cloud = vrm.Cloud([0.0], [0.0], [1.0], capacity=8)
+    ctx = vrm.Context(8)
+    for bad in (vrm.make_params(-1.0), vrm.make_params(0.1, q=4), vrm.make_params(0.1, r=2.0, R=1.0)):
+        with pytest.raises(vrm.VrmError) as e:
+            ctx.vrm_select_diffused(cloud, bad)
+        assert e.value.code == vrm.E_ARG
+    with pytest.raises(vrm.VrmError) as e:
+        ctx.vrm_rk_stage(cloud, vrm.make_params(0.1), 0)
+    assert e.value.code == vrm.E_STATE
+
+
+def test_all_zero_circulation(vrm):
+    """Gamma = 0 everywhere: nobody is diffused (Sec. 3.5), nothing inserted, nothing changes."""
+    wl = workloads.config_lattice_small()
+    cloud = vrm.Cloud(wl.x, wl.y, np.zeros_like(wl.gamma), capacity=2 * wl.n)
+    ctx = vrm.Context(cloud.capacity)
+    P = vrm.params_of(wl)
+    ctx.step(cloud, P)
+    cnt = ctx.vrm_read_counters()
+    assert cnt["n_diffused"] == 0 and cnt["n_inserted"] == 0 and cloud.n == wl.n
+    assert float(cloud.gamma[:wl.n].abs().max()) == 0.0
