@@ -107,6 +107,7 @@ typedef struct {
     int64_t redistributions;  /* stencils applied by vrm_rk_stage (cumulative) */
     int32_t capacity_needed;  /* set when an insertion failed for capacity */
     int32_t mis_rounds;       /* rounds of the last insertion's conflict resolution */
+    int64_t full_cols;        /* sum of the column counts of complete-neighbourhood LPs (cumulative) */
 } vrm_counters;
 
 /* Create a context on `device` that enqueues on `stream` (a hipStream_t; NULL
@@ -181,6 +182,25 @@ int vrm_read_counters(vrm_ctx* ctx, vrm_counters* out_host);
  * vort_dev = device floats [n_vort][4] (cx, cy, sigma, G). */
 int vrm_vortex_velocity(vrm_ctx* ctx, const vrm_cloud* cloud, const float* vort_dev, int32_t n_vort,
                         double nu, double t, float* u_dev, float* v_dev);
+
+/* Kernel timers (profiling).  While enabled, every launch of the kernel
+ * groups below is bracketed by HIP events recorded on the context's stream
+ * (a few microseconds of overhead per launch).  vrm_read_timing synchronises,
+ * adds the elapsed times per group into ms_host[VRM_NTIMER] and the launch
+ * counts into launches_host[VRM_NTIMER] (either may be NULL), and starts a new
+ * interval.  At most 8192 launches are timed per interval; later ones are
+ * counted in launches_host but not timed (the return value is then 1). */
+#define VRM_T_SELECT 0      /* reduced-operator selection (Sec. 3.5) */
+#define VRM_T_CELLS 1       /* cell list build */
+#define VRM_T_NBHD 2        /* small neighbourhoods (Sec. 4.3) */
+#define VRM_T_LP_SMALL 3    /* small-neighbourhood LPs + apply */
+#define VRM_T_LP_FULL 4     /* complete-neighbourhood LPs + apply */
+#define VRM_T_INSERT 5      /* insertion (Sec. 4.2), including its host synchronisations */
+#define VRM_T_COMBINE 6     /* Runge-Kutta stage combination */
+#define VRM_T_MLP 7         /* warm-start network */
+#define VRM_NTIMER 8
+int vrm_timing(vrm_ctx* ctx, int enable);
+int vrm_read_timing(vrm_ctx* ctx, double* ms_host, int64_t* launches_host);
 
 const char* vrm_last_error(void);
 const char* vrm_status_string(int code);

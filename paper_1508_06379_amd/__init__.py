@@ -57,7 +57,7 @@ class vrm_counters(ctypes.Structure):
                 ("n_infeasible", ctypes.c_int32), ("n_uncertified", ctypes.c_int32),
                 ("n_truncated", ctypes.c_int32), ("n_grid_clamped", ctypes.c_int32),
                 ("pivots", ctypes.c_int64), ("redistributions", ctypes.c_int64),
-                ("capacity_needed", ctypes.c_int32), ("mis_rounds", ctypes.c_int32)]
+                ("capacity_needed", ctypes.c_int32), ("mis_rounds", ctypes.c_int32), ("full_cols", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,7 +65,8 @@ class vrm_counters(ctypes.Structure):
 
 EXPORTS = ["vrm_create", "vrm_destroy", "vrm_select_diffused", "vrm_set_diffused", "vrm_build_neighbourhoods",
            "vrm_insert_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_verify", "vrm_read_counters",
-           "vrm_vortex_velocity", "vrm_last_error", "vrm_status_string"]
+           "vrm_vortex_velocity", "vrm_timing", "vrm_read_timing", "vrm_last_error", "vrm_status_string"]
+TIMERS = ["select", "cells", "nbhd", "lp_small", "lp_full", "insert", "combine", "mlp"]
 
 _lib = None
 
@@ -92,6 +93,8 @@ def lib():
         L.vrm_read_counters.argtypes = [vp, ctypes.POINTER(vrm_counters)]
         L.vrm_vortex_velocity.argtypes = [vp, ctypes.POINTER(vrm_cloud), vp, ctypes.c_int32, ctypes.c_double,
                                           ctypes.c_double, vp, vp]
+        L.vrm_timing.argtypes = [vp, ctypes.c_int]
+        L.vrm_read_timing.argtypes = [vp, vp, vp]
         L.vrm_last_error.restype = ctypes.c_char_p
         L.vrm_status_string.restype = ctypes.c_char_p
         L.vrm_status_string.argtypes = [ctypes.c_int]
@@ -238,6 +241,18 @@ class Context:
     def vrm_vortex_velocity(self, cloud: Cloud, vort, nu, t, u, v):
         _check(lib().vrm_vortex_velocity(self.handle, ctypes.byref(cloud.c), _ptr(vort), int(vort.shape[0]),
                                          float(nu), float(t), _ptr(u), _ptr(v)))
+
+    def vrm_timing(self, enable: bool):
+        _check(lib().vrm_timing(self.handle, 1 if enable else 0))
+
+    def vrm_read_timing(self):
+        """{group: (total ms, launches)} of the interval since the last read."""
+        ms = (ctypes.c_double * len(TIMERS))()
+        ln = (ctypes.c_int64 * len(TIMERS))()
+        rc = lib().vrm_read_timing(self.handle, ms, ln)
+        if rc < 0:
+            _check(rc)
+        return {k: (ms[i], ln[i]) for i, k in enumerate(TIMERS)}, rc == 1
 
     # --- convenience
     def step(self, cloud: Cloud, p: vrm_params, velocity=None, t=0.0, insertion=True):

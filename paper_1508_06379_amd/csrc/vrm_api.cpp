@@ -222,6 +222,15 @@ int vrm_destroy(vrm_ctx* c)
                     c->akey, c->aidx, c->tmp_f, c->tmp_i, c->tmp_u8, c->verify_buf, c->sort_tmp};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    if (c->ev_start) {
+        for (int k = 0; k < vrm::kMaxTimed; ++k) {
+            (void)hipEventDestroy(c->ev_start[k]);
+            (void)hipEventDestroy(c->ev_stop[k]);
+        }
+        delete[] c->ev_start;
+        delete[] c->ev_stop;
+        delete[] c->ev_group;
+    }
     delete c;
     return VRM_OK;
 }
@@ -233,7 +242,10 @@ int vrm_select_diffused(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, ui
     if (!r) r = read_n(c, cl);
     if (r) return r;
     double factor = p->c_diff * std::pow(p->h, p->q + 1);
-    r = vrm_select_run(c, cl->gamma_dev, c->n, factor);
+    {
+        vrm::ScopedTimer tm(c, VRM_T_SELECT);
+        r = vrm_select_run(c, cl->gamma_dev, c->n, factor);
+    }
     if (r) return r;
     if (mask_dev && c->n > 0) {
         hipLaunchKernelGGL(k_copy_mask, dim3((c->n + 255) / 256), dim3(256), 0, c->stream, c->n, c->diffused, mask_dev);
@@ -279,11 +291,18 @@ int vrm_insert_particles(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p)
     if (r) return r;
     vrm::LaunchParams L = launch_params(p);
     double factor = p->c_diff * std::pow(p->h, p->q + 1);
-    r = vrm_select_run(c, cl->gamma_dev, c->n, factor);
+    {
+        vrm::ScopedTimer tm(c, VRM_T_SELECT);
+        r = vrm_select_run(c, cl->gamma_dev, c->n, factor);
+    }
     if (!r) r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
     if (r) return r;
     c->n_diffused_valid = 1;
-    int n2 = vrm_insert_run(c, cl, c->n, L);
+    int n2;
+    {
+        vrm::ScopedTimer tm(c, VRM_T_INSERT);
+        n2 = vrm_insert_run(c, cl, c->n, L);
+    }
     if (n2 < 0) {
         c->cells_valid = 1;   // the cloud is unchanged
         return n2;
@@ -340,7 +359,10 @@ int vrm_rk_stage(vrm_ctx* c, vrm_cloud* cl, const float* u_dev, const float* v_d
         c->cells_valid = 1;
     }
     r = vrm_stencil_run(c, cl, n, L, nullptr, 1);
-    if (!r) r = vrm_combine_run(c, cl, n, u_dev, v_dev, p->dt, L.lam, stage);
+    if (!r) {
+        vrm::ScopedTimer tm(c, VRM_T_COMBINE);
+        r = vrm_combine_run(c, cl, n, u_dev, v_dev, p->dt, L.lam, stage);
+    }
     if (r) return r;
     if (u_dev) c->cells_valid = 0;
     if (stage == 2) c->base_valid = 0;
@@ -365,6 +387,47 @@ int vrm_read_counters(vrm_ctx* c, vrm_counters* out)
     VRM_HIP(hipStreamSynchronize(c->stream));
     out->n = c->n;
     return VRM_OK;
+}
+
+int vrm_timing(vrm_ctx* c, int enable)
+{
+    if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
+    if (enable && !c->ev_start) {
+        c->ev_start = new hipEvent_t[vrm::kMaxTimed];
+        c->ev_stop = new hipEvent_t[vrm::kMaxTimed];
+        c->ev_group = new int[vrm::kMaxTimed];
+        for (int k = 0; k < vrm::kMaxTimed; ++k) {
+            VRM_HIP(hipEventCreate(&c->ev_start[k]));
+            VRM_HIP(hipEventCreate(&c->ev_stop[k]));
+        }
+    }
+    c->timing = enable ? 1 : 0;
+    c->ntimed = 0;
+    for (int g = 0; g < VRM_NTIMER; ++g) c->launches[g] = 0;
+    return VRM_OK;
+}
+
+int vrm_read_timing(vrm_ctx* c, double* ms, int64_t* launches)
+{
+    if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
+    VRM_HIP(hipStreamSynchronize(c->stream));
+    double acc[VRM_NTIMER] = {0};
+    for (int k = 0; k < c->ntimed; ++k) {
+        float t = 0.0f;
+        VRM_HIP(hipEventElapsedTime(&t, c->ev_start[k], c->ev_stop[k]));
+        acc[c->ev_group[k]] += t;
+    }
+    int over = 0;
+    int64_t timed[VRM_NTIMER] = {0};
+    for (int k = 0; k < c->ntimed; ++k) timed[c->ev_group[k]] += 1;
+    for (int g = 0; g < VRM_NTIMER; ++g) {
+        if (ms) ms[g] = acc[g];
+        if (launches) launches[g] = c->launches[g];
+        over |= timed[g] != c->launches[g];
+        c->launches[g] = 0;
+    }
+    c->ntimed = 0;
+    return over ? 1 : VRM_OK;
 }
 
 int vrm_vortex_velocity(vrm_ctx* c, const vrm_cloud* cl, const float* vort_dev, int32_t n_vort, double nu, double t,

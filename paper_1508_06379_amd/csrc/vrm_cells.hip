@@ -491,6 +491,7 @@ int blocks_for(int n) { return n > 0 ? (n + 255) / 256 : 1; }
 // Cell list of (x, y) into ctx->cell_start / perm / xs, ys, ids (slot order).
 int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* id, int32_t n, const LaunchParams& lp)
 {
+    ScopedTimer tm(c, VRM_T_CELLS);
     hipStream_t s = c->stream;
     hipLaunchKernelGGL(k_grid_reset, dim3(1), dim3(1), 0, s, c->grid);
     int nbb = min(1024, blocks_for(n));

@@ -98,7 +98,36 @@ struct vrm_ctx {
     int32_t* tmp_i;       // [cap]
     uint8_t* tmp_u8;      // [cap]
     double* verify_buf;   // [8]
+    // kernel timers
+    int timing;
+    int ntimed;
+    hipEvent_t* ev_start; // [kMaxTimed]
+    hipEvent_t* ev_stop;
+    int* ev_group;
+    int64_t launches[VRM_NTIMER];
 };
+
+namespace vrm {
+constexpr int kMaxTimed = 8192;
+// Bracket a group of launches with events when timing is on.
+struct ScopedTimer {
+    vrm_ctx* c;
+    int slot;
+    ScopedTimer(vrm_ctx* ctx, int group) : c(ctx), slot(-1)
+    {
+        if (!c->timing) return;
+        c->launches[group] += 1;
+        if (c->ntimed >= kMaxTimed) return;
+        slot = c->ntimed++;
+        c->ev_group[slot] = group;
+        (void)hipEventRecord(c->ev_start[slot], c->stream);
+    }
+    ~ScopedTimer()
+    {
+        if (slot >= 0) (void)hipEventRecord(c->ev_stop[slot], c->stream);
+    }
+};
+}  // namespace vrm
 
 // launchers (vrm_cells.hip)
 int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* id, int32_t n,

@@ -1,0 +1,505 @@
+// One-thread revised simplex for the moment-condition LP of one particle
+// (Kirchhart & Obi, Sec. 2 eq. momcondmv and Sec. 4.1), and its certification.
+//
+//   minimise  sum_j c_j f_j   subject to  V f = b,  f >= 0,
+//
+// V has M rows (the monomials r^alpha, 1 <= |alpha| <= q, of the scaled
+// offsets) and k <= 64 columns.  As the paper describes, every iteration works
+// with the m x m matrix of the current basic columns; here its inverse B^-1
+// is kept explicitly in registers and updated by one elementary row
+// operation per pivot.  Phase I starts from the artificial basis with a
+// right-hand side perturbed by distinct small amounts (steps over degenerate
+// vertices), pricing is Dantzig's with Bland's rule as a fallback.  FP32.
+//
+// The basis it ends with is then certified against the exact problem: the
+// basic solution and the prices are refined with residuals evaluated in
+// double-float arithmetic from the exact particle offsets, every reduced cost
+// is recomputed the same way, and primal (Bland) or dual repair pivots are
+// taken until the basis is optimal to a relative 1e-9.
+#pragma once
+#include "vrm_device.h"
+#include "vrm_internal.h"
+
+namespace vrm {
+
+constexpr float kPerturb = 7.62939453125e-06f;   // 2^-17: relative rhs perturbation
+constexpr float kTolD = 1e-6f;                    // FP32 pricing tolerance (relative)
+constexpr float kTolPiv = 1e-6f;                  // FP32 pivot tolerance (relative to max |alpha|)
+constexpr float kTolFeas = 1e-3f;                 // phase-I infeasibility (relative to the rhs)
+constexpr float kCertD = 1e-9f;                   // certified reduced-cost tolerance (relative)
+constexpr float kCertX = 1e-9f;                   // certified primal tolerance (absolute, fhat units)
+constexpr int kMaxCert = 8;
+constexpr int kMaxRefine = 6;
+
+template <int M>
+__device__ __forceinline__ void mono(float x, float y, float (&v)[M])
+{
+    v[0] = x;
+    v[1] = y;
+    v[2] = x * x;
+    v[3] = x * y;
+    v[4] = y * y;
+    if constexpr (M == 9) {
+        v[5] = v[2] * x;
+        v[6] = v[2] * y;
+        v[7] = x * v[4];
+        v[8] = v[4] * y;
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void mono_df(df X, df Y, df (&v)[M])
+{
+    df XX = df_mul(X, X), XY = df_mul(X, Y), YY = df_mul(Y, Y);
+    v[0] = X;
+    v[1] = Y;
+    v[2] = XX;
+    v[3] = XY;
+    v[4] = YY;
+    if constexpr (M == 9) {
+        v[5] = df_mul(XX, X);
+        v[6] = df_mul(XX, Y);
+        v[7] = df_mul(X, YY);
+        v[8] = df_mul(YY, Y);
+    }
+}
+
+// |r|^(q+1) of the scaled exact offset, times (2^e/h)^(q+1): the canonical
+// cost in units of h, double-float
+__device__ __forceinline__ df cost_df(df X, df Y, const LaunchParams& P)
+{
+    df d2 = df_add(df_mul(X, X), df_mul(Y, Y));
+    df w = (P.q == 2) ? df_mul(d2, df_sqrt(d2)) : df_mul(d2, d2);
+    return df_mul(w, df{P.cs_hi, P.cs_lo});
+}
+
+// exact offset of particle j from particle i, scaled by 2^-e (exact)
+__device__ __forceinline__ void exact_offset(float xi, float yi, float xj, float yj, float s, df& X, df& Y)
+{
+    df dx = two_sum(xj, -xi);
+    df dy = two_sum(yj, -yi);
+    X = {dx.hi * s, dx.lo * s};
+    Y = {dy.hi * s, dy.lo * s};
+}
+
+__device__ __forceinline__ float rhs_hi(int a, const LaunchParams& P) { return (a == 2 || a == 4) ? P.bt_hi : 0.0f; }
+__device__ __forceinline__ df rhs_df(int a, const LaunchParams& P)
+{
+    return (a == 2 || a == 4) ? df{P.bt_hi, P.bt_lo} : df{0.0f, 0.0f};
+}
+
+// Column store interface (CS):
+//   int k;                                           number of columns
+//   void get(int j, float& rx, float& ry, float& c)  FP32 scaled offset and cost
+//   void exact(int j, df& X, df& Y, df& C)           exact offset and cost
+template <int M, class CS>
+struct ThreadSimplex {
+    float Bi[M][M];   // B^-1
+    float xb[M];      // basic values (perturbed rhs)
+    float cb[M];      // costs of the basic columns (0 for artificial ones)
+    int bs[M];        // basic column of each row; >= 64 means artificial (64 + row)
+    uint64_t isb;     // basic structural columns
+    uint64_t blk;     // columns blocked until the next pivot (no positive pivot element)
+    uint64_t dead;    // columns that do not exist
+
+    static constexpr int ART = 64;
+
+    __device__ void init(const LaunchParams& P)
+    {
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+#pragma unroll
+            for (int a = 0; a < M; ++a) Bi[r][a] = (r == a) ? 1.0f : 0.0f;
+            xb[r] = rhs_hi(r, P) + kPerturb * P.bt_hi * (1.0f + 0.618f * (float)r);
+            cb[r] = 0.0f;
+            bs[r] = ART + r;
+        }
+        isb = 0;
+        blk = 0;
+    }
+
+    __device__ __forceinline__ void prices(bool phase2, float (&y)[M]) const
+    {
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            float s = 0.0f;
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                float w = phase2 ? cb[r] : (bs[r] >= ART ? 1.0f : 0.0f);
+                s = __builtin_fmaf(w, Bi[r][a], s);
+            }
+            y[a] = s;
+        }
+    }
+
+    __device__ __forceinline__ void column_alpha(float rx, float ry, float (&alpha)[M]) const
+    {
+        float v[M];
+        mono<M>(rx, ry, v);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            float s = 0.0f;
+#pragma unroll
+            for (int a = 0; a < M; ++a) s = __builtin_fmaf(Bi[r][a], v[a], s);
+            alpha[r] = s;
+        }
+    }
+
+    // Ratio test (Bland's tie-break: lowest basic index); -1 if no row qualifies.
+    __device__ int ratio_test(const float (&alpha)[M], const float (&x)[M], bool phase2) const
+    {
+        float amax = 0.0f;
+#pragma unroll
+        for (int r = 0; r < M; ++r) amax = fmaxf(amax, fabsf(alpha[r]));
+        float eps = kTolPiv * amax;
+        int l = -1, bl = 0;
+        float best = 0.0f;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            bool art = bs[r] >= ART;
+            bool ok;
+            float ratio;
+            if (phase2 && art && fabsf(alpha[r]) > eps) {
+                ok = true;   // a redundant row's artificial must stay at zero: it leaves first
+                ratio = 0.0f;
+            } else {
+                ok = alpha[r] > eps;
+                ratio = fmaxf(x[r], 0.0f) / alpha[r];
+            }
+            if (ok && (l < 0 || ratio < best || (ratio == best && bs[r] < bl))) {
+                l = r;
+                best = ratio;
+                bl = bs[r];
+            }
+        }
+        return l;
+    }
+
+    __device__ void pivot(int l, int e, const float (&alpha)[M], float ce)
+    {
+        float al = 1.0f;
+#pragma unroll
+        for (int r = 0; r < M; ++r) al = (r == l) ? alpha[r] : al;
+        float inv = 1.0f / al;
+        float row[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            float v = 0.0f;
+#pragma unroll
+            for (int r = 0; r < M; ++r) v = (r == l) ? Bi[r][a] : v;
+            row[a] = v * inv;
+        }
+        float xl = 0.0f;
+#pragma unroll
+        for (int r = 0; r < M; ++r) xl = (r == l) ? xb[r] : xl;
+        xl *= inv;
+        int old = 0;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            bool me = (r == l);
+            old = me ? bs[r] : old;
+#pragma unroll
+            for (int a = 0; a < M; ++a) Bi[r][a] = me ? row[a] : __builtin_fmaf(-alpha[r], row[a], Bi[r][a]);
+            xb[r] = me ? xl : __builtin_fmaf(-alpha[r], xl, xb[r]);
+            bs[r] = me ? e : bs[r];
+            cb[r] = me ? ce : cb[r];
+        }
+        if (old < ART) isb &= ~(1ull << old);
+        isb |= 1ull << e;
+        blk = 0;
+    }
+
+    // FP32 two-phase simplex.  0 optimal, 1 infeasible, 2 iteration limit.
+    __device__ int run(const CS& cs, int& piv)
+    {
+        const int k = cs.k;
+        for (int phase = 1; phase <= 2; ++phase) {
+            const bool p2 = phase == 2;
+            int it = 0;
+            const int bland_after = 3 * (k + M);
+            const int limit = 10 * (k + M) + 20;
+            for (; it < limit; ++it) {
+                float y[M];
+                prices(p2, y);
+                int e = -1;
+                float best = 0.0f;
+                const bool bland = it >= bland_after;
+                for (int j = 0; j < k; ++j) {
+                    if (((isb | blk | dead) >> j) & 1ull) continue;
+                    float rx, ry, c;
+                    cs.get(j, rx, ry, c);
+                    float v[M];
+                    mono<M>(rx, ry, v);
+                    float d = p2 ? c : 0.0f, sc = fabsf(d);
+#pragma unroll
+                    for (int a = 0; a < M; ++a) {
+                        float t = y[a] * v[a];
+                        d -= t;
+                        sc += fabsf(t);
+                    }
+                    if (d < -kTolD * sc && (e < 0 || (!bland && d < best))) {
+                        e = j;
+                        best = d;
+                        if (bland) break;
+                    }
+                }
+                if (e < 0) break;
+                float rx, ry, ce;
+                cs.get(e, rx, ry, ce);
+                float alpha[M];
+                column_alpha(rx, ry, alpha);
+                int l = ratio_test(alpha, xb, p2);
+                if (l < 0) {
+                    blk |= 1ull << e;
+                    continue;
+                }
+                pivot(l, e, alpha, p2 ? ce : 0.0f);
+                ++piv;
+            }
+            if (it >= limit) return 2;
+            if (!p2) {
+                float art = 0.0f;
+#pragma unroll
+                for (int r = 0; r < M; ++r) art += bs[r] >= ART ? fabsf(xb[r]) : 0.0f;
+                if (art > kTolFeas * P_bt()) return 1;
+#pragma unroll
+                for (int r = 0; r < M; ++r) {
+                    float c = 0.0f;
+                    if (bs[r] < ART) {
+                        float rx, ry;
+                        cs.get(bs[r], rx, ry, c);
+                    }
+                    cb[r] = c;
+                }
+                blk = 0;
+            }
+        }
+        return 0;
+    }
+
+    float bt_;
+    __device__ __forceinline__ float P_bt() const { return bt_; }
+
+    // exact B x for the basic solution, residual b - B x
+    __device__ void primal_residual(const CS& cs, const df (&x)[M], const LaunchParams& P, float (&res)[M]) const
+    {
+        df acc[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) acc[a] = {0.0f, 0.0f};
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            int b = bs[r];
+            if (b < ART) {
+                df X, Y, C;
+                cs.exact(b, X, Y, C);
+                df v[M];
+                mono_df<M>(X, Y, v);
+#pragma unroll
+                for (int a = 0; a < M; ++a) acc[a] = df_add(acc[a], df_mul(v[a], x[r]));
+            } else {
+#pragma unroll
+                for (int a = 0; a < M; ++a)
+                    if (b - ART == a) acc[a] = df_add(acc[a], x[r]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            df rr = df_add(rhs_df(a, P), df_neg(acc[a]));
+            res[a] = rr.hi + rr.lo;
+        }
+    }
+
+    // exact c_B - B^T y, per basis row
+    __device__ void dual_residual(const CS& cs, const df (&y)[M], float (&res)[M]) const
+    {
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            int b = bs[r];
+            df s{0.0f, 0.0f};
+            if (b < ART) {
+                df X, Y, C;
+                cs.exact(b, X, Y, C);
+                df v[M];
+                mono_df<M>(X, Y, v);
+                s = C;
+#pragma unroll
+                for (int a = 0; a < M; ++a) s = df_add(s, df_neg(df_mul(v[a], y[a])));
+            } else {
+#pragma unroll
+                for (int a = 0; a < M; ++a)
+                    if (b - ART == a) s = df_neg(y[a]);
+            }
+            res[r] = s.hi + s.lo;
+        }
+    }
+
+    // Certify against the exact problem, repairing the basis if needed.
+    // 0 optimal, 1 infeasible, 3 not certified.  x receives the basic values.
+    __device__ int certify(const CS& cs, const LaunchParams& P, df (&x)[M], int& piv)
+    {
+        const int k = cs.k;
+        for (int round = 0; round < kMaxCert; ++round) {
+#pragma unroll
+            for (int r = 0; r < M; ++r) x[r] = {(Bi[r][2] + Bi[r][4]) * P.bt_hi, 0.0f};
+            for (int it = 0; it < kMaxRefine; ++it) {
+                float res[M];
+                primal_residual(cs, x, P, res);
+                float dmax = 0.0f, xmax = 0.0f;
+#pragma unroll
+                for (int r = 0; r < M; ++r) {
+                    float d = 0.0f;
+#pragma unroll
+                    for (int a = 0; a < M; ++a) d = __builtin_fmaf(Bi[r][a], res[a], d);
+                    x[r] = df_add(x[r], df{d, 0.0f});
+                    dmax = fmaxf(dmax, fabsf(d));
+                    xmax = fmaxf(xmax, fabsf(x[r].hi));
+                }
+                if (dmax <= 9.313225746154785e-10f * xmax) break;
+            }
+            float yf[M];
+            prices(true, yf);
+            df y[M];
+#pragma unroll
+            for (int a = 0; a < M; ++a) y[a] = {yf[a], 0.0f};
+            for (int it = 0; it < kMaxRefine; ++it) {
+                float res[M];
+                dual_residual(cs, y, res);
+                float dmax = 0.0f, ymax = 0.0f;
+#pragma unroll
+                for (int a = 0; a < M; ++a) {
+                    float d = 0.0f;
+#pragma unroll
+                    for (int r = 0; r < M; ++r) d = __builtin_fmaf(Bi[r][a], res[r], d);
+                    y[a] = df_add(y[a], df{d, 0.0f});
+                    dmax = fmaxf(dmax, fabsf(d));
+                    ymax = fmaxf(ymax, fabsf(y[a].hi));
+                }
+                if (dmax <= 9.313225746154785e-10f * ymax) break;
+            }
+            // primal feasibility of the exact basic solution
+            int lrow = -1;
+            float xmin = -kCertX;
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                float v = x[r].hi + x[r].lo;
+                if (bs[r] < ART && v < xmin) {
+                    xmin = v;
+                    lrow = r;
+                }
+            }
+            if (lrow >= 0) {
+                // dual repair: row lrow leaves, the entering column by the dual ratio test
+                float wrow[M];
+#pragma unroll
+                for (int a = 0; a < M; ++a) {
+                    float v = 0.0f;
+#pragma unroll
+                    for (int r = 0; r < M; ++r) v = (r == lrow) ? Bi[r][a] : v;
+                    wrow[a] = v;
+                }
+                int e = -1;
+                float best = 0.0f;
+                for (int j = 0; j < k; ++j) {
+                    if (((isb | dead) >> j) & 1ull) continue;
+                    df X, Y, C;
+                    cs.exact(j, X, Y, C);
+                    df v[M];
+                    mono_df<M>(X, Y, v);
+                    float w = 0.0f;
+                    df s = C;
+#pragma unroll
+                    for (int a = 0; a < M; ++a) {
+                        w = __builtin_fmaf(wrow[a], v[a].hi, w);
+                        s = df_add(s, df_neg(df_mul(v[a], y[a])));
+                    }
+                    if (w < -kTolPiv) {
+                        float ratio = fmaxf(s.hi + s.lo, 0.0f) / (-w);
+                        if (e < 0 || ratio < best) {
+                            e = j;
+                            best = ratio;
+                        }
+                    }
+                }
+                if (e < 0) return 1;
+                float rx, ry, ce;
+                cs.get(e, rx, ry, ce);
+                float alpha[M];
+                column_alpha(rx, ry, alpha);
+                pivot(lrow, e, alpha, ce);
+                ++piv;
+                continue;
+            }
+            // exact reduced costs; Bland's entering column
+            int e = -1;
+            for (int j = 0; j < k && e < 0; ++j) {
+                if (((isb | dead) >> j) & 1ull) continue;
+                df X, Y, C;
+                cs.exact(j, X, Y, C);
+                df v[M];
+                mono_df<M>(X, Y, v);
+                df s = C;
+                float sc = fabsf(C.hi);
+#pragma unroll
+                for (int a = 0; a < M; ++a) {
+                    df p = df_mul(v[a], y[a]);
+                    s = df_add(s, df_neg(p));
+                    sc += fabsf(p.hi);
+                }
+                if (s.hi + s.lo < -kCertD * sc) e = j;
+            }
+            if (e < 0) return 0;
+            float rx, ry, ce;
+            cs.get(e, rx, ry, ce);
+            float alpha[M], xf[M];
+            column_alpha(rx, ry, alpha);
+#pragma unroll
+            for (int r = 0; r < M; ++r) xf[r] = x[r].hi + x[r].lo;
+            int l = ratio_test(alpha, xf, true);
+            if (l < 0) return 3;
+            pivot(l, e, alpha, ce);
+            ++piv;
+        }
+        return 3;
+    }
+};
+
+// Solve, certify and extract the fractions: f (k entries, written through
+// store(j, value) for the non-zero ones) and fii = -sum f.
+// Returns 0 ok, 1 infeasible; *certified = 0 if optimality could not be shown.
+template <int M, class CS, class Store>
+__device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified)
+{
+    ThreadSimplex<M, CS> lp;
+    lp.bt_ = P.bt_hi;
+    lp.init(P);
+    lp.dead = cs.dead;
+    int st = lp.run(cs, piv);
+    certified = 1;
+    if (st == 1) return 1;
+    df x[M];
+    int c = lp.certify(cs, P, x, piv);
+    if (c == 1) return 1;
+    certified = (c == 0 && st == 0) ? 1 : 0;
+    float sum = 0.0f;
+    float v[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        float t = x[r].hi + x[r].lo;
+        v[r] = (lp.bs[r] < lp.ART && t > 0.0f) ? t : 0.0f;
+        sum += v[r];
+    }
+    // a basic value below 2^-30 of the stencil's sum is the round-off of a
+    // degenerate vertex (zero in exact arithmetic): make it zero
+    float tiny = 9.313225746154785e-10f * sum;
+    sum = 0.0f;
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        v[r] = v[r] < tiny ? 0.0f : v[r];
+        sum += v[r];
+        if (v[r] != 0.0f) store(lp.bs[r], v[r]);
+    }
+    fii = -sum;
+    return 0;
+}
+
+}  // namespace vrm

@@ -60,7 +60,7 @@ int main(void) {
   printf("vrm_stencils %zu\\n", sizeof(vrm_stencils));
   printf("vrm_counters %zu\\n", sizeof(vrm_counters));
   P(vrm_params, q) P(vrm_cloud, capacity) P(vrm_stencils, full_f_dev)
-  P(vrm_counters, pivots) P(vrm_counters, redistributions) P(vrm_counters, mis_rounds)
+  P(vrm_counters, pivots) P(vrm_counters, redistributions) P(vrm_counters, mis_rounds) P(vrm_counters, full_cols)
   return 0;
 }
 """)
@@ -77,6 +77,7 @@ int main(void) {
     assert int(out["vrm_counters.pivots"]) == vrm.vrm_counters.pivots.offset
     assert int(out["vrm_counters.redistributions"]) == vrm.vrm_counters.redistributions.offset
     assert int(out["vrm_counters.mis_rounds"]) == vrm.vrm_counters.mis_rounds.offset
+    assert int(out["vrm_counters.full_cols"]) == vrm.vrm_counters.full_cols.offset
 
 
 def test_product_path_has_no_cpu_fallback():
