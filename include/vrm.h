@@ -112,15 +112,17 @@ typedef struct {
 
 /* Create a context on `device` that enqueues on `stream` (a hipStream_t; NULL
  * = the null stream) for clouds of up to `capacity` particles.  The context
- * owns all scratch memory (about 120 bytes per particle of capacity) and
+ * owns all scratch memory (about 250 bytes per particle of capacity) and
  * frees it in vrm_destroy.  Synchronises. */
 int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity);
 int vrm_destroy(vrm_ctx* ctx);
 
 /* Sec. 3.5, eq. reduced_bound: choose the diffused set of the step from the
- * current circulations: leave out the particles of smallest |Gamma| (whole
- * groups of equal |Gamma|) while the l1 norm of the left-out ones stays
- * <= c_diff h^(q+1) ||Gamma||_1.  Kept in the context (and written to
+ * current circulations: leave out the particles of smallest |Gamma| while the
+ * l1 norm of the left-out ones stays <= c_diff h^(q+1) ||Gamma||_1.  Particles
+ * are ranked by |Gamma| truncated to 16 significant bits and whole groups of
+ * equal rank are left out together (values equal up to round-off form one
+ * group); the sums use the exact |Gamma| in FP64.  Kept in the context (and written to
  * mask_dev[N] as 0/1 when mask_dev != NULL). */
 int vrm_select_diffused(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params* p, uint8_t* mask_dev);
 
@@ -142,7 +144,8 @@ int vrm_build_neighbourhoods(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_par
  * vrm_select_diffused), inserts a Gamma = 0 particle on the centre line of
  * every empty segment of every diffused particle at radius 1.5 h, resolving
  * conflicts between candidates closer than 0.5 h greedily in (id, segment)
- * order, appends the new particles with ids max_id+1, ... in that order, and
+ * order, appends the new particles with ids N, N+1, ... in that order (the
+ * cloud's ids are expected to be 0..N-1 in some order), and
  * reorders the whole cloud by cell.  On VRM_E_CAPACITY (detected on the
  * device; reported by the next vrm_read_counters as capacity_needed) the
  * cloud is left unchanged. */
