@@ -108,10 +108,13 @@ typedef struct {
     int32_t capacity_needed;  /* set when an insertion failed for capacity */
     int32_t mis_rounds;       /* rounds of the last insertion's conflict resolution */
     int64_t full_cols;        /* sum of the column counts of complete-neighbourhood LPs (cumulative) */
+    int64_t warm_hit;         /* warm-started LPs whose predicted basis was optimal (cumulative) */
+    int64_t warm_phase2;      /* warm-started LPs that needed phase-II pivots from the predicted basis */
+    int64_t warm_cold;        /* predictions rejected (infeasible or incomplete basis): cold start */
 } vrm_counters;
 
 /* Create a context on `device` that enqueues on `stream` (a hipStream_t; NULL
- * = the null stream) for clouds of up to `capacity` particles.  The context
+ * = the null stream) for clouds of up to `capacity` particles (at most 2^26).  The context
  * owns all scratch memory (about 250 bytes per particle of capacity) and
  * frees it in vrm_destroy.  Synchronises. */
 int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity);
@@ -185,6 +188,49 @@ int vrm_read_counters(vrm_ctx* ctx, vrm_counters* out_host);
  * vort_dev = device floats [n_vort][4] (cx, cy, sigma, G). */
 int vrm_vortex_velocity(vrm_ctx* ctx, const vrm_cloud* cloud, const float* vort_dev, int32_t n_vort,
                         double nu, double t, float* u_dev, float* v_dev);
+
+/* ---- Learned warm start (build component; not in the paper) ------------
+ * A small network predicts, from the offsets of an LP's columns, which
+ * columns form the optimal basis.  Input row (BF16, VRM_MLP_IN values): for
+ * slots j < 32, (dx_j / h, dy_j / h) at [2j, 2j+1] and a 0/1 mask at [64 + j];
+ * q - 2 at [96]; zeros elsewhere.  Slots are the small-neighbourhood columns by
+ * segment (q = 2) or the complete-neighbourhood columns nearest first by
+ * (distance, id) (q = 3).  Output row (FP32, VRM_MLP_OUT): 32 basis logits,
+ * 32 fractions.  Layers 128 -> 128 (GELU) -> 128 (GELU) -> 64, BF16 matrix
+ * products with FP32 accumulation.  Parameters (FP32, VRM_MLP_PARAMS values):
+ * W1[128][128], b1[128], W2[128][128], b2[128], W3[128][64], b3[64].
+ * The warm start never changes results: the predicted basis only seeds the
+ * simplex, whose answer is certified exactly as without it. */
+#define VRM_MLP_IN 128
+#define VRM_MLP_OUT 64
+#define VRM_MLP_PARAMS 41280
+/* Copy parameters in (device FP32) / out. */
+int vrm_mlp_load(vrm_ctx* ctx, const float* params_dev);
+int vrm_mlp_read(vrm_ctx* ctx, float* params_dev);
+/* Enable (1) or disable (0) the warm start of vrm_solve_fractions / vrm_rk_stage
+ * (needs loaded parameters; allocates 512 bytes per particle of capacity). */
+int vrm_set_warm_start(vrm_ctx* ctx, int enable);
+/* Training data from the plain solver at the current positions and diffused
+ * set: for the LPs queued first (small ones for q = 2, complete ones for
+ * q = 3), input rows x_dev[max_rows][128] (BF16) and targets y_dev[max_rows][64]
+ * (32 basis indicators of the optimal stencil's non-zero fractions, 32
+ * fractions).  *rows_host = rows written.  Synchronises. */
+int vrm_collect_training(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params* p, uint16_t* x_dev, float* y_dev,
+                         int32_t max_rows, int32_t* rows_host);
+/* One AdamW step (lr, weight decay; beta 0.9 / 0.999) on the mean over rows of
+ * masked BCE-with-logits on the indicators plus frac_weight times the masked
+ * squared error of the fractions.  loss_dev (one double) and grad_dev
+ * (VRM_MLP_PARAMS floats, before the step) may be NULL.  lr = 0 computes the
+ * loss and gradient only. */
+int vrm_mlp_train_step(vrm_ctx* ctx, const uint16_t* x_dev, const float* y_dev, int32_t rows, float lr,
+                       float weight_decay, float frac_weight, double* loss_dev, float* grad_dev);
+/* Forward pass: y_dev[rows][64] from x_dev[rows][128]. */
+int vrm_mlp_infer(vrm_ctx* ctx, const uint16_t* x_dev, int32_t rows, float* y_dev);
+/* Matrix product on the BF16 matrix cores (test hook): C[M][N] (FP32, zeroed
+ * by the caller) += op(A) op(B) with A[M][K] (or [K][M] if transA) and B[K][N]
+ * (or [N][K] if transB), BF16 row-major. */
+int vrm_gemm_bf16(vrm_ctx* ctx, const uint16_t* a_dev, const uint16_t* b_dev, float* c_dev, int32_t M, int32_t N,
+                  int32_t K, int transA, int transB);
 
 /* Kernel timers (profiling).  While enabled, every launch of the kernel
  * groups below is bracketed by HIP events recorded on the context's stream

@@ -57,7 +57,8 @@ class vrm_counters(ctypes.Structure):
                 ("n_infeasible", ctypes.c_int32), ("n_uncertified", ctypes.c_int32),
                 ("n_truncated", ctypes.c_int32), ("n_grid_clamped", ctypes.c_int32),
                 ("pivots", ctypes.c_int64), ("redistributions", ctypes.c_int64),
-                ("capacity_needed", ctypes.c_int32), ("mis_rounds", ctypes.c_int32), ("full_cols", ctypes.c_int64)]
+                ("capacity_needed", ctypes.c_int32), ("mis_rounds", ctypes.c_int32), ("full_cols", ctypes.c_int64),
+                ("warm_hit", ctypes.c_int64), ("warm_phase2", ctypes.c_int64), ("warm_cold", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,7 +66,10 @@ class vrm_counters(ctypes.Structure):
 
 EXPORTS = ["vrm_create", "vrm_destroy", "vrm_select_diffused", "vrm_set_diffused", "vrm_build_neighbourhoods",
            "vrm_insert_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_verify", "vrm_read_counters",
-           "vrm_vortex_velocity", "vrm_timing", "vrm_read_timing", "vrm_last_error", "vrm_status_string"]
+           "vrm_vortex_velocity", "vrm_timing", "vrm_read_timing", "vrm_mlp_load", "vrm_mlp_read",
+           "vrm_set_warm_start", "vrm_collect_training", "vrm_mlp_train_step", "vrm_mlp_infer", "vrm_gemm_bf16",
+           "vrm_last_error", "vrm_status_string"]
+MLP_IN, MLP_OUT, MLP_PARAMS, MLP_SLOTS = 128, 64, 41280, 32
 TIMERS = ["select", "cells", "nbhd", "lp_small", "lp_full", "insert", "combine", "mlp"]
 
 _lib = None
@@ -93,6 +97,16 @@ def lib():
         L.vrm_read_counters.argtypes = [vp, ctypes.POINTER(vrm_counters)]
         L.vrm_vortex_velocity.argtypes = [vp, ctypes.POINTER(vrm_cloud), vp, ctypes.c_int32, ctypes.c_double,
                                           ctypes.c_double, vp, vp]
+        L.vrm_mlp_load.argtypes = [vp, vp]
+        L.vrm_mlp_read.argtypes = [vp, vp]
+        L.vrm_set_warm_start.argtypes = [vp, ctypes.c_int]
+        L.vrm_collect_training.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params), vp, vp,
+                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.vrm_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                         vp, vp]
+        L.vrm_mlp_infer.argtypes = [vp, vp, ctypes.c_int32, vp]
+        L.vrm_gemm_bf16.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
+                                    ctypes.c_int]
         L.vrm_timing.argtypes = [vp, ctypes.c_int]
         L.vrm_read_timing.argtypes = [vp, vp, vp]
         L.vrm_last_error.restype = ctypes.c_char_p
@@ -253,6 +267,32 @@ class Context:
         if rc < 0:
             _check(rc)
         return {k: (ms[i], ln[i]) for i, k in enumerate(TIMERS)}, rc == 1
+
+    # --- learned warm start
+    def vrm_mlp_load(self, params):
+        _check(lib().vrm_mlp_load(self.handle, _ptr(params)))
+
+    def vrm_mlp_read(self, params):
+        _check(lib().vrm_mlp_read(self.handle, _ptr(params)))
+
+    def vrm_set_warm_start(self, enable: bool):
+        _check(lib().vrm_set_warm_start(self.handle, 1 if enable else 0))
+
+    def vrm_collect_training(self, cloud: Cloud, p: vrm_params, x, y) -> int:
+        rows = ctypes.c_int32(0)
+        _check(lib().vrm_collect_training(self.handle, ctypes.byref(cloud.c), ctypes.byref(p), _ptr(x), _ptr(y),
+                                          int(x.shape[0]), ctypes.byref(rows)))
+        return rows.value
+
+    def vrm_mlp_train_step(self, x, y, rows, lr, weight_decay=0.0, frac_weight=1.0, loss=None, grad=None):
+        _check(lib().vrm_mlp_train_step(self.handle, _ptr(x), _ptr(y), int(rows), float(lr), float(weight_decay),
+                                        float(frac_weight), _ptr(loss), _ptr(grad)))
+
+    def vrm_mlp_infer(self, x, rows, y):
+        _check(lib().vrm_mlp_infer(self.handle, _ptr(x), int(rows), _ptr(y)))
+
+    def vrm_gemm_bf16(self, a, b, c, M, N, K, trans_a=False, trans_b=False):
+        _check(lib().vrm_gemm_bf16(self.handle, _ptr(a), _ptr(b), _ptr(c), M, N, K, int(trans_a), int(trans_b)))
 
     # --- convenience
     def step(self, cloud: Cloud, p: vrm_params, velocity=None, t=0.0, insertion=True):

@@ -7,7 +7,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvrm.so")
-SOURCES = ["vrm_api.cpp", "vrm_cells.hip", "vrm_lp.hip", "vrm_stage.hip"]
+SOURCES = ["vrm_api.cpp", "vrm_cells.hip", "vrm_lp.hip", "vrm_stage.hip", "vrm_mlp.hip"]
 ARCH = os.environ.get("VRM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -39,6 +39,7 @@ vrm::LaunchParams launch_params(const vrm_params* p)
     L.cs_hi = (float)cs;
     L.cs_lo = (float)(cs - (double)L.cs_hi);
     L.lam = (float)(p->nu / (h * h));
+    L.sc = (float)s;
     L.q = p->q;
     L.m = p->q == 2 ? 5 : 9;
     return L;
@@ -141,7 +142,8 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
 {
     if (!out) return vrm_fail(VRM_E_ARG, "out is NULL");
     *out = nullptr;
-    if (capacity <= 0 || capacity > (1 << 28)) return vrm_fail(VRM_E_ARG, "capacity %d outside (0, 2^28]", capacity);
+    // complete-neighbourhood LPs pack a particle slot in 26 bits
+    if (capacity <= 0 || capacity > (1 << 26)) return vrm_fail(VRM_E_ARG, "capacity %d outside (0, 2^26]", capacity);
     VRM_HIP(hipSetDevice(device));
     vrm_ctx* c = new vrm_ctx();
     std::memset(c, 0, sizeof(*c));
@@ -222,6 +224,9 @@ int vrm_destroy(vrm_ctx* c)
                     c->akey, c->aidx, c->tmp_f, c->tmp_i, c->tmp_u8, c->verify_buf, c->sort_tmp};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    if (c->feat) (void)hipFree(c->feat);
+    if (c->pred) (void)hipFree(c->pred);
+    vrm_mlp_free(c);
     if (c->ev_start) {
         for (int k = 0; k < vrm::kMaxTimed; ++k) {
             (void)hipEventDestroy(c->ev_start[k]);
@@ -387,6 +392,87 @@ int vrm_read_counters(vrm_ctx* c, vrm_counters* out)
     VRM_HIP(hipStreamSynchronize(c->stream));
     out->n = c->n;
     return VRM_OK;
+}
+
+int vrm_mlp_load(vrm_ctx* c, const float* w)
+{
+    if (!c || !w) return vrm_fail(VRM_E_ARG, "NULL argument");
+    int r = vrm_mlp_alloc(c, 0);
+    if (!r) r = vrm_mlp_set_weights(c, w);
+    return r;
+}
+
+int vrm_mlp_read(vrm_ctx* c, float* w)
+{
+    if (!c || !w) return vrm_fail(VRM_E_ARG, "NULL argument");
+    if (!c->mlp) return vrm_fail(VRM_E_STATE, "no network parameters");
+    return vrm_mlp_read_weights(c, w);
+}
+
+int vrm_set_warm_start(vrm_ctx* c, int enable)
+{
+    if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
+    if (enable) {
+        if (!c->mlp || !c->mlp->loaded) return vrm_fail(VRM_E_STATE, "warm start needs network parameters (vrm_mlp_load)");
+        if (!c->feat) {
+            void* p = nullptr;
+            VRM_HIP(hipMalloc(&p, sizeof(uint16_t) * (size_t)c->capacity * vrm::kMlpIn + 64));
+            c->feat = (uint16_t*)p;
+            VRM_HIP(hipMalloc(&p, sizeof(float) * (size_t)c->capacity * vrm::kMlpOut + 64));
+            c->pred = (float*)p;
+        }
+    }
+    c->warm = enable ? 1 : 0;
+    return VRM_OK;
+}
+
+int vrm_collect_training(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, uint16_t* x, float* y, int32_t max_rows,
+                         int32_t* rows)
+{
+    int r = check_cloud(c, cl);
+    if (!r) r = check_params(p);
+    if (!r) r = cached_n(c, cl);
+    if (!r && (!x || !y || !rows || max_rows <= 0)) r = vrm_fail(VRM_E_ARG, "training buffers");
+    if (r) return r;
+    vrm::LaunchParams L = launch_params(p);
+    if (!c->cells_valid) {
+        r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
+        if (r) return r;
+        c->cells_valid = 1;
+    }
+    r = vrm_stencil_run(c, cl, c->n, L, nullptr, 0, x, y, max_rows);
+    if (r) return r;
+    vrm::Queues q;
+    VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(q), hipMemcpyDeviceToHost, c->stream));
+    VRM_HIP(hipStreamSynchronize(c->stream));
+    int got = L.m == 5 ? q.n_small : q.n_full;
+    *rows = got < max_rows ? got : max_rows;
+    return VRM_OK;
+}
+
+int vrm_mlp_train_step(vrm_ctx* c, const uint16_t* x, const float* y, int32_t rows, float lr, float wd, float wf,
+                       double* loss, float* grad)
+{
+    if (!c || !x || !y || rows <= 0) return vrm_fail(VRM_E_ARG, "training arguments");
+    if (!c->mlp || !c->mlp->loaded) return vrm_fail(VRM_E_STATE, "no network parameters (vrm_mlp_load)");
+    int r = vrm_mlp_alloc(c, rows);
+    if (!r) r = vrm_mlp_train(c, x, y, rows, lr, wd, wf, loss, grad);
+    return r;
+}
+
+int vrm_mlp_infer(vrm_ctx* c, const uint16_t* x, int32_t rows, float* y)
+{
+    if (!c || !x || !y || rows < 0) return vrm_fail(VRM_E_ARG, "inference arguments");
+    if (!c->mlp || !c->mlp->loaded) return vrm_fail(VRM_E_STATE, "no network parameters (vrm_mlp_load)");
+    vrm::ScopedTimer tm(c, VRM_T_MLP);
+    return vrm_mlp_infer_run(c, x, (int)rows, y, nullptr);
+}
+
+int vrm_gemm_bf16(vrm_ctx* c, const uint16_t* a, const uint16_t* b, float* out, int32_t M, int32_t N, int32_t K,
+                  int ta, int tb)
+{
+    if (!c || !a || !b || !out || M <= 0 || N <= 0 || K <= 0) return vrm_fail(VRM_E_ARG, "gemm arguments");
+    return vrm_gemm_test(c, a, b, out, M, N, K, ta, tb);
 }
 
 int vrm_timing(vrm_ctx* c, int enable)

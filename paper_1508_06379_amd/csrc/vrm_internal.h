@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "vrm.h"
+#include "vrm_mlp.h"
 
 namespace vrm {
 
@@ -43,6 +44,7 @@ struct LaunchParams {
     float bt_hi, bt_lo;                  // rhs 2 h^2 / 4^e of the (2,0), (0,2) rows (double-float)
     float cs_hi, cs_lo;                  // (2^e / h)^(q+1): cost scale (double-float)
     float lam;                           // nu / h^2
+    float sc;                            // 2^e / h: scaled offset -> offset / h
     int q, m;
 };
 
@@ -105,6 +107,14 @@ struct vrm_ctx {
     hipEvent_t* ev_stop;
     int* ev_group;
     int64_t launches[VRM_NTIMER];
+    // warm-start network (allocated on first use)
+    vrm::MlpState* mlp;
+    int warm;             // LP solves use the network's basis prediction
+    uint16_t* feat;       // [cap][128] feature rows of the queued LPs (warm start / collection)
+    float* pred;          // [cap][64] network outputs
+    float* labels;        // [cap][64] collection targets
+    int32_t* full_cols;   // [cap][48] complete-neighbourhood columns sorted by (d2, id)
+    int32_t feat_cap;
 };
 
 namespace vrm {
@@ -137,7 +147,8 @@ int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const vrm::LaunchParams
 int vrm_reorder_cloud(vrm_ctx* c, vrm_cloud* cl, int32_t n);
 // launchers (vrm_lp.hip)
 int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp,
-                    const vrm_stencils* out, int apply);
+                    const vrm_stencils* out, int apply, uint16_t* feat_out = nullptr, float* label_out = nullptr,
+                    int max_rows = 0);
 int vrm_small_nbhd_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp,
                        int32_t* small_idx, int32_t* kfull);
 // launchers (vrm_stage.hip)
@@ -147,6 +158,18 @@ int vrm_verify_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::Launch
                    const vrm_stencils* st, double* report);
 int vrm_velocity_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const float* vort, int32_t nv, double nu,
                      double t, float* u, float* v);
+
+// launchers (vrm_mlp.hip)
+int vrm_mlp_alloc(vrm_ctx* c, int max_rows);
+void vrm_mlp_free(vrm_ctx* c);
+int vrm_mlp_set_weights(vrm_ctx* c, const float* w_dev);
+int vrm_mlp_forward(vrm_ctx* c, const uint16_t* X, int rows, float* Y, const int* rows_dev);
+int vrm_mlp_read_weights(vrm_ctx* c, float* w_dev);
+int vrm_mlp_infer_run(vrm_ctx* c, const uint16_t* X, int rows, float* Y, const int* rows_dev);
+int vrm_mlp_train(vrm_ctx* c, const uint16_t* X, const float* T, int rows, float lr, float wd, float wf,
+                  double* loss_out, float* grad_out);
+int vrm_gemm_test(vrm_ctx* c, const uint16_t* A, const uint16_t* B, float* C, int M, int N, int K, int transA,
+                  int transB);
 
 // error helpers (vrm_api.cpp)
 int vrm_fail(int code, const char* fmt, ...);

@@ -143,6 +143,10 @@ struct StencilOut {
     int32_t* full_k;
     int32_t* full_idx;
     float* full_f;
+    uint16_t* feat;      // feature rows of solved LPs (collection), or NULL
+    float* lab;          // label rows (basis indicators, fractions) of solved LPs, or NULL
+    int max_rows;
+    const float* pred;   // network outputs per queue item (warm start), or NULL
 };
 
 __device__ __forceinline__ void count_add(int* p, bool v)
@@ -150,37 +154,6 @@ __device__ __forceinline__ void count_add(int* p, bool v)
     uint64_t m = __ballot(v);
     if (m && lane_id() == __ffsll((unsigned long long)m) - 1) atomicAdd(p, __popcll(m));
 }
-
-// Columns of a small-neighbourhood LP, in registers (column j = segment j).
-struct RegCols8 {
-    int k;
-    uint64_t dead;
-    float rx[8], ry[8], c[8], rxl[8], ryl[8], cl[8];
-    __device__ __forceinline__ void get(int j, float& x, float& y, float& cc) const
-    {
-        x = 0.0f;
-        y = 0.0f;
-        cc = 0.0f;
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-            if (s == j) {
-                x = rx[s];
-                y = ry[s];
-                cc = c[s];
-            }
-    }
-    __device__ __forceinline__ void exact(int j, df& X, df& Y, df& C) const
-    {
-        X = Y = C = {0.0f, 0.0f};
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-            if (s == j) {
-                X = {rx[s], rxl[s]};
-                Y = {ry[s], ryl[s]};
-                C = {c[s], cl[s]};
-            }
-    }
-};
 
 // add 2^-10 rank(id) to a double-float cost (exact at these magnitudes)
 __device__ __forceinline__ df add_rank(df C, int rank)
@@ -190,58 +163,137 @@ __device__ __forceinline__ df add_rank(df C, int rank)
     return fast_two_sum(w.hi, w.lo);
 }
 
-// Small-neighbourhood LPs (5 rows, up to 8 columns), one thread per particle.
-__global__ __launch_bounds__(256) void k_lp_small(const int32_t* __restrict__ perm, const float* __restrict__ xs,
-                                                  const float* __restrict__ ys, const int32_t* __restrict__ ids,
-                                                  const int32_t* __restrict__ small_slot,
-                                                  const int32_t* __restrict__ q_small, Queues* qs,
-                                                  int32_t* q_full, const float* __restrict__ gamma,
-                                                  float* acc, LaunchParams P, StencilOut out, int apply,
-                                                  vrm_counters* cnt)
+__device__ __forceinline__ uint16_t f2bf(float f)
 {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// feature row of an LP: slot j < 32 holds column j's offset / h, its mask, and q - 2
+__device__ __forceinline__ void feature_zero(uint16_t* row)
+{
+#pragma unroll 4
+    for (int a = 0; a < kMlpIn; ++a) row[a] = 0;
+}
+__device__ __forceinline__ void feature_slot(uint16_t* row, int j, float dxh, float dyh)
+{
+    row[2 * j] = f2bf(dxh);
+    row[2 * j + 1] = f2bf(dyh);
+    row[2 * kMlpSlots + j] = 0x3f80;   // 1.0
+}
+__device__ __forceinline__ void feature_q(uint16_t* row, int q) { row[3 * kMlpSlots] = q == 3 ? 0x3f80 : 0; }
+
+__device__ __forceinline__ void count_warm(vrm_counters* cnt, bool live, int warm)
+{
+    uint64_t m1 = __ballot(live && warm == 1), m2 = __ballot(live && warm == 2), m3 = __ballot(live && warm == 3);
+    if (lane_id() == 0) {
+        if (m1) atomicAdd((unsigned long long*)&cnt->warm_hit, (unsigned long long)__popcll(m1));
+        if (m2) atomicAdd((unsigned long long*)&cnt->warm_phase2, (unsigned long long)__popcll(m2));
+        if (m3) atomicAdd((unsigned long long*)&cnt->warm_cold, (unsigned long long)__popcll(m3));
+    }
+}
+
+constexpr int kFullBlock = 64;
+
+// Columns of an LP in LDS, column-major per thread (stride = threads per block):
+// FP32 scaled offsets and cost, and (slot << 6) | id rank for the exact values.
+template <int BLK>
+struct LdsColsT {
+    int k;
+    uint64_t dead;
+    float* srx;
+    float* sry;
+    float* sc;
+    int* smeta;
+    int tid;
+    float xi, yi;
+    const float* xs;
+    const float* ys;
+    const LaunchParams* P;
+    __device__ __forceinline__ void get(int j, float& x, float& y, float& cc) const
+    {
+        x = srx[j * BLK + tid];
+        y = sry[j * BLK + tid];
+        cc = sc[j * BLK + tid];
+    }
+    __device__ __forceinline__ void exact(int j, df& X, df& Y, df& C) const
+    {
+        int meta = smeta[j * BLK + tid];
+        int u = (int)((unsigned)meta >> 6);
+        exact_offset(xi, yi, xs[u], ys[u], P->scale2e, X, Y);
+        C = add_rank(cost_df(X, Y, *P), meta & 63);
+    }
+};
+using LdsCols = LdsColsT<kFullBlock>;
+
+// Small-neighbourhood LPs (5 rows, up to 8 columns), one thread per particle;
+// the columns (column j = segment j) live in LDS.
+constexpr int kSmallBlock = 256;
+
+__global__ __launch_bounds__(kSmallBlock) void k_lp_small(const int32_t* __restrict__ perm,
+                                                          const float* __restrict__ xs, const float* __restrict__ ys,
+                                                          const int32_t* __restrict__ ids,
+                                                          const int32_t* __restrict__ small_slot,
+                                                          const int32_t* __restrict__ q_small, Queues* qs,
+                                                          int32_t* q_full, const float* __restrict__ gamma,
+                                                          float* acc, LaunchParams P, StencilOut out, int apply,
+                                                          vrm_counters* cnt)
+{
+    __shared__ float s_rx[8 * kSmallBlock];
+    __shared__ float s_ry[8 * kSmallBlock];
+    __shared__ float s_c[8 * kSmallBlock];
+    __shared__ int s_meta[8 * kSmallBlock];
+    const int tid = threadIdx.x;
     const int nitems = qs->n_small;
     const int stride = gridDim.x * blockDim.x;
     int loops = (nitems + stride - 1) / stride;
     for (int it = 0; it < loops; ++it) {
-        int item = blockIdx.x * blockDim.x + threadIdx.x + it * stride;
+        int item = blockIdx.x * blockDim.x + tid + it * stride;
         bool live = item < nitems;
-        int st = 1, piv = 0, certified = 1;
+        int st = 1, piv = 0, certified = 1, warm = 0;
         int t = 0, i = 0;
         if (live) {
             t = q_small[item];
             i = perm[t];
             const float xi = xs[t], yi = ys[t];
-            RegCols8 cs;
-            int us[8], idv[8];
-            cs.k = 8;
-            cs.dead = 0;
+            uint64_t dead = 0;
+            int idv[8];
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 int u = small_slot[(size_t)t * VRM_NSEG + s];
-                us[s] = u;
                 idv[s] = u >= 0 ? ids[u] : 0x7fffffff;
-                if (u < 0) {
-                    cs.dead |= 1ull << s;
-                    cs.rx[s] = cs.ry[s] = cs.c[s] = cs.rxl[s] = cs.ryl[s] = cs.cl[s] = 0.0f;
-                    continue;
-                }
-                df X, Y;
-                exact_offset(xi, yi, xs[u], ys[u], P.scale2e, X, Y);
-                cs.rx[s] = X.hi;
-                cs.rxl[s] = X.lo;
-                cs.ry[s] = Y.hi;
-                cs.ryl[s] = Y.lo;
+                s_meta[s * kSmallBlock + tid] = u;
+                if (u < 0) dead |= 1ull << s;
             }
+            const bool rec = out.feat && item < out.max_rows;
+            uint16_t* frow = rec ? out.feat + (size_t)item * kMlpIn : nullptr;
+            if (rec) feature_zero(frow);
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                if (us[s] < 0) continue;
-                int rank = 0;
+                int u = s_meta[s * kSmallBlock + tid];
+                float rx = 0.0f, ry = 0.0f, c = 0.0f;
+                int meta = 0;
+                if (u >= 0) {
+                    int rank = 0;
 #pragma unroll
-                for (int o = 0; o < 8; ++o) rank += idv[o] < idv[s] ? 1 : 0;
-                df C = add_rank(cost_df({cs.rx[s], cs.rxl[s]}, {cs.ry[s], cs.ryl[s]}, P), rank);
-                cs.c[s] = C.hi;
-                cs.cl[s] = C.lo;
+                    for (int o = 0; o < 8; ++o) rank += idv[o] < idv[s] ? 1 : 0;
+                    df X, Y;
+                    exact_offset(xi, yi, xs[u], ys[u], P.scale2e, X, Y);
+                    df C = add_rank(cost_df(X, Y, P), rank);
+                    rx = X.hi;
+                    ry = Y.hi;
+                    c = C.hi;
+                    meta = (int)(((unsigned)u << 6) | (unsigned)rank);
+                    if (rec) feature_slot(frow, s, rx * P.sc, ry * P.sc);
+                }
+                s_rx[s * kSmallBlock + tid] = rx;
+                s_ry[s * kSmallBlock + tid] = ry;
+                s_c[s * kSmallBlock + tid] = c;
+                s_meta[s * kSmallBlock + tid] = meta;
             }
+            if (rec) feature_q(frow, P.q);
+            LdsColsT<kSmallBlock> cs{8, dead, s_rx, s_ry, s_c, s_meta, tid, xi, yi, xs, ys, &P};
             float fv[8];
 #pragma unroll
             for (int s = 0; s < 8; ++s) fv[s] = 0.0f;
@@ -251,21 +303,32 @@ __global__ __launch_bounds__(256) void k_lp_small(const int32_t* __restrict__ pe
                 for (int s = 0; s < 8; ++s)
                     if (s == j) fv[s] = v;
             };
-            st = solve_lp<5>(cs, P, store, fii, piv, certified);
+            const float* logit = out.pred ? out.pred + (size_t)item * kMlpOut : nullptr;
+            st = solve_lp<5>(cs, P, store, fii, piv, certified, logit, warm);
+            if (rec) {
+                float* lab = out.lab + (size_t)item * kMlpOut;
+#pragma unroll
+                for (int s = 0; s < kMlpSlots; ++s) {
+                    float v = s < 8 ? fv[s] : 0.0f;
+                    lab[s] = (st == 0 && v > 0.0f) ? 1.0f : 0.0f;
+                    lab[kMlpSlots + s] = st == 0 ? v : 0.0f;
+                }
+            }
             if (st == 0) {
                 float g = gamma[i];
-                if (apply) {
 #pragma unroll
-                    for (int s = 0; s < 8; ++s)
-                        if (fv[s] != 0.0f) atomicAdd(&acc[perm[us[s]]], fv[s] * g);
-                    atomicAdd(&acc[i], fii * g);
-                }
-                if (out.small_f) {
-#pragma unroll
-                    for (int s = 0; s < 8; ++s) {
-                        out.small_idx[(size_t)i * VRM_NSEG + s] = us[s] >= 0 ? perm[us[s]] : -1;
+                for (int s = 0; s < 8; ++s) {
+                    int u = (int)((unsigned)s_meta[s * kSmallBlock + tid] >> 6);
+                    bool alive = !((dead >> s) & 1ull);
+                    int pj = alive ? perm[u] : -1;
+                    if (apply && fv[s] != 0.0f) atomicAdd(&acc[pj], fv[s] * g);
+                    if (out.small_f) {
+                        out.small_idx[(size_t)i * VRM_NSEG + s] = pj;
                         out.small_f[(size_t)i * VRM_NSEG + s] = fv[s];
                     }
+                }
+                if (apply) atomicAdd(&acc[i], fii * g);
+                if (out.small_f) {
                     out.fii[i] = fii;
                     out.status[i] = VRM_ST_SMALL;
                 }
@@ -275,6 +338,7 @@ __global__ __launch_bounds__(256) void k_lp_small(const int32_t* __restrict__ pe
         if (piv) atomicAdd((unsigned long long*)&cnt->pivots, (unsigned long long)piv);
         count_add(&cnt->n_small, ok);
         count_add(&cnt->n_uncertified, ok && !certified);
+        count_warm(cnt, live, warm);
         if (apply) {
             uint64_t m = __ballot(ok);
             if (m && lane_id() == __ffsll((unsigned long long)m) - 1)
@@ -286,39 +350,133 @@ __global__ __launch_bounds__(256) void k_lp_small(const int32_t* __restrict__ pe
     }
 }
 
-constexpr int kFullBlock = 64;
+// feature rows of the queued small LPs (warm start)
+__global__ __launch_bounds__(256) void k_feat_small(const float* __restrict__ xs, const float* __restrict__ ys,
+                                                    const int32_t* __restrict__ small_slot,
+                                                    const int32_t* __restrict__ q_small, const Queues* qs,
+                                                    LaunchParams P, uint16_t* feat)
+{
+    int item = blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= qs->n_small) return;
+    int t = q_small[item];
+    const float xi = xs[t], yi = ys[t];
+    uint16_t* row = feat + (size_t)item * kMlpIn;
+    feature_zero(row);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        int u = small_slot[(size_t)t * VRM_NSEG + s];
+        if (u >= 0) feature_slot(row, s, (xs[u] - xi) / P.h, (ys[u] - yi) / P.h);
+    }
+    feature_q(row, P.q);
+}
 
-// Columns of a complete-neighbourhood LP, in LDS (column-major per thread).
-struct LdsCols {
-    int k;
-    uint64_t dead;
-    float* srx;       // [VRM_KMAX][kFullBlock]
-    float* sry;
-    float* sc;
-    int* smeta;       // (slot << 6) | rank
-    int tid;
-    float xi, yi;
-    const float* xs;
-    const float* ys;
-    const LaunchParams* P;
-    __device__ __forceinline__ void get(int j, float& x, float& y, float& cc) const
-    {
-        x = srx[j * kFullBlock + tid];
-        y = sry[j * kFullBlock + tid];
-        cc = sc[j * kFullBlock + tid];
-    }
-    __device__ __forceinline__ void exact(int j, df& X, df& Y, df& C) const
-    {
-        int meta = smeta[j * kFullBlock + tid];
-        int u = meta >> 6;
-        exact_offset(xi, yi, xs[u], ys[u], P->scale2e, X, Y);
-        C = add_rank(cost_df(X, Y, *P), meta & 63);
-    }
-};
 
 __device__ __forceinline__ uint64_t member_key(float d2, int id)
 {
     return ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)id;
+}
+
+// Complete neighbourhood of slot t within R_full (its VRM_KMAX nearest by (d2, id)
+// if larger), sorted nearest first.  Slots go to su[j * kFullBlock], keys to
+// sd2 / sid (same layout).  Returns the count.
+__device__ int collect_full(int t, float xi, float yi, const GridState& g, const int32_t* __restrict__ cell_start,
+                            const float* __restrict__ xs, const float* __restrict__ ys,
+                            const int32_t* __restrict__ ids, const LaunchParams& P, int* su, float* sd2, int* sid,
+                            bool& truncated)
+{
+    int cx, cy;
+    cell_of_pos(g, xi, yi, cx, cy);
+    int count = 0;
+    for (int oy = -1; oy <= 1; ++oy) {
+        int yy = cy + oy;
+        if (yy < 0 || yy >= g.ny) continue;
+        for (int ox = -1; ox <= 1; ++ox) {
+            int xx = cx + ox;
+            if (xx < 0 || xx >= g.nx) continue;
+            int c = yy * g.nx + xx;
+            for (int u = cell_start[c]; u < cell_start[c + 1]; ++u) {
+                if (u == t) continue;
+                float d2 = d2_f32(xs[u] - xi, ys[u] - yi);
+                if (d2 < P.lo2f || d2 > P.hi2f) continue;
+                if (count < VRM_KMAX) {
+                    su[count * kFullBlock] = u;
+                    sd2[count * kFullBlock] = d2;
+                    sid[count * kFullBlock] = ids[u];
+                }
+                ++count;
+            }
+        }
+    }
+    truncated = count > VRM_KMAX;
+    if (truncated) {
+        // the VRM_KMAX-th smallest key, by bisection over the 64-bit keys
+        uint64_t lo = 0, hi = ~0ull;
+        while (lo < hi) {
+            uint64_t mid = lo + ((hi - lo) >> 1);
+            int below = 0;
+            for (int oy = -1; oy <= 1; ++oy) {
+                int yy = cy + oy;
+                if (yy < 0 || yy >= g.ny) continue;
+                for (int ox = -1; ox <= 1; ++ox) {
+                    int xx = cx + ox;
+                    if (xx < 0 || xx >= g.nx) continue;
+                    int c = yy * g.nx + xx;
+                    for (int u = cell_start[c]; u < cell_start[c + 1]; ++u) {
+                        if (u == t) continue;
+                        float d2 = d2_f32(xs[u] - xi, ys[u] - yi);
+                        if (d2 < P.lo2f || d2 > P.hi2f) continue;
+                        below += member_key(d2, ids[u]) <= mid ? 1 : 0;
+                    }
+                }
+            }
+            if (below >= VRM_KMAX)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        int kk = 0;
+        for (int oy = -1; oy <= 1; ++oy) {
+            int yy = cy + oy;
+            if (yy < 0 || yy >= g.ny) continue;
+            for (int ox = -1; ox <= 1; ++ox) {
+                int xx = cx + ox;
+                if (xx < 0 || xx >= g.nx) continue;
+                int c = yy * g.nx + xx;
+                for (int u = cell_start[c]; u < cell_start[c + 1]; ++u) {
+                    if (u == t) continue;
+                    float d2 = d2_f32(xs[u] - xi, ys[u] - yi);
+                    if (d2 < P.lo2f || d2 > P.hi2f) continue;
+                    if (member_key(d2, ids[u]) <= lo && kk < VRM_KMAX) {
+                        su[kk * kFullBlock] = u;
+                        sd2[kk * kFullBlock] = d2;
+                        sid[kk * kFullBlock] = ids[u];
+                        ++kk;
+                    }
+                }
+            }
+        }
+        count = kk;
+    }
+    // insertion sort by (d2, id)
+    for (int a = 1; a < count; ++a) {
+        int u = su[a * kFullBlock];
+        float d = sd2[a * kFullBlock];
+        int id = sid[a * kFullBlock];
+        int b = a - 1;
+        while (b >= 0) {
+            float db = sd2[b * kFullBlock];
+            int ib = sid[b * kFullBlock];
+            if (db < d || (db == d && ib < id)) break;
+            su[(b + 1) * kFullBlock] = su[b * kFullBlock];
+            sd2[(b + 1) * kFullBlock] = db;
+            sid[(b + 1) * kFullBlock] = ib;
+            --b;
+        }
+        su[(b + 1) * kFullBlock] = u;
+        sd2[(b + 1) * kFullBlock] = d;
+        sid[(b + 1) * kFullBlock] = id;
+    }
+    return count;
 }
 
 // Complete-neighbourhood LPs (Sec. 4.3 fallback), one thread per particle.
@@ -343,116 +501,59 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
     for (int it = 0; it < loops; ++it) {
         int item = blockIdx.x * blockDim.x + tid + it * stride;
         bool live = item < nitems;
-        int st = 1, piv = 0, certified = 1, k = 0;
+        int st = 1, piv = 0, certified = 1, k = 0, warm = 0;
         bool truncated = false;
         if (live) {
             int t = q_full[item];
             int i = perm[t];
             const float xi = xs[t], yi = ys[t];
-            int cx, cy;
-            cell_of_pos(g, xi, yi, cx, cy);
-            // members within R_full; if there are more than KMAX keep the KMAX nearest by (d2, id)
-            int count = 0;
-            for (int oy = -1; oy <= 1; ++oy) {
-                int yy = cy + oy;
-                if (yy < 0 || yy >= g.ny) continue;
-                for (int ox = -1; ox <= 1; ++ox) {
-                    int xx = cx + ox;
-                    if (xx < 0 || xx >= g.nx) continue;
-                    int c = yy * g.nx + xx;
-                    for (int u = cell_start[c]; u < cell_start[c + 1]; ++u) {
-                        if (u == t) continue;
-                        float d2 = d2_f32(xs[u] - xi, ys[u] - yi);
-                        if (d2 < P.lo2f || d2 > P.hi2f) continue;
-                        if (count < VRM_KMAX) s_meta[count * kFullBlock + tid] = u;
-                        ++count;
-                    }
-                }
-            }
-            uint64_t cut = ~0ull;
-            if (count > VRM_KMAX) {
-                truncated = true;
-                // the VRM_KMAX-th smallest key, by bisection over the 64-bit keys
-                uint64_t lo = 0, hi = ~0ull;
-                while (lo < hi) {
-                    uint64_t mid = lo + ((hi - lo) >> 1);
-                    int below = 0;
-                    for (int oy = -1; oy <= 1; ++oy) {
-                        int yy = cy + oy;
-                        if (yy < 0 || yy >= g.ny) continue;
-                        for (int ox = -1; ox <= 1; ++ox) {
-                            int xx = cx + ox;
-                            if (xx < 0 || xx >= g.nx) continue;
-                            int c = yy * g.nx + xx;
-                            for (int u = cell_start[c]; u < cell_start[c + 1]; ++u) {
-                                if (u == t) continue;
-                                float d2 = d2_f32(xs[u] - xi, ys[u] - yi);
-                                if (d2 < P.lo2f || d2 > P.hi2f) continue;
-                                below += member_key(d2, ids[u]) <= mid ? 1 : 0;
-                            }
-                        }
-                    }
-                    if (below >= VRM_KMAX)
-                        hi = mid;
-                    else
-                        lo = mid + 1;
-                }
-                cut = lo;
-                int kk = 0;
-                for (int oy = -1; oy <= 1; ++oy) {
-                    int yy = cy + oy;
-                    if (yy < 0 || yy >= g.ny) continue;
-                    for (int ox = -1; ox <= 1; ++ox) {
-                        int xx = cx + ox;
-                        if (xx < 0 || xx >= g.nx) continue;
-                        int c = yy * g.nx + xx;
-                        for (int u = cell_start[c]; u < cell_start[c + 1]; ++u) {
-                            if (u == t) continue;
-                            float d2 = d2_f32(xs[u] - xi, ys[u] - yi);
-                            if (d2 < P.lo2f || d2 > P.hi2f) continue;
-                            if (member_key(d2, ids[u]) <= cut && kk < VRM_KMAX) s_meta[kk++ * kFullBlock + tid] = u;
-                        }
-                    }
-                }
-                count = kk;
-            }
-            k = count;
-            // columns: exact offsets, id ranks, costs
+            // columns nearest first: slots in s_meta, d2 in s_rx, ids in s_c (as bits) during collection
+            k = collect_full(t, xi, yi, g, cell_start, xs, ys, ids, P, s_meta + tid, s_rx + tid,
+                             reinterpret_cast<int*>(s_c) + tid, truncated);
             for (int j = 0; j < k; ++j) {
-                int u = s_meta[j * kFullBlock + tid];
-                s_c[j * kFullBlock + tid] = __int_as_float(ids[u]);
-            }
-            for (int j = 0; j < k; ++j) {
-                int u = s_meta[j * kFullBlock + tid];
                 int idj = __float_as_int(s_c[j * kFullBlock + tid]);
                 int rank = 0;
                 for (int o = 0; o < k; ++o) rank += __float_as_int(s_c[o * kFullBlock + tid]) < idj ? 1 : 0;
-                s_meta[j * kFullBlock + tid] = (u << 6) | rank;
+                s_meta[j * kFullBlock + tid] = (int)(((unsigned)s_meta[j * kFullBlock + tid] << 6) | (unsigned)rank);
             }
+            const bool rec = out.feat && item < out.max_rows;
+            uint16_t* frow = rec ? out.feat + (size_t)item * kMlpIn : nullptr;
+            if (rec) feature_zero(frow);
             for (int j = 0; j < k; ++j) {
                 int meta = s_meta[j * kFullBlock + tid];
                 df X, Y;
-                exact_offset(xi, yi, xs[meta >> 6], ys[meta >> 6], P.scale2e, X, Y);
+                int um = (int)((unsigned)meta >> 6);
+                exact_offset(xi, yi, xs[um], ys[um], P.scale2e, X, Y);
                 df C = add_rank(cost_df(X, Y, P), meta & 63);
                 s_rx[j * kFullBlock + tid] = X.hi;
                 s_ry[j * kFullBlock + tid] = Y.hi;
                 s_c[j * kFullBlock + tid] = C.hi;
+                if (rec && j < kMlpSlots) feature_slot(frow, j, X.hi * P.sc, Y.hi * P.sc);
             }
+            if (rec) feature_q(frow, P.q);
             LdsCols cs{k, 0ull, s_rx, s_ry, s_c, s_meta, tid, xi, yi, xs, ys, &P};
             float fii = 0.0f;
             const float g_i = gamma[i];
             int nz = 0;
+            float* lab = rec ? out.lab + (size_t)item * kMlpOut : nullptr;
+            if (lab)
+                for (int a = 0; a < kMlpOut; ++a) lab[a] = 0.0f;
             auto store = [&](int j, float v) {
-                int u = s_meta[j * kFullBlock + tid] >> 6;
+                int u = (int)((unsigned)s_meta[j * kFullBlock + tid] >> 6);
                 int pj = perm[u];
                 if (apply) atomicAdd(&acc[pj], v * g_i);
                 if (out.full_idx) {
                     out.full_idx[(size_t)i * VRM_KMAX + nz] = pj;
                     out.full_f[(size_t)i * VRM_KMAX + nz] = v;
                 }
+                if (lab && j < kMlpSlots) {
+                    lab[j] = 1.0f;
+                    lab[kMlpSlots + j] = v;
+                }
                 ++nz;
             };
-            st = k > 0 ? solve_lp<M>(cs, P, store, fii, piv, certified) : 1;
+            const float* logit = out.pred ? out.pred + (size_t)item * kMlpOut : nullptr;
+            st = k > 0 ? solve_lp<M>(cs, P, store, fii, piv, certified, logit, warm) : 1;
             if (st == 0) {
                 if (apply) atomicAdd(&acc[i], fii * g_i);
                 if (out.full_k) {
@@ -460,8 +561,10 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
                     out.fii[i] = fii;
                     out.status[i] = VRM_ST_FULL;
                 }
-            } else if (out.status) {
-                out.status[i] = VRM_ST_INFEASIBLE;
+            } else {
+                if (out.status) out.status[i] = VRM_ST_INFEASIBLE;
+                if (lab)
+                    for (int a = 0; a < kMlpOut; ++a) lab[a] = 0.0f;
             }
         }
         bool ok = live && st == 0;
@@ -471,11 +574,43 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
         count_add(&cnt->n_infeasible, live && !ok);
         count_add(&cnt->n_uncertified, ok && !certified);
         count_add(&cnt->n_truncated, live && truncated);
+        count_warm(cnt, live, warm);
         if (apply) {
             uint64_t m = __ballot(ok);
             if (m && lane_id() == __ffsll((unsigned long long)m) - 1)
                 atomicAdd((unsigned long long*)&cnt->redistributions, (unsigned long long)__popcll(m));
         }
+    }
+}
+
+// feature rows of the queued complete-neighbourhood LPs (warm start)
+__global__ __launch_bounds__(kFullBlock) void k_feat_full(const float* __restrict__ xs, const float* __restrict__ ys,
+                                                          const int32_t* __restrict__ ids,
+                                                          const int32_t* __restrict__ cell_start, const GridState* gs,
+                                                          const int32_t* __restrict__ q_full, const Queues* qs,
+                                                          LaunchParams P, uint16_t* feat)
+{
+    __shared__ int s_u[VRM_KMAX * kFullBlock];
+    __shared__ float s_d2[VRM_KMAX * kFullBlock];
+    __shared__ int s_id[VRM_KMAX * kFullBlock];
+    const int tid = threadIdx.x;
+    const int nitems = qs->n_full;
+    const int stride = gridDim.x * blockDim.x;
+    const GridState g = *gs;
+    for (int item = blockIdx.x * blockDim.x + tid; item < nitems; item += stride) {
+        int t = q_full[item];
+        const float xi = xs[t], yi = ys[t];
+        bool tr;
+        int k = collect_full(t, xi, yi, g, cell_start, xs, ys, ids, P, s_u + tid, s_d2 + tid, s_id + tid, tr);
+        uint16_t* row = feat + (size_t)item * kMlpIn;
+        feature_zero(row);
+        for (int j = 0; j < k && j < kMlpSlots; ++j) {
+            int u = s_u[j * kFullBlock + tid];
+            df X, Y;
+            exact_offset(xi, yi, xs[u], ys[u], P.scale2e, X, Y);
+            feature_slot(row, j, X.hi * P.sc, Y.hi * P.sc);
+        }
+        feature_q(row, P.q);
     }
 }
 
@@ -525,7 +660,7 @@ int vrm_small_nbhd_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchP
 }
 
 int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchParams& lp, const vrm_stencils* st,
-                    int apply)
+                    int apply, uint16_t* feat_out, float* label_out, int max_rows)
 {
     if (n <= 0) return VRM_OK;
     StencilOut out{};
@@ -540,6 +675,9 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         hipLaunchKernelGGL(k_status_init, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, c->diffused, out);
         VRM_HIP(hipGetLastError());
     }
+    out.feat = feat_out;
+    out.lab = label_out;
+    out.max_rows = max_rows;
     hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(1), 0, c->stream, c->queues);
     int nb = (n + 255) / 256;
     {
@@ -549,22 +687,42 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
                            (int32_t*)nullptr, (int32_t*)nullptr, 0);
     }
     VRM_HIP(hipGetLastError());
+    const bool warm = c->warm && c->mlp && c->mlp->loaded && !feat_out;
+    if (warm) {
+        // network inputs of the queued LPs, then the forward pass (row count read on the device)
+        ScopedTimer tm(c, VRM_T_MLP);
+        if (lp.m == 5)
+            hipLaunchKernelGGL(k_feat_small, dim3(nb), dim3(256), 0, c->stream, c->xs, c->ys, c->small_slot, c->q_small,
+                               c->queues, lp, c->feat);
+        else
+            hipLaunchKernelGGL(k_feat_full, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->xs, c->ys, c->ids,
+                               c->cell_start, c->grid, c->q_full, c->queues, lp, c->feat);
+        VRM_HIP(hipGetLastError());
+        int r = vrm_mlp_infer_run(c, c->feat, n, c->pred, lp.m == 5 ? &c->queues->n_small : &c->queues->n_full);
+        if (r) return r;
+        out.pred = c->pred;
+    }
     if (lp.m == 5) {
         {
             ScopedTimer tm(c, VRM_T_LP_SMALL);
-            hipLaunchKernelGGL(k_lp_small, dim3(lp_grid_small(n)), dim3(256), 0, c->stream, c->perm, c->xs, c->ys, c->ids,
-                               c->small_slot, c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc, lp, out, apply,
-                               c->counters);
+            hipLaunchKernelGGL(k_lp_small, dim3(lp_grid_small(n)), dim3(kSmallBlock), 0, c->stream, c->perm, c->xs, c->ys,
+                               c->ids, c->small_slot, c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc, lp, out,
+                               apply, c->counters);
         }
         VRM_HIP(hipGetLastError());
+        // fallbacks of the small LPs: no network input for them
+        StencilOut o2 = out;
+        o2.pred = nullptr;
+        o2.feat = nullptr;
+        o2.lab = nullptr;
         ScopedTimer tm(c, VRM_T_LP_FULL);
-        hipLaunchKernelGGL(k_lp_full<5>, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys, c->ids,
-                           c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, out, apply,
+        hipLaunchKernelGGL(k_lp_full<5>, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
+                           c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, o2, apply,
                            c->counters);
     } else {
         ScopedTimer tm(c, VRM_T_LP_FULL);
-        hipLaunchKernelGGL(k_lp_full<9>, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys, c->ids,
-                           c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, out, apply,
+        hipLaunchKernelGGL(k_lp_full<9>, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
+                           c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, out, apply,
                            c->counters);
     }
     VRM_HIP(hipGetLastError());

@@ -30,6 +30,7 @@ constexpr float kCertD = 1e-9f;                   // certified reduced-cost tole
 constexpr float kCertX = 1e-9f;                   // certified primal tolerance (absolute, fhat units)
 constexpr int kMaxCert = 8;
 constexpr int kMaxRefine = 6;
+constexpr float kFastMargin = 1e-3f;              // FP32 reduced-cost margin of the fast certificate
 
 template <int M>
 __device__ __forceinline__ void mono(float x, float y, float (&v)[M])
@@ -209,11 +210,61 @@ struct ThreadSimplex {
         blk = 0;
     }
 
-    // FP32 two-phase simplex.  0 optimal, 1 infeasible, 2 iteration limit.
-    __device__ int run(const CS& cs, int& piv)
+    // Crash basis from a prediction: the columns of the M largest logits
+    // (slots j < 32 are columns j) enter in that order, each replacing the
+    // artificial row where its pivot element is largest.  Returns true if the
+    // resulting basis is complete and primal feasible (phase II can start).
+    __device__ bool crash(const CS& cs, const float* logit, int& piv)
+    {
+        const int kk = cs.k < 32 ? cs.k : 32;
+        uint64_t chosen = dead;
+        for (int t = 0; t < M; ++t) {
+            int best = -1;
+            float bl = 0.0f;
+            for (int j = 0; j < kk; ++j) {
+                if ((chosen >> j) & 1ull) continue;
+                float z = logit[j];
+                if (best < 0 || z > bl) {
+                    best = j;
+                    bl = z;
+                }
+            }
+            if (best < 0) break;
+            chosen |= 1ull << best;
+            float rx, ry, c;
+            cs.get(best, rx, ry, c);
+            float alpha[M];
+            column_alpha(rx, ry, alpha);
+            float amax = 0.0f, am = 0.0f;
+            int l = -1;
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                amax = fmaxf(amax, fabsf(alpha[r]));
+                if (bs[r] >= ART && fabsf(alpha[r]) > am) {
+                    am = fabsf(alpha[r]);
+                    l = r;
+                }
+            }
+            if (l < 0 || am <= 1e-4f * amax) continue;   // dependent on the columns already in
+            pivot(l, best, alpha, c);
+            ++piv;
+        }
+        const float tol = 1e-4f * bt_;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            if (bs[r] >= ART) return false;
+            if (xb[r] < -tol) return false;
+        }
+        return true;
+    }
+
+    // FP32 simplex from phase `first` (1: two phases from the artificial basis,
+    // 2: phase II from a feasible basis).  0 optimal, 1 infeasible, 2 iteration limit.
+    __device__ int run(const CS& cs, int& piv, int first = 1, const float* prio = nullptr)
     {
         const int k = cs.k;
-        for (int phase = 1; phase <= 2; ++phase) {
+        const int kp = k < 32 ? k : 32;
+        for (int phase = first; phase <= 2; ++phase) {
             const bool p2 = phase == 2;
             int it = 0;
             const int bland_after = 3 * (k + M);
@@ -223,6 +274,7 @@ struct ThreadSimplex {
                 prices(p2, y);
                 int e = -1;
                 float best = 0.0f;
+                bool best_p = false;
                 const bool bland = it >= bland_after;
                 for (int j = 0; j < k; ++j) {
                     if (((isb | blk | dead) >> j) & 1ull) continue;
@@ -237,10 +289,18 @@ struct ThreadSimplex {
                         d -= t;
                         sc += fabsf(t);
                     }
-                    if (d < -kTolD * sc && (e < 0 || (!bland && d < best))) {
-                        e = j;
-                        best = d;
-                        if (bland) break;
+                    // priority: Bland (lowest index) after many iterations; else the
+                    // largest predicted logit among improving columns, else Dantzig
+                    if (d < -kTolD * sc) {
+                        bool pj = prio && j < kp;
+                        float key = pj ? -prio[j] : d;
+                        bool better = e < 0 || (!bland && ((pj && !best_p) || (pj == best_p && key < best)));
+                        if (better) {
+                            e = j;
+                            best = key;
+                            best_p = pj;
+                            if (bland) break;
+                        }
                     }
                 }
                 if (e < 0) break;
@@ -341,6 +401,7 @@ struct ThreadSimplex {
         for (int round = 0; round < kMaxCert; ++round) {
 #pragma unroll
             for (int r = 0; r < M; ++r) x[r] = {(Bi[r][2] + Bi[r][4]) * P.bt_hi, 0.0f};
+            float first_corr = 1.0f;   // |first correction| / |x|: how far B^-1 is from the exact inverse
             for (int it = 0; it < kMaxRefine; ++it) {
                 float res[M];
                 primal_residual(cs, x, P, res);
@@ -354,7 +415,39 @@ struct ThreadSimplex {
                     dmax = fmaxf(dmax, fabsf(d));
                     xmax = fmaxf(xmax, fabsf(x[r].hi));
                 }
+                if (it == 0) first_corr = dmax / fmaxf(xmax, 1e-30f);
                 if (dmax <= 9.313225746154785e-10f * xmax) break;
+            }
+            // Fast certificate: when B^-1 is accurate (the first correction is
+            // tiny) and every FP32 reduced cost clears zero by a margin far above
+            // its rounding error, the basis is optimal without the double-float
+            // dual check.
+            if (first_corr <= 1e-5f) {
+                bool primal_ok = true;
+#pragma unroll
+                for (int r = 0; r < M; ++r)
+                    if (bs[r] < ART && x[r].hi + x[r].lo < -kCertX) primal_ok = false;
+                if (primal_ok) {
+                    float yf[M];
+                    prices(true, yf);
+                    bool dual_ok = true;
+                    for (int j = 0; j < k && dual_ok; ++j) {
+                        if (((isb | dead) >> j) & 1ull) continue;
+                        float rx, ry, c;
+                        cs.get(j, rx, ry, c);
+                        float v[M];
+                        mono<M>(rx, ry, v);
+                        float d = c, sc = fabsf(c);
+#pragma unroll
+                        for (int a = 0; a < M; ++a) {
+                            float t = yf[a] * v[a];
+                            d -= t;
+                            sc += fabsf(t);
+                        }
+                        if (d < kFastMargin * sc) dual_ok = false;
+                    }
+                    if (dual_ok) return 0;
+                }
             }
             float yf[M];
             prices(true, yf);
@@ -466,14 +559,36 @@ struct ThreadSimplex {
 // Solve, certify and extract the fractions: f (k entries, written through
 // store(j, value) for the non-zero ones) and fii = -sum f.
 // Returns 0 ok, 1 infeasible; *certified = 0 if optimality could not be shown.
+// With a prediction (logits of the first 32 columns), the simplex starts from
+// the crash basis when that is feasible; warm = 0 no prediction, 1 the
+// predicted basis was optimal, 2 phase II from it, 3 rejected (cold start).
 template <int M, class CS, class Store>
-__device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified)
+__device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified,
+                        const float* logit, int& warm)
 {
     ThreadSimplex<M, CS> lp;
     lp.bt_ = P.bt_hi;
     lp.init(P);
     lp.dead = cs.dead;
-    int st = lp.run(cs, piv);
+    int st;
+    warm = 0;
+    if (logit) {
+        int p0 = piv;
+        if (lp.crash(cs, logit, piv)) {
+            int p1 = piv;
+            st = lp.run(cs, piv, 2);
+            warm = piv == p1 ? 1 : 2;
+        } else {
+            // infeasible or incomplete prediction: cold start, pricing by the prediction
+            lp.init(P);
+            lp.dead = cs.dead;
+            st = lp.run(cs, piv, 1, logit);
+            warm = 3;
+        }
+        (void)p0;
+    } else {
+        st = lp.run(cs, piv, 1);
+    }
     certified = 1;
     if (st == 1) return 1;
     df x[M];

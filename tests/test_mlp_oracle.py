@@ -1,0 +1,58 @@
+"""Pins of the FP64 reference network: its gradient against central finite
+differences of its own loss, and GELU against its definition."""
+import math
+
+import numpy as np
+
+from oracle import mlp
+
+
+def _batch(rng, rows=7):
+    X = np.zeros((rows, mlp.IN))
+    k = rng.integers(3, 20, rows)
+    for r in range(rows):
+        X[r, :2 * k[r]] = rng.normal(0, 1, 2 * k[r])
+        X[r, 2 * mlp.SLOTS:2 * mlp.SLOTS + k[r]] = 1.0
+    X[:, 3 * mlp.SLOTS] = rng.integers(0, 2, rows)
+    T = np.zeros((rows, mlp.OUT))
+    T[:, :mlp.SLOTS] = rng.integers(0, 2, (rows, mlp.SLOTS))
+    T[:, mlp.SLOTS:] = rng.uniform(0, 1, (rows, mlp.SLOTS))
+    return X, T
+
+
+def test_gradient_matches_finite_differences():
+    rng = np.random.default_rng(1)
+    theta = mlp.init_params(3) * 0.5
+    X, T = _batch(rng)
+    _, g = mlp.loss_and_grad(theta, X, T, wf=0.7)
+    idx = np.concatenate([rng.integers(0, mlp.NPARAMS, 40),
+                          [mlp.NPARAMS - 1, 128 * 128, 128 * 128 + 128 + 5]])
+    eps = 1e-6
+    for i in idx:
+        e = np.zeros_like(theta)
+        e[i] = eps
+        lp, _ = mlp.loss_and_grad(theta + e, X, T, wf=0.7)
+        lm, _ = mlp.loss_and_grad(theta - e, X, T, wf=0.7)
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_gelu_definition():
+    z = np.linspace(-5, 5, 101)
+    ref = np.array([0.5 * v * (1 + math.erf(v / math.sqrt(2))) for v in z])
+    np.testing.assert_allclose(mlp.gelu(z), ref, rtol=1e-14, atol=1e-15)
+    h = 1e-6
+    np.testing.assert_allclose(mlp.gelu_grad(z), (mlp.gelu(z + h) - mlp.gelu(z - h)) / (2 * h), atol=1e-8)
+
+
+def test_masked_slots_do_not_contribute():
+    rng = np.random.default_rng(2)
+    theta = mlp.init_params(4)
+    X, T = _batch(rng)
+    X[:, 2 * mlp.SLOTS + 25:3 * mlp.SLOTS] = 0.0
+    l1, _ = mlp.loss_and_grad(theta, X, T)
+    T2 = T.copy()
+    T2[:, 25:mlp.SLOTS] = 1 - T2[:, 25:mlp.SLOTS]
+    T2[:, mlp.SLOTS + 25:] += 3.0
+    l2, _ = mlp.loss_and_grad(theta, X, T2)
+    assert l1 == l2
