@@ -55,18 +55,10 @@ def run_gpu(wl, steps, warmup):
     cloud = vrm.Cloud(wl.x, wl.y, wl.gamma, capacity=cap)
     ctx = vrm.Context(cap)
     vt = vrm.vortex_table(wl.vortices) if wl.vortices is not None else None
-    u = torch.zeros(cap, device="cuda")
-    v = torch.zeros(cap, device="cuda")
-
-    def vel(cl, t):
-        if vt is None:
-            return None
-        ctx.vrm_vortex_velocity(cl, vt, wl.nu, t, u, v)
-        return u, v
 
     t = wl.t0
     for _ in range(warmup):
-        ctx.step(cloud, P, velocity=vel, t=t)
+        ctx.vrm_step(cloud, P, vt, t)
         t += wl.dt
     torch.cuda.synchronize()
     c0 = ctx.vrm_read_counters()
@@ -75,7 +67,7 @@ def run_gpu(wl, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.step(cloud, P, velocity=vel, t=t)
+        ctx.vrm_step(cloud, P, vt, t)
         t += wl.dt
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0

@@ -171,6 +171,14 @@ int vrm_solve_fractions(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params* 
 int vrm_rk_stage(vrm_ctx* ctx, vrm_cloud* cloud, const float* u_dev, const float* v_dev,
                  const vrm_params* p, int stage);
 
+/* One whole SSP-RK3 step: vrm_insert_particles, then stages 0, 1, 2 of
+ * vrm_rk_stage.  With n_vort > 0 each stage's velocity is the prescribed
+ * vortex field of vrm_vortex_velocity at the stage time (t, t + dt, t + dt/2);
+ * otherwise zero.  The context caches the cell list and the cell order of the
+ * cloud between calls: a caller that changes positions or the count itself
+ * must not rely on that cache (a different cloud or count resets it). */
+int vrm_step(vrm_ctx* ctx, vrm_cloud* cloud, const vrm_params* p, const float* vort_dev, int32_t n_vort, double t);
+
 /* Sec. 2 eqs. cond_two/cond_alpha, Sec. 3.4: FP64 checks of a stencil set.
  * Writes, to report_dev[4] (device doubles): the maximum over particles of
  * max_alpha |sum_j fhat_ij r_ij^alpha / h^|alpha| - b_alpha| / 2, the circulation

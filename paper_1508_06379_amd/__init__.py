@@ -65,7 +65,7 @@ class vrm_counters(ctypes.Structure):
 
 
 EXPORTS = ["vrm_create", "vrm_destroy", "vrm_select_diffused", "vrm_set_diffused", "vrm_build_neighbourhoods",
-           "vrm_insert_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_verify", "vrm_read_counters",
+           "vrm_insert_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_step", "vrm_verify", "vrm_read_counters",
            "vrm_vortex_velocity", "vrm_timing", "vrm_read_timing", "vrm_mlp_load", "vrm_mlp_read",
            "vrm_set_warm_start", "vrm_collect_training", "vrm_mlp_train_step", "vrm_mlp_infer", "vrm_gemm_bf16",
            "vrm_last_error", "vrm_status_string"]
@@ -92,6 +92,8 @@ def lib():
         L.vrm_solve_fractions.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params),
                                           ctypes.POINTER(vrm_stencils)]
         L.vrm_rk_stage.argtypes = [vp, ctypes.POINTER(vrm_cloud), vp, vp, ctypes.POINTER(vrm_params), ctypes.c_int]
+        L.vrm_step.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params), vp, ctypes.c_int32,
+                               ctypes.c_double]
         L.vrm_verify.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params),
                                  ctypes.POINTER(vrm_stencils), vp]
         L.vrm_read_counters.argtypes = [vp, ctypes.POINTER(vrm_counters)]
@@ -241,6 +243,10 @@ class Context:
 
     def vrm_rk_stage(self, cloud: Cloud, p: vrm_params, stage: int, u=None, v=None):
         _check(lib().vrm_rk_stage(self.handle, ctypes.byref(cloud.c), _ptr(u), _ptr(v), ctypes.byref(p), stage))
+
+    def vrm_step(self, cloud: Cloud, p: vrm_params, vort=None, t=0.0):
+        _check(lib().vrm_step(self.handle, ctypes.byref(cloud.c), ctypes.byref(p), _ptr(vort),
+                              int(vort.shape[0]) if vort is not None else 0, float(t)))
 
     def vrm_verify(self, cloud: Cloud, p: vrm_params, st: Stencils, report):
         sc = st.c() if st is not None else None

@@ -77,8 +77,14 @@ int read_n(vrm_ctx* c, const vrm_cloud* cl)
     VRM_HIP(hipMemcpyAsync(&n, cl->n_dev, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     VRM_HIP(hipStreamSynchronize(c->stream));
     if (n < 0 || n > cl->capacity) return vrm_fail(VRM_E_ARG, "particle count %d outside [0, %d]", n, cl->capacity);
+    if (c->n_ptr != cl->n_dev || c->cloud_x != cl->x_dev || c->n != n) {
+        // another cloud, or the count changed behind the context: cached cells are stale
+        c->cells_valid = 0;
+        c->sorted = 0;
+    }
     c->n = n;
     c->n_ptr = cl->n_dev;
+    c->cloud_x = cl->x_dev;
     return VRM_OK;
 }
 
@@ -225,6 +231,7 @@ int vrm_destroy(vrm_ctx* c)
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->feat) (void)hipFree(c->feat);
+    if (c->u_tmp) (void)hipFree(c->u_tmp);
     if (c->pred) (void)hipFree(c->pred);
     vrm_mlp_free(c);
     if (c->ev_start) {
@@ -285,6 +292,7 @@ int vrm_build_neighbourhoods(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* 
     r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
     if (r) return r;
     c->cells_valid = 1;
+    c->sorted = 0;
     return vrm_small_nbhd_run(c, cl, c->n, L, small_idx_dev, kfull_dev);
 }
 
@@ -300,24 +308,32 @@ int vrm_insert_particles(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p)
         vrm::ScopedTimer tm(c, VRM_T_SELECT);
         r = vrm_select_run(c, cl->gamma_dev, c->n, factor);
     }
-    if (!r) r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
     if (r) return r;
+    // the cell list of the last reorder is still valid if nothing moved since
+    if (!(c->sorted && c->cells_valid)) {
+        r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
+        if (r) return r;
+        c->cells_valid = 1;
+        c->sorted = 0;
+    }
     c->n_diffused_valid = 1;
     int n2;
     {
         vrm::ScopedTimer tm(c, VRM_T_INSERT);
         n2 = vrm_insert_run(c, cl, c->n, L);
     }
-    if (n2 < 0) {
-        c->cells_valid = 1;   // the cloud is unchanged
-        return n2;
+    if (n2 < 0) return n2;   // the cloud is unchanged
+    c->base_valid = 0;
+    if (n2 == c->n && c->sorted) return VRM_OK;   // nothing appended, already in cell order
+    if (n2 != c->n) {
+        r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, n2, L);
+        if (r) return r;
     }
     c->n = n2;
-    r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, n2, L);
-    if (!r) r = vrm_reorder_cloud(c, cl, n2);
+    r = vrm_reorder_cloud(c, cl, n2);
     if (r) return r;
     c->cells_valid = 1;
-    c->base_valid = 0;
+    c->sorted = 1;
     return VRM_OK;
 }
 
@@ -351,11 +367,8 @@ int vrm_rk_stage(vrm_ctx* c, vrm_cloud* cl, const float* u_dev, const float* v_d
     int n = c->n;
     vrm::LaunchParams L = launch_params(p);
     if (stage == 0) {
-        if (n > 0) {
-            VRM_HIP(hipMemcpyAsync(c->x0, cl->x_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
-            VRM_HIP(hipMemcpyAsync(c->y0, cl->y_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
-            VRM_HIP(hipMemcpyAsync(c->g0, cl->gamma_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
-        }
+        r = vrm_save_base_run(c, cl, n);
+        if (r) return r;
         c->base_valid = 1;
     }
     if (!c->cells_valid) {
@@ -369,8 +382,37 @@ int vrm_rk_stage(vrm_ctx* c, vrm_cloud* cl, const float* u_dev, const float* v_d
         r = vrm_combine_run(c, cl, n, u_dev, v_dev, p->dt, L.lam, stage);
     }
     if (r) return r;
-    if (u_dev) c->cells_valid = 0;
+    if (u_dev) {
+        c->cells_valid = 0;
+        c->sorted = 0;
+    }
     if (stage == 2) c->base_valid = 0;
+    return VRM_OK;
+}
+
+int vrm_step(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p, const float* vort_dev, int32_t n_vort, double t)
+{
+    if (n_vort < 0 || (n_vort > 0 && !vort_dev)) return vrm_fail(VRM_E_ARG, "vortex table");
+    int r = vrm_insert_particles(c, cl, p);
+    if (r) return r;
+    if (n_vort > 0 && !c->u_tmp) {
+        void* q = nullptr;
+        VRM_HIP(hipMalloc(&q, sizeof(float) * (size_t)c->capacity * 2 + 64));
+        c->u_tmp = (float*)q;
+        c->v_tmp = c->u_tmp + c->capacity;
+    }
+    static const double tc[3] = {0.0, 1.0, 0.5};
+    for (int s = 0; s < 3; ++s) {
+        const float *u = nullptr, *v = nullptr;
+        if (n_vort > 0) {
+            r = vrm_velocity_run(c, cl, c->n, vort_dev, n_vort, p->nu, t + tc[s] * p->dt, c->u_tmp, c->v_tmp);
+            if (r) return r;
+            u = c->u_tmp;
+            v = c->v_tmp;
+        }
+        r = vrm_rk_stage(c, cl, u, v, p, s);
+        if (r) return r;
+    }
     return VRM_OK;
 }
 

@@ -47,7 +47,23 @@ __global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ x, const
         mxx = max(mxx, (uint32_t)__shfl_xor((int)mxx, o, VRM_WAVE));
         mxy = max(mxy, (uint32_t)__shfl_xor((int)mxy, o, VRM_WAVE));
     }
+    __shared__ uint32_t red[4][8];
+    int w = threadIdx.x >> 6;
     if (lane_id() == 0) {
+        red[0][w] = mnx;
+        red[1][w] = mny;
+        red[2][w] = mxx;
+        red[3][w] = mxy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nw = blockDim.x >> 6;
+        for (int k = 1; k < nw; ++k) {
+            mnx = min(mnx, red[0][k]);
+            mny = min(mny, red[1][k]);
+            mxx = max(mxx, red[2][k]);
+            mxy = max(mxy, red[3][k]);
+        }
         atomicMin(&g->bbox[0], mnx);
         atomicMin(&g->bbox[1], mny);
         atomicMax(&g->bbox[2], mxx);
@@ -246,40 +262,61 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ g, i
     }
 }
 
-__global__ void k_sel_pick(SelectState* s, int shift, double factor)
+// Pick the bin where the cumulative sum first exceeds the bound (256 threads,
+// one bin each; an FP64 block scan in bin order).
+__global__ __launch_bounds__(256) void k_sel_pick(SelectState* s, int shift, double factor)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ double wtot[4];
+    __shared__ int first;
+    const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
+    double v = s->bin_sum[t];
+    // inclusive scan of the bin sums (the same association in every run)
+    double incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        double u = __shfl_up(incl, o, VRM_WAVE);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wtot[w] = incl;
+    if (t == 0) first = 256;
+    __syncthreads();
+    double off = 0.0, total = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        if (k < w) off += wtot[k];
+        total += wtot[k];
+    }
+    incl += off;
     if (shift == 24) {
-        double tot = 0.0;
-        for (int b = 0; b < 256; ++b) tot += s->bin_sum[b];
-        s->norm1 = tot;
-        s->bound = factor * tot;
-        s->prefix = 0.0;
-    }
-    if (s->done) return;
-    double cum = s->prefix;
-    int b = 0;
-    for (; b < 256; ++b) {
-        if (cum + s->bin_sum[b] > s->bound) break;
-        cum += s->bin_sum[b];
-    }
-    if (b == 256) {
-        // every particle in the current key range is left out
-        uint64_t top = (uint64_t)s->key_prefix + ((uint64_t)256 << shift);
-        s->threshold = top > 0xffffffffull ? 0xffffffffu : (uint32_t)top;
-        s->done = top > 0xffffffffull ? 2u : 1u;
-    } else {
-        s->key_prefix |= (uint32_t)b << shift;
-        s->prefix = cum;
-        if (shift == 0) {
-            s->threshold = s->key_prefix;
-            s->done = 1u;
+        if (t == 0) {
+            s->norm1 = total;
+            s->bound = factor * total;
+            s->prefix = 0.0;
         }
     }
-    for (int k = 0; k < 256; ++k) {
-        s->bin_sum[k] = 0.0;
-        s->bin_cnt[k] = 0u;
+    __syncthreads();
+    const bool done = s->done != 0u;
+    const double bound = s->bound, prefix = s->prefix;
+    if (!done && prefix + incl > bound) atomicMin(&first, t);
+    __syncthreads();
+    if (t == 0 && !done) {
+        int b = first;
+        if (b == 256) {
+            // every particle in the current key range is left out
+            uint64_t top = (uint64_t)s->key_prefix + ((uint64_t)256 << shift);
+            s->threshold = top > 0xffffffffull ? 0xffffffffu : (uint32_t)top;
+            s->done = top > 0xffffffffull ? 2u : 1u;
+        } else {
+            s->key_prefix |= (uint32_t)b << shift;
+            if (shift == 8) {
+                s->threshold = s->key_prefix;
+                s->done = 1u;
+            }
+        }
     }
+    // cumulative sum below the chosen bin (from its own scan) for the next pass
+    if (!done && t == first && first < 256) s->prefix = prefix + incl - v;
+    __syncthreads();
+    s->bin_sum[t] = 0.0;
+    s->bin_cnt[t] = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_sel_mask(const float* __restrict__ g, int n, const SelectState* s,
@@ -337,11 +374,11 @@ __global__ __launch_bounds__(256) void k_candidates(int n, const int32_t* __rest
         for (int oy = -1; oy <= 1; ++oy) {
             int yy = cyi + oy;
             if (yy < 0 || yy >= g.ny) continue;
-            for (int ox = -1; ox <= 1; ++ox) {
-                int xx = cxi + ox;
-                if (xx < 0 || xx >= g.nx) continue;
-                int c = yy * g.nx + xx;
-                for (int u = cell_start[c]; u < cell_start[c + 1]; ++u) {
+            {
+                // the three cells of this row are contiguous in slot order
+                int c0 = yy * g.nx + max(cxi - 1, 0), c1 = yy * g.nx + min(cxi + 1, g.nx - 1);
+                int u0 = cell_start[c0], u1 = cell_start[c1 + 1];
+                for (int u = u0; u < u1; ++u) {
                     if (u == t) continue;
                     float dx = xs[u] - xi;
                     float dy = ys[u] - yi;
@@ -462,10 +499,20 @@ __global__ __launch_bounds__(256) void k_gather_cloud(int n, const int32_t* __re
     tdif[t] = dif[i];
 }
 
-__global__ __launch_bounds__(256) void k_iota(int n, int32_t* perm)
+// the cloud in slot order; the permutation becomes the identity
+__global__ __launch_bounds__(256) void k_copy_back(int n, const float* __restrict__ xs, const float* __restrict__ ys,
+                                                   const int32_t* __restrict__ ids, const float* __restrict__ tg,
+                                                   const uint8_t* __restrict__ tdif, float* x, float* y, int32_t* id,
+                                                   float* g, uint8_t* dif, int32_t* perm)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) perm[t] = t;
+    if (t >= n) return;
+    x[t] = xs[t];
+    y[t] = ys[t];
+    id[t] = ids[t];
+    g[t] = tg[t];
+    dif[t] = tdif[t];
+    perm[t] = t;
 }
 
 __global__ void k_reset_insert(Queues* q)
@@ -494,7 +541,7 @@ int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* i
     ScopedTimer tm(c, VRM_T_CELLS);
     hipStream_t s = c->stream;
     hipLaunchKernelGGL(k_grid_reset, dim3(1), dim3(1), 0, s, c->grid);
-    int nbb = min(1024, blocks_for(n));
+    int nbb = min(256, blocks_for(n));
     hipLaunchKernelGGL(k_bbox, dim3(nbb), dim3(256), 0, s, x, y, n, c->grid);
     float Rmax = (float)fmax((double)lp.hi2, (double)lp.hi2f);
     float cs = sqrtf(Rmax) * (1.0f + 1.0f / 1024.0f);
@@ -520,9 +567,9 @@ int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double factor)
     hipStream_t s = c->stream;
     hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c->sel);
     int nb = min(2048, blocks_for(n));
-    for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int shift = 24; shift >= 8; shift -= 8) {   // the ranking key has no bits below 8
         if (n > 0) hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, s, gamma, n, c->sel, shift);
-        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(64), 0, s, c->sel, shift, factor);
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, c->sel, shift, factor);
     }
     hipLaunchKernelGGL(k_zero_diffused_count, dim3(1), dim3(1), 0, s, c->counters);
     if (n > 0)
@@ -616,12 +663,8 @@ int vrm_reorder_cloud(vrm_ctx* c, vrm_cloud* cl, int32_t n)
     hipLaunchKernelGGL(k_gather_cloud, dim3(blocks_for(n)), dim3(256), 0, s, n, c->perm, cl->gamma_dev, c->diffused,
                        c->tmp_f, c->tmp_u8);
     VRM_HIP(hipGetLastError());
-    VRM_HIP(hipMemcpyAsync(cl->x_dev, c->xs, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
-    VRM_HIP(hipMemcpyAsync(cl->y_dev, c->ys, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
-    VRM_HIP(hipMemcpyAsync(cl->id_dev, c->ids, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
-    VRM_HIP(hipMemcpyAsync(cl->gamma_dev, c->tmp_f, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
-    VRM_HIP(hipMemcpyAsync(c->diffused, c->tmp_u8, sizeof(uint8_t) * n, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_iota, dim3(blocks_for(n)), dim3(256), 0, s, n, c->perm);
+    hipLaunchKernelGGL(k_copy_back, dim3(blocks_for(n)), dim3(256), 0, s, n, c->xs, c->ys, c->ids, c->tmp_f, c->tmp_u8,
+                       cl->x_dev, cl->y_dev, cl->id_dev, cl->gamma_dev, c->diffused, c->perm);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }

@@ -61,6 +61,10 @@ struct vrm_ctx {
     int32_t n_diffused_valid;   // the diffused set matches the cloud
     int32_t cells_valid;        // cell list matches the current positions
     int32_t base_valid;         // y^n recorded (stage 0 done)
+    int32_t sorted;             // cloud in cell order of the current cell list (perm is the identity)
+    const float* cloud_x;       // cloud seen last (cached state belongs to it)
+    float* u_tmp;               // [cap] stage velocity (vrm_step with prescribed vortices)
+    float* v_tmp;
     // device buffers
     vrm::GridState* grid;
     vrm::Queues* queues;
@@ -154,6 +158,7 @@ int vrm_small_nbhd_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::La
 // launchers (vrm_stage.hip)
 int vrm_combine_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const float* u, const float* v, double dt,
                     float lam, int stage);
+int vrm_save_base_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n);
 int vrm_verify_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp,
                    const vrm_stencils* st, double* report);
 int vrm_velocity_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const float* vort, int32_t nv, double nu,

@@ -76,11 +76,10 @@ __global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __rest
         for (int oy = -1; oy <= 1; ++oy) {
             int yy = cy + oy;
             if (yy < 0 || yy >= g.ny) continue;
-            for (int ox = -1; ox <= 1; ++ox) {
-                int xx = cx + ox;
-                if (xx < 0 || xx >= g.nx) continue;
-                int c = yy * g.nx + xx;
-                int u0 = cell_start[c], u1 = cell_start[c + 1];
+            {
+                // the three cells of this row are contiguous in slot order
+                int c0 = yy * g.nx + max(cx - 1, 0), c1 = yy * g.nx + min(cx + 1, g.nx - 1);
+                int u0 = cell_start[c0], u1 = cell_start[c1 + 1];
                 for (int u = u0; u < u1; ++u) {
                     if (u == t) continue;
                     float dx = xs[u] - xi;
@@ -223,6 +222,11 @@ struct LdsColsT {
         int u = (int)((unsigned)meta >> 6);
         exact_offset(xi, yi, xs[u], ys[u], P->scale2e, X, Y);
         C = add_rank(cost_df(X, Y, *P), meta & 63);
+    }
+    __device__ __forceinline__ void exact_xy(int j, df& X, df& Y) const
+    {
+        int u = (int)((unsigned)smeta[j * BLK + tid] >> 6);
+        exact_offset(xi, yi, xs[u], ys[u], P->scale2e, X, Y);
     }
 };
 using LdsCols = LdsColsT<kFullBlock>;
@@ -390,11 +394,11 @@ __device__ int collect_full(int t, float xi, float yi, const GridState& g, const
     for (int oy = -1; oy <= 1; ++oy) {
         int yy = cy + oy;
         if (yy < 0 || yy >= g.ny) continue;
-        for (int ox = -1; ox <= 1; ++ox) {
-            int xx = cx + ox;
-            if (xx < 0 || xx >= g.nx) continue;
-            int c = yy * g.nx + xx;
-            for (int u = cell_start[c]; u < cell_start[c + 1]; ++u) {
+        {
+            // the three cells of this row are contiguous in slot order
+            int c0 = yy * g.nx + max(cx - 1, 0), c1 = yy * g.nx + min(cx + 1, g.nx - 1);
+            int u0 = cell_start[c0], u1 = cell_start[c1 + 1];
+            for (int u = u0; u < u1; ++u) {
                 if (u == t) continue;
                 float d2 = d2_f32(xs[u] - xi, ys[u] - yi);
                 if (d2 < P.lo2f || d2 > P.hi2f) continue;
@@ -417,11 +421,11 @@ __device__ int collect_full(int t, float xi, float yi, const GridState& g, const
             for (int oy = -1; oy <= 1; ++oy) {
                 int yy = cy + oy;
                 if (yy < 0 || yy >= g.ny) continue;
-                for (int ox = -1; ox <= 1; ++ox) {
-                    int xx = cx + ox;
-                    if (xx < 0 || xx >= g.nx) continue;
-                    int c = yy * g.nx + xx;
-                    for (int u = cell_start[c]; u < cell_start[c + 1]; ++u) {
+                {
+                    // the three cells of this row are contiguous in slot order
+                    int c0 = yy * g.nx + max(cx - 1, 0), c1 = yy * g.nx + min(cx + 1, g.nx - 1);
+                    int u0 = cell_start[c0], u1 = cell_start[c1 + 1];
+                    for (int u = u0; u < u1; ++u) {
                         if (u == t) continue;
                         float d2 = d2_f32(xs[u] - xi, ys[u] - yi);
                         if (d2 < P.lo2f || d2 > P.hi2f) continue;
@@ -438,11 +442,11 @@ __device__ int collect_full(int t, float xi, float yi, const GridState& g, const
         for (int oy = -1; oy <= 1; ++oy) {
             int yy = cy + oy;
             if (yy < 0 || yy >= g.ny) continue;
-            for (int ox = -1; ox <= 1; ++ox) {
-                int xx = cx + ox;
-                if (xx < 0 || xx >= g.nx) continue;
-                int c = yy * g.nx + xx;
-                for (int u = cell_start[c]; u < cell_start[c + 1]; ++u) {
+            {
+                // the three cells of this row are contiguous in slot order
+                int c0 = yy * g.nx + max(cx - 1, 0), c1 = yy * g.nx + min(cx + 1, g.nx - 1);
+                int u0 = cell_start[c0], u1 = cell_start[c1 + 1];
+                for (int u = u0; u < u1; ++u) {
                     if (u == t) continue;
                     float d2 = d2_f32(xs[u] - xi, ys[u] - yi);
                     if (d2 < P.lo2f || d2 > P.hi2f) continue;
@@ -716,7 +720,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         o2.feat = nullptr;
         o2.lab = nullptr;
         ScopedTimer tm(c, VRM_T_LP_FULL);
-        hipLaunchKernelGGL(k_lp_full<5>, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
+        hipLaunchKernelGGL(k_lp_full<5>, dim3(min(lp_grid_full(n), 64)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
                            c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, o2, apply,
                            c->counters);
     } else {

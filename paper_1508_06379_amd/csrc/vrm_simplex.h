@@ -90,9 +90,10 @@ __device__ __forceinline__ df rhs_df(int a, const LaunchParams& P)
 }
 
 // Column store interface (CS):
-//   int k;                                           number of columns
+//   int k; uint64_t dead;                            number of columns, absent ones
 //   void get(int j, float& rx, float& ry, float& c)  FP32 scaled offset and cost
 //   void exact(int j, df& X, df& Y, df& C)           exact offset and cost
+//   void exact_xy(int j, df& X, df& Y)               exact offset
 template <int M, class CS>
 struct ThreadSimplex {
     float Bi[M][M];   // B^-1
@@ -165,7 +166,7 @@ struct ThreadSimplex {
                 ratio = 0.0f;
             } else {
                 ok = alpha[r] > eps;
-                ratio = fmaxf(x[r], 0.0f) / alpha[r];
+                ratio = fmaxf(x[r], 0.0f) * __builtin_amdgcn_rcpf(alpha[r]);
             }
             if (ok && (l < 0 || ratio < best || (ratio == best && bs[r] < bl))) {
                 l = r;
@@ -285,9 +286,8 @@ struct ThreadSimplex {
                     float d = p2 ? c : 0.0f, sc = fabsf(d);
 #pragma unroll
                     for (int a = 0; a < M; ++a) {
-                        float t = y[a] * v[a];
-                        d -= t;
-                        sc += fabsf(t);
+                        d = __builtin_fmaf(-y[a], v[a], d);
+                        sc = __builtin_fmaf(fabsf(y[a]), fabsf(v[a]), sc);
                     }
                     // priority: Bland (lowest index) after many iterations; else the
                     // largest predicted logit among improving columns, else Dantzig
@@ -350,8 +350,8 @@ struct ThreadSimplex {
         for (int r = 0; r < M; ++r) {
             int b = bs[r];
             if (b < ART) {
-                df X, Y, C;
-                cs.exact(b, X, Y, C);
+                df X, Y;
+                cs.exact_xy(b, X, Y);
                 df v[M];
                 mono_df<M>(X, Y, v);
 #pragma unroll
@@ -440,9 +440,8 @@ struct ThreadSimplex {
                         float d = c, sc = fabsf(c);
 #pragma unroll
                         for (int a = 0; a < M; ++a) {
-                            float t = yf[a] * v[a];
-                            d -= t;
-                            sc += fabsf(t);
+                            d = __builtin_fmaf(-yf[a], v[a], d);
+                            sc = __builtin_fmaf(fabsf(yf[a]), fabsf(v[a]), sc);
                         }
                         if (d < kFastMargin * sc) dual_ok = false;
                     }

@@ -107,6 +107,16 @@ __global__ __launch_bounds__(256) void k_verify(int n, const float* __restrict__
     }
 }
 
+__global__ __launch_bounds__(256) void k_save_base(int n, const float* __restrict__ x, const float* __restrict__ y,
+                                                   const float* __restrict__ g, float* x0, float* y0, float* g0)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    x0[i] = x[i];
+    y0[i] = y[i];
+    g0[i] = g[i];
+}
+
 __global__ void k_verify_init(unsigned long long* out)
 {
     out[0] = 0ull;
@@ -150,6 +160,15 @@ int vrm_combine_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const float* u, const 
     if (n <= 0) return VRM_OK;
     hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, A[stage], B[stage], (float)dt, lam,
                        c->x0, c->y0, c->g0, cl->x_dev, cl->y_dev, cl->gamma_dev, u, v, c->acc);
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
+}
+
+int vrm_save_base_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n)
+{
+    if (n <= 0) return VRM_OK;
+    hipLaunchKernelGGL(k_save_base, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, cl->x_dev, cl->y_dev, cl->gamma_dev,
+                       c->x0, c->y0, c->g0);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }

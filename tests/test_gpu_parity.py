@@ -235,6 +235,29 @@ def test_run_gamma_matches_oracle(vrm, orc, name, steps):
     assert abs(g.astype(np.float64).sum() - wl.gamma.astype(np.float64).sum()) <= 1e-5 * np.abs(wl.gamma).sum()
 
 
+def test_native_step_with_moving_particles(vrm, orc):
+    """vrm_step with the prescribed vortex velocity (positions move every stage):
+    same particle count and Gamma within 1e-5 relative L2 of the oracle after 3 steps."""
+    wl = CONFIGS["vortices_h0.02"]
+    P = vrm.params_of(wl)
+    cloud = _gpu_cloud(vrm, wl, cap_factor=4)
+    ctx = vrm.Context(cloud.capacity)
+    vt = vrm.vortex_table(wl.vortices)
+    t = wl.t0
+    for _ in range(3):
+        ctx.vrm_step(cloud, P, vt, t)
+        t += wl.dt
+    torch.cuda.synchronize()
+    ref = orc.run(wl, steps=3)
+    x, y, g, ids = cloud.numpy()
+    err = _rel_l2_by_id(ids, g, ref.ids, ref.gamma)
+    o = np.argsort(ids)
+    perr = np.abs(x[o].astype(np.float64) - ref.x[:x.size]).max() if x.size == ref.x.size else -1
+    _say("moving: N", x.size, ref.x.size, "rel L2", err, "max |dx|", perr, ctx.vrm_read_counters())
+    assert x.size == ref.x.size
+    assert err <= 1e-5
+
+
 # ------------------------------------------------------------------ edges
 def test_empty_and_single(vrm, orc):
     """N = 0 does nothing; a lone particle gets the eight Dirac-start neighbours (Sec. 5)."""
