@@ -106,7 +106,8 @@ typedef struct {
     int64_t pivots;           /* simplex pivots (cumulative) */
     int64_t redistributions;  /* stencils applied by vrm_rk_stage (cumulative) */
     int32_t capacity_needed;  /* set when an insertion failed for capacity */
-    int32_t mis_rounds;       /* rounds of the last insertion's conflict resolution */
+    int32_t mis_rounds;       /* rounds of the last insertion's parallel conflict resolution; 0 when at most 1024
+                                 candidates were resolved greedily in one workgroup (same result) */
     int64_t full_cols;        /* sum of the column counts of complete-neighbourhood LPs (cumulative) */
     int64_t warm_hit;         /* warm-started LPs whose predicted basis was optimal (cumulative) */
     int64_t warm_phase2;      /* warm-started LPs that needed phase-II pivots from the predicted basis */

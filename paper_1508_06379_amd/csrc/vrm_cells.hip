@@ -487,6 +487,114 @@ __global__ __launch_bounds__(256) void k_append(int n0, int na, const int32_t* _
     diffused[n0 + r] = 0;
 }
 
+// Few candidates: the whole conflict resolution in one workgroup.  The
+// candidates are sorted by key (bitonic, in LDS) and decided greedily in that
+// order, each against the accepted ones; this is the same set as the rounds of
+// k_mis_round (the lexicographically first maximal independent set), and the
+// accepted ones are appended in key order as after the radix sort.
+constexpr int kInsSmallMax = 1024;
+
+__global__ __launch_bounds__(1024) void k_insert_small(int n0, int capacity, int cand_cap,
+                                                       const float* __restrict__ cx, const float* __restrict__ cy,
+                                                       const uint64_t* __restrict__ ckey, float ex2, float* x, float* y,
+                                                       float* gamma, int32_t* id, uint8_t* diffused, int32_t* n_dev,
+                                                       Queues* qs, vrm_counters* cnt)
+{
+    __shared__ uint64_t key[kInsSmallMax];
+    __shared__ int32_t src[kInsSmallMax];
+    __shared__ float sx[kInsSmallMax], sy[kInsSmallMax];
+    __shared__ float ax[kInsSmallMax], ay[kInsSmallMax];
+    __shared__ int32_t asrc[kInsSmallMax];
+    __shared__ int32_t na_s;
+    const int t = threadIdx.x;
+    const int nc = qs->n_cand;
+    if (nc > kInsSmallMax || nc > cand_cap) {
+        if (t == 0) qs->small_state = 0;
+        return;
+    }
+    int np = 1;
+    while (np < nc) np <<= 1;
+    if (t < np) {
+        key[t] = t < nc ? ckey[t] : ~0ull;   // keys are distinct and below 2^35
+        src[t] = t;
+    }
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            int p = t ^ j;
+            if (t < np && p > t) {
+                uint64_t a = key[t], b = key[p];
+                bool up = (t & k) == 0;
+                if ((a > b) == up) {
+                    key[t] = b;
+                    key[p] = a;
+                    int v = src[t];
+                    src[t] = src[p];
+                    src[p] = v;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (t < nc) {
+        sx[t] = cx[src[t]];
+        sy[t] = cy[src[t]];
+    }
+    __syncthreads();
+    if (t < 64) {
+        int na = 0;
+        for (int r = 0; r < nc; ++r) {
+            float xa = sx[r], ya = sy[r];
+            bool conflict = false;
+            for (int b = t; b < na; b += 64) {
+                float dx = ax[b] - xa;
+                float dy = ay[b] - ya;
+                conflict |= d2_f32(dx, dy) < ex2;
+            }
+            if (!__any(conflict)) {
+                if (t == 0) {
+                    ax[na] = xa;
+                    ay[na] = ya;
+                    asrc[na] = src[r];
+                }
+                ++na;
+                // the next candidate's lanes read what lane 0 wrote
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+        if (t == 0) na_s = na;
+    }
+    __syncthreads();
+    const int na = na_s;
+    if (n0 + na > capacity) {
+        if (t == 0) {
+            qs->n_accepted = na;
+            qs->small_state = 2;
+            cnt->capacity_needed = n0 + na;
+        }
+        return;
+    }
+    for (int r = t; r < na; r += blockDim.x) {
+        int a = asrc[r];
+        x[n0 + r] = cx[a];
+        y[n0 + r] = cy[a];
+        gamma[n0 + r] = 0.0f;
+        id[n0 + r] = n0 + r;
+        diffused[n0 + r] = 0;
+    }
+    if (t == 0) {
+        *n_dev = n0 + na;
+        qs->n_accepted = na;
+        qs->small_state = 1;
+        cnt->n_candidates = nc;
+        cnt->n_inserted = na;
+        cnt->mis_rounds = 0;
+        cnt->n = n0 + na;
+    }
+}
+
 // ------------------------------------------------------------- reorder
 __global__ __launch_bounds__(256) void k_gather_cloud(int n, const int32_t* __restrict__ perm,
                                                       const float* __restrict__ g, const uint8_t* __restrict__ dif,
@@ -520,6 +628,7 @@ __global__ void k_reset_insert(Queues* q)
     q->n_cand = 0;
     q->n_undecided = 0;
     q->n_accepted = 0;
+    q->small_state = 0;
 }
 __global__ void k_reset_undecided(Queues* q) { q->n_undecided = 0; }
 
@@ -589,10 +698,18 @@ int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp)
         hipLaunchKernelGGL(k_candidates, dim3(blocks_for(n)), dim3(256), 0, s, n, c->perm, c->xs, c->ys, c->ids,
                            c->cell_start, c->diffused, c->grid, lp, c->queues, cand_cap, c->cx, c->cy, c->ckey,
                            c->cstate);
+    if (n > 0)
+        hipLaunchKernelGGL(k_insert_small, dim3(1), dim3(1024), 0, s, n, cl->capacity, cand_cap, c->cx, c->cy, c->ckey,
+                           lp.ex2, cl->x_dev, cl->y_dev, cl->gamma_dev, cl->id_dev, c->diffused, cl->n_dev, c->queues,
+                           c->counters);
     VRM_HIP(hipGetLastError());
     Queues q;
     VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
     VRM_HIP(hipStreamSynchronize(s));
+    if (q.small_state == 2)
+        return vrm_fail(VRM_E_CAPACITY, "insertion needs %d particles, capacity is %d", n + q.n_accepted,
+                        cl->capacity);
+    if (q.small_state == 1) return n + q.n_accepted;
     int nc = q.n_cand;
     if (nc > cand_cap) return vrm_fail(VRM_E_CAPACITY, "insertion: %d candidates exceed the buffer of %d", nc, cand_cap);
     int rounds = 0;

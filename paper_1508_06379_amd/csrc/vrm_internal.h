@@ -23,7 +23,8 @@ struct Queues {
     int32_t n_cand;        // insertion candidates
     int32_t n_undecided;   // insertion candidates not yet decided
     int32_t n_accepted;    // accepted insertion candidates
-    int32_t pad[3];
+    int32_t small_state;   // single-workgroup insertion: 0 not taken, 1 done, 2 capacity exceeded
+    int32_t pad[2];
 };
 
 // Reduced-operator selection state (device side).

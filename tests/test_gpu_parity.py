@@ -91,14 +91,24 @@ def _oracle_inserted(orc, wl):
     return x, y, g, ids, mask
 
 
-@pytest.mark.parametrize("name", list(CONFIGS))
+INSERT_CONFIGS = dict(CONFIGS, vortices_h0_01_many_candidates=workloads.config_vortices(h=0.01, lo=-2.0, hi=2.0))
+SMALL_INSERT_MAX = 1024   # candidates resolved by the single-workgroup greedy
+
+
+@pytest.mark.parametrize("name", list(INSERT_CONFIGS))
 def test_insertion_bit_exact(vrm, orc, name):
-    """Sec. 4.2: same new particles (positions, ids), Gamma = 0, and the same count."""
-    wl = CONFIGS[name]
+    """Sec. 4.2: same new particles (positions, ids), Gamma = 0, and the same count,
+    through the single-workgroup greedy (few candidates) and the parallel rounds (many)."""
+    wl = INSERT_CONFIGS[name]
     _say("case", name)
     cloud = _gpu_cloud(vrm, wl)
     ctx = vrm.Context(cloud.capacity)
     ctx.vrm_insert_particles(cloud, vrm.params_of(wl))
+    cnt = ctx.vrm_read_counters()
+    _say("candidates", cnt["n_candidates"], "inserted", cnt["n_inserted"], "rounds", cnt["mis_rounds"])
+    if name == "vortices_h0_01_many_candidates":
+        assert cnt["n_candidates"] > SMALL_INSERT_MAX
+    assert (cnt["mis_rounds"] == 0) == (cnt["n_candidates"] <= SMALL_INSERT_MAX)
     x, y, g, ids = cloud.numpy()
     rx, ry, rg, rids, _ = _oracle_inserted(orc, wl)
     assert x.size == rx.size
