@@ -45,7 +45,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(wl, steps, warmup):
+def run_gpu(wl, steps, warmup, theta=None):
     import torch
     import paper_1508_06379_amd as vrm
 
@@ -54,6 +54,9 @@ def run_gpu(wl, steps, warmup):
     cap = int(wl.n * (4 if wl.n < 200000 else 2.2)) + 1024
     cloud = vrm.Cloud(wl.x, wl.y, wl.gamma, capacity=cap)
     ctx = vrm.Context(cap)
+    if theta is not None:
+        ctx.vrm_mlp_load(theta)
+        ctx.vrm_set_warm_start(True)
     vt = vrm.vortex_table(wl.vortices) if wl.vortices is not None else None
 
     t = wl.t0
@@ -75,7 +78,7 @@ def run_gpu(wl, steps, warmup):
     ctx.vrm_timing(False)
     c1 = ctx.vrm_read_counters()
     d = {k: c1[k] - c0[k] for k in ("redistributions", "pivots", "n_small", "n_full", "n_infeasible",
-                                     "n_uncertified", "full_cols")}
+                                     "n_uncertified", "full_cols", "warm_hit", "warm_phase2", "warm_cold")}
     return dict(elapsed=elapsed, counters=d, timers=timers, timer_overflow=overflow, n_start=n0, n_end=cloud.n,
                 final=c1)
 

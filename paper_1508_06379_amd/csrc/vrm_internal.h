@@ -24,7 +24,8 @@ struct Queues {
     int32_t n_undecided;   // insertion candidates not yet decided
     int32_t n_accepted;    // accepted insertion candidates
     int32_t small_state;   // single-workgroup insertion: 0 not taken, 1 done, 2 capacity exceeded
-    int32_t pad[2];
+    int32_t n_retry;       // LPs left by the warm pass for a cold solve
+    int32_t pad[1];
 };
 
 // Reduced-operator selection state (device side).
@@ -86,6 +87,7 @@ struct vrm_ctx {
     float* g0;
     int32_t* q_small;     // [cap] slots queued for the small LP
     int32_t* q_full;      // [cap] slots queued for the complete LP
+    int32_t* q_retry;     // [cap] slots the warm pass leaves for a cold solve
     int32_t* small_slot;  // [cap][8] small neighbourhood, slot indices
     // insertion
     float* cx;            // [2 cap] candidate positions
@@ -172,6 +174,9 @@ int vrm_mlp_set_weights(vrm_ctx* c, const float* w_dev);
 int vrm_mlp_forward(vrm_ctx* c, const uint16_t* X, int rows, float* Y, const int* rows_dev);
 int vrm_mlp_read_weights(vrm_ctx* c, float* w_dev);
 int vrm_mlp_infer_run(vrm_ctx* c, const uint16_t* X, int rows, float* Y, const int* rows_dev);
+// warm-start logits (8 per queued small LP) with the network input built from the positions
+int vrm_mlp_infer_small_run(vrm_ctx* c, int rows, const int* rows_dev, const int32_t* q_small,
+                            const int32_t* small_slot, const float* xs, const float* ys, float h, int q, float* L);
 int vrm_mlp_train(vrm_ctx* c, const uint16_t* X, const float* T, int rows, float lr, float wd, float wf,
                   double* loss_out, float* grad_out);
 int vrm_gemm_test(vrm_ctx* c, const uint16_t* A, const uint16_t* B, float* C, int M, int N, int K, int transA,

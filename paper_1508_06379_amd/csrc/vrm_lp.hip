@@ -145,7 +145,7 @@ struct StencilOut {
     uint16_t* feat;      // feature rows of solved LPs (collection), or NULL
     float* lab;          // label rows (basis indicators, fractions) of solved LPs, or NULL
     int max_rows;
-    const float* pred;   // network outputs per queue item (warm start), or NULL
+    const float* pred;   // warm start: small LPs 8 logits, complete ones kMlpOut outputs per queue item; or NULL
 };
 
 __device__ __forceinline__ void count_add(int* p, bool v)
@@ -195,10 +195,20 @@ __device__ __forceinline__ void count_warm(vrm_counters* cnt, bool live, int war
 
 constexpr int kFullBlock = 64;
 
+
+// LP kernel passes: plain (cold start), warm (from the predicted basis; what
+// it cannot settle cheaply goes to the retry queue), retry (cold start over
+// the retry queue).  Splitting the passes keeps the cheap warm-started LPs
+// from waiting for expensive cold ones in the same wave.
+constexpr int kLpPlain = 0;
+constexpr int kLpWarm = 1;
+constexpr int kLpRetry = 2;
+
 // Columns of an LP in LDS, column-major per thread (stride = threads per block):
 // FP32 scaled offsets and cost, and (slot << 6) | id rank for the exact values.
 template <int BLK>
 struct LdsColsT {
+    static constexpr int KC = 0;   // column count known at run time only
     int k;
     uint64_t dead;
     float* srx;
@@ -231,6 +241,16 @@ struct LdsColsT {
 };
 using LdsCols = LdsColsT<kFullBlock>;
 
+// Small-neighbourhood columns: the LDS store plus the monomials and costs of
+// all eight columns in registers, for pricing without LDS traffic.
+template <int BLK>
+struct SmallColsT : LdsColsT<BLK> {
+    static constexpr int KC = VRM_NSEG;
+    float v[VRM_NSEG][5];
+    float cc[VRM_NSEG];
+    float lg[VRM_NSEG];   // predicted logits (warm pass)
+};
+
 // Small-neighbourhood LPs (5 rows, up to 8 columns), one thread per particle;
 // the columns (column j = segment j) live in LDS.
 constexpr int kSmallBlock = 256;
@@ -242,23 +262,24 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(const int32_t* __restr
                                                           const int32_t* __restrict__ q_small, Queues* qs,
                                                           int32_t* q_full, const float* __restrict__ gamma,
                                                           float* acc, LaunchParams P, StencilOut out, int apply,
-                                                          vrm_counters* cnt)
+                                                          vrm_counters* cnt, int mode, int32_t* q_retry)
 {
     __shared__ float s_rx[8 * kSmallBlock];
     __shared__ float s_ry[8 * kSmallBlock];
     __shared__ float s_c[8 * kSmallBlock];
     __shared__ int s_meta[8 * kSmallBlock];
     const int tid = threadIdx.x;
-    const int nitems = qs->n_small;
+    const int32_t* queue = mode == kLpRetry ? q_retry : q_small;
+    const int nitems = mode == kLpRetry ? qs->n_retry : qs->n_small;
     const int stride = gridDim.x * blockDim.x;
-    int loops = (nitems + stride - 1) / stride;
+    const int loops = (nitems + stride - 1) / stride;
     for (int it = 0; it < loops; ++it) {
-        int item = blockIdx.x * blockDim.x + tid + it * stride;
-        bool live = item < nitems;
+        const int item = blockIdx.x * blockDim.x + tid + it * stride;
+        const bool live = item < nitems;
         int st = 1, piv = 0, certified = 1, warm = 0;
         int t = 0, i = 0;
         if (live) {
-            t = q_small[item];
+            t = queue[item];
             i = perm[t];
             const float xi = xs[t], yi = ys[t];
             uint64_t dead = 0;
@@ -270,7 +291,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(const int32_t* __restr
                 s_meta[s * kSmallBlock + tid] = u;
                 if (u < 0) dead |= 1ull << s;
             }
-            const bool rec = out.feat && item < out.max_rows;
+            const bool rec = mode == kLpPlain && out.feat && item < out.max_rows;
             uint16_t* frow = rec ? out.feat + (size_t)item * kMlpIn : nullptr;
             if (rec) feature_zero(frow);
 #pragma unroll
@@ -297,7 +318,14 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(const int32_t* __restr
                 s_meta[s * kSmallBlock + tid] = meta;
             }
             if (rec) feature_q(frow, P.q);
-            LdsColsT<kSmallBlock> cs{8, dead, s_rx, s_ry, s_c, s_meta, tid, xi, yi, xs, ys, &P};
+            SmallColsT<kSmallBlock> cs;
+            static_cast<LdsColsT<kSmallBlock>&>(cs) = {8, dead, s_rx, s_ry, s_c, s_meta, tid, xi, yi, xs, ys, &P};
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                float rx, ry;
+                cs.get(s, rx, ry, cs.cc[s]);
+                mono<5>(rx, ry, cs.v[s]);
+            }
             float fv[8];
 #pragma unroll
             for (int s = 0; s < 8; ++s) fv[s] = 0.0f;
@@ -307,8 +335,14 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(const int32_t* __restr
                 for (int s = 0; s < 8; ++s)
                     if (s == j) fv[s] = v;
             };
-            const float* logit = out.pred ? out.pred + (size_t)item * kMlpOut : nullptr;
-            st = solve_lp<5>(cs, P, store, fii, piv, certified, logit, warm);
+            const bool warm_pass = mode == kLpWarm && out.pred;
+            if (warm_pass) {
+                const float4* lg4 = reinterpret_cast<const float4*>(out.pred + (size_t)item * VRM_NSEG);
+                const float4 a = lg4[0], b = lg4[1];
+                cs.lg[0] = a.x, cs.lg[1] = a.y, cs.lg[2] = a.z, cs.lg[3] = a.w;
+                cs.lg[4] = b.x, cs.lg[5] = b.y, cs.lg[6] = b.z, cs.lg[7] = b.w;
+            }
+            st = solve_lp<5>(cs, P, store, fii, piv, certified, warm_pass, nullptr, warm);
             if (rec) {
                 float* lab = out.lab + (size_t)item * kMlpOut;
 #pragma unroll
@@ -348,32 +382,14 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(const int32_t* __restr
             if (m && lane_id() == __ffsll((unsigned long long)m) - 1)
                 atomicAdd((unsigned long long*)&cnt->redistributions, (unsigned long long)__popcll(m));
         }
-        bool fail = live && st != 0;
+        bool fail = live && st == 1;
         int p = wave_append(&qs->n_full, fail);
         if (fail) q_full[p] = t;
+        bool retry = live && st == 4;
+        int pr = wave_append(&qs->n_retry, retry);
+        if (retry) q_retry[pr] = t;
     }
 }
-
-// feature rows of the queued small LPs (warm start)
-__global__ __launch_bounds__(256) void k_feat_small(const float* __restrict__ xs, const float* __restrict__ ys,
-                                                    const int32_t* __restrict__ small_slot,
-                                                    const int32_t* __restrict__ q_small, const Queues* qs,
-                                                    LaunchParams P, uint16_t* feat)
-{
-    int item = blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= qs->n_small) return;
-    int t = q_small[item];
-    const float xi = xs[t], yi = ys[t];
-    uint16_t* row = feat + (size_t)item * kMlpIn;
-    feature_zero(row);
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        int u = small_slot[(size_t)t * VRM_NSEG + s];
-        if (u >= 0) feature_slot(row, s, (xs[u] - xi) / P.h, (ys[u] - yi) / P.h);
-    }
-    feature_q(row, P.q);
-}
-
 
 __device__ __forceinline__ uint64_t member_key(float d2, int id)
 {
@@ -489,26 +505,28 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
                                                         const float* __restrict__ xs, const float* __restrict__ ys,
                                                         const int32_t* __restrict__ ids,
                                                         const int32_t* __restrict__ cell_start, const GridState* gs,
-                                                        const int32_t* __restrict__ q_full, const Queues* qs,
+                                                        const int32_t* __restrict__ q_full, Queues* qs,
                                                         const float* __restrict__ gamma, float* acc, LaunchParams P,
-                                                        StencilOut out, int apply, vrm_counters* cnt)
+                                                        StencilOut out, int apply, vrm_counters* cnt, int mode,
+                                                        int32_t* q_retry)
 {
     __shared__ float s_rx[VRM_KMAX * kFullBlock];
     __shared__ float s_ry[VRM_KMAX * kFullBlock];
     __shared__ float s_c[VRM_KMAX * kFullBlock];
     __shared__ int s_meta[VRM_KMAX * kFullBlock];
     const int tid = threadIdx.x;
-    const int nitems = qs->n_full;
-    const int stride = gridDim.x * blockDim.x;
+    const int32_t* queue = mode == kLpRetry ? q_retry : q_full;
+    const int nitems = mode == kLpRetry ? qs->n_retry : qs->n_full;
     const GridState g = *gs;
-    int loops = (nitems + stride - 1) / stride;
+    const int stride = gridDim.x * blockDim.x;
+    const int loops = (nitems + stride - 1) / stride;
     for (int it = 0; it < loops; ++it) {
-        int item = blockIdx.x * blockDim.x + tid + it * stride;
-        bool live = item < nitems;
-        int st = 1, piv = 0, certified = 1, k = 0, warm = 0;
+        const int item = blockIdx.x * blockDim.x + tid + it * stride;
+        const bool live = item < nitems;
+        int st = 1, piv = 0, certified = 1, k = 0, warm = 0, t = 0;
         bool truncated = false;
         if (live) {
-            int t = q_full[item];
+            t = queue[item];
             int i = perm[t];
             const float xi = xs[t], yi = ys[t];
             // columns nearest first: slots in s_meta, d2 in s_rx, ids in s_c (as bits) during collection
@@ -520,7 +538,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
                 for (int o = 0; o < k; ++o) rank += __float_as_int(s_c[o * kFullBlock + tid]) < idj ? 1 : 0;
                 s_meta[j * kFullBlock + tid] = (int)(((unsigned)s_meta[j * kFullBlock + tid] << 6) | (unsigned)rank);
             }
-            const bool rec = out.feat && item < out.max_rows;
+            const bool rec = mode == kLpPlain && out.feat && item < out.max_rows;
             uint16_t* frow = rec ? out.feat + (size_t)item * kMlpIn : nullptr;
             if (rec) feature_zero(frow);
             for (int j = 0; j < k; ++j) {
@@ -556,8 +574,9 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
                 }
                 ++nz;
             };
-            const float* logit = out.pred ? out.pred + (size_t)item * kMlpOut : nullptr;
-            st = k > 0 ? solve_lp<M>(cs, P, store, fii, piv, certified, logit, warm) : 1;
+            const bool warm_pass = mode == kLpWarm && out.pred;
+            const float* logit = warm_pass ? out.pred + (size_t)item * kMlpOut : nullptr;
+            st = k > 0 ? solve_lp<M>(cs, P, store, fii, piv, certified, warm_pass, logit, warm) : 1;
             if (st == 0) {
                 if (apply) atomicAdd(&acc[i], fii * g_i);
                 if (out.full_k) {
@@ -565,7 +584,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
                     out.fii[i] = fii;
                     out.status[i] = VRM_ST_FULL;
                 }
-            } else {
+            } else if (st == 1) {
                 if (out.status) out.status[i] = VRM_ST_INFEASIBLE;
                 if (lab)
                     for (int a = 0; a < kMlpOut; ++a) lab[a] = 0.0f;
@@ -575,7 +594,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
         if (piv) atomicAdd((unsigned long long*)&cnt->pivots, (unsigned long long)piv);
         if (ok) atomicAdd((unsigned long long*)&cnt->full_cols, (unsigned long long)k);
         count_add(&cnt->n_full, ok);
-        count_add(&cnt->n_infeasible, live && !ok);
+        count_add(&cnt->n_infeasible, live && st == 1);
         count_add(&cnt->n_uncertified, ok && !certified);
         count_add(&cnt->n_truncated, live && truncated);
         count_warm(cnt, live, warm);
@@ -584,6 +603,9 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
             if (m && lane_id() == __ffsll((unsigned long long)m) - 1)
                 atomicAdd((unsigned long long*)&cnt->redistributions, (unsigned long long)__popcll(m));
         }
+        bool retry = live && st == 4;
+        int pr = wave_append(&qs->n_retry, retry);
+        if (retry) q_retry[pr] = t;
     }
 }
 
@@ -642,8 +664,10 @@ __global__ void k_reset_queues(Queues* q)
 {
     q->n_small = 0;
     q->n_full = 0;
+    q->n_retry = 0;
 }
 
+// persistent launches: enough threads for every CU, each loops over its items
 // persistent launches: enough threads for every CU, each loops over its items
 int lp_grid_small(int n) { return n > 0 ? min((n + 255) / 256, 256 * 8) : 1; }
 int lp_grid_full(int n) { return n > 0 ? min((n + kFullBlock - 1) / kFullBlock, 256 * 4) : 1; }
@@ -695,39 +719,48 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
     if (warm) {
         // network inputs of the queued LPs, then the forward pass (row count read on the device)
         ScopedTimer tm(c, VRM_T_MLP);
-        if (lp.m == 5)
-            hipLaunchKernelGGL(k_feat_small, dim3(nb), dim3(256), 0, c->stream, c->xs, c->ys, c->small_slot, c->q_small,
-                               c->queues, lp, c->feat);
-        else
+        int r;
+        if (lp.m == 5) {
+            r = vrm_mlp_infer_small_run(c, n, &c->queues->n_small, c->q_small, c->small_slot, c->xs, c->ys,
+                                        (float)lp.h, lp.q, c->pred);
+        } else {
             hipLaunchKernelGGL(k_feat_full, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->xs, c->ys, c->ids,
                                c->cell_start, c->grid, c->q_full, c->queues, lp, c->feat);
-        VRM_HIP(hipGetLastError());
-        int r = vrm_mlp_infer_run(c, c->feat, n, c->pred, lp.m == 5 ? &c->queues->n_small : &c->queues->n_full);
+            VRM_HIP(hipGetLastError());
+            r = vrm_mlp_infer_run(c, c->feat, n, c->pred, &c->queues->n_full);
+        }
         if (r) return r;
         out.pred = c->pred;
     }
+    // warm: the pass from the predicted bases, then a cold pass over what it left
+    const int first = warm ? kLpWarm : kLpPlain;
     if (lp.m == 5) {
         {
             ScopedTimer tm(c, VRM_T_LP_SMALL);
-            hipLaunchKernelGGL(k_lp_small, dim3(lp_grid_small(n)), dim3(kSmallBlock), 0, c->stream, c->perm, c->xs, c->ys,
-                               c->ids, c->small_slot, c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc, lp, out,
-                               apply, c->counters);
+            for (int mode = first; mode <= (warm ? kLpRetry : kLpPlain); ++mode) {
+                hipLaunchKernelGGL(k_lp_small, dim3(lp_grid_small(n)), dim3(kSmallBlock), 0, c->stream, c->perm, c->xs,
+                                   c->ys, c->ids, c->small_slot, c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc,
+                                   lp, out, apply, c->counters, mode, c->q_retry);
+                VRM_HIP(hipGetLastError());
+            }
         }
-        VRM_HIP(hipGetLastError());
         // fallbacks of the small LPs: no network input for them
         StencilOut o2 = out;
         o2.pred = nullptr;
         o2.feat = nullptr;
         o2.lab = nullptr;
         ScopedTimer tm(c, VRM_T_LP_FULL);
-        hipLaunchKernelGGL(k_lp_full<5>, dim3(min(lp_grid_full(n), 64)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
-                           c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, o2, apply,
-                           c->counters);
+        hipLaunchKernelGGL(k_lp_full<5>, dim3(min(lp_grid_full(n), 64)), dim3(kFullBlock), 0, c->stream, c->perm,
+                           c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
+                           o2, apply, c->counters, kLpPlain, c->q_retry);
     } else {
         ScopedTimer tm(c, VRM_T_LP_FULL);
-        hipLaunchKernelGGL(k_lp_full<9>, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
-                           c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, out, apply,
-                           c->counters);
+        for (int mode = first; mode <= (warm ? kLpRetry : kLpPlain); ++mode) {
+            hipLaunchKernelGGL(k_lp_full<9>, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
+                               c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
+                               out, apply, c->counters, mode, c->q_retry);
+            VRM_HIP(hipGetLastError());
+        }
     }
     VRM_HIP(hipGetLastError());
     return VRM_OK;

@@ -213,6 +213,69 @@ __global__ __launch_bounds__(256) void k_transpose_w(const uint16_t* __restrict_
 constexpr int FR = 64;               // rows per tile
 constexpr int FKP = kMlpHid + 8;     // padded LDS row (bank spread)
 
+// The two hidden layers on the tile in Ta: Ta -> Tb -> Ta (GELU, BF16).
+// Wave wv computes all 64 rows x columns [32 wv, 32 wv + 32).
+__device__ __forceinline__ void mlp_hidden(uint16_t* Ta, uint16_t* Tb, const uint16_t* __restrict__ wt,
+                                           const float* __restrict__ w, int tid)
+{
+    const int lane = tid & 63, wv = tid >> 6;
+    const int row = lane & 15, kq = (lane >> 4) * 8;
+    for (int layer = 0; layer < 2; ++layer) {
+        const uint16_t* A = layer == 0 ? Ta : Tb;
+        uint16_t* O = layer == 0 ? Tb : Ta;
+        const uint16_t* Wt = wt + (layer == 0 ? kOffT1 : kOffT2);
+        const float* bias = w + (layer == 0 ? kOffB1 : kOffB2);
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k0 = 0; k0 < kMlpHid; k0 += 32) {
+            bf16x8 b[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(&Wt[(wv * 32 + j * 16 + row) * kMlpHid + k0 + kq]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bf16x8 a = *reinterpret_cast<const bf16x8*>(&A[(i * 16 + row) * FKP + k0 + kq]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int m = i * 16 + (lane >> 4) * 4 + v;
+                    int n = wv * 32 + j * 16 + (lane & 15);
+                    O[m * FKP + n] = to_bf16(gelu(acc[i][j][v] + bias[n]));
+                }
+        __syncthreads();
+    }
+}
+
+// Output columns [n0, n0 + 16) of the last layer for the 64 rows of the tile
+// in Ta: lane holds rows i * 16 + 4 (lane / 16) + v, column n0 + lane % 16.
+__device__ __forceinline__ void mlp_out16(const uint16_t* Ta, const uint16_t* __restrict__ wt, int n0, int lane,
+                                          f32x4 (&acc)[4])
+{
+    const int row = lane & 15, kq = (lane >> 4) * 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k0 = 0; k0 < kMlpHid; k0 += 32) {
+        bf16x8 b = *reinterpret_cast<const bf16x8*>(&wt[kOffT3 + (n0 + row) * kMlpHid + k0 + kq]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bf16x8 a = *reinterpret_cast<const bf16x8*>(&Ta[(i * 16 + row) * FKP + k0 + kq]);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i], 0, 0, 0);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_mlp_infer(int rows, const int* rows_dev, const uint16_t* __restrict__ X,
                                                    const uint16_t* __restrict__ wt, const float* __restrict__ w,
                                                    float* __restrict__ Y)
@@ -221,7 +284,6 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int rows, const int* rows_dev
     __shared__ __attribute__((aligned(16))) uint16_t Tb[FR * FKP];
     if (rows_dev) rows = *rows_dev;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int row = lane & 15, kq = (lane >> 4) * 8;
     for (int r0 = blockIdx.x * FR; r0 < rows; r0 += gridDim.x * FR) {
         for (int e = tid; e < FR * kMlpIn / 8; e += 256) {
             int r = e / (kMlpIn / 8), c8 = (e % (kMlpIn / 8)) * 8;
@@ -230,64 +292,93 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int rows, const int* rows_dev
             *reinterpret_cast<uint4*>(&Ta[r * FKP + c8]) = v;
         }
         __syncthreads();
-        // two hidden layers: wave wv computes all 64 rows x columns [32 wv, 32 wv + 32)
-        for (int layer = 0; layer < 2; ++layer) {
-            const uint16_t* A = layer == 0 ? Ta : Tb;
-            uint16_t* O = layer == 0 ? Tb : Ta;
-            const uint16_t* Wt = wt + (layer == 0 ? kOffT1 : kOffT2);
-            const float* bias = w + (layer == 0 ? kOffB1 : kOffB2);
-            f32x4 acc[4][2];
+        mlp_hidden(Ta, Tb, wt, w, tid);
+        // output layer: wave wv computes columns [16 wv, 16 wv + 16)
+        f32x4 acc[4];
+        mlp_out16(Ta, wt, wv * 16, lane, acc);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int v = 0; v < 4; ++v) {
+                int m = r0 + i * 16 + (lane >> 4) * 4 + v;
+                int n = wv * 16 + (lane & 15);
+                if (m < rows) Y[(long)m * kMlpOut + n] = acc[i][v] + w[kOffB3 + n];
+            }
+        __syncthreads();
+    }
+}
+
+// Inference for the queued small-neighbourhood LPs with the network input
+// built in LDS from the particle positions (slot s = segment s: offset / h
+// and mask; q - 2), and only the logits of the eight columns written:
+// L[item][8].  The gathers of the next tile are issued before the current
+// tile's products, so their latency overlaps the matrix work.
+__global__ __launch_bounds__(256) void k_mlp_infer_small(const int* rows_dev, const int32_t* __restrict__ q_small,
+                                                         const int32_t* __restrict__ small_slot,
+                                                         const float* __restrict__ xs, const float* __restrict__ ys,
+                                                         float h, int q, const uint16_t* __restrict__ wt,
+                                                         const float* __restrict__ w, float* __restrict__ L)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t Ta[FR * FKP];
+    __shared__ __attribute__((aligned(16))) uint16_t Tb[FR * FKP];
+    const int rows = *rows_dev;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int kPer = FR * VRM_NSEG / 256;   // (row, slot) entries of a thread
+    // offsets of this thread's entries of the tile at r0: NaN = no column, row out of range = no row
+    float gx[kPer], gy[kPer];
+    bool grow[kPer];
+    auto gather = [&](int r0) {
 #pragma unroll
-            for (int k0 = 0; k0 < kMlpHid; k0 += 32) {
-                bf16x8 b[2];
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    b[j] = *reinterpret_cast<const bf16x8*>(&Wt[(wv * 32 + j * 16 + row) * kMlpHid + k0 + kq]);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    bf16x8 a = *reinterpret_cast<const bf16x8*>(&A[(i * 16 + row) * FKP + k0 + kq]);
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+        for (int k = 0; k < kPer; ++k) {
+            const int e = tid + 256 * k, r = e / VRM_NSEG, s = e % VRM_NSEG;
+            const int item = r0 + r;
+            grow[k] = item < rows;
+            gx[k] = gy[k] = __builtin_nanf("");
+            if (grow[k]) {
+                const int t = q_small[item];
+                const int u = small_slot[(size_t)t * VRM_NSEG + s];
+                if (u >= 0) {
+                    gx[k] = (xs[u] - xs[t]) / h;
+                    gy[k] = (ys[u] - ys[t]) / h;
                 }
             }
+        }
+    };
+    const int stride = gridDim.x * FR;
+    int r0 = blockIdx.x * FR;
+    if (r0 < rows) gather(r0);
+    for (; r0 < rows; r0 += stride) {
+        for (int e = tid; e < FR * kMlpIn / 8; e += 256) {
+            int r = e / (kMlpIn / 8), c8 = (e % (kMlpIn / 8)) * 8;
+            *reinterpret_cast<uint4*>(&Ta[r * FKP + c8]) = uint4{0u, 0u, 0u, 0u};
+        }
+        __syncthreads();
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+        for (int k = 0; k < kPer; ++k) {
+            const int e = tid + 256 * k, r = e / VRM_NSEG, s = e % VRM_NSEG;
+            if (grow[k] && gx[k] == gx[k]) {
+                Ta[r * FKP + 2 * s] = to_bf16(gx[k]);
+                Ta[r * FKP + 2 * s + 1] = to_bf16(gy[k]);
+                Ta[r * FKP + 2 * kMlpSlots + s] = 0x3f80;   // 1.0
+            }
+            if (grow[k] && s == 0) Ta[r * FKP + 3 * kMlpSlots] = q == 3 ? 0x3f80 : 0;
+        }
+        __syncthreads();
+        if (r0 + stride < rows) gather(r0 + stride);
+        mlp_hidden(Ta, Tb, wt, w, tid);
+        if (wv == 0) {
+            f32x4 acc[4];
+            mlp_out16(Ta, wt, 0, lane, acc);
+            const int n = lane & 15;
+            if (n < VRM_NSEG) {
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        int m = i * 16 + (lane >> 4) * 4 + v;
-                        int n = wv * 32 + j * 16 + (lane & 15);
-                        O[m * FKP + n] = to_bf16(gelu(acc[i][j][v] + bias[n]));
+                        int m = r0 + i * 16 + (lane >> 4) * 4 + v;
+                        if (m < rows) L[(long)m * VRM_NSEG + n] = acc[i][v] + w[kOffB3 + n];
                     }
-            __syncthreads();
-        }
-        // output layer: 64 x 64, wave wv computes columns [16 wv, 16 wv + 16)
-        {
-            f32x4 acc[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int k0 = 0; k0 < kMlpHid; k0 += 32) {
-                bf16x8 b = *reinterpret_cast<const bf16x8*>(&wt[kOffT3 + (wv * 16 + row) * kMlpHid + k0 + kq]);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    bf16x8 a = *reinterpret_cast<const bf16x8*>(&Ta[(i * 16 + row) * FKP + k0 + kq]);
-                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i], 0, 0, 0);
-                }
             }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    int m = r0 + i * 16 + (lane >> 4) * 4 + v;
-                    int n = wv * 16 + (lane & 15);
-                    if (m < rows) Y[(long)m * kMlpOut + n] = acc[i][v] + w[kOffB3 + n];
-                }
         }
         __syncthreads();
     }
@@ -411,6 +502,19 @@ int vrm_mlp_forward(vrm_ctx* c, const uint16_t* X, int rows, float* Y, const int
 }
 
 // fused forward for inference (no intermediate buffers); rows may be an upper bound with rows_dev
+int vrm_mlp_infer_small_run(vrm_ctx* c, int rows, const int* rows_dev, const int32_t* q_small,
+                            const int32_t* small_slot, const float* xs, const float* ys, float h, int q, float* L)
+{
+    if (rows <= 0) return VRM_OK;
+    MlpState* m = c->mlp;
+    int tiles = (rows + FR - 1) / FR;
+    int grid = tiles < 256 * 4 ? tiles : 256 * 4;   // four blocks per CU are resident
+    hipLaunchKernelGGL(k_mlp_infer_small, dim3(grid), dim3(256), 0, c->stream, rows_dev, q_small, small_slot, xs, ys,
+                       h, q, m->wt, m->w, L);
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
+}
+
 int vrm_mlp_infer_run(vrm_ctx* c, const uint16_t* X, int rows, float* Y, const int* rows_dev)
 {
     if (rows <= 0) return VRM_OK;

@@ -212,7 +212,8 @@ struct ThreadSimplex {
     }
 
     // Crash basis from a prediction: the columns of the M largest logits
-    // (slots j < 32 are columns j) enter in that order, each replacing the
+    // (slots j < 32 are columns j; a store with KC > 0 columns holds them in
+    // cs.lg, otherwise they are read from logit) enter in that order, each replacing the
     // artificial row where its pivot element is largest.  Returns true if the
     // resulting basis is complete and primal feasible (phase II can start).
     __device__ bool crash(const CS& cs, const float* logit, int& piv)
@@ -222,12 +223,25 @@ struct ThreadSimplex {
         for (int t = 0; t < M; ++t) {
             int best = -1;
             float bl = 0.0f;
-            for (int j = 0; j < kk; ++j) {
-                if ((chosen >> j) & 1ull) continue;
-                float z = logit[j];
-                if (best < 0 || z > bl) {
-                    best = j;
-                    bl = z;
+            if constexpr (CS::KC > 0) {
+                // the logits of the columns are in registers
+#pragma unroll
+                for (int j = 0; j < CS::KC; ++j) {
+                    if ((chosen >> j) & 1ull) continue;
+                    const float z = cs.lg[j];
+                    if (best < 0 || z > bl) {
+                        best = j;
+                        bl = z;
+                    }
+                }
+            } else {
+                for (int j = 0; j < kk; ++j) {
+                    if ((chosen >> j) & 1ull) continue;
+                    float z = logit[j];
+                    if (best < 0 || z > bl) {
+                        best = j;
+                        bl = z;
+                    }
                 }
             }
             if (best < 0) break;
@@ -259,65 +273,81 @@ struct ThreadSimplex {
         return true;
     }
 
+    // Reduced cost d_j = c_j - y . v_j (phase II; 0 - y . v_j in phase I) and
+    // the scale sum |c_j| + sum |y_a v_ja| its tolerance is relative to.
+    __device__ __forceinline__ static void reduced(const float (&v)[M], float c, const float (&y)[M], bool p2,
+                                                   float& d, float& sc)
+    {
+        d = p2 ? c : 0.0f;
+        sc = fabsf(d);
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            d = __builtin_fmaf(-y[a], v[a], d);
+            sc = __builtin_fmaf(fabsf(y[a]), fabsf(v[a]), sc);
+        }
+    }
+
+    // Entering column: Dantzig (most negative reduced cost), Bland (lowest
+    // index) after many iterations.
+    __device__ __forceinline__ int price(const CS& cs, const float (&y)[M], bool p2, bool bland) const
+    {
+        const uint64_t excl = isb | blk | dead;
+        int e = -1;
+        float best = 0.0f;
+        auto consider = [&](int j, float d, float sc) -> bool {
+            if (!(d < -kTolD * sc)) return false;
+            if (bland) {
+                e = j;
+                return true;
+            }
+            if (e < 0 || d < best) {
+                e = j;
+                best = d;
+            }
+            return false;
+        };
+        if constexpr (CS::KC > 0) {
+            // columns with their monomials in registers (compile-time count)
+#pragma unroll
+            for (int j = 0; j < CS::KC; ++j) {
+                if ((excl >> j) & 1ull) continue;
+                float d, sc;
+                reduced(cs.v[j], cs.cc[j], y, p2, d, sc);
+                if (consider(j, d, sc)) break;
+            }
+        } else {
+            for (int j = 0; j < cs.k; ++j) {
+                if ((excl >> j) & 1ull) continue;
+                float rx, ry, c;
+                cs.get(j, rx, ry, c);
+                float v[M];
+                mono<M>(rx, ry, v);
+                float d, sc;
+                reduced(v, c, y, p2, d, sc);
+                if (consider(j, d, sc)) break;
+            }
+        }
+        return e;
+    }
+
     // FP32 simplex from phase `first` (1: two phases from the artificial basis,
-    // 2: phase II from a feasible basis).  0 optimal, 1 infeasible, 2 iteration limit.
-    __device__ int run(const CS& cs, int& piv, int first = 1, const float* prio = nullptr)
+    // 2: phase II from a feasible basis).  0 optimal, 1 infeasible, 2 iteration
+    // limit (cap >= 0: at most cap iterations per phase).  Both phases share one
+    // loop, so the lanes of a wave step through their own phases together.
+    __device__ int run(const CS& cs, int& piv, int first, int cap = -1)
     {
         const int k = cs.k;
-        const int kp = k < 32 ? k : 32;
-        for (int phase = first; phase <= 2; ++phase) {
-            const bool p2 = phase == 2;
-            int it = 0;
-            const int bland_after = 3 * (k + M);
-            const int limit = 10 * (k + M) + 20;
-            for (; it < limit; ++it) {
-                float y[M];
-                prices(p2, y);
-                int e = -1;
-                float best = 0.0f;
-                bool best_p = false;
-                const bool bland = it >= bland_after;
-                for (int j = 0; j < k; ++j) {
-                    if (((isb | blk | dead) >> j) & 1ull) continue;
-                    float rx, ry, c;
-                    cs.get(j, rx, ry, c);
-                    float v[M];
-                    mono<M>(rx, ry, v);
-                    float d = p2 ? c : 0.0f, sc = fabsf(d);
-#pragma unroll
-                    for (int a = 0; a < M; ++a) {
-                        d = __builtin_fmaf(-y[a], v[a], d);
-                        sc = __builtin_fmaf(fabsf(y[a]), fabsf(v[a]), sc);
-                    }
-                    // priority: Bland (lowest index) after many iterations; else the
-                    // largest predicted logit among improving columns, else Dantzig
-                    if (d < -kTolD * sc) {
-                        bool pj = prio && j < kp;
-                        float key = pj ? -prio[j] : d;
-                        bool better = e < 0 || (!bland && ((pj && !best_p) || (pj == best_p && key < best)));
-                        if (better) {
-                            e = j;
-                            best = key;
-                            best_p = pj;
-                            if (bland) break;
-                        }
-                    }
-                }
-                if (e < 0) break;
-                float rx, ry, ce;
-                cs.get(e, rx, ry, ce);
-                float alpha[M];
-                column_alpha(rx, ry, alpha);
-                int l = ratio_test(alpha, xb, p2);
-                if (l < 0) {
-                    blk |= 1ull << e;
-                    continue;
-                }
-                pivot(l, e, alpha, p2 ? ce : 0.0f);
-                ++piv;
-            }
+        const int bland_after = 3 * (k + M);
+        const int limit = cap >= 0 ? cap : 10 * (k + M) + 20;
+        bool p2 = first == 2;
+        for (int it = 0;; ++it) {
             if (it >= limit) return 2;
-            if (!p2) {
+            float y[M];
+            prices(p2, y);
+            const int e = price(cs, y, p2, it >= bland_after);
+            if (e < 0) {
+                if (p2) return 0;
+                // end of phase I: feasible iff the artificial variables vanished
                 float art = 0.0f;
 #pragma unroll
                 for (int r = 0; r < M; ++r) art += bs[r] >= ART ? fabsf(xb[r]) : 0.0f;
@@ -332,9 +362,22 @@ struct ThreadSimplex {
                     cb[r] = c;
                 }
                 blk = 0;
+                p2 = true;
+                it = -1;
+                continue;
             }
+            float rx, ry, ce;
+            cs.get(e, rx, ry, ce);
+            float alpha[M];
+            column_alpha(rx, ry, alpha);
+            const int l = ratio_test(alpha, xb, p2);
+            if (l < 0) {
+                blk |= 1ull << e;
+                continue;
+            }
+            pivot(l, e, alpha, p2 ? ce : 0.0f);
+            ++piv;
         }
-        return 0;
     }
 
     float bt_;
@@ -431,19 +474,26 @@ struct ThreadSimplex {
                     float yf[M];
                     prices(true, yf);
                     bool dual_ok = true;
-                    for (int j = 0; j < k && dual_ok; ++j) {
-                        if (((isb | dead) >> j) & 1ull) continue;
-                        float rx, ry, c;
-                        cs.get(j, rx, ry, c);
-                        float v[M];
-                        mono<M>(rx, ry, v);
-                        float d = c, sc = fabsf(c);
+                    const uint64_t excl = isb | dead;
+                    if constexpr (CS::KC > 0) {
 #pragma unroll
-                        for (int a = 0; a < M; ++a) {
-                            d = __builtin_fmaf(-yf[a], v[a], d);
-                            sc = __builtin_fmaf(fabsf(yf[a]), fabsf(v[a]), sc);
+                        for (int j = 0; j < CS::KC; ++j) {
+                            if ((excl >> j) & 1ull) continue;
+                            float d, sc;
+                            reduced(cs.v[j], cs.cc[j], yf, true, d, sc);
+                            dual_ok = dual_ok && !(d < kFastMargin * sc);
                         }
-                        if (d < kFastMargin * sc) dual_ok = false;
+                    } else {
+                        for (int j = 0; j < k && dual_ok; ++j) {
+                            if ((excl >> j) & 1ull) continue;
+                            float rx, ry, c;
+                            cs.get(j, rx, ry, c);
+                            float v[M];
+                            mono<M>(rx, ry, v);
+                            float d, sc;
+                            reduced(v, c, yf, true, d, sc);
+                            if (d < kFastMargin * sc) dual_ok = false;
+                        }
                     }
                     if (dual_ok) return 0;
                 }
@@ -557,13 +607,18 @@ struct ThreadSimplex {
 
 // Solve, certify and extract the fractions: f (k entries, written through
 // store(j, value) for the non-zero ones) and fii = -sum f.
-// Returns 0 ok, 1 infeasible; *certified = 0 if optimality could not be shown.
-// With a prediction (logits of the first 32 columns), the simplex starts from
-// the crash basis when that is feasible; warm = 0 no prediction, 1 the
-// predicted basis was optimal, 2 phase II from it, 3 rejected (cold start).
+// Returns 0 ok, 1 infeasible, 4 left for a cold solve (warm pass);
+// *certified = 0 if optimality could not be shown.
+// Warm pass (warm_pass): the simplex starts from the crash basis of the
+// prediction (logits of the first 32 columns); a rejected crash basis, or one
+// that needs more than kWarmCap phase-II pivots, is given up (status 4).
+// warm = 0 cold, 1 the predicted basis was optimal, 2 phase II from it,
+// 3 given up.
+constexpr int kWarmCap = 3;
+
 template <int M, class CS, class Store>
 __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified,
-                        const float* logit, int& warm)
+                        bool warm_pass, const float* logit, int& warm)
 {
     ThreadSimplex<M, CS> lp;
     lp.bt_ = P.bt_hi;
@@ -571,20 +626,18 @@ __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float&
     lp.dead = cs.dead;
     int st;
     warm = 0;
-    if (logit) {
-        int p0 = piv;
-        if (lp.crash(cs, logit, piv)) {
-            int p1 = piv;
-            st = lp.run(cs, piv, 2);
-            warm = piv == p1 ? 1 : 2;
-        } else {
-            // infeasible or incomplete prediction: cold start, pricing by the prediction
-            lp.init(P);
-            lp.dead = cs.dead;
-            st = lp.run(cs, piv, 1, logit);
+    if (warm_pass) {
+        if (!lp.crash(cs, logit, piv)) {
             warm = 3;
+            return 4;
         }
-        (void)p0;
+        const int p1 = piv;
+        st = lp.run(cs, piv, 2, kWarmCap);
+        if (st == 2) {
+            warm = 3;
+            return 4;
+        }
+        warm = piv == p1 ? 1 : 2;
     } else {
         st = lp.run(cs, piv, 1);
     }

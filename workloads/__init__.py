@@ -183,9 +183,15 @@ def config_scale(h: float = 0.004, lo: float = -8.0, hi: float = 8.0, q: int = 3
     return w
 
 
-def training_snapshot(seed: int, h: float = 0.01, q: int = 2) -> Workload:
-    """Training geometry: the jittered Lamb-Oseen generator with its own seed."""
-    return config_jittered(h=h, q=q, seed=seed, steps=0)
+def training_snapshot(seed: int, h: float = 0.01, q: int = 2, kind: str = "lamb_oseen") -> Workload:
+    """Training geometry with its own seed: the jittered Lamb-Oseen generator
+    (kind "lamb_oseen"), or the vortex-cloud generator with lattice jitter
+    +-0.4h and 20% deletion ("vortices") or none ("vortices_dense") over
+    [-4, 4]^2.  Only offsets / h enter the network, so h sets the cloud size."""
+    if kind == "lamb_oseen":
+        return config_jittered(h=h, q=q, seed=seed, steps=0)
+    p_delete = 0.2 if kind == "vortices" else 0.0
+    return _vortex_cloud(f"train_{kind}_{seed}", -4.0, 4.0, h, 64, seed, seed + 7919, seed + 104729, p_delete, q)
 
 
 def lone_particle(h: float = 0.05, gamma: float = 1.0) -> Workload:
