@@ -1,7 +1,8 @@
 """FP64 reference of the warm-start network (TEST INFRASTRUCTURE ONLY).
 
 Plain numpy: forward pass, the masked loss and its gradient by the chain rule,
-written from the definitions (a 3-layer perceptron with GELU activations,
+written from the definitions (a 3-layer perceptron with GELU activations in
+their tanh form, 0.5 z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))),
 BCE-with-logits on 32 basis indicators, squared error on 32 fractions, both
 masked by the input's slot mask and averaged over rows).  Used to check the
 GPU's BF16 matrix-core forward and backward passes.
@@ -9,7 +10,6 @@ GPU's BF16 matrix-core forward and backward passes.
 import math
 
 import numpy as np
-from scipy.special import erf
 
 IN, HID, OUT, SLOTS = 128, 128, 64, 32
 SHAPES = [("W1", (IN, HID)), ("b1", (HID,)), ("W2", (HID, HID)), ("b2", (HID,)), ("W3", (HID, OUT)), ("b3", (OUT,))]
@@ -29,12 +29,17 @@ def pack(d):
     return np.concatenate([np.asarray(d[name], np.float64).ravel() for name, _ in SHAPES])
 
 
+GELU_C = math.sqrt(2.0 / math.pi)
+GELU_A = 0.044715
+
+
 def gelu(z):
-    return 0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))
+    return 0.5 * z * (1.0 + np.tanh(GELU_C * (z + GELU_A * z ** 3)))
 
 
 def gelu_grad(z):
-    return 0.5 * (1.0 + erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+    t = np.tanh(GELU_C * (z + GELU_A * z ** 3))
+    return 0.5 * (1.0 + t) + 0.5 * z * (1.0 - t * t) * GELU_C * (1.0 + 3.0 * GELU_A * z * z)
 
 
 def forward(theta, X):

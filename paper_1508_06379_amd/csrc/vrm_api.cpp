@@ -181,7 +181,11 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
     A(q_small, cap);
     A(q_full, cap);
     A(q_retry, cap);
-    A(small_slot, cap * VRM_NSEG);
+    A(srec.i, cap);
+    A(srec.rank, cap);
+    A(srec.pj, cap * VRM_NSEG);
+    A(srec.off, cap * 4 * VRM_NSEG);
+    c->srec.cap = capacity;
     A(cx, cap2);
     A(cy, cap2);
     A(ckey, cap2);
@@ -227,7 +231,7 @@ int vrm_destroy(vrm_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->grid, c->queues, c->sel, c->counters, c->cell_of, c->rank, c->cell_start, c->scan_part,
                     c->perm, c->xs, c->ys, c->ids, c->diffused, c->acc, c->x0, c->y0, c->g0, c->q_small, c->q_full, c->q_retry,
-                    c->small_slot, c->cx, c->cy, c->ckey, c->cstate, c->ccell, c->crank, c->cstart, c->cperm,
+                    c->srec.i, c->srec.rank, c->srec.pj, c->srec.off, c->cx, c->cy, c->ckey, c->cstate, c->ccell, c->crank, c->cstart, c->cperm,
                     c->akey, c->aidx, c->tmp_f, c->tmp_i, c->tmp_u8, c->verify_buf, c->sort_tmp};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);

@@ -28,6 +28,17 @@ struct Queues {
     int32_t pad[1];
 };
 
+// Column records of the queued small-neighbourhood LPs, in queue order and
+// plane-major (plane p of item r at p * cap + r) so that the LP and network
+// kernels read them coalesced instead of gathering neighbours.
+struct SmallRec {
+    int32_t cap;     // plane stride
+    int32_t* i;      // [cap] cloud index of the particle
+    int32_t* rank;   // [cap] id ranks of its 8 columns, 3 bits each (segment s at bit 3 s)
+    int32_t* pj;     // [8][cap] cloud index of the column of segment s, -1 if the segment is empty
+    float* off;      // [32][cap] exact scaled offset of segment s: planes 4s..4s+3 = X.hi, X.lo, Y.hi, Y.lo
+};
+
 // Reduced-operator selection state (device side).
 struct SelectState {
     double norm1, bound, prefix;
@@ -88,7 +99,7 @@ struct vrm_ctx {
     int32_t* q_small;     // [cap] slots queued for the small LP
     int32_t* q_full;      // [cap] slots queued for the complete LP
     int32_t* q_retry;     // [cap] slots the warm pass leaves for a cold solve
-    int32_t* small_slot;  // [cap][8] small neighbourhood, slot indices
+    vrm::SmallRec srec;   // column records of the queued small LPs
     // insertion
     float* cx;            // [2 cap] candidate positions
     float* cy;
@@ -175,8 +186,8 @@ int vrm_mlp_forward(vrm_ctx* c, const uint16_t* X, int rows, float* Y, const int
 int vrm_mlp_read_weights(vrm_ctx* c, float* w_dev);
 int vrm_mlp_infer_run(vrm_ctx* c, const uint16_t* X, int rows, float* Y, const int* rows_dev);
 // warm-start logits (8 per queued small LP) with the network input built from the positions
-int vrm_mlp_infer_small_run(vrm_ctx* c, int rows, const int* rows_dev, const int32_t* q_small,
-                            const int32_t* small_slot, const float* xs, const float* ys, float h, int q, float* L);
+int vrm_mlp_infer_small_run(vrm_ctx* c, int rows, const int* rows_dev, const vrm::SmallRec& rec, float sc, int q,
+                            float* L);
 int vrm_mlp_train(vrm_ctx* c, const uint16_t* X, const float* T, int rows, float lr, float wd, float wf,
                   double* loss_out, float* grad_out);
 int vrm_gemm_test(vrm_ctx* c, const uint16_t* A, const uint16_t* B, float* C, int M, int N, int K, int transA,

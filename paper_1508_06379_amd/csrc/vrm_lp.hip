@@ -46,13 +46,14 @@ __device__ __forceinline__ int wave_append(int* counter, bool want)
 
 // ------------------------------------------------------------- kernels
 // Small neighbourhoods (Sec. 4.3) of the diffused particles, in slot order.
+// With queues: the LP queues, and the column record of each queued small LP.
 __global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __restrict__ perm,
                                                     const float* __restrict__ xs, const float* __restrict__ ys,
                                                     const int32_t* __restrict__ ids,
                                                     const int32_t* __restrict__ cell_start,
                                                     const uint8_t* __restrict__ diffused, const GridState* gs,
-                                                    LaunchParams P, int32_t* __restrict__ small_slot,
-                                                    int32_t* q_small, int32_t* q_full, Queues* qs,
+                                                    LaunchParams P, SmallRec rec, int32_t* q_small,
+                                                    int32_t* q_full, Queues* qs,
                                                     int32_t* out_small_idx, int32_t* out_kfull, int want_kfull)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -113,10 +114,6 @@ __global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __rest
         for (int s = 0; s < VRM_NSEG; ++s) ksmall += best[s] >= 0 ? 1 : 0;
     }
     if (active) {
-        if (small_slot) {
-#pragma unroll
-            for (int s = 0; s < VRM_NSEG; ++s) small_slot[(size_t)t * VRM_NSEG + s] = best[s];
-        }
         if (out_small_idx) {
 #pragma unroll
             for (int s = 0; s < VRM_NSEG; ++s)
@@ -127,7 +124,36 @@ __global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __rest
     if (q_small) {
         bool small_ok = dif && P.m <= VRM_NSEG && ksmall >= P.m;
         int p1 = wave_append(&qs->n_small, small_ok);
-        if (small_ok) q_small[p1] = t;
+        if (small_ok) {
+            q_small[p1] = t;
+            rec.i[p1] = i;
+            const size_t cap = (size_t)rec.cap;
+            const float xi = xs[t], yi = ys[t];
+            int idb[VRM_NSEG];
+#pragma unroll
+            for (int s = 0; s < VRM_NSEG; ++s) idb[s] = best[s] >= 0 ? ids[best[s]] : 0x7fffffff;
+            int packed = 0;
+#pragma unroll
+            for (int s = 0; s < VRM_NSEG; ++s) {
+                int rank = 0;
+#pragma unroll
+                for (int o = 0; o < VRM_NSEG; ++o) rank += idb[o] < idb[s] ? 1 : 0;
+                packed |= rank << (3 * s);
+                const int u = best[s];
+                df X{0.0f, 0.0f}, Y{0.0f, 0.0f};
+                int pj = -1;
+                if (u >= 0) {
+                    exact_offset(xi, yi, xs[u], ys[u], P.scale2e, X, Y);
+                    pj = perm[u];
+                }
+                rec.pj[s * cap + p1] = pj;
+                rec.off[(4 * s + 0) * cap + p1] = X.hi;
+                rec.off[(4 * s + 1) * cap + p1] = X.lo;
+                rec.off[(4 * s + 2) * cap + p1] = Y.hi;
+                rec.off[(4 * s + 3) * cap + p1] = Y.lo;
+            }
+            rec.rank[p1] = packed;
+        }
         bool full = dif && !small_ok;
         int p2 = wave_append(&qs->n_full, full);
         if (full) q_full[p2] = t;
@@ -220,45 +246,47 @@ struct LdsColsT {
     const float* xs;
     const float* ys;
     const LaunchParams* P;
+    float* sxlo;   // low parts of the exact scaled offsets (hi parts are srx, sry), or NULL:
+    float* sylo;   // then the exact offsets are recomputed from the positions
     __device__ __forceinline__ void get(int j, float& x, float& y, float& cc) const
     {
         x = srx[j * BLK + tid];
         y = sry[j * BLK + tid];
         cc = sc[j * BLK + tid];
     }
-    __device__ __forceinline__ void exact(int j, df& X, df& Y, df& C) const
-    {
-        int meta = smeta[j * BLK + tid];
-        int u = (int)((unsigned)meta >> 6);
-        exact_offset(xi, yi, xs[u], ys[u], P->scale2e, X, Y);
-        C = add_rank(cost_df(X, Y, *P), meta & 63);
-    }
     __device__ __forceinline__ void exact_xy(int j, df& X, df& Y) const
     {
-        int u = (int)((unsigned)smeta[j * BLK + tid] >> 6);
-        exact_offset(xi, yi, xs[u], ys[u], P->scale2e, X, Y);
+        if (sxlo) {
+            X = {srx[j * BLK + tid], sxlo[j * BLK + tid]};
+            Y = {sry[j * BLK + tid], sylo[j * BLK + tid]};
+        } else {
+            int u = (int)((unsigned)smeta[j * BLK + tid] >> 6);
+            exact_offset(xi, yi, xs[u], ys[u], P->scale2e, X, Y);
+        }
+    }
+    __device__ __forceinline__ void exact(int j, df& X, df& Y, df& C) const
+    {
+        exact_xy(j, X, Y);
+        C = add_rank(cost_df(X, Y, *P), smeta[j * BLK + tid] & 63);
     }
 };
 using LdsCols = LdsColsT<kFullBlock>;
 
-// Small-neighbourhood columns: the LDS store plus the monomials and costs of
-// all eight columns in registers, for pricing without LDS traffic.
+// Small-neighbourhood columns: eight, a compile-time count, plus their
+// predicted logits in registers (warm pass).
 template <int BLK>
 struct SmallColsT : LdsColsT<BLK> {
     static constexpr int KC = VRM_NSEG;
-    float v[VRM_NSEG][5];
-    float cc[VRM_NSEG];
-    float lg[VRM_NSEG];   // predicted logits (warm pass)
+    float lg[VRM_NSEG];
 };
 
 // Small-neighbourhood LPs (5 rows, up to 8 columns), one thread per particle;
 // the columns (column j = segment j) live in LDS.
 constexpr int kSmallBlock = 256;
 
-__global__ __launch_bounds__(kSmallBlock) void k_lp_small(const int32_t* __restrict__ perm,
+__global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_lp_small(const int32_t* __restrict__ perm,
                                                           const float* __restrict__ xs, const float* __restrict__ ys,
-                                                          const int32_t* __restrict__ ids,
-                                                          const int32_t* __restrict__ small_slot,
+                                                          const int32_t* __restrict__ ids, SmallRec rec,
                                                           const int32_t* __restrict__ q_small, Queues* qs,
                                                           int32_t* q_full, const float* __restrict__ gamma,
                                                           float* acc, LaunchParams P, StencilOut out, int apply,
@@ -266,66 +294,55 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(const int32_t* __restr
 {
     __shared__ float s_rx[8 * kSmallBlock];
     __shared__ float s_ry[8 * kSmallBlock];
+    __shared__ float s_xlo[8 * kSmallBlock];
+    __shared__ float s_ylo[8 * kSmallBlock];
     __shared__ float s_c[8 * kSmallBlock];
     __shared__ int s_meta[8 * kSmallBlock];
     const int tid = threadIdx.x;
-    const int32_t* queue = mode == kLpRetry ? q_retry : q_small;
     const int nitems = mode == kLpRetry ? qs->n_retry : qs->n_small;
+    const size_t cap = (size_t)rec.cap;
     const int stride = gridDim.x * blockDim.x;
     const int loops = (nitems + stride - 1) / stride;
     for (int it = 0; it < loops; ++it) {
         const int item = blockIdx.x * blockDim.x + tid + it * stride;
         const bool live = item < nitems;
         int st = 1, piv = 0, certified = 1, warm = 0;
-        int t = 0, i = 0;
+        int t = 0, i = 0, r = 0;
         if (live) {
-            t = queue[item];
-            i = perm[t];
-            const float xi = xs[t], yi = ys[t];
+            r = mode == kLpRetry ? q_retry[item] : item;   // the LP's column record
+            t = q_small[r];
+            i = rec.i[r];
+            const int packed = rec.rank[r];
             uint64_t dead = 0;
-            int idv[8];
+            const bool record = mode == kLpPlain && out.feat && item < out.max_rows;
+            uint16_t* frow = record ? out.feat + (size_t)item * kMlpIn : nullptr;
+            if (record) feature_zero(frow);
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                int u = small_slot[(size_t)t * VRM_NSEG + s];
-                idv[s] = u >= 0 ? ids[u] : 0x7fffffff;
-                s_meta[s * kSmallBlock + tid] = u;
-                if (u < 0) dead |= 1ull << s;
-            }
-            const bool rec = mode == kLpPlain && out.feat && item < out.max_rows;
-            uint16_t* frow = rec ? out.feat + (size_t)item * kMlpIn : nullptr;
-            if (rec) feature_zero(frow);
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                int u = s_meta[s * kSmallBlock + tid];
-                float rx = 0.0f, ry = 0.0f, c = 0.0f;
+                const int pj = rec.pj[s * cap + r];
+                df X{rec.off[(4 * s + 0) * cap + r], rec.off[(4 * s + 1) * cap + r]};
+                df Y{rec.off[(4 * s + 2) * cap + r], rec.off[(4 * s + 3) * cap + r]};
+                float c = 0.0f;
                 int meta = 0;
-                if (u >= 0) {
-                    int rank = 0;
-#pragma unroll
-                    for (int o = 0; o < 8; ++o) rank += idv[o] < idv[s] ? 1 : 0;
-                    df X, Y;
-                    exact_offset(xi, yi, xs[u], ys[u], P.scale2e, X, Y);
+                if (pj >= 0) {
+                    const int rank = (packed >> (3 * s)) & 7;
                     df C = add_rank(cost_df(X, Y, P), rank);
-                    rx = X.hi;
-                    ry = Y.hi;
                     c = C.hi;
-                    meta = (int)(((unsigned)u << 6) | (unsigned)rank);
-                    if (rec) feature_slot(frow, s, rx * P.sc, ry * P.sc);
+                    meta = (int)(((unsigned)pj << 6) | (unsigned)rank);
+                    if (record) feature_slot(frow, s, X.hi * P.sc, Y.hi * P.sc);
+                } else {
+                    dead |= 1ull << s;
                 }
-                s_rx[s * kSmallBlock + tid] = rx;
-                s_ry[s * kSmallBlock + tid] = ry;
+                s_rx[s * kSmallBlock + tid] = X.hi;
+                s_ry[s * kSmallBlock + tid] = Y.hi;
+                s_xlo[s * kSmallBlock + tid] = X.lo;
+                s_ylo[s * kSmallBlock + tid] = Y.lo;
                 s_c[s * kSmallBlock + tid] = c;
                 s_meta[s * kSmallBlock + tid] = meta;
             }
-            if (rec) feature_q(frow, P.q);
+            if (record) feature_q(frow, P.q);
             SmallColsT<kSmallBlock> cs;
-            static_cast<LdsColsT<kSmallBlock>&>(cs) = {8, dead, s_rx, s_ry, s_c, s_meta, tid, xi, yi, xs, ys, &P};
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                float rx, ry;
-                cs.get(s, rx, ry, cs.cc[s]);
-                mono<5>(rx, ry, cs.v[s]);
-            }
+            static_cast<LdsColsT<kSmallBlock>&>(cs) = {8, dead, s_rx, s_ry, s_c, s_meta, tid, 0.0f, 0.0f, xs, ys, &P, s_xlo, s_ylo};
             float fv[8];
 #pragma unroll
             for (int s = 0; s < 8; ++s) fv[s] = 0.0f;
@@ -337,13 +354,13 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(const int32_t* __restr
             };
             const bool warm_pass = mode == kLpWarm && out.pred;
             if (warm_pass) {
-                const float4* lg4 = reinterpret_cast<const float4*>(out.pred + (size_t)item * VRM_NSEG);
+                const float4* lg4 = reinterpret_cast<const float4*>(out.pred + (size_t)r * VRM_NSEG);
                 const float4 a = lg4[0], b = lg4[1];
                 cs.lg[0] = a.x, cs.lg[1] = a.y, cs.lg[2] = a.z, cs.lg[3] = a.w;
                 cs.lg[4] = b.x, cs.lg[5] = b.y, cs.lg[6] = b.z, cs.lg[7] = b.w;
             }
             st = solve_lp<5>(cs, P, store, fii, piv, certified, warm_pass, nullptr, warm);
-            if (rec) {
+            if (record) {
                 float* lab = out.lab + (size_t)item * kMlpOut;
 #pragma unroll
                 for (int s = 0; s < kMlpSlots; ++s) {
@@ -356,9 +373,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(const int32_t* __restr
                 float g = gamma[i];
 #pragma unroll
                 for (int s = 0; s < 8; ++s) {
-                    int u = (int)((unsigned)s_meta[s * kSmallBlock + tid] >> 6);
                     bool alive = !((dead >> s) & 1ull);
-                    int pj = alive ? perm[u] : -1;
+                    int pj = alive ? (int)((unsigned)s_meta[s * kSmallBlock + tid] >> 6) : -1;
                     if (apply && fv[s] != 0.0f) atomicAdd(&acc[pj], fv[s] * g);
                     if (out.small_f) {
                         out.small_idx[(size_t)i * VRM_NSEG + s] = pj;
@@ -387,7 +403,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(const int32_t* __restr
         if (fail) q_full[p] = t;
         bool retry = live && st == 4;
         int pr = wave_append(&qs->n_retry, retry);
-        if (retry) q_retry[pr] = t;
+        if (retry) q_retry[pr] = r;
     }
 }
 
@@ -553,7 +569,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
                 if (rec && j < kMlpSlots) feature_slot(frow, j, X.hi * P.sc, Y.hi * P.sc);
             }
             if (rec) feature_q(frow, P.q);
-            LdsCols cs{k, 0ull, s_rx, s_ry, s_c, s_meta, tid, xi, yi, xs, ys, &P};
+            LdsCols cs{k, 0ull, s_rx, s_ry, s_c, s_meta, tid, xi, yi, xs, ys, &P, nullptr, nullptr};
             float fii = 0.0f;
             const float g_i = gamma[i];
             int nz = 0;
@@ -681,8 +697,8 @@ int vrm_small_nbhd_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchP
     if (n <= 0) return VRM_OK;
     int nb = (n + 255) / 256;
     hipLaunchKernelGGL(k_small_nbhd, dim3(nb), dim3(256), 0, c->stream, n, c->perm, c->xs, c->ys, c->ids,
-                       c->cell_start, c->diffused, c->grid, lp, (int32_t*)nullptr, (int32_t*)nullptr,
-                       (int32_t*)nullptr, c->queues, small_idx, kfull, kfull != nullptr ? 1 : 0);
+                       c->cell_start, c->diffused, c->grid, lp, SmallRec{}, (int32_t*)nullptr, (int32_t*)nullptr,
+                       c->queues, small_idx, kfull, kfull != nullptr ? 1 : 0);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }
@@ -711,7 +727,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
     {
         ScopedTimer tm(c, VRM_T_NBHD);
         hipLaunchKernelGGL(k_small_nbhd, dim3(nb), dim3(256), 0, c->stream, n, c->perm, c->xs, c->ys, c->ids,
-                           c->cell_start, c->diffused, c->grid, lp, c->small_slot, c->q_small, c->q_full, c->queues,
+                           c->cell_start, c->diffused, c->grid, lp, c->srec, c->q_small, c->q_full, c->queues,
                            (int32_t*)nullptr, (int32_t*)nullptr, 0);
     }
     VRM_HIP(hipGetLastError());
@@ -721,8 +737,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         ScopedTimer tm(c, VRM_T_MLP);
         int r;
         if (lp.m == 5) {
-            r = vrm_mlp_infer_small_run(c, n, &c->queues->n_small, c->q_small, c->small_slot, c->xs, c->ys,
-                                        (float)lp.h, lp.q, c->pred);
+            r = vrm_mlp_infer_small_run(c, n, &c->queues->n_small, c->srec, lp.sc, lp.q, c->pred);
         } else {
             hipLaunchKernelGGL(k_feat_full, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->xs, c->ys, c->ids,
                                c->cell_start, c->grid, c->q_full, c->queues, lp, c->feat);
@@ -739,7 +754,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
             ScopedTimer tm(c, VRM_T_LP_SMALL);
             for (int mode = first; mode <= (warm ? kLpRetry : kLpPlain); ++mode) {
                 hipLaunchKernelGGL(k_lp_small, dim3(lp_grid_small(n)), dim3(kSmallBlock), 0, c->stream, c->perm, c->xs,
-                                   c->ys, c->ids, c->small_slot, c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc,
+                                   c->ys, c->ids, c->srec, c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc,
                                    lp, out, apply, c->counters, mode, c->q_retry);
                 VRM_HIP(hipGetLastError());
             }

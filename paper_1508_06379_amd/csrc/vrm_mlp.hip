@@ -30,12 +30,20 @@ __device__ __forceinline__ uint16_t to_bf16(float f)
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU in its tanh form: z sigma(2u) with u = sqrt(2/pi) (z + 0.044715 z^3)
+// (0.5 z (1 + tanh u)); one exponential and one reciprocal
+__device__ __forceinline__ float gelu(float z)
+{
+    const float u = z * (0.7978845608028654f + 0.0356774081363001f * z * z);
+    return z * __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));
+}
 __device__ __forceinline__ float gelu_grad(float z)
 {
-    float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
-    float pdf = 0.3989422804014327f * __expf(-0.5f * z * z);
-    return cdf + z * pdf;
+    const float z2 = z * z;
+    const float u = z * (0.7978845608028654f + 0.0356774081363001f * z2);
+    const float s = __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));   // (1 + tanh u) / 2
+    const float du = 0.7978845608028654f + 0.1070322244089003f * z2;
+    return s + 2.0f * z * s * (1.0f - s) * du;
 }
 
 constexpr int TM = 64, TN = 64, TK = 32, KPAD = 8;
@@ -308,63 +316,39 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int rows, const int* rows_dev
     }
 }
 
-// Inference for the queued small-neighbourhood LPs with the network input
-// built in LDS from the particle positions (slot s = segment s: offset / h
-// and mask; q - 2), and only the logits of the eight columns written:
-// L[item][8].  The gathers of the next tile are issued before the current
-// tile's products, so their latency overlaps the matrix work.
-__global__ __launch_bounds__(256) void k_mlp_infer_small(const int* rows_dev, const int32_t* __restrict__ q_small,
-                                                         const int32_t* __restrict__ small_slot,
-                                                         const float* __restrict__ xs, const float* __restrict__ ys,
-                                                         float h, int q, const uint16_t* __restrict__ wt,
-                                                         const float* __restrict__ w, float* __restrict__ L)
+// Inference for the queued small-neighbourhood LPs, with the network input
+// built in LDS from their column records (slot s = segment s: exact offset /
+// h and mask; q - 2), and only the logits of the eight columns written:
+// L[item][8].
+__global__ __launch_bounds__(256) void k_mlp_infer_small(const int* rows_dev, SmallRec rec, float sc, int q,
+                                                         const uint16_t* __restrict__ wt, const float* __restrict__ w,
+                                                         float* __restrict__ L)
 {
     __shared__ __attribute__((aligned(16))) uint16_t Ta[FR * FKP];
     __shared__ __attribute__((aligned(16))) uint16_t Tb[FR * FKP];
     const int rows = *rows_dev;
+    const size_t cap = (size_t)rec.cap;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    constexpr int kPer = FR * VRM_NSEG / 256;   // (row, slot) entries of a thread
-    // offsets of this thread's entries of the tile at r0: NaN = no column, row out of range = no row
-    float gx[kPer], gy[kPer];
-    bool grow[kPer];
-    auto gather = [&](int r0) {
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int e = tid + 256 * k, r = e / VRM_NSEG, s = e % VRM_NSEG;
-            const int item = r0 + r;
-            grow[k] = item < rows;
-            gx[k] = gy[k] = __builtin_nanf("");
-            if (grow[k]) {
-                const int t = q_small[item];
-                const int u = small_slot[(size_t)t * VRM_NSEG + s];
-                if (u >= 0) {
-                    gx[k] = (xs[u] - xs[t]) / h;
-                    gy[k] = (ys[u] - ys[t]) / h;
-                }
-            }
-        }
-    };
-    const int stride = gridDim.x * FR;
-    int r0 = blockIdx.x * FR;
-    if (r0 < rows) gather(r0);
-    for (; r0 < rows; r0 += stride) {
+    for (int r0 = blockIdx.x * FR; r0 < rows; r0 += gridDim.x * FR) {
         for (int e = tid; e < FR * kMlpIn / 8; e += 256) {
             int r = e / (kMlpIn / 8), c8 = (e % (kMlpIn / 8)) * 8;
             *reinterpret_cast<uint4*>(&Ta[r * FKP + c8]) = uint4{0u, 0u, 0u, 0u};
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int e = tid + 256 * k, r = e / VRM_NSEG, s = e % VRM_NSEG;
-            if (grow[k] && gx[k] == gx[k]) {
-                Ta[r * FKP + 2 * s] = to_bf16(gx[k]);
-                Ta[r * FKP + 2 * s + 1] = to_bf16(gy[k]);
-                Ta[r * FKP + 2 * kMlpSlots + s] = 0x3f80;   // 1.0
+        for (int e = tid; e < FR * VRM_NSEG; e += 256) {
+            // consecutive threads take consecutive rows of one segment plane
+            const int s = e / FR, r = e % FR;
+            const int item = r0 + r;
+            if (item < rows) {
+                if (rec.pj[s * cap + item] >= 0) {
+                    Ta[r * FKP + 2 * s] = to_bf16(rec.off[(4 * s + 0) * cap + item] * sc);
+                    Ta[r * FKP + 2 * s + 1] = to_bf16(rec.off[(4 * s + 2) * cap + item] * sc);
+                    Ta[r * FKP + 2 * kMlpSlots + s] = 0x3f80;   // 1.0
+                }
+                if (s == 0) Ta[r * FKP + 3 * kMlpSlots] = q == 3 ? 0x3f80 : 0;
             }
-            if (grow[k] && s == 0) Ta[r * FKP + 3 * kMlpSlots] = q == 3 ? 0x3f80 : 0;
         }
         __syncthreads();
-        if (r0 + stride < rows) gather(r0 + stride);
         mlp_hidden(Ta, Tb, wt, w, tid);
         if (wv == 0) {
             f32x4 acc[4];
@@ -502,15 +486,13 @@ int vrm_mlp_forward(vrm_ctx* c, const uint16_t* X, int rows, float* Y, const int
 }
 
 // fused forward for inference (no intermediate buffers); rows may be an upper bound with rows_dev
-int vrm_mlp_infer_small_run(vrm_ctx* c, int rows, const int* rows_dev, const int32_t* q_small,
-                            const int32_t* small_slot, const float* xs, const float* ys, float h, int q, float* L)
+int vrm_mlp_infer_small_run(vrm_ctx* c, int rows, const int* rows_dev, const SmallRec& rec, float sc, int q, float* L)
 {
     if (rows <= 0) return VRM_OK;
     MlpState* m = c->mlp;
     int tiles = (rows + FR - 1) / FR;
-    int grid = tiles < 256 * 4 ? tiles : 256 * 4;   // four blocks per CU are resident
-    hipLaunchKernelGGL(k_mlp_infer_small, dim3(grid), dim3(256), 0, c->stream, rows_dev, q_small, small_slot, xs, ys,
-                       h, q, m->wt, m->w, L);
+    int grid = tiles < 256 * 2 ? tiles : 256 * 2;
+    hipLaunchKernelGGL(k_mlp_infer_small, dim3(grid), dim3(256), 0, c->stream, rows_dev, rec, sc, q, m->wt, m->w, L);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }

@@ -307,12 +307,16 @@ struct ThreadSimplex {
             return false;
         };
         if constexpr (CS::KC > 0) {
-            // columns with their monomials in registers (compile-time count)
+            // compile-time column count: the loop is unrolled
 #pragma unroll
             for (int j = 0; j < CS::KC; ++j) {
                 if ((excl >> j) & 1ull) continue;
+                float rx, ry, c;
+                cs.get(j, rx, ry, c);
+                float v[M];
+                mono<M>(rx, ry, v);
                 float d, sc;
-                reduced(cs.v[j], cs.cc[j], y, p2, d, sc);
+                reduced(v, c, y, p2, d, sc);
                 if (consider(j, d, sc)) break;
             }
         } else {
@@ -479,8 +483,12 @@ struct ThreadSimplex {
 #pragma unroll
                         for (int j = 0; j < CS::KC; ++j) {
                             if ((excl >> j) & 1ull) continue;
+                            float rx, ry, c;
+                            cs.get(j, rx, ry, c);
+                            float v[M];
+                            mono<M>(rx, ry, v);
                             float d, sc;
-                            reduced(cs.v[j], cs.cc[j], yf, true, d, sc);
+                            reduced(v, c, yf, true, d, sc);
                             dual_ok = dual_ok && !(d < kFastMargin * sc);
                         }
                     } else {
