@@ -83,7 +83,65 @@ def run_gpu(wl, steps, warmup, theta=None):
                 final=c1)
 
 
-def roofline(wl, res):
+# training geometry of the warm-start network for each workload (other seeds, same generator)
+TRAINING = {
+    "lamb_oseen_h0.01_q2": dict(kind="lamb_oseen", h=0.01, q=2),
+    "lamb_oseen_h0.01_q3": dict(kind="lamb_oseen", h=0.01, q=3),
+    "vortices64_h0.005": dict(kind="vortices", h=0.02, q=2),
+    "vortices256_h0.004_q3": dict(kind="vortices_dense", h=0.02, q=3),
+}
+
+
+def train_network(name, seeds, epochs):
+    """Warm-start network trained on the GPU from the plain solver's stencils of
+    `seeds` snapshots of the workload's generator (seeds 1000+, never the timed one)."""
+    import torch
+    import paper_1508_06379_amd as vrm
+    import paper_1508_06379_amd.learned as L
+    spec = TRAINING[name]
+    t0 = time.perf_counter()
+    X, Y = L.collect(lambda s: workloads.training_snapshot(1000 + s, h=spec["h"], q=spec["q"], kind=spec["kind"]),
+                     range(seeds))
+    t1 = time.perf_counter()
+    ctx = vrm.Context(64)
+    hist = L.train(ctx, X, Y, epochs=epochs, batch=4096, lr=1e-3, weight_decay=1e-4, seed=spec["q"])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    acc = L.basis_accuracy(ctx, X[:200000], Y[:200000], spec["q"])
+    theta = torch.zeros(vrm.MLP_PARAMS, device="cuda")
+    ctx.vrm_mlp_read(theta)
+    info = {"rows": int(X.shape[0]), "snapshots": seeds, "generator": spec, "epochs": epochs,
+            "loss_first_last": [round(hist[0], 4), round(hist[-1], 4)], "train_basis_accuracy": round(acc, 4),
+            "collect_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)}
+    return theta, info
+
+
+def kernel_sources_sha():
+    """SHA-256 of the HIP sources: stored byte counts are used only for the build they were taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1508_06379_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, group):
+    """HBM bytes per launch of `group` from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    summarised under profiles/ (copy-calibrated), or None if the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(workload)
+    if not rec or rec.get("group") != group or rec.get("sources_sha256") != kernel_sources_sha():
+        return None
+    return rec["bytes_per_launch"]
+
+
+def roofline(wl, res, workload):
     """Roofline of the kernel group with the largest time in the timed region."""
     T = res["timers"]
     cand = {k: v for k, v in T.items() if k not in ("insert",) and v[1] > 0}
@@ -93,25 +151,26 @@ def roofline(wl, res):
     c = res["counters"]
     m = 5 if wl.q == 2 else 9
     if dom in ("lp_small", "lp_full"):
-        # dense tableau simplex: one multiply-add per tableau entry and pivot,
-        # tableau m x (k + 1); k = 8 (small) or the mean complete-neighbourhood size
+        # revised simplex with an explicit m x m inverse, per pivot: reduced costs of
+        # the k columns (2 m k), prices, entering column and rank-one update of the
+        # inverse (2 m^2 each); k = 8 (small) or the mean complete-neighbourhood size
         nlp = c["n_small"] if dom == "lp_small" else max(1, c["n_full"])
         k = 8.0 if dom == "lp_small" else c["full_cols"] / max(1, c["n_full"])
-        flops = c["pivots"] * 2.0 * m * (k + 1.0)
+        flops = c["pivots"] * (2.0 * m * k + 6.0 * m * m)
         per_launch = flops / launches
         ach = per_launch / avg_s / 1e12
         return {"kernel": dom, "bound": "alu", "achieved": ach, "peak": PEAK_FP32_NONPACKED_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_NONPACKED_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_NONPACKED_TFLOPS, "traffic": measured_traffic(workload, dom),
                 "avg_launch_ms": avg_s * 1e3, "launches": launches,
-                "flop_model": f"pivots x 2 m (k+1), m={m}, k={k:.2f}, {c['pivots'] / max(1, nlp):.2f} pivots/LP"}
+                "flop_model": f"pivots x (2 m k + 6 m^2), m={m}, k={k:.2f}, {c['pivots'] / max(1, nlp):.2f} pivots/LP"}
     npart = 0.5 * (res["n_start"] + res["n_end"])
     per_launch = BYTES_PER_PARTICLE[dom] * npart
     ach = per_launch / avg_s / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": ach / PEAK_HBM_GBS, "traffic": None, "avg_launch_ms": avg_s * 1e3, "launches": launches}
+            "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic(workload, dom), "avg_launch_ms": avg_s * 1e3, "launches": launches}
 
 
-def cpu_baseline(wl, budget_s=15.0, max_steps=100):
+def cpu_baseline(wl, budget_s=15.0, max_steps=10000):
     """The FP64 oracle on the host cores, on the first steps of the same run."""
     import oracle
     oracle.build()
@@ -139,6 +198,12 @@ def main():
     ap.add_argument("--workload", default="lamb_oseen_h0.01_q2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--solver", default="both", choices=["both", "plain", "learned"],
+                    help="plain batched solver, learned warm start, or both on the same workload")
+    ap.add_argument("--train-snapshots", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also copy a 256 MiB buffer five times (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the redistribution path has no multi-GPU mode "
@@ -146,25 +211,57 @@ def main():
         sys.exit(2)
     wl = WORKLOADS[args.workload]()
     log(f"workload {args.workload}: N={wl.n} h={wl.h} q={wl.q} dt={wl.dt}")
-    res = run_gpu(wl, args.steps, args.warmup)
+    runs = {}
+    if args.solver in ("both", "plain"):
+        runs["plain"] = run_gpu(wl, args.steps, args.warmup)
+    train_info = None
+    if args.solver in ("both", "learned"):
+        theta, train_info = train_network(args.workload, args.train_snapshots, args.epochs)
+        log(f"network: {train_info}")
+        runs["learned"] = run_gpu(wl, args.steps, args.warmup, theta=theta)
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 5 copies of {src.numel() * 4} bytes")
+    main_solver = "plain" if "plain" in runs else "learned"
+    res = runs[main_solver]
     c = res["counters"]
     value = c["redistributions"] / res["elapsed"]
-    log(f"elapsed {res['elapsed']:.4f} s, counters {c}, timers {res['timers']}")
-    rl = roofline(wl, res)
+    for k, r in runs.items():
+        log(f"{k}: elapsed {r['elapsed']:.4f} s, counters {r['counters']}, timers {r['timers']}")
+    rl = roofline(wl, res, args.workload)
     line = {
-        "metric": "particle redistributions/s (plain batched GPU solver), FP32, moments <= 1e-6",
+        "metric": "particle redistributions/s (learned warm start vs plain), FP32, moments <= 1e-6",
         "value": value, "unit": "redistributions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": res["elapsed"] * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "h": wl.h, "q": wl.q, "n_start": res["n_start"],
-                   "n_end": res["n_end"], "dt": wl.dt, "solver": "plain"},
+                   "n_end": res["n_end"], "dt": wl.dt, "solver": main_solver},
         "roofline": rl,
         "timers_ms": {k: round(v[0], 4) for k, v in res["timers"].items()},
         "lp": {"small": c["n_small"], "full": c["n_full"], "infeasible": c["n_infeasible"],
                "uncertified": c["n_uncertified"], "pivots": c["pivots"]},
     }
+    if "learned" in runs:
+        r = runs["learned"]
+        cl = r["counters"]
+        lv = cl["redistributions"] / r["elapsed"]
+        nlp = max(1, cl["warm_hit"] + cl["warm_phase2"] + cl["warm_cold"])
+        line["learned"] = {
+            "value": lv, "ms_per_step": r["elapsed"] * 1e3 / args.steps,
+            "vs_plain": lv / value if main_solver == "plain" else None,
+            "warm_start": {"optimal_from_prediction": cl["warm_hit"] / nlp, "phase2_from_prediction": cl["warm_phase2"] / nlp,
+                           "left_for_cold_solve": cl["warm_cold"] / nlp},
+            "pivots": cl["pivots"], "uncertified": cl["n_uncertified"],
+            "timers_ms": {k: round(v[0], 4) for k, v in r["timers"].items()},
+            "network": train_info,
+        }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl, budget_s=args.cpu_budget, max_steps=args.steps)
+        line["cpu_baseline"] = cpu_baseline(wl, budget_s=args.cpu_budget)
     print(json.dumps(line), flush=True)
 
 
