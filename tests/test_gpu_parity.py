@@ -319,3 +319,30 @@ def test_all_zero_circulation(vrm):
     cnt = ctx.vrm_read_counters()
     assert cnt["n_diffused"] == 0 and cnt["n_inserted"] == 0 and cloud.n == wl.n
     assert float(cloud.gamma[:wl.n].abs().max()) == 0.0
+
+
+# ------------------------------------------------------------------ convergence
+def test_gpu_lamb_oseen_second_order(vrm):
+    """Sec. 5.1 on the GPU path: jittered Lamb-Oseen clouds (the h = 0.01 workload's
+    generator) at h = 0.04, 0.02, 0.01, SSP-RK3 with insertion to T = 0.16; the weak
+    error against the closed-form solution falls at least at second order in h (one
+    order above the proven bound, as the paper observes; measured 2.1 and 2.9)."""
+    from test_oracle_pins import _weak_error
+    T = 0.16
+    errs = []
+    for h in (0.04, 0.02, 0.01):
+        wl = workloads.config_jittered(h=h, q=2, seed=2)
+        _say("case convergence h", h)
+        cloud = _gpu_cloud(vrm, wl, cap_factor=3)
+        ctx = vrm.Context(cloud.capacity)
+        P = vrm.params_of(wl)
+        t = wl.t0
+        for _ in range(int(round(T / wl.dt))):
+            ctx.vrm_step(cloud, P, None, t)
+            t += wl.dt
+        torch.cuda.synchronize()
+        x, y, g, _ = cloud.numpy()
+        errs.append(_weak_error(x.astype(np.float64), y.astype(np.float64), g.astype(np.float64), wl.t0 + T, wl.nu))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    _say("weak errors", errs, "orders", orders)
+    assert ((orders > 1.8) & (orders < 3.5)).all(), (errs, orders)
