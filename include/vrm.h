@@ -111,7 +111,9 @@ typedef struct {
     int64_t full_cols;        /* sum of the column counts of complete-neighbourhood LPs (cumulative) */
     int64_t warm_hit;         /* warm-started LPs whose predicted basis was optimal (cumulative) */
     int64_t warm_phase2;      /* warm-started LPs that needed phase-II pivots from the predicted basis */
-    int64_t warm_cold;        /* predictions rejected (infeasible or incomplete basis): cold start */
+    int64_t warm_cold;        /* predictions given up by the warm pass (rejected crash basis or more than a
+                                 few phase-II pivots): solved by the cold pass (cumulative) */
+    int64_t graph_replays;    /* vrm_step stage sequences replayed from the recorded graph (cumulative; host count) */
 } vrm_counters;
 
 /* Create a context on `device` that enqueues on `stream` (a hipStream_t; NULL
@@ -177,8 +179,20 @@ int vrm_rk_stage(vrm_ctx* ctx, vrm_cloud* cloud, const float* u_dev, const float
  * vortex field of vrm_vortex_velocity at the stage time (t, t + dt, t + dt/2);
  * otherwise zero.  The context caches the cell list and the cell order of the
  * cloud between calls: a caller that changes positions or the count itself
- * must not rely on that cache (a different cloud or count resets it). */
+ * must not rely on that cache (a different cloud or count resets it).
+ * The three stages are recorded once as a HIP graph (on a stream of the
+ * context's own) and replayed on the context's stream at every later call
+ * with the same cloud, parameters, vortex table and warm-start and timing
+ * settings; the stage kernels read N on the device, and the graph is
+ * recorded again when N outgrows the bound its launches were sized for.
+ * Results are those of the direct launches (up to the order of the
+ * floating-point atomic sums).  Synchronises once (insertion). */
 int vrm_step(vrm_ctx* ctx, vrm_cloud* cloud, const vrm_params* p, const float* vort_dev, int32_t n_vort, double t);
+
+/* Enable (default) or disable the graph replay of vrm_step's stages; with it
+ * disabled every stage kernel is launched directly.  Disabling synchronises
+ * the stream and releases the recorded graph. */
+int vrm_set_graph(vrm_ctx* ctx, int enable);
 
 /* Sec. 2 eqs. cond_two/cond_alpha, Sec. 3.4: FP64 checks of a stencil set.
  * Writes, to report_dev[4] (device doubles): the maximum over particles of

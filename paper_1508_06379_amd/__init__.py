@@ -58,14 +58,16 @@ class vrm_counters(ctypes.Structure):
                 ("n_truncated", ctypes.c_int32), ("n_grid_clamped", ctypes.c_int32),
                 ("pivots", ctypes.c_int64), ("redistributions", ctypes.c_int64),
                 ("capacity_needed", ctypes.c_int32), ("mis_rounds", ctypes.c_int32), ("full_cols", ctypes.c_int64),
-                ("warm_hit", ctypes.c_int64), ("warm_phase2", ctypes.c_int64), ("warm_cold", ctypes.c_int64)]
+                ("warm_hit", ctypes.c_int64), ("warm_phase2", ctypes.c_int64), ("warm_cold", ctypes.c_int64),
+                ("graph_replays", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 EXPORTS = ["vrm_create", "vrm_destroy", "vrm_select_diffused", "vrm_set_diffused", "vrm_build_neighbourhoods",
-           "vrm_insert_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_step", "vrm_verify", "vrm_read_counters",
+           "vrm_insert_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_step", "vrm_set_graph", "vrm_verify",
+           "vrm_read_counters",
            "vrm_vortex_velocity", "vrm_timing", "vrm_read_timing", "vrm_mlp_load", "vrm_mlp_read",
            "vrm_set_warm_start", "vrm_collect_training", "vrm_mlp_train_step", "vrm_mlp_infer", "vrm_gemm_bf16",
            "vrm_last_error", "vrm_status_string"]
@@ -94,6 +96,7 @@ def lib():
         L.vrm_rk_stage.argtypes = [vp, ctypes.POINTER(vrm_cloud), vp, vp, ctypes.POINTER(vrm_params), ctypes.c_int]
         L.vrm_step.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params), vp, ctypes.c_int32,
                                ctypes.c_double]
+        L.vrm_set_graph.argtypes = [vp, ctypes.c_int]
         L.vrm_verify.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params),
                                  ctypes.POINTER(vrm_stencils), vp]
         L.vrm_read_counters.argtypes = [vp, ctypes.POINTER(vrm_counters)]
@@ -247,6 +250,9 @@ class Context:
     def vrm_step(self, cloud: Cloud, p: vrm_params, vort=None, t=0.0):
         _check(lib().vrm_step(self.handle, ctypes.byref(cloud.c), ctypes.byref(p), _ptr(vort),
                               int(vort.shape[0]) if vort is not None else 0, float(t)))
+
+    def vrm_set_graph(self, enable: bool):
+        _check(lib().vrm_set_graph(self.handle, 1 if enable else 0))
 
     def vrm_verify(self, cloud: Cloud, p: vrm_params, st: Stencils, report):
         sc = st.c() if st is not None else None

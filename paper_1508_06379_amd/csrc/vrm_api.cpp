@@ -3,6 +3,7 @@
 // in include/vrm.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -153,6 +154,7 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
     VRM_HIP(hipSetDevice(device));
     vrm_ctx* c = new vrm_ctx();
     std::memset(c, 0, sizeof(*c));
+    c->graph_enabled = 1;
     c->device = device;
     c->stream = (hipStream_t)stream;
     c->capacity = capacity;
@@ -235,6 +237,10 @@ int vrm_destroy(vrm_ctx* c)
                     c->akey, c->aidx, c->tmp_f, c->tmp_i, c->tmp_u8, c->verify_buf, c->sort_tmp};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->t_dev) (void)hipFree(c->t_dev);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->feat) (void)hipFree(c->feat);
     if (c->u_tmp) (void)hipFree(c->u_tmp);
     if (c->pred) (void)hipFree(c->pred);
@@ -360,31 +366,32 @@ int vrm_solve_fractions(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, vr
     return vrm_stencil_run(c, cl, c->n, L, out, 0);
 }
 
-int vrm_rk_stage(vrm_ctx* c, vrm_cloud* cl, const float* u_dev, const float* v_dev, const vrm_params* p, int stage)
+}  // extern "C"
+
+namespace {
+
+// One SSP-RK3 stage as launches only (no host synchronisation, so that it can
+// be captured): the stage kernels read the particle count on the device and
+// size their grids for nb >= N.
+int stage_launch(vrm_ctx* c, vrm_cloud* cl, const float* u_dev, const float* v_dev, const vrm_params* p, int stage,
+                 int nb)
 {
-    int r = check_cloud(c, cl);
-    if (!r) r = check_params(p);
-    if (!r) r = cached_n(c, cl);
-    if (!r && (stage < 0 || stage > 2)) r = vrm_fail(VRM_E_ARG, "stage must be 0, 1 or 2 (got %d)", stage);
-    if (!r && ((u_dev == nullptr) != (v_dev == nullptr))) r = vrm_fail(VRM_E_ARG, "u and v must both be given or both NULL");
-    if (!r && stage > 0 && !c->base_valid) r = vrm_fail(VRM_E_STATE, "stage %d before stage 0", stage);
-    if (r) return r;
-    int n = c->n;
+    int r;
     vrm::LaunchParams L = launch_params(p);
     if (stage == 0) {
-        r = vrm_save_base_run(c, cl, n);
+        r = vrm_save_base_run(c, cl, nb);
         if (r) return r;
         c->base_valid = 1;
     }
     if (!c->cells_valid) {
-        r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, n, L);
+        r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, nb, L, cl->n_dev);
         if (r) return r;
         c->cells_valid = 1;
     }
-    r = vrm_stencil_run(c, cl, n, L, nullptr, 1);
+    r = vrm_stencil_run(c, cl, nb, L, nullptr, 1);
     if (!r) {
         vrm::ScopedTimer tm(c, VRM_T_COMBINE);
-        r = vrm_combine_run(c, cl, n, u_dev, v_dev, p->dt, L.lam, stage);
+        r = vrm_combine_run(c, cl, nb, u_dev, v_dev, p->dt, L.lam, stage);
     }
     if (r) return r;
     if (u_dev) {
@@ -395,10 +402,109 @@ int vrm_rk_stage(vrm_ctx* c, vrm_cloud* cl, const float* u_dev, const float* v_d
     return VRM_OK;
 }
 
+// The three stages of a step after insertion; with vortices, the stage times
+// are t + c_s dt, or *t_dev + c_s dt when t_dev is given.
+int step_stages(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p, const float* vort_dev, int32_t n_vort, double t,
+                const double* t_dev, int nb)
+{
+    static const double tc[3] = {0.0, 1.0, 0.5};
+    for (int s = 0; s < 3; ++s) {
+        const float *u = nullptr, *v = nullptr;
+        if (n_vort > 0) {
+            const double ts = t_dev ? tc[s] * p->dt : t + tc[s] * p->dt;
+            int r = vrm_velocity_run(c, cl, nb, vort_dev, n_vort, p->nu, ts, c->u_tmp, c->v_tmp, t_dev);
+            if (r) return r;
+            u = c->u_tmp;
+            v = c->v_tmp;
+        }
+        int r = stage_launch(c, cl, u, v, p, s, nb);
+        if (r) return r;
+    }
+    return VRM_OK;
+}
+
+__global__ void k_set_time(double* t_dev, double t) { *t_dev = t; }
+
+// Timer events of the last graph replay into the accumulated totals.
+int collect_graph_timing(vrm_ctx* c)
+{
+    if (!c->graph_pending) return VRM_OK;
+    c->graph_pending = 0;
+    const int s0 = vrm::kMaxTimed - vrm::kGraphTimed;
+    VRM_HIP(hipEventSynchronize(c->ev_stop[s0 + c->graph_slots - 1]));
+    for (int k = s0; k < s0 + c->graph_slots; ++k) {
+        float ms = 0.0f;
+        VRM_HIP(hipEventElapsedTime(&ms, c->ev_start[k], c->ev_stop[k]));
+        c->acc_ms[c->ev_group[k]] += ms;
+        c->acc_n[c->ev_group[k]] += 1;
+        c->launches[c->ev_group[k]] += 1;
+    }
+    return VRM_OK;
+}
+
+void drop_graph(vrm_ctx* c)
+{
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+// What a captured step depends on besides the device state it reads.
+void graph_key(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, const float* vort_dev, int32_t n_vort,
+               unsigned char (&key)[160])
+{
+    std::memset(key, 0, sizeof(key));
+    size_t o = 0;
+    auto put = [&](const void* v, size_t n) {
+        std::memcpy(key + o, v, n);
+        o += n;
+    };
+    put(cl, sizeof(vrm_cloud));
+    put(p, sizeof(vrm_params));
+    put(&vort_dev, sizeof(vort_dev));
+    put(&n_vort, sizeof(n_vort));
+    int flags[3] = {c->timing, c->warm, c->mlp ? c->mlp->loaded : 0};
+    put(flags, sizeof(flags));
+    const void* mp = c->mlp;
+    put(&mp, sizeof(mp));
+}
+
+}  // namespace
+
+extern "C" {
+
+int vrm_rk_stage(vrm_ctx* c, vrm_cloud* cl, const float* u_dev, const float* v_dev, const vrm_params* p, int stage)
+{
+    int r = check_cloud(c, cl);
+    if (!r) r = check_params(p);
+    if (!r) r = cached_n(c, cl);
+    if (!r && (stage < 0 || stage > 2)) r = vrm_fail(VRM_E_ARG, "stage must be 0, 1 or 2 (got %d)", stage);
+    if (!r && ((u_dev == nullptr) != (v_dev == nullptr))) r = vrm_fail(VRM_E_ARG, "u and v must both be given or both NULL");
+    if (!r && stage > 0 && !c->base_valid) r = vrm_fail(VRM_E_STATE, "stage %d before stage 0", stage);
+    if (r) return r;
+    return stage_launch(c, cl, u_dev, v_dev, p, stage, c->n);
+}
+
+int vrm_set_graph(vrm_ctx* c, int enable)
+{
+    if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
+    c->graph_enabled = enable ? 1 : 0;
+    if (!enable) {
+        VRM_HIP(hipStreamSynchronize(c->stream));
+        int r = collect_graph_timing(c);
+        drop_graph(c);
+        if (r) return r;
+    }
+    return VRM_OK;
+}
+
 int vrm_step(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p, const float* vort_dev, int32_t n_vort, double t)
 {
     if (n_vort < 0 || (n_vort > 0 && !vort_dev)) return vrm_fail(VRM_E_ARG, "vortex table");
-    int r = vrm_insert_particles(c, cl, p);
+    int r = vrm_insert_particles(c, cl, p);   // synchronises: the previous replay has finished
+    if (r) return r;
+    r = collect_graph_timing(c);
     if (r) return r;
     if (n_vort > 0 && !c->u_tmp) {
         void* q = nullptr;
@@ -406,18 +512,66 @@ int vrm_step(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p, const float* vort_d
         c->u_tmp = (float*)q;
         c->v_tmp = c->u_tmp + c->capacity;
     }
-    static const double tc[3] = {0.0, 1.0, 0.5};
-    for (int s = 0; s < 3; ++s) {
-        const float *u = nullptr, *v = nullptr;
-        if (n_vort > 0) {
-            r = vrm_velocity_run(c, cl, c->n, vort_dev, n_vort, p->nu, t + tc[s] * p->dt, c->u_tmp, c->v_tmp);
-            if (r) return r;
-            u = c->u_tmp;
-            v = c->v_tmp;
+    const int n = c->n;
+    // timer events recorded by graph nodes cannot be read back (hipEventElapsedTime rejects
+    // them), so timed steps launch their stages directly
+    if (!c->graph_enabled || c->timing || c->graph_failed[0] || n <= 0)
+        return step_stages(c, cl, p, vort_dev, n_vort, t, nullptr, n);
+
+    unsigned char key[160];
+    graph_key(c, cl, p, vort_dev, n_vort, key);
+    const int f0[3] = {c->cells_valid, c->sorted, c->base_valid};
+    if (!c->graph_exec || n > c->graph_nb || std::memcmp(key, c->graph_key, sizeof(key)) != 0 ||
+        f0[0] != 1 || f0[2] != 0) {
+        drop_graph(c);
+        if (!c->t_dev) {
+            void* q = nullptr;
+            VRM_HIP(hipMalloc(&q, 64));
+            c->t_dev = (double*)q;
         }
-        r = vrm_rk_stage(c, cl, u, v, p, s);
-        if (r) return r;
+        if (!c->cap_stream) VRM_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        const int nb = std::min(c->capacity, n + std::max(4096, n / 8));
+        // the stages are recorded on the capture stream and replayed on the context's stream
+        hipStream_t own = c->stream;
+        c->stream = c->cap_stream;
+        c->capturing = 1;
+        c->graph_slots = 0;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        int rr = VRM_OK;
+        if (e == hipSuccess) rr = step_stages(c, cl, p, vort_dev, n_vort, 0.0, c->t_dev, nb);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(c->stream, &g) : e;
+        c->capturing = 0;
+        c->stream = own;
+        hipGraphExec_t ex = nullptr;
+        if (e == hipSuccess && e2 == hipSuccess && rr == VRM_OK && g)
+            e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        const int f1[3] = {c->cells_valid, c->sorted, c->base_valid};
+        c->cells_valid = f0[0];
+        c->sorted = f0[1];
+        c->base_valid = f0[2];
+        if (e != hipSuccess || e2 != hipSuccess || rr != VRM_OK || !ex) {
+            // this runtime cannot capture the stages: launch them directly from now on
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            c->graph_failed[0] = 1;
+            c->graph_slots = 0;
+            return step_stages(c, cl, p, vort_dev, n_vort, t, nullptr, n);
+        }
+        c->graph = g;
+        c->graph_exec = ex;
+        c->graph_nb = nb;
+        std::memcpy(c->graph_key, key, sizeof(key));
+        std::memcpy(c->graph_flags, f1, sizeof(f1));
     }
+    hipLaunchKernelGGL(k_set_time, dim3(1), dim3(1), 0, c->stream, c->t_dev, t);
+    VRM_HIP(hipGetLastError());
+    VRM_HIP(hipGraphLaunch(c->graph_exec, c->stream));
+    c->graph_replays += 1;
+    c->graph_pending = c->timing && c->graph_slots > 0;
+    c->cells_valid = c->graph_flags[0];
+    c->sorted = c->graph_flags[1];
+    c->base_valid = c->graph_flags[2];
     return VRM_OK;
 }
 
@@ -438,6 +592,7 @@ int vrm_read_counters(vrm_ctx* c, vrm_counters* out)
     VRM_HIP(hipMemcpyAsync(out, c->counters, sizeof(vrm_counters), hipMemcpyDeviceToHost, c->stream));
     VRM_HIP(hipStreamSynchronize(c->stream));
     out->n = c->n;
+    out->graph_replays = c->graph_replays;
     return VRM_OK;
 }
 
@@ -534,9 +689,18 @@ int vrm_timing(vrm_ctx* c, int enable)
             VRM_HIP(hipEventCreate(&c->ev_stop[k]));
         }
     }
+    if (c->graph_pending) {
+        VRM_HIP(hipStreamSynchronize(c->stream));
+        int r = collect_graph_timing(c);
+        if (r) return r;
+    }
     c->timing = enable ? 1 : 0;
     c->ntimed = 0;
-    for (int g = 0; g < VRM_NTIMER; ++g) c->launches[g] = 0;
+    for (int g = 0; g < VRM_NTIMER; ++g) {
+        c->launches[g] = 0;
+        c->acc_ms[g] = 0.0;
+        c->acc_n[g] = 0;
+    }
     return VRM_OK;
 }
 
@@ -544,20 +708,24 @@ int vrm_read_timing(vrm_ctx* c, double* ms, int64_t* launches)
 {
     if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
     VRM_HIP(hipStreamSynchronize(c->stream));
+    int r = collect_graph_timing(c);
+    if (r) return r;
     double acc[VRM_NTIMER] = {0};
+    int64_t timed[VRM_NTIMER] = {0};
     for (int k = 0; k < c->ntimed; ++k) {
         float t = 0.0f;
         VRM_HIP(hipEventElapsedTime(&t, c->ev_start[k], c->ev_stop[k]));
         acc[c->ev_group[k]] += t;
+        timed[c->ev_group[k]] += 1;
     }
     int over = 0;
-    int64_t timed[VRM_NTIMER] = {0};
-    for (int k = 0; k < c->ntimed; ++k) timed[c->ev_group[k]] += 1;
     for (int g = 0; g < VRM_NTIMER; ++g) {
-        if (ms) ms[g] = acc[g];
+        if (ms) ms[g] = acc[g] + c->acc_ms[g];
         if (launches) launches[g] = c->launches[g];
-        over |= timed[g] != c->launches[g];
+        over |= timed[g] + c->acc_n[g] != c->launches[g];
         c->launches[g] = 0;
+        c->acc_ms[g] = 0.0;
+        c->acc_n[g] = 0;
     }
     c->ntimed = 0;
     return over ? 1 : VRM_OK;

@@ -29,8 +29,9 @@ __global__ void k_grid_reset(GridState* g)
 }
 
 __global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ x, const float* __restrict__ y, int n,
-                                              GridState* g)
+                                              const int32_t* __restrict__ n_dev, GridState* g)
 {
+    if (n_dev) n = *n_dev;
     uint32_t mnx = 0xffffffffu, mny = 0xffffffffu, mxx = 0u, mxy = 0u;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float xv = x[i], yv = y[i];
@@ -119,8 +120,10 @@ __global__ __launch_bounds__(256) void k_clear_cells(int32_t* start, const GridS
 }
 
 __global__ __launch_bounds__(256) void k_count(const float* __restrict__ x, const float* __restrict__ y, int n,
-                                               const GridState* gs, int32_t* start, int32_t* cell_of, int32_t* rank)
+                                               const int32_t* __restrict__ n_dev, const GridState* gs, int32_t* start,
+                                               int32_t* cell_of, int32_t* rank)
 {
+    if (n_dev) n = *n_dev;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     GridState g = *gs;
@@ -193,10 +196,12 @@ __global__ __launch_bounds__(256) void k_scan_final(int32_t* start, const GridSt
 
 __global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ x, const float* __restrict__ y,
                                                  const int32_t* __restrict__ id, int n,
+                                                 const int32_t* __restrict__ n_dev,
                                                  const int32_t* __restrict__ start, const int32_t* __restrict__ cell_of,
                                                  const int32_t* __restrict__ rank, int32_t* perm, float* xs, float* ys,
                                                  int32_t* ids)
 {
+    if (n_dev) n = *n_dev;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int t = start[cell_of[i]] + rank[i];
@@ -645,27 +650,28 @@ int blocks_for(int n) { return n > 0 ? (n + 255) / 256 : 1; }
 }  // namespace
 
 // Cell list of (x, y) into ctx->cell_start / perm / xs, ys, ids (slot order).
-int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* id, int32_t n, const LaunchParams& lp)
+int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* id, int32_t n, const LaunchParams& lp,
+                    const int32_t* n_dev)
 {
     ScopedTimer tm(c, VRM_T_CELLS);
     hipStream_t s = c->stream;
     hipLaunchKernelGGL(k_grid_reset, dim3(1), dim3(1), 0, s, c->grid);
     int nbb = min(256, blocks_for(n));
-    hipLaunchKernelGGL(k_bbox, dim3(nbb), dim3(256), 0, s, x, y, n, c->grid);
+    hipLaunchKernelGGL(k_bbox, dim3(nbb), dim3(256), 0, s, x, y, n, n_dev, c->grid);
     float Rmax = (float)fmax((double)lp.hi2, (double)lp.hi2f);
     float cs = sqrtf(Rmax) * (1.0f + 1.0f / 1024.0f);
     hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(1), 0, s, c->grid, cs, c->ncell_cap, c->counters);
     hipLaunchKernelGGL(k_clear_cells, dim3(1024), dim3(256), 0, s, c->cell_start, c->grid);
     if (n > 0) {
-        hipLaunchKernelGGL(k_count, dim3(blocks_for(n)), dim3(256), 0, s, x, y, n, c->grid, c->cell_start, c->cell_of,
-                           c->rank);
+        hipLaunchKernelGGL(k_count, dim3(blocks_for(n)), dim3(256), 0, s, x, y, n, n_dev, c->grid, c->cell_start,
+                           c->cell_of, c->rank);
     }
     VRM_HIP(hipGetLastError());
     int r = scan_cells(c, c->cell_start);
     if (r) return r;
     if (n > 0) {
-        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(256), 0, s, x, y, id, n, c->cell_start, c->cell_of,
-                           c->rank, c->perm, c->xs, c->ys, c->ids);
+        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(256), 0, s, x, y, id, n, n_dev, c->cell_start,
+                           c->cell_of, c->rank, c->perm, c->xs, c->ys, c->ids);
     }
     VRM_HIP(hipGetLastError());
     return VRM_OK;
@@ -717,14 +723,14 @@ int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp)
     if (nc > 0) {
         // cell list of the candidates on the particles' grid
         hipLaunchKernelGGL(k_clear_cells, dim3(1024), dim3(256), 0, s, c->cstart, c->grid);
-        hipLaunchKernelGGL(k_count, dim3(blocks_for(nc)), dim3(256), 0, s, c->cx, c->cy, nc, c->grid, c->cstart,
-                           c->ccell, c->crank);
+        hipLaunchKernelGGL(k_count, dim3(blocks_for(nc)), dim3(256), 0, s, c->cx, c->cy, nc, (const int32_t*)nullptr,
+                           c->grid, c->cstart, c->ccell, c->crank);
         VRM_HIP(hipGetLastError());
         int r = scan_cells(c, c->cstart);
         if (r) return r;
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nc)), dim3(256), 0, s, c->cx, c->cy, (const int32_t*)nullptr,
-                           nc, c->cstart, c->ccell, c->crank, c->cperm, (float*)nullptr, (float*)nullptr,
-                           (int32_t*)nullptr);
+                           nc, (const int32_t*)nullptr, c->cstart, c->ccell, c->crank, c->cperm, (float*)nullptr,
+                           (float*)nullptr, (int32_t*)nullptr);
         VRM_HIP(hipGetLastError());
         for (;;) {
             const int batch = 4;

@@ -125,6 +125,22 @@ struct vrm_ctx {
     hipEvent_t* ev_stop;
     int* ev_group;
     int64_t launches[VRM_NTIMER];
+    double acc_ms[VRM_NTIMER];   // timings accumulated from graph replays
+    int64_t acc_n[VRM_NTIMER];
+    // the three stages of vrm_step as one HIP graph
+    int capturing;               // the stream is being captured: timers take graph slots
+    int graph_enabled;
+    int64_t graph_replays;
+    int graph_failed[2];         // capture failed (without / with timers): launch directly
+    int graph_slots;             // timer slots used by the graph
+    int graph_pending;           // a replay whose timer events are not yet accumulated
+    int graph_nb;                // particle bound the graph's grids are sized for
+    int graph_flags[3];          // cells_valid, sorted, base_valid after the stages
+    hipGraph_t graph;
+    hipGraphExec_t graph_exec;
+    unsigned char graph_key[160];
+    double* t_dev;               // step start time read by the graph's velocity kernels
+    hipStream_t cap_stream;      // stream the graph is captured on (the context's may be the null stream)
     // warm-start network (allocated on first use)
     vrm::MlpState* mlp;
     int warm;             // LP solves use the network's basis prediction
@@ -137,6 +153,7 @@ struct vrm_ctx {
 
 namespace vrm {
 constexpr int kMaxTimed = 8192;
+constexpr int kGraphTimed = 64;   // the last kGraphTimed event pairs belong to the step graph
 // Bracket a group of launches with events when timing is on.
 struct ScopedTimer {
     vrm_ctx* c;
@@ -144,9 +161,15 @@ struct ScopedTimer {
     ScopedTimer(vrm_ctx* ctx, int group) : c(ctx), slot(-1)
     {
         if (!c->timing) return;
-        c->launches[group] += 1;
-        if (c->ntimed >= kMaxTimed) return;
-        slot = c->ntimed++;
+        if (c->capturing) {
+            // an event-record node of the step graph; counted when a replay is accumulated
+            if (c->graph_slots >= kGraphTimed) return;
+            slot = kMaxTimed - kGraphTimed + c->graph_slots++;
+        } else {
+            c->launches[group] += 1;
+            if (c->ntimed >= kMaxTimed - kGraphTimed) return;
+            slot = c->ntimed++;
+        }
         c->ev_group[slot] = group;
         (void)hipEventRecord(c->ev_start[slot], c->stream);
     }
@@ -159,7 +182,7 @@ struct ScopedTimer {
 
 // launchers (vrm_cells.hip)
 int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* id, int32_t n,
-                    const vrm::LaunchParams& lp);
+                    const vrm::LaunchParams& lp, const int32_t* n_dev = nullptr);
 int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double bound_factor);
 int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp);
 int vrm_reorder_cloud(vrm_ctx* c, vrm_cloud* cl, int32_t n);
@@ -176,7 +199,7 @@ int vrm_save_base_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n);
 int vrm_verify_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp,
                    const vrm_stencils* st, double* report);
 int vrm_velocity_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const float* vort, int32_t nv, double nu,
-                     double t, float* u, float* v);
+                     double t, float* u, float* v, const double* t_dev = nullptr);
 
 // launchers (vrm_mlp.hip)
 int vrm_mlp_alloc(vrm_ctx* c, int max_rows);

@@ -47,7 +47,8 @@ __device__ __forceinline__ int wave_append(int* counter, bool want)
 // ------------------------------------------------------------- kernels
 // Small neighbourhoods (Sec. 4.3) of the diffused particles, in slot order.
 // With queues: the LP queues, and the column record of each queued small LP.
-__global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __restrict__ perm,
+__global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __restrict__ n_dev,
+                                                    const int32_t* __restrict__ perm,
                                                     const float* __restrict__ xs, const float* __restrict__ ys,
                                                     const int32_t* __restrict__ ids,
                                                     const int32_t* __restrict__ cell_start,
@@ -56,6 +57,7 @@ __global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __rest
                                                     int32_t* q_full, Queues* qs,
                                                     int32_t* out_small_idx, int32_t* out_kfull, int want_kfull)
 {
+    if (n_dev) n = *n_dev;
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     bool active = t < n;
     int i = active ? perm[t] : 0;
@@ -696,7 +698,7 @@ int vrm_small_nbhd_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchP
     (void)cl;
     if (n <= 0) return VRM_OK;
     int nb = (n + 255) / 256;
-    hipLaunchKernelGGL(k_small_nbhd, dim3(nb), dim3(256), 0, c->stream, n, c->perm, c->xs, c->ys, c->ids,
+    hipLaunchKernelGGL(k_small_nbhd, dim3(nb), dim3(256), 0, c->stream, n, cl->n_dev, c->perm, c->xs, c->ys, c->ids,
                        c->cell_start, c->diffused, c->grid, lp, SmallRec{}, (int32_t*)nullptr, (int32_t*)nullptr,
                        c->queues, small_idx, kfull, kfull != nullptr ? 1 : 0);
     VRM_HIP(hipGetLastError());
@@ -726,7 +728,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
     int nb = (n + 255) / 256;
     {
         ScopedTimer tm(c, VRM_T_NBHD);
-        hipLaunchKernelGGL(k_small_nbhd, dim3(nb), dim3(256), 0, c->stream, n, c->perm, c->xs, c->ys, c->ids,
+        hipLaunchKernelGGL(k_small_nbhd, dim3(nb), dim3(256), 0, c->stream, n, cl->n_dev, c->perm, c->xs, c->ys, c->ids,
                            c->cell_start, c->diffused, c->grid, lp, c->srec, c->q_small, c->q_full, c->queues,
                            (int32_t*)nullptr, (int32_t*)nullptr, 0);
     }

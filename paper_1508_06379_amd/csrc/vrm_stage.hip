@@ -14,11 +14,13 @@ using namespace vrm;
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_combine(int n, float a, float b, float dt, float lam, const float* __restrict__ x0,
-                                                 const float* __restrict__ y0, const float* __restrict__ g0, float* x,
-                                                 float* y, float* g, const float* __restrict__ u,
-                                                 const float* __restrict__ v, float* acc)
+// n_dev (optional): the particle count read on the device (graph replays), else n
+__global__ __launch_bounds__(256) void k_combine(int n, const int32_t* __restrict__ n_dev, float a, float b, float dt,
+                                                 float lam, const float* __restrict__ x0, const float* __restrict__ y0,
+                                                 const float* __restrict__ g0, float* x, float* y, float* g,
+                                                 const float* __restrict__ u, const float* __restrict__ v, float* acc)
 {
+    if (n_dev) n = *n_dev;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float dg = lam * acc[i];
@@ -107,9 +109,11 @@ __global__ __launch_bounds__(256) void k_verify(int n, const float* __restrict__
     }
 }
 
-__global__ __launch_bounds__(256) void k_save_base(int n, const float* __restrict__ x, const float* __restrict__ y,
+__global__ __launch_bounds__(256) void k_save_base(int n, const int32_t* __restrict__ n_dev,
+                                                   const float* __restrict__ x, const float* __restrict__ y,
                                                    const float* __restrict__ g, float* x0, float* y0, float* g0)
 {
+    if (n_dev) n = *n_dev;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     x0[i] = x[i];
@@ -125,12 +129,17 @@ __global__ void k_verify_init(unsigned long long* out)
     out[3] = 0ull;
 }
 
-__global__ __launch_bounds__(256) void k_velocity(int n, const float* __restrict__ x, const float* __restrict__ y,
-                                                  const float* __restrict__ vort, int nv, float four_nu_t, float* u,
-                                                  float* v)
+// time = t, or *t_dev + t when t_dev is given (graph replays)
+__global__ __launch_bounds__(256) void k_velocity(int n, const int32_t* __restrict__ n_dev,
+                                                  const float* __restrict__ x, const float* __restrict__ y,
+                                                  const float* __restrict__ vort, int nv, double nu, double t,
+                                                  const double* __restrict__ t_dev, float* u, float* v)
 {
+    if (n_dev) n = *n_dev;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const double tt = t_dev ? *t_dev + t : t;
+    const float four_nu_t = (float)(4.0 * nu * tt);
     float xi = x[i], yi = y[i];
     float su = 0.0f, sv = 0.0f;
     const float inv2pi = 0.15915494309189535f;
@@ -158,8 +167,8 @@ int vrm_combine_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const float* u, const 
     static const float A[3] = {0.0f, 0.75f, 1.0f / 3.0f};
     static const float B[3] = {1.0f, 0.25f, 2.0f / 3.0f};
     if (n <= 0) return VRM_OK;
-    hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, A[stage], B[stage], (float)dt, lam,
-                       c->x0, c->y0, c->g0, cl->x_dev, cl->y_dev, cl->gamma_dev, u, v, c->acc);
+    hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, cl->n_dev, A[stage], B[stage],
+                       (float)dt, lam, c->x0, c->y0, c->g0, cl->x_dev, cl->y_dev, cl->gamma_dev, u, v, c->acc);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }
@@ -167,8 +176,8 @@ int vrm_combine_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const float* u, const 
 int vrm_save_base_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n)
 {
     if (n <= 0) return VRM_OK;
-    hipLaunchKernelGGL(k_save_base, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, cl->x_dev, cl->y_dev, cl->gamma_dev,
-                       c->x0, c->y0, c->g0);
+    hipLaunchKernelGGL(k_save_base, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, cl->n_dev, cl->x_dev, cl->y_dev,
+                       cl->gamma_dev, c->x0, c->y0, c->g0);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }
@@ -190,11 +199,11 @@ int vrm_verify_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchParam
 }
 
 int vrm_velocity_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const float* vort, int32_t nv, double nu, double t,
-                     float* u, float* v)
+                     float* u, float* v, const double* t_dev)
 {
     if (n <= 0) return VRM_OK;
-    hipLaunchKernelGGL(k_velocity, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, cl->x_dev, cl->y_dev, vort, nv,
-                       (float)(4.0 * nu * t), u, v);
+    hipLaunchKernelGGL(k_velocity, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, cl->n_dev, cl->x_dev, cl->y_dev,
+                       vort, nv, nu, t, t_dev, u, v);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }

@@ -346,3 +346,42 @@ def test_gpu_lamb_oseen_second_order(vrm):
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     _say("weak errors", errs, "orders", orders)
     assert ((orders > 1.8) & (orders < 3.5)).all(), (errs, orders)
+
+
+# ------------------------------------------------------------------ graph replay
+@pytest.mark.parametrize("moving", [False, True])
+def test_step_graph_replays_match_direct_launches(vrm, moving):
+    """vrm_step's graph replay against the same steps launched directly, after
+    every step (eager insertion and a synchronisation between the replays):
+    same particles, Gamma and positions up to the order of the atomic sums."""
+    wl = CONFIGS["vortices_h0.02"] if moving else CONFIGS["jittered_q2_h0.02"]
+    P = vrm.params_of(wl)
+    vt = vrm.vortex_table(wl.vortices) if moving else None
+    runs = []
+    for graph in (False, True):
+        cloud = _gpu_cloud(vrm, wl, cap_factor=4)
+        ctx = vrm.Context(cloud.capacity)
+        ctx.vrm_set_graph(graph)
+        runs.append((cloud, ctx))
+    t = wl.t0
+    for step in range(6):
+        for cloud, ctx in runs:
+            ctx.vrm_step(cloud, P, vt, t)
+        torch.cuda.synchronize()
+        (xa, ya, ga, ia), (xb, yb, gb, ib) = (c.numpy() for c, _ in runs)
+        _say("case graph step", step, "moving", moving, "N", xa.size, xb.size)
+        oa, ob = np.argsort(ia), np.argsort(ib)   # slot order within a cell is not deterministic
+        np.testing.assert_array_equal(ia[oa], ib[ob])
+        assert _rel_l2_by_id(ib, gb, ia, ga) <= 1e-6
+        np.testing.assert_allclose(xb[ob], xa[oa], rtol=0, atol=1e-6)
+        np.testing.assert_allclose(yb[ob], ya[oa], rtol=0, atol=1e-6)
+        t += wl.dt
+    assert runs[0][1].vrm_read_counters()["graph_replays"] == 0
+    assert runs[1][1].vrm_read_counters()["graph_replays"] == 6
+    # with the timers on, the stages are launched directly and every launch is timed
+    cloud, ctx = runs[1]
+    ctx.vrm_timing(True)
+    ctx.vrm_step(cloud, P, vt, t)
+    timers, overflow = ctx.vrm_read_timing()
+    assert not overflow and timers["lp_small"][1] == 3 and timers["lp_small"][0] > 0.0
+    assert ctx.vrm_read_counters()["graph_replays"] == 6
