@@ -213,6 +213,8 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
     if (r == VRM_OK) {
         hipError_t e = hipMemsetAsync(c->acc, 0, cap * sizeof(float), c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->counters, 0, sizeof(vrm_counters), c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->queues, 0, sizeof(vrm::Queues), c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->sel, 0, sizeof(vrm::SelectState), c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) r = vrm_hip_check(e, "initialisation");
     }
@@ -647,7 +649,7 @@ int vrm_collect_training(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, u
     vrm::Queues q;
     VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(q), hipMemcpyDeviceToHost, c->stream));
     VRM_HIP(hipStreamSynchronize(c->stream));
-    int got = L.m == 5 ? q.n_small : q.n_full;
+    int got = L.m == 5 ? q.last_small : q.last_full;
     *rows = got < max_rows ? got : max_rows;
     return VRM_OK;
 }

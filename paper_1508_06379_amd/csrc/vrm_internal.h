@@ -25,7 +25,9 @@ struct Queues {
     int32_t n_accepted;    // accepted insertion candidates
     int32_t small_state;   // single-workgroup insertion: 0 not taken, 1 done, 2 capacity exceeded
     int32_t n_retry;       // LPs left by the warm pass for a cold solve
-    int32_t pad[1];
+    int32_t blocks_done;   // blocks of the last LP launch that have finished
+    int32_t last_small;    // n_small and n_full of the last stencil run (the queues
+    int32_t last_full;     // themselves are zero between runs)
 };
 
 // Column records of the queued small-neighbourhood LPs, in queue order and
@@ -45,7 +47,7 @@ struct SelectState {
     uint32_t key_prefix;   // resolved high bits of the threshold key
     uint32_t done;         // 1 once the threshold is known
     uint32_t threshold;    // particles with key < threshold are left out
-    uint32_t pad;
+    uint32_t blocks_done;  // blocks of the current histogram pass that have merged their counts
     double bin_sum[256];
     uint32_t bin_cnt[256];
 };

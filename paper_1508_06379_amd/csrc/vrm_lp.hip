@@ -526,7 +526,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
                                                         const int32_t* __restrict__ q_full, Queues* qs,
                                                         const float* __restrict__ gamma, float* acc, LaunchParams P,
                                                         StencilOut out, int apply, vrm_counters* cnt, int mode,
-                                                        int32_t* q_retry)
+                                                        int32_t* q_retry, int last_launch)
 {
     __shared__ float s_rx[VRM_KMAX * kFullBlock];
     __shared__ float s_ry[VRM_KMAX * kFullBlock];
@@ -625,6 +625,24 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
         int pr = wave_append(&qs->n_retry, retry);
         if (retry) q_retry[pr] = t;
     }
+    if (last_launch) {
+        // the last LP launch of a stencil run: its last block to finish empties the
+        // queues for the next run (keeping the counts for the host)
+        __shared__ int last;
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) last = atomicAdd(&qs->blocks_done, 1) == (int)gridDim.x - 1;
+        __syncthreads();
+        if (last && threadIdx.x == 0) {
+            __threadfence();
+            qs->last_small = qs->n_small;
+            qs->last_full = qs->n_full;
+            qs->n_small = 0;
+            qs->n_full = 0;
+            qs->n_retry = 0;
+            qs->blocks_done = 0;
+        }
+    }
 }
 
 // feature rows of the queued complete-neighbourhood LPs (warm start)
@@ -678,12 +696,6 @@ __global__ void k_status_init(int n, const uint8_t* __restrict__ diffused, Stenc
     }
 }
 
-__global__ void k_reset_queues(Queues* q)
-{
-    q->n_small = 0;
-    q->n_full = 0;
-    q->n_retry = 0;
-}
 
 // persistent launches: enough threads for every CU, each loops over its items
 // persistent launches: enough threads for every CU, each loops over its items
@@ -724,7 +736,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
     out.feat = feat_out;
     out.lab = label_out;
     out.max_rows = max_rows;
-    hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(1), 0, c->stream, c->queues);
+    // the LP queues are empty here: the last LP launch of every run empties them
     int nb = (n + 255) / 256;
     {
         ScopedTimer tm(c, VRM_T_NBHD);
@@ -769,13 +781,14 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         ScopedTimer tm(c, VRM_T_LP_FULL);
         hipLaunchKernelGGL(k_lp_full<5>, dim3(min(lp_grid_full(n), 64)), dim3(kFullBlock), 0, c->stream, c->perm,
                            c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
-                           o2, apply, c->counters, kLpPlain, c->q_retry);
+                           o2, apply, c->counters, kLpPlain, c->q_retry, 1);
     } else {
         ScopedTimer tm(c, VRM_T_LP_FULL);
-        for (int mode = first; mode <= (warm ? kLpRetry : kLpPlain); ++mode) {
+        const int last = warm ? kLpRetry : kLpPlain;
+        for (int mode = first; mode <= last; ++mode) {
             hipLaunchKernelGGL(k_lp_full<9>, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
                                c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
-                               out, apply, c->counters, mode, c->q_retry);
+                               out, apply, c->counters, mode, c->q_retry, mode == last ? 1 : 0);
             VRM_HIP(hipGetLastError());
         }
     }
