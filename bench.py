@@ -45,7 +45,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(wl, steps, warmup, theta=None):
+def run_gpu(wl, steps, warmup, theta=None, warm_mode=0):
     import torch
     import paper_1508_06379_amd as vrm
 
@@ -56,7 +56,9 @@ def run_gpu(wl, steps, warmup, theta=None):
     ctx = vrm.Context(cap)
     if theta is not None:
         ctx.vrm_mlp_load(theta)
-        ctx.vrm_set_warm_start(True)
+        ctx.vrm_set_warm_start(1)
+    elif warm_mode:
+        ctx.vrm_set_warm_start(warm_mode)
     vt = vrm.vortex_table(wl.vortices) if wl.vortices is not None else None
 
     t = wl.t0
@@ -198,8 +200,9 @@ def main():
     ap.add_argument("--workload", default="lamb_oseen_h0.01_q2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--solver", default="both", choices=["both", "plain", "learned"],
-                    help="plain batched solver, learned warm start, or both on the same workload")
+    ap.add_argument("--solver", default="all", choices=["all", "both", "plain", "learned", "previous"],
+                    help="plain batched solver, learned warm start, previous-basis warm start; "
+                         "both = plain + learned, all = the three on the same workload")
     ap.add_argument("--train-snapshots", type=int, default=30)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -212,10 +215,12 @@ def main():
     wl = WORKLOADS[args.workload]()
     log(f"workload {args.workload}: N={wl.n} h={wl.h} q={wl.q} dt={wl.dt}")
     runs = {}
-    if args.solver in ("both", "plain"):
+    if args.solver in ("all", "both", "plain"):
         runs["plain"] = run_gpu(wl, args.steps, args.warmup)
     train_info = None
-    if args.solver in ("both", "learned"):
+    if args.solver in ("all", "previous"):
+        runs["previous"] = run_gpu(wl, args.steps, args.warmup, warm_mode=2)
+    if args.solver in ("all", "both", "learned"):
         theta, train_info = train_network(args.workload, args.train_snapshots, args.epochs)
         log(f"network: {train_info}")
         runs["learned"] = run_gpu(wl, args.steps, args.warmup, theta=theta)
@@ -227,7 +232,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copy calibration: 5 copies of {src.numel() * 4} bytes")
-    main_solver = "plain" if "plain" in runs else "learned"
+    main_solver = "plain" if "plain" in runs else ("learned" if "learned" in runs else "previous")
     res = runs[main_solver]
     c = res["counters"]
     value = c["redistributions"] / res["elapsed"]
@@ -246,6 +251,18 @@ def main():
         "lp": {"small": c["n_small"], "full": c["n_full"], "infeasible": c["n_infeasible"],
                "uncertified": c["n_uncertified"], "pivots": c["pivots"]},
     }
+    if "previous" in runs and main_solver != "previous":
+        r = runs["previous"]
+        cp = r["counters"]
+        pv = cp["redistributions"] / r["elapsed"]
+        nlp = max(1, cp["warm_hit"] + cp["warm_phase2"] + cp["warm_cold"])
+        line["previous_basis"] = {
+            "value": pv, "ms_per_step": r["elapsed"] * 1e3 / args.steps, "vs_plain": pv / value,
+            "warm_start": {"optimal_from_previous": cp["warm_hit"] / nlp, "phase2_from_previous": cp["warm_phase2"] / nlp,
+                           "left_for_cold_solve": cp["warm_cold"] / nlp},
+            "pivots": cp["pivots"], "uncertified": cp["n_uncertified"],
+            "timers_ms": {k: round(v[0], 4) for k, v in r["timers"].items()},
+        }
     if "learned" in runs:
         r = runs["learned"]
         cl = r["counters"]

@@ -230,8 +230,16 @@ int vrm_vortex_velocity(vrm_ctx* ctx, const vrm_cloud* cloud, const float* vort_
 /* Copy parameters in (device FP32) / out. */
 int vrm_mlp_load(vrm_ctx* ctx, const float* params_dev);
 int vrm_mlp_read(vrm_ctx* ctx, float* params_dev);
-/* Enable (1) or disable (0) the warm start of vrm_solve_fractions / vrm_rk_stage
- * (needs loaded parameters; allocates 512 bytes per particle of capacity). */
+/* Warm start of vrm_solve_fractions / vrm_rk_stage / vrm_step:
+ *   0  off (every LP starts from the artificial basis);
+ *   1  from the network's predicted basis (needs loaded parameters; allocates
+ *      512 bytes per particle of capacity);
+ *   2  from the basis of the particle's previous stencil (matched by column
+ *      ids; allocates 36 bytes per particle of capacity).
+ * In modes 1 and 2 a first LP pass starts from the predicted basis and a
+ * second, cold pass solves what the first could not settle with a few
+ * pivots; every accepted basis is certified exactly, so the stencils are
+ * those of mode 0. */
 int vrm_set_warm_start(vrm_ctx* ctx, int enable);
 /* Training data from the plain solver at the current positions and diffused
  * set: for the LPs queued first (small ones for q = 2, complete ones for

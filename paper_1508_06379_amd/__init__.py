@@ -287,8 +287,9 @@ class Context:
     def vrm_mlp_read(self, params):
         _check(lib().vrm_mlp_read(self.handle, _ptr(params)))
 
-    def vrm_set_warm_start(self, enable: bool):
-        _check(lib().vrm_set_warm_start(self.handle, 1 if enable else 0))
+    def vrm_set_warm_start(self, mode):
+        """0/False off, 1/True from the network, 2 from each particle's previous basis."""
+        _check(lib().vrm_set_warm_start(self.handle, int(mode)))
 
     def vrm_collect_training(self, cloud: Cloud, p: vrm_params, x, y) -> int:
         rows = ctypes.c_int32(0)

@@ -242,6 +242,7 @@ int vrm_destroy(vrm_ctx* c)
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->t_dev) (void)hipFree(c->t_dev);
+    if (c->prev) (void)hipFree(c->prev);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->feat) (void)hipFree(c->feat);
     if (c->u_tmp) (void)hipFree(c->u_tmp);
@@ -616,6 +617,17 @@ int vrm_mlp_read(vrm_ctx* c, float* w)
 int vrm_set_warm_start(vrm_ctx* c, int enable)
 {
     if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
+    if (enable < 0 || enable > 2) return vrm_fail(VRM_E_ARG, "warm start mode %d (0, 1 or 2)", enable);
+    if (enable == 2) {
+        if (!c->prev) {
+            void* p = nullptr;
+            VRM_HIP(hipMalloc(&p, sizeof(int32_t) * (size_t)c->capacity * 9 + 64));
+            c->prev = (int32_t*)p;
+            VRM_HIP(hipMemsetAsync(c->prev, 0xff, sizeof(int32_t) * (size_t)c->capacity * 9, c->stream));
+        }
+        c->warm = 2;
+        return VRM_OK;
+    }
     if (enable) {
         if (!c->mlp || !c->mlp->loaded) return vrm_fail(VRM_E_STATE, "warm start needs network parameters (vrm_mlp_load)");
         if (!c->feat) {

@@ -142,6 +142,7 @@ struct vrm_ctx {
     hipGraphExec_t graph_exec;
     unsigned char graph_key[160];
     double* t_dev;               // step start time read by the graph's velocity kernels
+    int32_t* prev;               // [cap][9] basis (column ids) of each particle's last stencil, by id
     hipStream_t cap_stream;      // stream the graph is captured on (the context's may be the null stream)
     // warm-start network (allocated on first use)
     vrm::MlpState* mlp;

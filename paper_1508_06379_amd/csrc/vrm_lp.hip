@@ -174,7 +174,44 @@ struct StencilOut {
     float* lab;          // label rows (basis indicators, fractions) of solved LPs, or NULL
     int max_rows;
     const float* pred;   // warm start: small LPs 8 logits, complete ones kMlpOut outputs per queue item; or NULL
+    int32_t* prev;       // basis (column ids) of each particle's last stencil, [id][kPrevIds]: recorded if non-NULL
+    int use_prev;        // warm start from prev instead of pred
+    const int32_t* cloud_id;   // ids by cloud index
 };
+
+constexpr int kPrevIds = 9;
+
+// the previous basis of particle `own` as a mask over columns with ids cid(j), j < k
+template <class ColId>
+__device__ __forceinline__ uint64_t prev_mask(const int32_t* prev, int own, int k, ColId cid)
+{
+    int pv[kPrevIds];
+#pragma unroll
+    for (int r = 0; r < kPrevIds; ++r) pv[r] = prev[(size_t)own * kPrevIds + r];
+    uint64_t m = 0;
+    for (int j = 0; j < k; ++j) {
+        const int id = cid(j);
+        if (id < 0) continue;
+        bool in = false;
+#pragma unroll
+        for (int r = 0; r < kPrevIds; ++r) in = in || pv[r] == id;
+        if (in) m |= 1ull << j;
+    }
+    return m;
+}
+
+// record the basic columns' ids as the particle's basis
+template <class ColId>
+__device__ __forceinline__ void record_basis(int32_t* prev, int own, uint64_t basis, ColId cid)
+{
+    int c = 0;
+    while (basis && c < kPrevIds) {
+        const int j = __ffsll((unsigned long long)basis) - 1;
+        basis &= basis - 1;
+        prev[(size_t)own * kPrevIds + c++] = cid(j);
+    }
+    for (; c < kPrevIds; ++c) prev[(size_t)own * kPrevIds + c] = -1;
+}
 
 __device__ __forceinline__ void count_add(int* p, bool v)
 {
@@ -354,14 +391,24 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
                 for (int s = 0; s < 8; ++s)
                     if (s == j) fv[s] = v;
             };
-            const bool warm_pass = mode == kLpWarm && out.pred;
-            if (warm_pass) {
+            const bool warm_pass = mode == kLpWarm && (out.pred || out.use_prev);
+            const int own = ids[t];
+            auto col_id = [&](int j) {
+                return ((dead >> j) & 1ull) ? -1 : out.cloud_id[(unsigned)s_meta[j * kSmallBlock + tid] >> 6];
+            };
+            uint64_t pref = 0;
+            if (warm_pass && out.use_prev) {
+                pref = prev_mask(out.prev, own, 8, col_id);
+            } else if (warm_pass) {
                 const float4* lg4 = reinterpret_cast<const float4*>(out.pred + (size_t)r * VRM_NSEG);
                 const float4 a = lg4[0], b = lg4[1];
                 cs.lg[0] = a.x, cs.lg[1] = a.y, cs.lg[2] = a.z, cs.lg[3] = a.w;
                 cs.lg[4] = b.x, cs.lg[5] = b.y, cs.lg[6] = b.z, cs.lg[7] = b.w;
             }
-            st = solve_lp<5>(cs, P, store, fii, piv, certified, warm_pass, nullptr, warm);
+            uint64_t basis = 0;
+            st = solve_lp<5>(cs, P, store, fii, piv, certified, warm_pass, nullptr, warm, basis,
+                             warm_pass && out.use_prev, pref);
+            if (st == 0 && out.prev) record_basis(out.prev, own, basis, col_id);
             if (record) {
                 float* lab = out.lab + (size_t)item * kMlpOut;
 #pragma unroll
@@ -592,9 +639,16 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
                 }
                 ++nz;
             };
-            const bool warm_pass = mode == kLpWarm && out.pred;
-            const float* logit = warm_pass ? out.pred + (size_t)item * kMlpOut : nullptr;
-            st = k > 0 ? solve_lp<M>(cs, P, store, fii, piv, certified, warm_pass, logit, warm) : 1;
+            const bool warm_pass = mode == kLpWarm && (out.pred || out.use_prev);
+            const float* logit = (warm_pass && !out.use_prev) ? out.pred + (size_t)item * kMlpOut : nullptr;
+            const int own = ids[t];
+            auto col_id = [&](int j) { return ids[(unsigned)s_meta[j * kFullBlock + tid] >> 6]; };
+            const uint64_t pref = (warm_pass && out.use_prev) ? prev_mask(out.prev, own, k, col_id) : 0ull;
+            uint64_t basis = 0;
+            st = k > 0 ? solve_lp<M>(cs, P, store, fii, piv, certified, warm_pass, logit, warm, basis,
+                                     warm_pass && out.use_prev, pref)
+                       : 1;
+            if (st == 0 && out.prev) record_basis(out.prev, own, basis, col_id);
             if (st == 0) {
                 if (apply) atomicAdd(&acc[i], fii * g_i);
                 if (out.full_k) {
@@ -745,8 +799,14 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
                            (int32_t*)nullptr, (int32_t*)nullptr, 0);
     }
     VRM_HIP(hipGetLastError());
-    const bool warm = c->warm && c->mlp && c->mlp->loaded && !feat_out;
-    if (warm) {
+    const bool net = c->warm == 1 && c->mlp && c->mlp->loaded && !feat_out;
+    const bool warm = net || (c->warm == 2 && !feat_out);
+    out.cloud_id = cl->id_dev;
+    if (c->warm == 2 && c->prev && !feat_out) {
+        out.prev = c->prev;
+        out.use_prev = 1;
+    }
+    if (net) {
         // network inputs of the queued LPs, then the forward pass (row count read on the device)
         ScopedTimer tm(c, VRM_T_MLP);
         int r;

@@ -213,17 +213,22 @@ struct ThreadSimplex {
 
     // Crash basis from a prediction: the columns of the M largest logits
     // (slots j < 32 are columns j; a store with KC > 0 columns holds them in
-    // cs.lg, otherwise they are read from logit) enter in that order, each replacing the
+    // cs.lg, otherwise they are read from logit), or the columns of the set
+    // pref (use_pref), enter in that order, each replacing the
     // artificial row where its pivot element is largest.  Returns true if the
     // resulting basis is complete and primal feasible (phase II can start).
-    __device__ bool crash(const CS& cs, const float* logit, int& piv)
+    __device__ bool crash(const CS& cs, const float* logit, int& piv, bool use_pref = false, uint64_t pref = 0)
     {
         const int kk = cs.k < 32 ? cs.k : 32;
         uint64_t chosen = dead;
         for (int t = 0; t < M; ++t) {
             int best = -1;
             float bl = 0.0f;
-            if constexpr (CS::KC > 0) {
+            if (use_pref) {
+                // a given set of columns (the previous basis), in column order
+                const uint64_t left = pref & ~chosen;
+                if (left) best = __ffsll((unsigned long long)left) - 1;
+            } else if constexpr (CS::KC > 0) {
                 // the logits of the columns are in registers
 #pragma unroll
                 for (int j = 0; j < CS::KC; ++j) {
@@ -618,15 +623,17 @@ struct ThreadSimplex {
 // Returns 0 ok, 1 infeasible, 4 left for a cold solve (warm pass);
 // *certified = 0 if optimality could not be shown.
 // Warm pass (warm_pass): the simplex starts from the crash basis of the
-// prediction (logits of the first 32 columns); a rejected crash basis, or one
-// that needs more than kWarmCap phase-II pivots, is given up (status 4).
+// prediction (logits of the first 32 columns, or the column set pref with
+// use_pref); a rejected crash basis, or one that needs more than kWarmCap
+// phase-II pivots, is given up (status 4).  basis: the final basic columns.
 // warm = 0 cold, 1 the predicted basis was optimal, 2 phase II from it,
 // 3 given up.
 constexpr int kWarmCap = 3;
 
 template <int M, class CS, class Store>
 __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified,
-                        bool warm_pass, const float* logit, int& warm)
+                        bool warm_pass, const float* logit, int& warm, uint64_t& basis, bool use_pref = false,
+                        uint64_t pref = 0)
 {
     ThreadSimplex<M, CS> lp;
     lp.bt_ = P.bt_hi;
@@ -634,8 +641,9 @@ __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float&
     lp.dead = cs.dead;
     int st;
     warm = 0;
+    basis = 0;
     if (warm_pass) {
-        if (!lp.crash(cs, logit, piv)) {
+        if (!lp.crash(cs, logit, piv, use_pref, pref)) {
             warm = 3;
             return 4;
         }
@@ -674,6 +682,9 @@ __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float&
         if (v[r] != 0.0f) store(lp.bs[r], v[r]);
     }
     fii = -sum;
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+        if (lp.bs[r] < lp.ART) basis |= 1ull << lp.bs[r];
     return 0;
 }
 

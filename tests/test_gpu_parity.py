@@ -385,3 +385,33 @@ def test_step_graph_replays_match_direct_launches(vrm, moving):
     timers, overflow = ctx.vrm_read_timing()
     assert not overflow and timers["lp_small"][1] == 3 and timers["lp_small"][0] > 0.0
     assert ctx.vrm_read_counters()["graph_replays"] == 6
+
+
+# ------------------------------------------------------------------ previous-basis warm start
+@pytest.mark.parametrize("name", ["jittered_q2_h0.02", "jittered_q3_h0.02", "vortices_h0.02"])
+def test_previous_basis_warm_start(vrm, name):
+    """Warm start from each particle's previous basis: the same stencils as the cold
+    solver (Gamma after 4 steps up to the order of the atomic sums), most LPs settled
+    from the previous basis, fewer pivots."""
+    wl = CONFIGS[name]
+    P = vrm.params_of(wl)
+    vt = vrm.vortex_table(wl.vortices) if wl.vortices is not None else None
+    res = []
+    for mode in (0, 2):
+        cloud = _gpu_cloud(vrm, wl, cap_factor=4)
+        ctx = vrm.Context(cloud.capacity)
+        ctx.vrm_set_warm_start(mode)
+        t = wl.t0
+        for _ in range(4):
+            ctx.vrm_step(cloud, P, vt, t)
+            t += wl.dt
+        torch.cuda.synchronize()
+        res.append((cloud.numpy(), ctx.vrm_read_counters()))
+    ((xa, ya, ga, ia), ca), ((xb, yb, gb, ib), cb) = res
+    _say("case prev-basis", name, "plain", ca, "\nwarm", cb)
+    assert xa.size == xb.size
+    assert _rel_l2_by_id(ib, gb, ia, ga) <= 1e-6
+    assert cb["n_uncertified"] == 0 and cb["n_infeasible"] == ca["n_infeasible"]
+    settled = cb["warm_hit"] + cb["warm_phase2"]
+    assert settled >= 0.5 * (settled + cb["warm_cold"])
+    assert cb["pivots"] < ca["pivots"]
