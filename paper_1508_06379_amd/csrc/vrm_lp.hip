@@ -271,14 +271,15 @@ constexpr int kLpRetry = 2;
 
 // Columns of an LP in LDS, column-major per thread (stride = threads per block):
 // FP32 scaled offsets and cost, and (slot << 6) | id rank for the exact values.
-template <int BLK>
+// STORED: FP32 costs in sc, else computed from the offsets when read.
+template <int BLK, bool STORED = true>
 struct LdsColsT {
     static constexpr int KC = 0;   // column count known at run time only
     int k;
     uint64_t dead;
     float* srx;
     float* sry;
-    float* sc;
+    float* sc;     // FP32 costs (STORED)
     int* smeta;
     int tid;
     float xi, yi;
@@ -291,7 +292,14 @@ struct LdsColsT {
     {
         x = srx[j * BLK + tid];
         y = sry[j * BLK + tid];
-        cc = sc[j * BLK + tid];
+        if constexpr (STORED) {
+            cc = sc[j * BLK + tid];
+        } else {
+            // FP32 cost from the FP32 offset (the exact cost is recomputed for certification)
+            const float d2 = x * x + y * y;
+            const float w = P->q == 2 ? d2 * __builtin_sqrtf(d2) : d2 * d2;
+            cc = __builtin_fmaf(w, P->cs_hi, 0.0009765625f * (float)(smeta[j * BLK + tid] & 63));
+        }
     }
     __device__ __forceinline__ void exact_xy(int j, df& X, df& Y) const
     {
@@ -309,7 +317,6 @@ struct LdsColsT {
         C = add_rank(cost_df(X, Y, *P), smeta[j * BLK + tid] & 63);
     }
 };
-using LdsCols = LdsColsT<kFullBlock>;
 
 // Small-neighbourhood columns: eight, a compile-time count, plus their
 // predicted logits in registers (warm pass).
@@ -565,7 +572,11 @@ __device__ int collect_full(int t, float xi, float yi, const GridState& g, const
 }
 
 // Complete-neighbourhood LPs (Sec. 4.3 fallback), one thread per particle.
-template <int M>
+// SC: FP32 costs stored in LDS (48 KB per block: fewer instructions per
+// pricing, three resident blocks per CU) or computed from the offsets when
+// priced (36 KB: four blocks per CU).  Small clouds, whose launches are one
+// wave's latency, take the first; large ones, throughput-bound, the second.
+template <int M, bool SC>
 __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restrict__ perm,
                                                         const float* __restrict__ xs, const float* __restrict__ ys,
                                                         const int32_t* __restrict__ ids,
@@ -577,8 +588,8 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
 {
     __shared__ float s_rx[VRM_KMAX * kFullBlock];
     __shared__ float s_ry[VRM_KMAX * kFullBlock];
-    __shared__ float s_c[VRM_KMAX * kFullBlock];
     __shared__ int s_meta[VRM_KMAX * kFullBlock];
+    __shared__ float s_c[SC ? VRM_KMAX * kFullBlock : 1];
     const int tid = threadIdx.x;
     const int32_t* queue = mode == kLpRetry ? q_retry : q_full;
     const int nitems = mode == kLpRetry ? qs->n_retry : qs->n_full;
@@ -594,13 +605,13 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
             t = queue[item];
             int i = perm[t];
             const float xi = xs[t], yi = ys[t];
-            // columns nearest first: slots in s_meta, d2 in s_rx, ids in s_c (as bits) during collection
+            // columns nearest first: slots in s_meta, d2 in s_rx, ids in s_ry (as bits) during collection
             k = collect_full(t, xi, yi, g, cell_start, xs, ys, ids, P, s_meta + tid, s_rx + tid,
-                             reinterpret_cast<int*>(s_c) + tid, truncated);
+                             reinterpret_cast<int*>(s_ry) + tid, truncated);
             for (int j = 0; j < k; ++j) {
-                int idj = __float_as_int(s_c[j * kFullBlock + tid]);
+                int idj = __float_as_int(s_ry[j * kFullBlock + tid]);
                 int rank = 0;
-                for (int o = 0; o < k; ++o) rank += __float_as_int(s_c[o * kFullBlock + tid]) < idj ? 1 : 0;
+                for (int o = 0; o < k; ++o) rank += __float_as_int(s_ry[o * kFullBlock + tid]) < idj ? 1 : 0;
                 s_meta[j * kFullBlock + tid] = (int)(((unsigned)s_meta[j * kFullBlock + tid] << 6) | (unsigned)rank);
             }
             const bool rec = mode == kLpPlain && out.feat && item < out.max_rows;
@@ -611,14 +622,13 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
                 df X, Y;
                 int um = (int)((unsigned)meta >> 6);
                 exact_offset(xi, yi, xs[um], ys[um], P.scale2e, X, Y);
-                df C = add_rank(cost_df(X, Y, P), meta & 63);
                 s_rx[j * kFullBlock + tid] = X.hi;
                 s_ry[j * kFullBlock + tid] = Y.hi;
-                s_c[j * kFullBlock + tid] = C.hi;
+                if constexpr (SC) s_c[j * kFullBlock + tid] = add_rank(cost_df(X, Y, P), meta & 63).hi;
                 if (rec && j < kMlpSlots) feature_slot(frow, j, X.hi * P.sc, Y.hi * P.sc);
             }
             if (rec) feature_q(frow, P.q);
-            LdsCols cs{k, 0ull, s_rx, s_ry, s_c, s_meta, tid, xi, yi, xs, ys, &P, nullptr, nullptr};
+            LdsColsT<kFullBlock, SC> cs{k, 0ull, s_rx, s_ry, s_c, s_meta, tid, xi, yi, xs, ys, &P, nullptr, nullptr};
             float fii = 0.0f;
             const float g_i = gamma[i];
             int nz = 0;
@@ -750,8 +760,9 @@ __global__ void k_status_init(int n, const uint8_t* __restrict__ diffused, Stenc
     }
 }
 
+// clouds up to this size launch the complete-LP kernel with stored costs
+constexpr int kLpFullSmallCloud = 200000;
 
-// persistent launches: enough threads for every CU, each loops over its items
 // persistent launches: enough threads for every CU, each loops over its items
 int lp_grid_small(int n) { return n > 0 ? min((n + 255) / 256, 256 * 8) : 1; }
 int lp_grid_full(int n) { return n > 0 ? min((n + kFullBlock - 1) / kFullBlock, 256 * 4) : 1; }
@@ -839,14 +850,14 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         o2.feat = nullptr;
         o2.lab = nullptr;
         ScopedTimer tm(c, VRM_T_LP_FULL);
-        hipLaunchKernelGGL(k_lp_full<5>, dim3(min(lp_grid_full(n), 64)), dim3(kFullBlock), 0, c->stream, c->perm,
+        hipLaunchKernelGGL((n <= kLpFullSmallCloud ? k_lp_full<5, true> : k_lp_full<5, false>), dim3(min(lp_grid_full(n), 64)), dim3(kFullBlock), 0, c->stream, c->perm,
                            c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                            o2, apply, c->counters, kLpPlain, c->q_retry, 1);
     } else {
         ScopedTimer tm(c, VRM_T_LP_FULL);
         const int last = warm ? kLpRetry : kLpPlain;
         for (int mode = first; mode <= last; ++mode) {
-            hipLaunchKernelGGL(k_lp_full<9>, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
+            hipLaunchKernelGGL((n <= kLpFullSmallCloud ? k_lp_full<9, true> : k_lp_full<9, false>), dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
                                c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                                out, apply, c->counters, mode, c->q_retry, mode == last ? 1 : 0);
             VRM_HIP(hipGetLastError());
