@@ -45,7 +45,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(wl, steps, warmup, theta=None, warm_mode=0):
+def run_gpu(wl, steps, warmup, theta=None, warm_mode=0, tuning=None):
     import torch
     import paper_1508_06379_amd as vrm
 
@@ -54,6 +54,8 @@ def run_gpu(wl, steps, warmup, theta=None, warm_mode=0):
     cap = int(wl.n * (4 if wl.n < 200000 else 2.2)) + 1024
     cloud = vrm.Cloud(wl.x, wl.y, wl.gamma, capacity=cap)
     ctx = vrm.Context(cap)
+    if tuning:
+        ctx.vrm_set_tuning(tuning)
     if theta is not None:
         ctx.vrm_mlp_load(theta)
         ctx.vrm_set_warm_start(1)
@@ -214,16 +216,19 @@ def main():
         sys.exit(2)
     wl = WORKLOADS[args.workload]()
     log(f"workload {args.workload}: N={wl.n} h={wl.h} q={wl.q} dt={wl.dt}")
+    from paper_1508_06379_amd import autotune
+    tuning = autotune.load(args.workload)   # launch shapes chosen by the autotuner, if any
+    log(f"tuning: {tuning}")
     runs = {}
     if args.solver in ("all", "both", "plain"):
-        runs["plain"] = run_gpu(wl, args.steps, args.warmup)
+        runs["plain"] = run_gpu(wl, args.steps, args.warmup, tuning=tuning)
     train_info = None
     if args.solver in ("all", "previous"):
-        runs["previous"] = run_gpu(wl, args.steps, args.warmup, warm_mode=2)
+        runs["previous"] = run_gpu(wl, args.steps, args.warmup, warm_mode=2, tuning=tuning)
     if args.solver in ("all", "both", "learned"):
         theta, train_info = train_network(args.workload, args.train_snapshots, args.epochs)
         log(f"network: {train_info}")
-        runs["learned"] = run_gpu(wl, args.steps, args.warmup, theta=theta)
+        runs["learned"] = run_gpu(wl, args.steps, args.warmup, theta=theta, tuning=tuning)
     if args.calibrate_copy:
         import torch
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -247,6 +252,7 @@ def main():
         "config": {"workload": args.workload, "h": wl.h, "q": wl.q, "n_start": res["n_start"],
                    "n_end": res["n_end"], "dt": wl.dt, "solver": main_solver},
         "roofline": rl,
+        "tuning": tuning,
         "timers_ms": {k: round(v[0], 4) for k, v in res["timers"].items()},
         "lp": {"small": c["n_small"], "full": c["n_full"], "infeasible": c["n_infeasible"],
                "uncertified": c["n_uncertified"], "pivots": c["pivots"]},

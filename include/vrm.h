@@ -189,6 +189,22 @@ int vrm_rk_stage(vrm_ctx* ctx, vrm_cloud* cloud, const float* u_dev, const float
  * floating-point atomic sums).  Synchronises once (insertion). */
 int vrm_step(vrm_ctx* ctx, vrm_cloud* cloud, const vrm_params* p, const float* vort_dev, int32_t n_vort, double t);
 
+/* Launch shapes (performance only; results do not depend on them).  A zero
+ * field keeps the library's default.  The values are device-independent
+ * numbers of workgroups; an autotuner (paper_1508_06379_amd/autotune.py)
+ * picks them per workload by timing steps. */
+typedef struct vrm_tuning {
+    int32_t lp_small_blocks;     /* most workgroups (256 threads) of the small-LP launch; default 2048 */
+    int32_t lp_full_blocks;      /* most workgroups (64 threads) of the complete-LP launch; default 1024 */
+    int32_t full_stored_cost_n;  /* clouds with N up to this keep complete-LP costs in LDS; default 200000;
+                                    -1: never */
+    int32_t infer_blocks;        /* most workgroups (256 threads) of the network's inference; default 512 */
+    int32_t reserved[4];
+} vrm_tuning;
+/* Set (t = NULL: restore the defaults) or read the launch shapes. */
+int vrm_set_tuning(vrm_ctx* ctx, const vrm_tuning* t);
+int vrm_get_tuning(vrm_ctx* ctx, vrm_tuning* out);
+
 /* Enable (default) or disable the graph replay of vrm_step's stages; with it
  * disabled every stage kernel is launched directly.  Disabling synchronises
  * the stream and releases the recorded graph. */

@@ -40,6 +40,13 @@ class vrm_params(ctypes.Structure):
                 ("q", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class vrm_tuning(ctypes.Structure):
+    _fields_ = [("lp_small_blocks", ctypes.c_int32), ("lp_full_blocks", ctypes.c_int32),
+                ("full_stored_cost_n", ctypes.c_int32), ("infer_blocks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+    FIELDS = ("lp_small_blocks", "lp_full_blocks", "full_stored_cost_n", "infer_blocks")
+
+
 class vrm_cloud(ctypes.Structure):
     _fields_ = [("x_dev", ctypes.c_void_p), ("y_dev", ctypes.c_void_p), ("gamma_dev", ctypes.c_void_p),
                 ("id_dev", ctypes.c_void_p), ("n_dev", ctypes.c_void_p), ("capacity", ctypes.c_int32)]
@@ -66,7 +73,8 @@ class vrm_counters(ctypes.Structure):
 
 
 EXPORTS = ["vrm_create", "vrm_destroy", "vrm_select_diffused", "vrm_set_diffused", "vrm_build_neighbourhoods",
-           "vrm_insert_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_step", "vrm_set_graph", "vrm_verify",
+           "vrm_insert_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_step", "vrm_set_graph", "vrm_set_tuning",
+           "vrm_get_tuning", "vrm_verify",
            "vrm_read_counters",
            "vrm_vortex_velocity", "vrm_timing", "vrm_read_timing", "vrm_mlp_load", "vrm_mlp_read",
            "vrm_set_warm_start", "vrm_collect_training", "vrm_mlp_train_step", "vrm_mlp_infer", "vrm_gemm_bf16",
@@ -97,6 +105,8 @@ def lib():
         L.vrm_step.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params), vp, ctypes.c_int32,
                                ctypes.c_double]
         L.vrm_set_graph.argtypes = [vp, ctypes.c_int]
+        L.vrm_set_tuning.argtypes = [vp, ctypes.POINTER(vrm_tuning)]
+        L.vrm_get_tuning.argtypes = [vp, ctypes.POINTER(vrm_tuning)]
         L.vrm_verify.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params),
                                  ctypes.POINTER(vrm_stencils), vp]
         L.vrm_read_counters.argtypes = [vp, ctypes.POINTER(vrm_counters)]
@@ -250,6 +260,23 @@ class Context:
     def vrm_step(self, cloud: Cloud, p: vrm_params, vort=None, t=0.0):
         _check(lib().vrm_step(self.handle, ctypes.byref(cloud.c), ctypes.byref(p), _ptr(vort),
                               int(vort.shape[0]) if vort is not None else 0, float(t)))
+
+    def vrm_set_tuning(self, tuning=None):
+        """Launch shapes from a dict of vrm_tuning fields (missing or 0: default); None: defaults."""
+        if tuning is None:
+            _check(lib().vrm_set_tuning(self.handle, None))
+            return
+        t = vrm_tuning()
+        for k, v in tuning.items():
+            if k not in vrm_tuning.FIELDS:
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        _check(lib().vrm_set_tuning(self.handle, ctypes.byref(t)))
+
+    def vrm_get_tuning(self) -> dict:
+        t = vrm_tuning()
+        _check(lib().vrm_get_tuning(self.handle, ctypes.byref(t)))
+        return {k: getattr(t, k) for k in vrm_tuning.FIELDS}
 
     def vrm_set_graph(self, enable: bool):
         _check(lib().vrm_set_graph(self.handle, 1 if enable else 0))

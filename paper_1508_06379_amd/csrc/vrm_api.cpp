@@ -155,6 +155,7 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
     vrm_ctx* c = new vrm_ctx();
     std::memset(c, 0, sizeof(*c));
     c->graph_enabled = 1;
+    vrm_set_tuning(c, nullptr);
     c->device = device;
     c->stream = (hipStream_t)stream;
     c->capacity = capacity;
@@ -455,7 +456,7 @@ void drop_graph(vrm_ctx* c)
 
 // What a captured step depends on besides the device state it reads.
 void graph_key(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, const float* vort_dev, int32_t n_vort,
-               unsigned char (&key)[160])
+               unsigned char (&key)[192])
 {
     std::memset(key, 0, sizeof(key));
     size_t o = 0;
@@ -471,6 +472,7 @@ void graph_key(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, const float
     put(flags, sizeof(flags));
     const void* mp = c->mlp;
     put(&mp, sizeof(mp));
+    put(&c->tuning, sizeof(vrm_tuning));
 }
 
 }  // namespace
@@ -487,6 +489,34 @@ int vrm_rk_stage(vrm_ctx* c, vrm_cloud* cl, const float* u_dev, const float* v_d
     if (!r && stage > 0 && !c->base_valid) r = vrm_fail(VRM_E_STATE, "stage %d before stage 0", stage);
     if (r) return r;
     return stage_launch(c, cl, u_dev, v_dev, p, stage, c->n);
+}
+
+int vrm_set_tuning(vrm_ctx* c, const vrm_tuning* t)
+{
+    if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
+    vrm_tuning d{};
+    d.lp_small_blocks = 2048;
+    d.lp_full_blocks = 1024;
+    d.full_stored_cost_n = 200000;
+    d.infer_blocks = 512;
+    if (t) {
+        if (t->lp_small_blocks < 0 || t->lp_full_blocks < 0 || t->infer_blocks < 0 || t->full_stored_cost_n < -1 ||
+            t->lp_small_blocks > (1 << 20) || t->lp_full_blocks > (1 << 22) || t->infer_blocks > (1 << 20))
+            return vrm_fail(VRM_E_ARG, "tuning values out of range");
+        if (t->lp_small_blocks) d.lp_small_blocks = t->lp_small_blocks;
+        if (t->lp_full_blocks) d.lp_full_blocks = t->lp_full_blocks;
+        if (t->full_stored_cost_n) d.full_stored_cost_n = t->full_stored_cost_n;
+        if (t->infer_blocks) d.infer_blocks = t->infer_blocks;
+    }
+    c->tuning = d;
+    return VRM_OK;
+}
+
+int vrm_get_tuning(vrm_ctx* c, vrm_tuning* out)
+{
+    if (!c || !out) return vrm_fail(VRM_E_ARG, "NULL argument");
+    *out = c->tuning;
+    return VRM_OK;
 }
 
 int vrm_set_graph(vrm_ctx* c, int enable)
@@ -521,7 +551,7 @@ int vrm_step(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p, const float* vort_d
     if (!c->graph_enabled || c->timing || c->graph_failed[0] || n <= 0)
         return step_stages(c, cl, p, vort_dev, n_vort, t, nullptr, n);
 
-    unsigned char key[160];
+    unsigned char key[192];
     graph_key(c, cl, p, vort_dev, n_vort, key);
     const int f0[3] = {c->cells_valid, c->sorted, c->base_valid};
     if (!c->graph_exec || n > c->graph_nb || std::memcmp(key, c->graph_key, sizeof(key)) != 0 ||

@@ -227,12 +227,10 @@ int scan_cells(vrm_ctx* c, int32_t* start)
 // are equal up to round-off form one group (whole groups are left out).
 __device__ __forceinline__ uint32_t selection_key(float a) { return __float_as_uint(a) & 0xffffff00u; }
 
-__global__ void k_sel_init(SelectState* s, vrm_counters* cnt)
+__global__ void k_sel_init(SelectState* s)
 {
     int t = threadIdx.x;
     if (t == 0) {
-        cnt->n_diffused = 0;
-        s->blocks_done = 0u;
         s->norm1 = 0.0;
         s->bound = 0.0;
         s->prefix = 0.0;
@@ -244,16 +242,39 @@ __global__ void k_sel_init(SelectState* s, vrm_counters* cnt)
     s->bin_cnt[t] = 0u;
 }
 
+__global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ g, int n, SelectState* s, int shift)
+{
+    __shared__ double h_sum[256];
+    __shared__ uint32_t h_cnt[256];
+    h_sum[threadIdx.x] = 0.0;
+    h_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    if (!s->done) {
+        uint32_t pre = s->key_prefix;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            float a = fabsf(g[i]);
+            uint32_t key = selection_key(a);
+            if (shift < 24 && (key >> (shift + 8)) != (pre >> (shift + 8))) continue;
+            int b = (key >> shift) & 255u;
+            atomicAdd(&h_sum[b], (double)a);
+            atomicAdd(&h_cnt[b], 1u);
+        }
+    }
+    __syncthreads();
+    if (h_cnt[threadIdx.x]) {
+        atomicAdd(&s->bin_sum[threadIdx.x], h_sum[threadIdx.x]);
+        atomicAdd(&s->bin_cnt[threadIdx.x], h_cnt[threadIdx.x]);
+    }
+}
+
 // Pick the bin where the cumulative sum first exceeds the bound (256 threads,
-// one bin each; an FP64 block scan in bin order).  Run by the last block of
-// the histogram pass.
-__device__ void sel_pick(SelectState* s, int shift, double factor)
+// one bin each; an FP64 block scan in bin order).
+__global__ __launch_bounds__(256) void k_sel_pick(SelectState* s, int shift, double factor)
 {
     __shared__ double wtot[4];
     __shared__ int first;
     const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
-    // the other blocks' atomic sums, read at device scope
-    double v = __hip_atomic_load(&s->bin_sum[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double v = s->bin_sum[t];
     // inclusive scan of the bin sums (the same association in every run)
     double incl = v;
     for (int o = 1; o < 64; o <<= 1) {
@@ -303,42 +324,6 @@ __device__ void sel_pick(SelectState* s, int shift, double factor)
     s->bin_cnt[t] = 0u;
 }
 
-__global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ g, int n, SelectState* s, int shift,
-                                                  double factor)
-{
-    __shared__ double h_sum[256];
-    __shared__ uint32_t h_cnt[256];
-    h_sum[threadIdx.x] = 0.0;
-    h_cnt[threadIdx.x] = 0u;
-    __syncthreads();
-    if (!s->done) {
-        uint32_t pre = s->key_prefix;
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-            float a = fabsf(g[i]);
-            uint32_t key = selection_key(a);
-            if (shift < 24 && (key >> (shift + 8)) != (pre >> (shift + 8))) continue;
-            int b = (key >> shift) & 255u;
-            atomicAdd(&h_sum[b], (double)a);
-            atomicAdd(&h_cnt[b], 1u);
-        }
-    }
-    __syncthreads();
-    if (h_cnt[threadIdx.x]) {
-        atomicAdd(&s->bin_sum[threadIdx.x], h_sum[threadIdx.x]);
-        atomicAdd(&s->bin_cnt[threadIdx.x], h_cnt[threadIdx.x]);
-    }
-    // the last block to merge its counts picks the bin
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&s->blocks_done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    sel_pick(s, shift, factor);
-    if (threadIdx.x == 0) s->blocks_done = 0u;
-}
-
 __global__ __launch_bounds__(256) void k_sel_mask(const float* __restrict__ g, int n, const SelectState* s,
                                                   uint8_t* diffused, uint8_t* mask_out, vrm_counters* cnt)
 {
@@ -354,6 +339,7 @@ __global__ __launch_bounds__(256) void k_sel_mask(const float* __restrict__ g, i
     if (lane_id() == 0 && m) atomicAdd(&cnt->n_diffused, __popcll(m));
 }
 
+__global__ void k_zero_diffused_count(vrm_counters* cnt) { cnt->n_diffused = 0; }
 
 // ------------------------------------------------------------ insertion
 __device__ __forceinline__ int wave_append_n(int* counter, int want)
@@ -694,10 +680,13 @@ int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* i
 int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double factor)
 {
     hipStream_t s = c->stream;
-    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c->sel, c->counters);
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c->sel);
     int nb = min(2048, blocks_for(n));
-    for (int shift = 24; shift >= 8; shift -= 8)   // the ranking key has no bits below 8
-        hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, s, gamma, n, c->sel, shift, factor);
+    for (int shift = 24; shift >= 8; shift -= 8) {   // the ranking key has no bits below 8
+        if (n > 0) hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, s, gamma, n, c->sel, shift);
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, c->sel, shift, factor);
+    }
+    hipLaunchKernelGGL(k_zero_diffused_count, dim3(1), dim3(1), 0, s, c->counters);
     if (n > 0)
         hipLaunchKernelGGL(k_sel_mask, dim3(blocks_for(n)), dim3(256), 0, s, gamma, n, c->sel, c->diffused,
                            (uint8_t*)nullptr, c->counters);

@@ -47,7 +47,7 @@ struct SelectState {
     uint32_t key_prefix;   // resolved high bits of the threshold key
     uint32_t done;         // 1 once the threshold is known
     uint32_t threshold;    // particles with key < threshold are left out
-    uint32_t blocks_done;  // blocks of the current histogram pass that have merged their counts
+    uint32_t pad;
     double bin_sum[256];
     uint32_t bin_cnt[256];
 };
@@ -140,9 +140,10 @@ struct vrm_ctx {
     int graph_flags[3];          // cells_valid, sorted, base_valid after the stages
     hipGraph_t graph;
     hipGraphExec_t graph_exec;
-    unsigned char graph_key[160];
+    unsigned char graph_key[192];
     double* t_dev;               // step start time read by the graph's velocity kernels
     int32_t* prev;               // [cap][9] basis (column ids) of each particle's last stencil, by id
+    vrm_tuning tuning;           // launch shapes in force (defaults filled in)
     hipStream_t cap_stream;      // stream the graph is captured on (the context's may be the null stream)
     // warm-start network (allocated on first use)
     vrm::MlpState* mlp;

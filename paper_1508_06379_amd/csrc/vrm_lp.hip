@@ -760,12 +760,15 @@ __global__ void k_status_init(int n, const uint8_t* __restrict__ diffused, Stenc
     }
 }
 
-// clouds up to this size launch the complete-LP kernel with stored costs
-constexpr int kLpFullSmallCloud = 200000;
-
-// persistent launches: enough threads for every CU, each loops over its items
-int lp_grid_small(int n) { return n > 0 ? min((n + 255) / 256, 256 * 8) : 1; }
-int lp_grid_full(int n) { return n > 0 ? min((n + kFullBlock - 1) / kFullBlock, 256 * 4) : 1; }
+// persistent launches: enough threads for every CU (at most the tuned number
+// of workgroups), each loops over its items
+int lp_grid_small(const vrm_ctx* c, int n) { return n > 0 ? min((n + 255) / 256, c->tuning.lp_small_blocks) : 1; }
+int lp_grid_full(const vrm_ctx* c, int n)
+{
+    return n > 0 ? min((n + kFullBlock - 1) / kFullBlock, c->tuning.lp_full_blocks) : 1;
+}
+// clouds up to the tuned size launch the complete-LP kernel with stored costs
+bool full_stored_costs(const vrm_ctx* c, int n) { return n <= c->tuning.full_stored_cost_n; }
 
 }  // namespace
 
@@ -824,7 +827,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         if (lp.m == 5) {
             r = vrm_mlp_infer_small_run(c, n, &c->queues->n_small, c->srec, lp.sc, lp.q, c->pred);
         } else {
-            hipLaunchKernelGGL(k_feat_full, dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->xs, c->ys, c->ids,
+            hipLaunchKernelGGL(k_feat_full, dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->xs, c->ys, c->ids,
                                c->cell_start, c->grid, c->q_full, c->queues, lp, c->feat);
             VRM_HIP(hipGetLastError());
             r = vrm_mlp_infer_run(c, c->feat, n, c->pred, &c->queues->n_full);
@@ -838,7 +841,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         {
             ScopedTimer tm(c, VRM_T_LP_SMALL);
             for (int mode = first; mode <= (warm ? kLpRetry : kLpPlain); ++mode) {
-                hipLaunchKernelGGL(k_lp_small, dim3(lp_grid_small(n)), dim3(kSmallBlock), 0, c->stream, c->perm, c->xs,
+                hipLaunchKernelGGL(k_lp_small, dim3(lp_grid_small(c, n)), dim3(kSmallBlock), 0, c->stream, c->perm, c->xs,
                                    c->ys, c->ids, c->srec, c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc,
                                    lp, out, apply, c->counters, mode, c->q_retry);
                 VRM_HIP(hipGetLastError());
@@ -850,14 +853,14 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         o2.feat = nullptr;
         o2.lab = nullptr;
         ScopedTimer tm(c, VRM_T_LP_FULL);
-        hipLaunchKernelGGL((n <= kLpFullSmallCloud ? k_lp_full<5, true> : k_lp_full<5, false>), dim3(min(lp_grid_full(n), 64)), dim3(kFullBlock), 0, c->stream, c->perm,
+        hipLaunchKernelGGL((full_stored_costs(c, n) ? k_lp_full<5, true> : k_lp_full<5, false>), dim3(min(lp_grid_full(c, n), 64)), dim3(kFullBlock), 0, c->stream, c->perm,
                            c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                            o2, apply, c->counters, kLpPlain, c->q_retry, 1);
     } else {
         ScopedTimer tm(c, VRM_T_LP_FULL);
         const int last = warm ? kLpRetry : kLpPlain;
         for (int mode = first; mode <= last; ++mode) {
-            hipLaunchKernelGGL((n <= kLpFullSmallCloud ? k_lp_full<9, true> : k_lp_full<9, false>), dim3(lp_grid_full(n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
+            hipLaunchKernelGGL((full_stored_costs(c, n) ? k_lp_full<9, true> : k_lp_full<9, false>), dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
                                c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                                out, apply, c->counters, mode, c->q_retry, mode == last ? 1 : 0);
             VRM_HIP(hipGetLastError());

@@ -491,7 +491,7 @@ int vrm_mlp_infer_small_run(vrm_ctx* c, int rows, const int* rows_dev, const Sma
     if (rows <= 0) return VRM_OK;
     MlpState* m = c->mlp;
     int tiles = (rows + FR - 1) / FR;
-    int grid = tiles < 256 * 2 ? tiles : 256 * 2;
+    int grid = tiles < c->tuning.infer_blocks ? tiles : c->tuning.infer_blocks;
     hipLaunchKernelGGL(k_mlp_infer_small, dim3(grid), dim3(256), 0, c->stream, rows_dev, rec, sc, q, m->wt, m->w, L);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
@@ -502,7 +502,7 @@ int vrm_mlp_infer_run(vrm_ctx* c, const uint16_t* X, int rows, float* Y, const i
     if (rows <= 0) return VRM_OK;
     MlpState* m = c->mlp;
     int tiles = (rows + FR - 1) / FR;
-    int grid = tiles < 256 * 2 ? tiles : 256 * 2;
+    int grid = tiles < c->tuning.infer_blocks ? tiles : c->tuning.infer_blocks;
     hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, c->stream, rows, rows_dev, X, m->wt, m->w, Y);
     VRM_HIP(hipGetLastError());
     return VRM_OK;

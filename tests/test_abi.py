@@ -59,8 +59,10 @@ int main(void) {
   printf("vrm_cloud %zu\\n", sizeof(vrm_cloud));
   printf("vrm_stencils %zu\\n", sizeof(vrm_stencils));
   printf("vrm_counters %zu\\n", sizeof(vrm_counters));
+  printf("vrm_tuning %zu\\n", sizeof(vrm_tuning));
   P(vrm_params, q) P(vrm_cloud, capacity) P(vrm_stencils, full_f_dev)
   P(vrm_counters, pivots) P(vrm_counters, redistributions) P(vrm_counters, mis_rounds) P(vrm_counters, full_cols)
+  P(vrm_counters, graph_replays) P(vrm_tuning, infer_blocks)
   return 0;
 }
 """)
@@ -78,6 +80,9 @@ int main(void) {
     assert int(out["vrm_counters.redistributions"]) == vrm.vrm_counters.redistributions.offset
     assert int(out["vrm_counters.mis_rounds"]) == vrm.vrm_counters.mis_rounds.offset
     assert int(out["vrm_counters.full_cols"]) == vrm.vrm_counters.full_cols.offset
+    assert int(out["vrm_counters.graph_replays"]) == vrm.vrm_counters.graph_replays.offset
+    assert int(out["vrm_tuning"]) == ctypes.sizeof(vrm.vrm_tuning)
+    assert int(out["vrm_tuning.infer_blocks"]) == vrm.vrm_tuning.infer_blocks.offset
 
 
 def test_product_path_has_no_cpu_fallback():
