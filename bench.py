@@ -108,13 +108,18 @@ def train_network(name, seeds, epochs):
                      range(seeds))
     t1 = time.perf_counter()
     ctx = vrm.Context(64)
-    hist = L.train(ctx, X, Y, epochs=epochs, batch=4096, lr=1e-3, weight_decay=1e-4, seed=spec["q"])
+    # 9-row bases learn better with a light fraction term and a higher rate
+    wf, lr = (1.0, 1e-3) if spec["q"] == 2 else (0.1, 3e-3)
+    if spec["q"] == 3:
+        epochs = max(epochs, 20)
+    hist = L.train(ctx, X, Y, epochs=epochs, batch=4096, lr=lr, weight_decay=1e-4, frac_weight=wf, seed=spec["q"])
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     acc = L.basis_accuracy(ctx, X[:200000], Y[:200000], spec["q"])
     theta = torch.zeros(vrm.MLP_PARAMS, device="cuda")
     ctx.vrm_mlp_read(theta)
-    info = {"rows": int(X.shape[0]), "snapshots": seeds, "generator": spec, "epochs": epochs,
+    info = {"rows": int(X.shape[0]), "snapshots": seeds, "generator": spec, "epochs": epochs, "lr": lr,
+            "fraction_loss_weight": wf,
             "loss_first_last": [round(hist[0], 4), round(hist[-1], 4)], "train_basis_accuracy": round(acc, 4),
             "collect_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)}
     return theta, info

@@ -221,7 +221,10 @@ struct ThreadSimplex {
     {
         const int kk = cs.k < 32 ? cs.k : 32;
         uint64_t chosen = dead;
-        for (int t = 0; t < M; ++t) {
+        // columns enter by decreasing preference until the basis is complete or
+        // the candidates run out (a dependent column is passed over)
+        int entered = 0;
+        for (int t = 0; t < kk && entered < M; ++t) {
             int best = -1;
             float bl = 0.0f;
             if (use_pref) {
@@ -268,6 +271,7 @@ struct ThreadSimplex {
             if (l < 0 || am <= 1e-4f * amax) continue;   // dependent on the columns already in
             pivot(l, best, alpha, c);
             ++piv;
+            ++entered;
         }
         const float tol = 1e-4f * bt_;
 #pragma unroll
@@ -624,11 +628,14 @@ struct ThreadSimplex {
 // *certified = 0 if optimality could not be shown.
 // Warm pass (warm_pass): the simplex starts from the crash basis of the
 // prediction (logits of the first 32 columns, or the column set pref with
-// use_pref); a rejected crash basis, or one that needs more than kWarmCap
+// use_pref); a rejected crash basis, or one that needs more than warm_cap<M>()
 // phase-II pivots, is given up (status 4).  basis: the final basic columns.
 // warm = 0 cold, 1 the predicted basis was optimal, 2 phase II from it,
 // 3 given up.
-constexpr int kWarmCap = 3;
+// phase-II pivots allowed from a predicted basis in the warm pass: a few for
+// 5-row LPs (a cold solve takes ~8), more for 9-row ones (~30)
+template <int M>
+constexpr int warm_cap() { return M == 5 ? 3 : 12; }
 
 template <int M, class CS, class Store>
 __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified,
@@ -648,7 +655,7 @@ __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float&
             return 4;
         }
         const int p1 = piv;
-        st = lp.run(cs, piv, 2, kWarmCap);
+        st = lp.run(cs, piv, 2, warm_cap<M>());
         if (st == 2) {
             warm = 3;
             return 4;
