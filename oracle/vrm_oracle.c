@@ -713,15 +713,22 @@ int orc_insert(int n, int cap, double* x, double* y, double* gamma, int32_t* id,
         if (t == 0 || c[t].x > bx1) bx1 = c[t].x;
         if (t == 0 || c[t].y > by1) by1 = c[t].y;
     }
+    /* any cell edge >= 0.5 h keeps the 3 x 3 search exact: widen the cells until
+     * the bucket array stays below 50M entries */
     double ce = 0.5 * P->h * 1.001;
-    long long gnx = (long long)((bx1 - bx0) / ce) + 3, gny = (long long)((by1 - by0) / ce) + 3;
-    if (gnx * gny > 50000000LL) { gnx = 1; gny = 1; ce = 1e300; }   /* degenerate: plain scan */
+    long long gnx, gny;
+    for (;;) {
+        gnx = (long long)((bx1 - bx0) / ce) + 3;
+        gny = (long long)((by1 - by0) / ce) + 3;
+        if (gnx * gny <= 50000000LL) break;
+        ce *= 1.25;
+    }
     int* head = (int*)malloc(sizeof(int) * (size_t)(gnx * gny));
     int* next = (int*)malloc(sizeof(int) * (size_t)(ncand > 0 ? ncand : 1));
     for (long long q = 0; q < gnx * gny; ++q) head[q] = -1;
     for (int t = 0; t < ncand; ++t) {
-        long long cxq = gnx > 1 ? (long long)((c[t].x - bx0) / ce) + 1 : 0;
-        long long cyq = gny > 1 ? (long long)((c[t].y - by0) / ce) + 1 : 0;
+        long long cxq = (long long)((c[t].x - bx0) / ce) + 1;
+        long long cyq = (long long)((c[t].y - by0) / ce) + 1;
         int ok = 1;
         for (long long oy = -1; oy <= 1 && ok; ++oy) {
             long long yy = cyq + oy;
