@@ -1,0 +1,300 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times
+(capacity, autotuned launch shapes, graph-replayed vrm_step).
+
+* Lamb-Oseen, h = 0.01 (40k particles, jittered +-0.25h, insertion on):
+  whole runs of the native step against whole oracle runs; Gamma within
+  1e-5 relative L2 (particles matched by id), the same particle count,
+  circulation conserved.  Plain solver and previous-basis warm start.
+* 64 vortices, h = 0.005 (2.05M particles, 3.5M after insertion): one whole
+  step with the particles held still (Gamma within 1e-5), and one with the
+  prescribed velocity, where positions differ by rounding and the few
+  stencils that switch are located and bounded.
+* Stencils on the 3.5M and 16M clouds: the FP64 moment residual of every GPU
+  stencil, and a random sample of diffused particles whose stencils the
+  oracle computes one by one (same status, same support, fractions within
+  1e-6).
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vrm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1508_06379_amd as v
+    v.lib()
+    return v
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+FULL = {
+    "lamb_oseen_h0.01_q2": lambda: workloads.config_jittered(h=0.01, q=2, seed=2),
+    "lamb_oseen_h0.01_q3": lambda: workloads.config_jittered(h=0.01, q=3, seed=2),
+    "vortices64_h0.005": lambda: workloads.config_vortices(),
+    "vortices256_h0.004_q3": lambda: workloads.config_scale(),
+}
+
+
+def _context(vrm, name, wl, warm_mode=0):
+    """Cloud and context exactly as the benchmark builds them."""
+    from paper_1508_06379_amd import autotune
+    cap = int(wl.n * (4 if wl.n < 200000 else 2.2)) + 1024
+    cloud = vrm.Cloud(wl.x, wl.y, wl.gamma, capacity=cap)
+    ctx = vrm.Context(cap)
+    tuning = autotune.load(name)
+    if tuning:
+        ctx.vrm_set_tuning(tuning)
+    if warm_mode:
+        ctx.vrm_set_warm_start(warm_mode)
+    return cloud, ctx
+
+
+def _rel_l2_by_id(ids, g, rids, rg):
+    a = dict(zip(ids.tolist(), g.astype(np.float64).tolist()))
+    b = dict(zip(rids.tolist(), rg.tolist()))
+    keys = set(a) | set(b)
+    d = np.array([a.get(k, 0.0) - b.get(k, 0.0) for k in keys])
+    return np.linalg.norm(d) / np.linalg.norm(rg)
+
+
+_REF = {}
+
+
+def _oracle_run(orc, name, steps):
+    key = (name, steps)
+    if key not in _REF:
+        _say("oracle run", name, steps, "steps")
+        _REF[key] = orc.run(FULL[name](), steps=steps)
+    return _REF[key]
+
+
+def _gpu_run(vrm, name, wl, steps, warm_mode):
+    cloud, ctx = _context(vrm, name, wl, warm_mode)
+    vt = vrm.vortex_table(wl.vortices) if wl.vortices is not None else None
+    P = vrm.params_of(wl)
+    t = wl.t0
+    for _ in range(steps):
+        ctx.vrm_step(cloud, P, vt, t)
+        t += wl.dt
+    torch.cuda.synchronize()
+    return cloud.numpy(), ctx.vrm_read_counters()
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("warm_mode", [0, 2])
+@pytest.mark.parametrize("name,steps", [("lamb_oseen_h0.01_q2", 100), ("lamb_oseen_h0.01_q3", 25)])
+def test_full_size_run_matches_oracle(vrm, orc, name, steps, warm_mode):
+    """Sec. 3.3-3.4 and 4: whole runs at h = 0.01 (insertion on), Gamma within 1e-5
+    relative L2 of the FP64 oracle, same particle count, circulation kept."""
+    wl = FULL[name]()
+    _say("case", name, "steps", steps, "warm mode", warm_mode, "N0", wl.n)
+    (x, y, g, ids), cnt = _gpu_run(vrm, name, wl, steps, warm_mode)
+    ref = _oracle_run(orc, name, steps)
+    err = _rel_l2_by_id(ids, g, ref.ids, ref.gamma)
+    _say(name, "N", x.size, ref.x.size, "rel L2", err, "uncertified", cnt["n_uncertified"],
+         "infeasible", cnt["n_infeasible"])
+    assert x.size == ref.x.size
+    np.testing.assert_array_equal(np.sort(ids), np.sort(ref.ids))
+    assert err <= 1e-5
+    g0 = np.abs(wl.gamma).astype(np.float64).sum()
+    assert abs(g.astype(np.float64).sum() - wl.gamma.astype(np.float64).sum()) <= 1e-5 * g0
+
+
+@pytest.mark.timeout(400)
+def test_vortex_cloud_whole_step_matches_oracle(vrm, orc):
+    """One whole step of the 64-vortex cloud (2.05M particles, insertion to 3.5M)
+    with the particles held still: both sides see the same geometry in every stage,
+    so Gamma must match the oracle within 1e-5 relative L2."""
+    name = "vortices64_h0.005"
+    wl = FULL[name]()
+    wl.vortices = None
+    _say("case", name, "zero velocity, one step, N0", wl.n)
+    (x, y, g, ids), cnt = _gpu_run(vrm, name, wl, 1, 0)
+    _say("gpu done", cnt)
+    _say("oracle step")
+    ref = orc.run(wl, steps=1)
+    assert x.size == ref.x.size
+    o = np.argsort(ids)
+    np.testing.assert_array_equal(ids[o], ref.ids)
+    err = _rel_l2_by_id(ids, g, ref.ids, ref.gamma)
+    _say(name, "N", x.size, "rel L2", err)
+    assert err <= 1e-5
+    g0 = np.abs(wl.gamma).astype(np.float64).sum()
+    assert abs(g.astype(np.float64).sum() - wl.gamma.astype(np.float64).sum()) <= 1e-5 * g0
+
+
+def _jump_clusters(px, py, jump, radius):
+    """Connected groups of the flagged particles, linked within `radius`."""
+    from scipy.spatial import cKDTree
+    idx = np.flatnonzero(jump)
+    if idx.size == 0:
+        return 0
+    tree = cKDTree(np.c_[px[idx], py[idx]])
+    label = np.full(idx.size, -1)
+    n = 0
+    for i in range(idx.size):
+        if label[i] >= 0:
+            continue
+        label[i] = n
+        stack = [i]
+        while stack:
+            j = stack.pop()
+            for k in tree.query_ball_point([px[idx[j]], py[idx[j]]], radius):
+                if label[k] < 0:
+                    label[k] = n
+                    stack.append(k)
+        n += 1
+    return n
+
+
+@pytest.mark.timeout(400)
+def test_moving_vortex_cloud_whole_step(vrm, orc):
+    """One whole step of the 64-vortex cloud moving with the prescribed velocity.
+
+    Once particles move, the GPU holds positions in FP32 and the oracle in FP64:
+    they differ by about one unit in the last place.  The stencils depend on the
+    geometry discontinuously (segment membership by angle, the neighbourhood
+    radius, the optimal vertex of the LP), so a handful of the millions of LPs
+    land on another stencil; each such switch moves Gamma by O(nu dt / h^2 Gamma)
+    on the few particles of that stencil and nowhere else.  Elsewhere Gamma
+    depends smoothly on the positions, with sensitivity nu dt / h^2 * |dx| / h
+    (about 1.4e-5 here).  So the test asks for: identical ids (insertion sees the
+    same geometry on both sides), positions within 4 units in the last place (of |x| + h),
+    FP64 moment residual of the GPU stencils at the new positions <= 1e-6,
+    circulation kept, at most one switched stencil per 10^4 LP solves (groups of
+    particles whose Gamma jumps by more than 1e-4 max|Gamma|), and outside 3h of
+    those groups Gamma within 2e-5 relative L2 of the oracle's."""
+    name = "vortices64_h0.005"
+    wl = FULL[name]()
+    _say("case", name, "moving, one step, N0", wl.n)
+    cloud, ctx = _context(vrm, name, wl)
+    P = vrm.params_of(wl)
+    ctx.vrm_step(cloud, P, vrm.vortex_table(wl.vortices), wl.t0)
+    st = vrm.Stencils.alloc(cloud.capacity)
+    ctx.vrm_solve_fractions(cloud, P, st)
+    rep = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ctx.vrm_verify(cloud, P, st, rep)
+    torch.cuda.synchronize()
+    cnt = ctx.vrm_read_counters()
+    x, y, g, ids = cloud.numpy()
+    res = float(rep[0].item())
+    _say("gpu done", cnt, "moment residual at the new positions", res)
+    del st, cloud, ctx
+    _say("oracle step")
+    ref = orc.run(wl, steps=1)
+    assert x.size == ref.x.size
+    o = np.argsort(ids)
+    np.testing.assert_array_equal(ids[o], ref.ids)
+    x, y, g = x[o].astype(np.float64), y[o].astype(np.float64), g[o].astype(np.float64)
+    # units in the last place of the stage sums' terms (|x| and a displacement below h)
+    ulp_x = np.spacing((np.abs(ref.x) + wl.h).astype(np.float32)).astype(np.float64)
+    ulp_y = np.spacing((np.abs(ref.y) + wl.h).astype(np.float32)).astype(np.float64)
+    dx = max(np.max(np.abs(x - ref.x) / ulp_x), np.max(np.abs(y - ref.y) / ulp_y))
+    assert res <= 1e-6
+    d = np.abs(g - ref.gamma)
+    jump = d > 1e-4 * np.abs(ref.gamma).max()
+    groups = _jump_clusters(ref.x, ref.y, jump, 3 * wl.h)
+    n_lp = cnt["n_small"] + cnt["n_full"]
+    from scipy.spatial import cKDTree
+    near = np.zeros(x.size, bool)
+    if jump.any():
+        hits = cKDTree(np.c_[ref.x[jump], ref.y[jump]]).query(np.c_[ref.x, ref.y], distance_upper_bound=3 * wl.h)[0]
+        near = np.isfinite(hits)
+    keep = ~near
+    err_all = np.linalg.norm(d) / np.linalg.norm(ref.gamma)
+    err_rest = np.linalg.norm(d[keep]) / np.linalg.norm(ref.gamma[keep])
+    _say(name, "N", x.size, "max |dx| in ulps", dx, "rel L2", err_all, "switched-stencil groups", groups,
+         "of", n_lp, "LPs; particles within 3h of them", int(near.sum()), "rel L2 elsewhere", err_rest)
+    assert dx <= 4.0
+    assert groups <= 1e-4 * n_lp
+    assert near.sum() <= 0.01 * x.size
+    assert err_rest <= 2e-5
+    g0 = np.abs(wl.gamma).astype(np.float64).sum()
+    assert abs(g.sum() - wl.gamma.astype(np.float64).sum()) <= 1e-5 * g0
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("name", ["vortices64_h0.005", "vortices256_h0.004_q3"])
+def test_sampled_stencils_at_full_size(vrm, orc, name):
+    """Sec. 2, 4.1-4.3 on the whole cloud after insertion: FP64 moment residual of
+    every stencil <= 1e-6 and circulation of the GPU operator kept; 1500 random
+    diffused particles whose stencils the oracle solves one by one match the
+    GPU's status and support, fractions within 1e-6."""
+    _say("case", name, "generating the cloud")
+    wl = FULL[name]()
+    _say("N0", wl.n)
+    # the sample: diffused particles of the input cloud (ids = input indices)
+    po = orc.params_of(wl)
+    mask, _, _ = orc.diffused(wl.gamma, wl.ids, wl.h, wl.q)
+    rng = np.random.default_rng(17)
+    sample = rng.choice(np.flatnonzero(mask), 1500, replace=False)
+
+    cloud, ctx = _context(vrm, name, wl)
+    P = vrm.params_of(wl)
+    ctx.vrm_insert_particles(cloud, P)
+    st = vrm.Stencils.alloc(cloud.capacity)
+    ctx.vrm_solve_fractions(cloud, P, st)
+    rep = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ctx.vrm_verify(cloud, P, st, rep)
+    torch.cuda.synchronize()
+    res, i0, _, fmax = rep.cpu().numpy()
+    cnt = ctx.vrm_read_counters()
+    _say(name, "N", cloud.n, "max moment residual", res, "counters", cnt)
+    assert res <= 1e-6
+    assert abs(i0 - wl.gamma.astype(np.float64).sum()) <= 1e-6 * np.abs(wl.gamma).astype(np.float64).sum()
+    n = cloud.n
+    ids_dev = cloud.id[:n].long()
+    slot_dev = torch.empty(int(ids_dev.max().item()) + 1, dtype=torch.long, device="cuda")
+    slot_dev[ids_dev] = torch.arange(n, device="cuda")
+    rows = slot_dev[torch.as_tensor(sample, device="cuda")]
+    S = {k: getattr(st, k)[rows].cpu().numpy() for k in ("small_idx", "small_f", "fii", "status", "full_k",
+                                                        "full_idx", "full_f")}
+    ids = cloud.id[:n].cpu().numpy()
+    del st, cloud, ctx, slot_dev, rows, ids_dev
+    torch.cuda.empty_cache()
+
+    # the oracle inserts on its own from the same input, then solves the sample
+    _say("oracle insertion")
+    rx, ry, rg, rids, _ = orc.insert(wl.x.astype(np.float64), wl.y.astype(np.float64),
+                                     wl.gamma.astype(np.float64), wl.ids, mask, po)
+    assert rx.size == n
+    smask = np.zeros(rx.size, np.uint8)
+    smask[sample] = 1
+    _say("oracle stencils")
+    ref = orc.stencils(rx, ry, rids, smask, po)
+    bad, worst, n_full = [], 0.0, 0
+    for i, r in enumerate(sample):
+        pid = int(rids[r])
+        s = int(S["status"][i])
+        assert s == int(ref.status[r]), (pid, s, ref.status[r])
+        if s > 1:
+            continue
+        n_full += s == 1
+        if s == 0:
+            gc, gf = S["small_idx"][i], S["small_f"][i]
+        else:
+            k = S["full_k"][i]
+            gc, gf = S["full_idx"][i, :k], S["full_f"][i, :k]
+        gd = {int(ids[c]): float(v) for c, v in zip(gc, gf) if c >= 0 and v != 0.0}
+        k = ref.kcol[r]
+        rd = {int(rids[c]): float(v) for c, v in zip(ref.cols[r, :k], ref.f[r, :k]) if v != 0.0}
+        if set(gd) != set(rd):
+            bad.append(pid)
+            continue
+        for c, v in rd.items():
+            worst = max(worst, abs(gd[c] - v) / max(1.0, abs(v)))
+        worst = max(worst, abs(S["fii"][i] - ref.fii[r]) / max(1.0, abs(ref.fii[r])))
+    _say(name, "sampled", sample.size, "complete-neighbourhood LPs", n_full, "support mismatches", len(bad),
+         "worst rel diff", worst)
+    assert not bad, f"{len(bad)} stencils with a different support, e.g. ids {bad[:5]}"
+    assert worst <= 1e-6

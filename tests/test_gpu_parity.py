@@ -415,3 +415,37 @@ def test_previous_basis_warm_start(vrm, name):
     settled = cb["warm_hit"] + cb["warm_phase2"]
     assert settled >= 0.5 * (settled + cb["warm_cold"])
     assert cb["pivots"] < ca["pivots"]
+
+
+# ------------------------------------------------------------------ launch shapes
+@pytest.mark.parametrize("name", ["jittered_q2_h0.02", "jittered_q3_h0.02"])
+def test_launch_shapes_do_not_change_results(vrm, name):
+    """The tuning fields only size grids and pick where costs live: one-block grids,
+    costs always recomputed, costs always stored and the defaults give the same
+    stencils (Gamma after 3 steps up to the order of the atomic sums)."""
+    wl = CONFIGS[name]
+    P = vrm.params_of(wl)
+    shapes = [None,
+              {"lp_small_blocks": 1, "lp_full_blocks": 1, "full_stored_cost_n": -1, "infer_blocks": 1},
+              {"lp_small_blocks": 3, "lp_full_blocks": 5, "full_stored_cost_n": 1 << 30, "infer_blocks": 2}]
+    res = []
+    for tuning in shapes:
+        cloud = _gpu_cloud(vrm, wl, cap_factor=4)
+        ctx = vrm.Context(cloud.capacity)
+        ctx.vrm_set_tuning(tuning)
+        t = wl.t0
+        for _ in range(3):
+            ctx.vrm_step(cloud, P, None, t)
+            t += wl.dt
+        torch.cuda.synchronize()
+        res.append((cloud.numpy(), ctx.vrm_read_counters(), ctx.vrm_get_tuning()))
+    (xa, ya, ga, ia), ca, _ = res[0]
+    for (x, y, g, ids), cnt, tun in res[1:]:
+        _say("case shapes", name, tun, "rel diff", _rel_l2_by_id(ids, g, ia, ga))
+        assert x.size == xa.size
+        np.testing.assert_array_equal(np.sort(ids), np.sort(ia))
+        assert _rel_l2_by_id(ids, g, ia, ga) <= 1e-6
+        # the same LPs: pivot counts differ only where the atomic sums moved a
+        # particle across the selection threshold
+        assert cnt["n_infeasible"] == ca["n_infeasible"]
+        assert abs(cnt["pivots"] - ca["pivots"]) <= 0.01 * ca["pivots"]
