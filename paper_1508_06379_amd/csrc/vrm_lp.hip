@@ -57,19 +57,24 @@ __global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __rest
                                                     int32_t* q_full, Queues* qs,
                                                     int32_t* out_small_idx, int32_t* out_kfull, int want_kfull)
 {
+    // each thread's closest candidate per segment lives in LDS (indexed by the
+    // segment: no register selects per candidate)
+    __shared__ float s_bd[VRM_NSEG * 256];
+    __shared__ int s_best[VRM_NSEG * 256];
     if (n_dev) n = *n_dev;
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int tid = threadIdx.x;
+    int t = blockIdx.x * blockDim.x + tid;
     bool active = t < n;
     int i = active ? perm[t] : 0;
     bool dif = active && diffused[i];
     int best[VRM_NSEG];
-    float bd[VRM_NSEG];
     int kfull = 0;
     int ksmall = 0;
 #pragma unroll
     for (int s = 0; s < VRM_NSEG; ++s) {
         best[s] = -1;
-        bd[s] = INFINITY;
+        s_bd[s * 256 + tid] = INFINITY;
+        s_best[s * 256 + tid] = -1;
     }
     if (dif && (P.m <= VRM_NSEG || want_kfull)) {
         GridState g = *gs;
@@ -91,29 +96,28 @@ __global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __rest
                     if (d2 < P.lo2) continue;
                     if (d2 <= P.hi2f) ++kfull;
                     if (d2 > P.hi2) continue;
-                    int s = segment_f32(dx, dy);
-                    float cur = 0.0f;
-                    int cb = -1;
-#pragma unroll
-                    for (int k = 0; k < VRM_NSEG; ++k)
-                        if (k == s) {
-                            cur = bd[k];
-                            cb = best[k];
+                    const int at = segment_f32(dx, dy) * 256 + tid;
+                    const float cur = s_bd[at];
+                    if (d2 <= cur) {
+                        bool take = d2 < cur;
+                        if (!take) {
+                            // equal distance: the smaller id wins
+                            const int cb = s_best[at];
+                            take = cb >= 0 && ids[u] < ids[cb];
                         }
-                    bool take = d2 < cur || (d2 == cur && cb >= 0 && ids[u] < ids[cb]);
-                    if (take) {
-#pragma unroll
-                        for (int k = 0; k < VRM_NSEG; ++k)
-                            if (k == s) {
-                                bd[k] = d2;
-                                best[k] = u;
-                            }
+                        if (take) {
+                            s_bd[at] = d2;
+                            s_best[at] = u;
+                        }
                     }
                 }
             }
         }
 #pragma unroll
-        for (int s = 0; s < VRM_NSEG; ++s) ksmall += best[s] >= 0 ? 1 : 0;
+        for (int s = 0; s < VRM_NSEG; ++s) {
+            best[s] = s_best[s * 256 + tid];
+            ksmall += best[s] >= 0 ? 1 : 0;
+        }
     }
     if (active) {
         if (out_small_idx) {
