@@ -167,7 +167,7 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
     A(grid, 1);
     A(queues, 1);
     A(sel, 1);
-    A(counters, 1);
+    A(counters, (vrm::kCounterStripes * vrm::kCounterStride + sizeof(vrm_counters) - 1) / sizeof(vrm_counters));
     A(cell_of, cap);
     A(rank, cap);
     A(cell_start, nc);
@@ -213,7 +213,7 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
     }
     if (r == VRM_OK) {
         hipError_t e = hipMemsetAsync(c->acc, 0, cap * sizeof(float), c->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(c->counters, 0, sizeof(vrm_counters), c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->counters, 0, vrm::kCounterStripes * vrm::kCounterStride, c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->queues, 0, sizeof(vrm::Queues), c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->sel, 0, sizeof(vrm::SelectState), c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -622,8 +622,27 @@ int vrm_verify(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, const vrm_s
 int vrm_read_counters(vrm_ctx* c, vrm_counters* out)
 {
     if (!c || !out) return vrm_fail(VRM_E_ARG, "NULL argument");
-    VRM_HIP(hipMemcpyAsync(out, c->counters, sizeof(vrm_counters), hipMemcpyDeviceToHost, c->stream));
+    // the copies of the counters: accumulated fields are summed, assigned ones are in copy 0
+    static thread_local char buf[vrm::kCounterStripes * vrm::kCounterStride];
+    VRM_HIP(hipMemcpyAsync(buf, c->counters, sizeof(buf), hipMemcpyDeviceToHost, c->stream));
     VRM_HIP(hipStreamSynchronize(c->stream));
+    *out = *reinterpret_cast<const vrm_counters*>(buf);
+    for (int k = 1; k < vrm::kCounterStripes; ++k) {
+        const vrm_counters& s = *reinterpret_cast<const vrm_counters*>(buf + k * vrm::kCounterStride);
+        out->n_diffused += s.n_diffused;
+        out->n_small += s.n_small;
+        out->n_full += s.n_full;
+        out->n_infeasible += s.n_infeasible;
+        out->n_uncertified += s.n_uncertified;
+        out->n_truncated += s.n_truncated;
+        out->n_grid_clamped += s.n_grid_clamped;
+        out->pivots += s.pivots;
+        out->redistributions += s.redistributions;
+        out->full_cols += s.full_cols;
+        out->warm_hit += s.warm_hit;
+        out->warm_phase2 += s.warm_phase2;
+        out->warm_cold += s.warm_cold;
+    }
     out->n = c->n;
     out->graph_replays = c->graph_replays;
     return VRM_OK;

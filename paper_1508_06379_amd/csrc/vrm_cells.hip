@@ -327,6 +327,7 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelectState* s, int shift, dou
 __global__ __launch_bounds__(256) void k_sel_mask(const float* __restrict__ g, int n, const SelectState* s,
                                                   uint8_t* diffused, uint8_t* mask_out, vrm_counters* cnt)
 {
+    cnt = counter_stripe(cnt);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool d = false;
     if (i < n) {
@@ -339,24 +340,13 @@ __global__ __launch_bounds__(256) void k_sel_mask(const float* __restrict__ g, i
     if (lane_id() == 0 && m) atomicAdd(&cnt->n_diffused, __popcll(m));
 }
 
-__global__ void k_zero_diffused_count(vrm_counters* cnt) { cnt->n_diffused = 0; }
-
-// ------------------------------------------------------------ insertion
-__device__ __forceinline__ int wave_append_n(int* counter, int want)
+// one thread per counter copy
+__global__ void k_zero_diffused_count(vrm_counters* cnt)
 {
-    int lane = lane_id();
-    int incl = want;
-    for (int o = 1; o < 64; o <<= 1) {
-        int t = __shfl_up(incl, o, VRM_WAVE);
-        if (lane >= o) incl += t;
-    }
-    int total = __shfl(incl, 63, VRM_WAVE);
-    int base = 0;
-    if (lane == 0 && total) base = atomicAdd(counter, total);
-    base = __shfl(base, 0, VRM_WAVE);
-    return base + incl - want;
+    reinterpret_cast<vrm_counters*>(reinterpret_cast<char*>(cnt) + threadIdx.x * kCounterStride)->n_diffused = 0;
 }
 
+// ------------------------------------------------------------ insertion
 // Candidates: every empty segment of a diffused particle (slot order).
 __global__ __launch_bounds__(256) void k_candidates(int n, const int32_t* __restrict__ perm,
                                                     const float* __restrict__ xs, const float* __restrict__ ys,
@@ -394,9 +384,10 @@ __global__ __launch_bounds__(256) void k_candidates(int n, const int32_t* __rest
             }
         }
     }
+    __shared__ int s_app[17];
     int empty = (~occupied) & 0xff;
     int want = __popc(empty);
-    int base = wave_append_n(&qs->n_cand, want);
+    int base = block_append_n(&qs->n_cand, want, s_app);
     if (want) {
         int id = ids[t];
         int k = 0;
@@ -460,17 +451,18 @@ __global__ __launch_bounds__(256) void k_mis_round(int nc, const float* __restri
         else
             undecided = true;
     }
-    uint64_t m = __ballot(undecided);
-    if (lane_id() == 0 && m) atomicAdd(&qs->n_undecided, __popcll(m));
+    // a flag (the host only asks whether any candidate is left)
+    if (undecided) qs->n_undecided = 1;
 }
 
 __global__ __launch_bounds__(256) void k_accepted(int nc, const uint64_t* __restrict__ ckey,
                                                   const uint8_t* __restrict__ cstate, Queues* qs, uint64_t* akey,
                                                   int32_t* aidx)
 {
+    __shared__ int s_app[17];
     int a = blockIdx.x * blockDim.x + threadIdx.x;
     bool acc = a < nc && cstate[a] == 1;
-    int p = wave_append_n(&qs->n_accepted, acc ? 1 : 0);
+    int p = block_append_n(&qs->n_accepted, acc ? 1 : 0, s_app);
     if (acc) {
         akey[p] = ckey[a];
         aidx[p] = a;
@@ -686,7 +678,7 @@ int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double factor)
         if (n > 0) hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, s, gamma, n, c->sel, shift);
         hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, c->sel, shift, factor);
     }
-    hipLaunchKernelGGL(k_zero_diffused_count, dim3(1), dim3(1), 0, s, c->counters);
+    hipLaunchKernelGGL(k_zero_diffused_count, dim3(1), dim3(kCounterStripes), 0, s, c->counters);
     if (n > 0)
         hipLaunchKernelGGL(k_sel_mask, dim3(blocks_for(n)), dim3(256), 0, s, gamma, n, c->sel, c->diffused,
                            (uint8_t*)nullptr, c->counters);

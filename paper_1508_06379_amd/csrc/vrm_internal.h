@@ -9,6 +9,48 @@
 
 namespace vrm {
 
+// The device counters live in kCounterStripes copies, one per 256-byte line.
+// Accumulating kernels add to the copy of their workgroup, so that the waves of
+// a large launch do not queue on one address; vrm_read_counters sums the
+// copies.  Fields that are assigned (not accumulated) live in copy 0.
+constexpr int kCounterStripes = 64;
+constexpr size_t kCounterStride = (sizeof(vrm_counters) + 255) / 256 * 256;
+
+// Append `want` entries per thread to a queue whose tail is *counter: positions
+// follow the thread order of the workgroup, with one atomic per workgroup (a
+// large launch then does not queue on one address).  Every thread of the
+// workgroup must call it; s_tmp is __shared__ int[17].
+__device__ __forceinline__ int block_append_n(int* counter, int want, int* s_tmp)
+{
+    const int lane = __lane_id(), w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    int incl = want;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) s_tmp[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int k = 0; k < nw; ++k) {
+            const int c = s_tmp[k];
+            s_tmp[k] = tot;
+            tot += c;
+        }
+        s_tmp[16] = tot ? atomicAdd(counter, tot) : 0;
+    }
+    __syncthreads();
+    const int pos = s_tmp[16] + s_tmp[w] + incl - want;
+    __syncthreads();
+    return pos;
+}
+
+__device__ __forceinline__ vrm_counters* counter_stripe(vrm_counters* base)
+{
+    return reinterpret_cast<vrm_counters*>(reinterpret_cast<char*>(base) +
+                                           (size_t)(blockIdx.x % kCounterStripes) * kCounterStride);
+}
+
 // Grid of square cells over the bounding box of the cloud (device side).
 struct GridState {
     uint32_t bbox[4];      // ordered keys: min x, min y, max x, max y
@@ -21,7 +63,7 @@ struct Queues {
     int32_t n_small;       // items in the small-LP queue
     int32_t n_full;        // items in the complete-LP queue
     int32_t n_cand;        // insertion candidates
-    int32_t n_undecided;   // insertion candidates not yet decided
+    int32_t n_undecided;   // non-zero while insertion candidates are undecided
     int32_t n_accepted;    // accepted insertion candidates
     int32_t small_state;   // single-workgroup insertion: 0 not taken, 1 done, 2 capacity exceeded
     int32_t n_retry;       // LPs left by the warm pass for a cold solve

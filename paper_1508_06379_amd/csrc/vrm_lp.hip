@@ -128,8 +128,9 @@ __global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __rest
         if (out_kfull) out_kfull[i] = dif ? kfull : 0;
     }
     if (q_small) {
+        __shared__ int s_app[17];
         bool small_ok = dif && P.m <= VRM_NSEG && ksmall >= P.m;
-        int p1 = wave_append(&qs->n_small, small_ok);
+        int p1 = block_append_n(&qs->n_small, small_ok ? 1 : 0, s_app);
         if (small_ok) {
             q_small[p1] = t;
             rec.i[p1] = i;
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __rest
             rec.rank[p1] = packed;
         }
         bool full = dif && !small_ok;
-        int p2 = wave_append(&qs->n_full, full);
+        int p2 = block_append_n(&qs->n_full, full ? 1 : 0, s_app);
         if (full) q_full[p2] = t;
     }
 }
@@ -348,6 +349,7 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
     __shared__ float s_ylo[8 * kSmallBlock];
     __shared__ float s_c[8 * kSmallBlock];
     __shared__ int s_meta[8 * kSmallBlock];
+    cnt = counter_stripe(cnt);
     const int tid = threadIdx.x;
     const int nitems = mode == kLpRetry ? qs->n_retry : qs->n_small;
     const size_t cap = (size_t)rec.cap;
@@ -594,6 +596,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
     __shared__ float s_ry[VRM_KMAX * kFullBlock];
     __shared__ int s_meta[VRM_KMAX * kFullBlock];
     __shared__ float s_c[SC ? VRM_KMAX * kFullBlock : 1];
+    cnt = counter_stripe(cnt);
     const int tid = threadIdx.x;
     const int32_t* queue = mode == kLpRetry ? q_retry : q_full;
     const int nitems = mode == kLpRetry ? qs->n_retry : qs->n_full;
