@@ -64,13 +64,23 @@ def run_gpu(wl, steps, warmup, theta=None, warm_mode=0, tuning=None):
     vt = vrm.vortex_table(wl.vortices) if wl.vortices is not None else None
 
     t = wl.t0
-    for _ in range(warmup):
+    # warmup; its last step has every kernel group timed, to find the dominant
+    # one (the first step carries first-launch costs)
+    for k in range(warmup):
+        if k == warmup - 1:
+            torch.cuda.synchronize()
+            ctx.vrm_timing(True)
         ctx.vrm_step(cloud, P, vt, t)
         t += wl.dt
     torch.cuda.synchronize()
+    warm_timers, _ = ctx.vrm_read_timing()
+    ctx.vrm_timing(False)
+    dom = dominant_group(warm_timers, wl.q)
     c0 = ctx.vrm_read_counters()
     n0 = cloud.n
-    ctx.vrm_timing(True)
+    # timed region: HIP events around the dominant group's launches only (the
+    # other launches carry no events)
+    ctx.vrm_timing_groups([dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -83,8 +93,29 @@ def run_gpu(wl, steps, warmup, theta=None, warm_mode=0, tuning=None):
     c1 = ctx.vrm_read_counters()
     d = {k: c1[k] - c0[k] for k in ("redistributions", "pivots", "n_small", "n_full", "n_infeasible",
                                      "n_uncertified", "full_cols", "warm_hit", "warm_phase2", "warm_cold")}
+    # breakdown over every group, from a few further steps (outside the timed region)
+    ctx.vrm_timing(True)
+    nb = min(steps, 10)
+    for _ in range(nb):
+        ctx.vrm_step(cloud, P, vt, t)
+        t += wl.dt
+    torch.cuda.synchronize()
+    breakdown, _ = ctx.vrm_read_timing()
+    ctx.vrm_timing(False)
     return dict(elapsed=elapsed, counters=d, timers=timers, timer_overflow=overflow, n_start=n0, n_end=cloud.n,
-                final=c1)
+                final=c1, dominant=dom, breakdown=breakdown, breakdown_steps=nb)
+
+
+def breakdown(res):
+    return {k: round(v[0] / max(1, res["breakdown_steps"]), 4) for k, v in res["breakdown"].items() if v[1] > 0}
+
+
+def dominant_group(timers, q):
+    """The kernel group with the largest time (insertion, with its host synchronisations, excluded)."""
+    cand = {k: v for k, v in timers.items() if k != "insert" and v[1] > 0}
+    if not cand:
+        return "lp_small" if q == 2 else "lp_full"
+    return max(cand, key=lambda k: cand[k][0])
 
 
 # training geometry of the warm-start network for each workload (other seeds, same generator)
@@ -151,11 +182,9 @@ def measured_traffic(workload, group):
 
 
 def roofline(wl, res, workload):
-    """Roofline of the kernel group with the largest time in the timed region."""
-    T = res["timers"]
-    cand = {k: v for k, v in T.items() if k not in ("insert",) and v[1] > 0}
-    dom = max(cand, key=lambda k: cand[k][0])
-    ms, launches = cand[dom]
+    """Roofline of the dominant kernel group, timed by HIP events in the timed region."""
+    dom = res["dominant"]
+    ms, launches = res["timers"][dom]
     avg_s = ms / 1e3 / launches
     c = res["counters"]
     m = 5 if wl.q == 2 else 9
@@ -247,7 +276,8 @@ def main():
     c = res["counters"]
     value = c["redistributions"] / res["elapsed"]
     for k, r in runs.items():
-        log(f"{k}: elapsed {r['elapsed']:.4f} s, counters {r['counters']}, timers {r['timers']}")
+        log(f"{k}: elapsed {r['elapsed']:.4f} s, counters {r['counters']}, timed group {r['dominant']} "
+            f"{r['timers'][r['dominant']]}, breakdown {r['breakdown']}")
     rl = roofline(wl, res, args.workload)
     line = {
         "metric": "particle redistributions/s (learned warm start vs plain), FP32, moments <= 1e-6",
@@ -258,7 +288,8 @@ def main():
                    "n_end": res["n_end"], "dt": wl.dt, "solver": main_solver},
         "roofline": rl,
         "tuning": tuning,
-        "timers_ms": {k: round(v[0], 4) for k, v in res["timers"].items()},
+        # kernel time per step and group, from steps after the timed region with every group timed
+        "breakdown_ms_per_step": breakdown(res),
         "lp": {"small": c["n_small"], "full": c["n_full"], "infeasible": c["n_infeasible"],
                "uncertified": c["n_uncertified"], "pivots": c["pivots"]},
     }
@@ -272,7 +303,7 @@ def main():
             "warm_start": {"optimal_from_previous": cp["warm_hit"] / nlp, "phase2_from_previous": cp["warm_phase2"] / nlp,
                            "left_for_cold_solve": cp["warm_cold"] / nlp},
             "pivots": cp["pivots"], "uncertified": cp["n_uncertified"],
-            "timers_ms": {k: round(v[0], 4) for k, v in r["timers"].items()},
+            "breakdown_ms_per_step": breakdown(r),
         }
     if "learned" in runs:
         r = runs["learned"]
@@ -285,7 +316,7 @@ def main():
             "warm_start": {"optimal_from_prediction": cl["warm_hit"] / nlp, "phase2_from_prediction": cl["warm_phase2"] / nlp,
                            "left_for_cold_solve": cl["warm_cold"] / nlp},
             "pivots": cl["pivots"], "uncertified": cl["n_uncertified"],
-            "timers_ms": {k: round(v[0], 4) for k, v in r["timers"].items()},
+            "breakdown_ms_per_step": breakdown(r),
             "network": train_info,
         }
     if not args.no_cpu_baseline:

@@ -296,6 +296,9 @@ int vrm_gemm_bf16(vrm_ctx* ctx, const uint16_t* a_dev, const uint16_t* b_dev, fl
 #define VRM_T_MLP 7         /* warm-start network */
 #define VRM_NTIMER 8
 int vrm_timing(vrm_ctx* ctx, int enable);
+/* The same for the groups whose bit (1 << VRM_T_*) is set in `groups` only:
+ * the other groups launch without events (0: timers off). */
+int vrm_timing_groups(vrm_ctx* ctx, uint32_t groups);
 int vrm_read_timing(vrm_ctx* ctx, double* ms_host, int64_t* launches_host);
 
 const char* vrm_last_error(void);

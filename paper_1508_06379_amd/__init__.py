@@ -76,7 +76,7 @@ EXPORTS = ["vrm_create", "vrm_destroy", "vrm_select_diffused", "vrm_set_diffused
            "vrm_insert_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_step", "vrm_set_graph", "vrm_set_tuning",
            "vrm_get_tuning", "vrm_verify",
            "vrm_read_counters",
-           "vrm_vortex_velocity", "vrm_timing", "vrm_read_timing", "vrm_mlp_load", "vrm_mlp_read",
+           "vrm_vortex_velocity", "vrm_timing", "vrm_timing_groups", "vrm_read_timing", "vrm_mlp_load", "vrm_mlp_read",
            "vrm_set_warm_start", "vrm_collect_training", "vrm_mlp_train_step", "vrm_mlp_infer", "vrm_gemm_bf16",
            "vrm_last_error", "vrm_status_string"]
 MLP_IN, MLP_OUT, MLP_PARAMS, MLP_SLOTS = 128, 64, 41280, 32
@@ -123,6 +123,7 @@ def lib():
         L.vrm_gemm_bf16.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
                                     ctypes.c_int]
         L.vrm_timing.argtypes = [vp, ctypes.c_int]
+        L.vrm_timing_groups.argtypes = [vp, ctypes.c_uint32]
         L.vrm_read_timing.argtypes = [vp, vp, vp]
         L.vrm_last_error.restype = ctypes.c_char_p
         L.vrm_status_string.restype = ctypes.c_char_p
@@ -297,6 +298,13 @@ class Context:
 
     def vrm_timing(self, enable: bool):
         _check(lib().vrm_timing(self.handle, 1 if enable else 0))
+
+    def vrm_timing_groups(self, groups):
+        """Time only the named groups (an iterable of TIMERS names; empty: off)."""
+        mask = 0
+        for g in groups:
+            mask |= 1 << TIMERS.index(g)
+        _check(lib().vrm_timing_groups(self.handle, mask))
 
     def vrm_read_timing(self):
         """{group: (total ms, launches)} of the interval since the last read."""

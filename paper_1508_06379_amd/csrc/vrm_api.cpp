@@ -740,16 +740,22 @@ int vrm_gemm_bf16(vrm_ctx* c, const uint16_t* a, const uint16_t* b, float* out, 
     return vrm_gemm_test(c, a, b, out, M, N, K, ta, tb);
 }
 
-int vrm_timing(vrm_ctx* c, int enable)
+int vrm_timing(vrm_ctx* c, int enable) { return vrm_timing_groups(c, enable ? (1u << VRM_NTIMER) - 1u : 0u); }
+
+int vrm_timing_groups(vrm_ctx* c, uint32_t groups)
 {
     if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
+    groups &= (1u << VRM_NTIMER) - 1u;
+    const int enable = groups != 0u;
     if (enable && !c->ev_start) {
         c->ev_start = new hipEvent_t[vrm::kMaxTimed];
         c->ev_stop = new hipEvent_t[vrm::kMaxTimed];
         c->ev_group = new int[vrm::kMaxTimed];
+        // timing-only events: no system-scope fence (vrm_read_timing synchronises
+        // the stream before reading them)
         for (int k = 0; k < vrm::kMaxTimed; ++k) {
-            VRM_HIP(hipEventCreate(&c->ev_start[k]));
-            VRM_HIP(hipEventCreate(&c->ev_stop[k]));
+            VRM_HIP(hipEventCreateWithFlags(&c->ev_start[k], hipEventDisableSystemFence));
+            VRM_HIP(hipEventCreateWithFlags(&c->ev_stop[k], hipEventDisableSystemFence));
         }
     }
     if (c->graph_pending) {
@@ -758,6 +764,7 @@ int vrm_timing(vrm_ctx* c, int enable)
         if (r) return r;
     }
     c->timing = enable ? 1 : 0;
+    c->timing_groups = groups;
     c->ntimed = 0;
     for (int g = 0; g < VRM_NTIMER; ++g) {
         c->launches[g] = 0;

@@ -164,6 +164,7 @@ struct vrm_ctx {
     double* verify_buf;   // [8]
     // kernel timers
     int timing;
+    uint32_t timing_groups;   // bit g: group g is timed
     int ntimed;
     hipEvent_t* ev_start; // [kMaxTimed]
     hipEvent_t* ev_stop;
@@ -206,7 +207,7 @@ struct ScopedTimer {
     int slot;
     ScopedTimer(vrm_ctx* ctx, int group) : c(ctx), slot(-1)
     {
-        if (!c->timing) return;
+        if (!c->timing || !((c->timing_groups >> group) & 1u)) return;
         if (c->capturing) {
             // an event-record node of the step graph; counted when a replay is accumulated
             if (c->graph_slots >= kGraphTimed) return;
