@@ -178,6 +178,7 @@ class StepInfo:
     status_counts: list
     i0: float
     seconds: float = 0.0
+    redistributed_gamma: float = 0.0   # sum of Gamma^n over the particles that redistributed (Euler steps)
 
 
 @dataclass
@@ -227,6 +228,34 @@ def step(state: OracleState, wl, insertion: bool = True, record: bool = True, st
         out.history.append(StepInfo(x.shape[0], int(mask.sum()), x.shape[0] - n_before, counts,
                                     float(g.sum()), time.perf_counter() - t_start))
     return out
+
+
+def euler_step(state: OracleState, wl, record: bool = True) -> OracleState:
+    """One step of Euler's method for the heat equation (Sec. 3.3; the case without
+    convection of Sec. 5): diffused set and insertion at t^n, then
+    Gamma^{n+1} = Gamma^n + dt * nu sum_j f_ji Gamma_j^n on the new cloud; the
+    particles do not move."""
+    P = params_of(wl)
+    t_start = time.perf_counter()
+    mask, _, _ = diffused(state.gamma, state.ids, wl.h, wl.q, wl.c_diff)
+    n_before = state.x.shape[0]
+    x, y, g, ids, _ = insert(state.x, state.y, state.gamma, state.ids, mask, P)
+    mask = np.concatenate([mask, np.zeros(x.shape[0] - n_before, np.uint8)])
+    st = stencils(x, y, ids, mask, P)
+    g_new = g + wl.dt * apply(st, g, P)
+    out = OracleState(x, y, g_new, ids, state.t + wl.dt, state.history)
+    if record:
+        counts = [int(np.count_nonzero(st.status == c)) for c in range(3)]
+        out.history.append(StepInfo(x.shape[0], int(mask.sum()), x.shape[0] - n_before, counts, float(g_new.sum()),
+                                    time.perf_counter() - t_start, float(g[st.status < 2].sum())))
+    return out
+
+
+def run_euler(wl, steps=None) -> OracleState:
+    st = initial_state(wl)
+    for _ in range(wl.steps if steps is None else steps):
+        st = euler_step(st, wl)
+    return st
 
 
 def run(wl, steps=None, insertion=True) -> OracleState:

@@ -201,6 +201,17 @@ def lone_particle(h: float = 0.05, gamma: float = 1.0) -> Workload:
                     q=2, dt=0.1 * h * h / 0.02, steps=1)
 
 
+def dirac_lamb_oseen(h: float) -> Workload:
+    """The paper's Lamb-Oseen test with the heat equation (Sec. 5): a single particle
+    of circulation 2 pi at the origin, nu = 1/50, C_diff = 1, q = 2, Euler steps of
+    dt = (r h)^2 / (32 nu) with r = 1/2 up to t = 1 (2.56 / h^2 steps)."""
+    nu = 1.0 / 50.0
+    dt = (0.5 * h) ** 2 / (32.0 * nu)
+    z = np.zeros(1, np.float32)
+    return Workload(f"dirac_h{h}", z.copy(), z.copy(), np.array([2.0 * np.pi], np.float32), h=h, nu=nu, q=2,
+                    dt=dt, steps=int(round(1.0 / dt)), t0=0.0)
+
+
 PRESETS = {
     "lattice": config_lattice_small,
     "jittered_q2": lambda: config_jittered(q=2),
