@@ -199,7 +199,8 @@ typedef struct vrm_tuning {
     int32_t full_stored_cost_n;  /* clouds with N up to this keep complete-LP costs in LDS; default 200000;
                                     -1: never */
     int32_t infer_blocks;        /* most workgroups (256 threads) of the network's inference; default 512 */
-    int32_t reserved[4];
+    int32_t lp_small_lanes;      /* small LPs per wave of the small-LP launch (1, 2, 4, ..., 64); default 64 */
+    int32_t reserved[3];
 } vrm_tuning;
 /* Set (t = NULL: restore the defaults) or read the launch shapes. */
 int vrm_set_tuning(vrm_ctx* ctx, const vrm_tuning* t);

@@ -43,8 +43,8 @@ class vrm_params(ctypes.Structure):
 class vrm_tuning(ctypes.Structure):
     _fields_ = [("lp_small_blocks", ctypes.c_int32), ("lp_full_blocks", ctypes.c_int32),
                 ("full_stored_cost_n", ctypes.c_int32), ("infer_blocks", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
-    FIELDS = ("lp_small_blocks", "lp_full_blocks", "full_stored_cost_n", "infer_blocks")
+                ("lp_small_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+    FIELDS = ("lp_small_blocks", "lp_full_blocks", "full_stored_cost_n", "infer_blocks", "lp_small_lanes")
 
 
 class vrm_cloud(ctypes.Structure):

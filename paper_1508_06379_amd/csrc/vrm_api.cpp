@@ -499,7 +499,11 @@ int vrm_set_tuning(vrm_ctx* c, const vrm_tuning* t)
     d.lp_full_blocks = 1024;
     d.full_stored_cost_n = 200000;
     d.infer_blocks = 512;
+    d.lp_small_lanes = 64;
     if (t) {
+        const int ln = t->lp_small_lanes;
+        if (ln < 0 || ln > 64 || (ln & (ln - 1)) != 0)
+            return vrm_fail(VRM_E_ARG, "lp_small_lanes must be 0 or a power of two <= 64 (got %d)", ln);
         if (t->lp_small_blocks < 0 || t->lp_full_blocks < 0 || t->infer_blocks < 0 || t->full_stored_cost_n < -1 ||
             t->lp_small_blocks > (1 << 20) || t->lp_full_blocks > (1 << 22) || t->infer_blocks > (1 << 20))
             return vrm_fail(VRM_E_ARG, "tuning values out of range");
@@ -507,6 +511,7 @@ int vrm_set_tuning(vrm_ctx* c, const vrm_tuning* t)
         if (t->lp_full_blocks) d.lp_full_blocks = t->lp_full_blocks;
         if (t->full_stored_cost_n) d.full_stored_cost_n = t->full_stored_cost_n;
         if (t->infer_blocks) d.infer_blocks = t->infer_blocks;
+        if (t->lp_small_lanes) d.lp_small_lanes = t->lp_small_lanes;
     }
     c->tuning = d;
     return VRM_OK;

@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
                                                           const int32_t* __restrict__ q_small, Queues* qs,
                                                           int32_t* q_full, const float* __restrict__ gamma,
                                                           float* acc, LaunchParams P, StencilOut out, int apply,
-                                                          vrm_counters* cnt, int mode, int32_t* q_retry)
+                                                          vrm_counters* cnt, int mode, int32_t* q_retry, int lanes)
 {
     __shared__ float s_rx[8 * kSmallBlock];
     __shared__ float s_ry[8 * kSmallBlock];
@@ -353,11 +353,14 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
     const int tid = threadIdx.x;
     const int nitems = mode == kLpRetry ? qs->n_retry : qs->n_small;
     const size_t cap = (size_t)rec.cap;
-    const int stride = gridDim.x * blockDim.x;
+    // `lanes` LPs per wave (a power of two <= 64): fewer per wave shortens a wave,
+    // which lasts as long as its slowest LP, where the launch has SIMDs to spare
+    const int wave = (blockIdx.x * blockDim.x + tid) >> 6, lane = tid & 63;
+    const int stride = ((gridDim.x * blockDim.x) >> 6) * lanes;
     const int loops = (nitems + stride - 1) / stride;
     for (int it = 0; it < loops; ++it) {
-        const int item = blockIdx.x * blockDim.x + tid + it * stride;
-        const bool live = item < nitems;
+        const int item = wave * lanes + lane + it * stride;
+        const bool live = lane < lanes && item < nitems;
         int st = 1, piv = 0, certified = 1, warm = 0;
         int t = 0, i = 0, r = 0;
         if (live) {
@@ -769,7 +772,11 @@ __global__ void k_status_init(int n, const uint8_t* __restrict__ diffused, Stenc
 
 // persistent launches: enough threads for every CU (at most the tuned number
 // of workgroups), each loops over its items
-int lp_grid_small(const vrm_ctx* c, int n) { return n > 0 ? min((n + 255) / 256, c->tuning.lp_small_blocks) : 1; }
+int lp_grid_small(const vrm_ctx* c, int n)
+{
+    const int per_block = (kSmallBlock / 64) * c->tuning.lp_small_lanes;
+    return n > 0 ? min((n + per_block - 1) / per_block, c->tuning.lp_small_blocks) : 1;
+}
 int lp_grid_full(const vrm_ctx* c, int n)
 {
     return n > 0 ? min((n + kFullBlock - 1) / kFullBlock, c->tuning.lp_full_blocks) : 1;
@@ -850,7 +857,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
             for (int mode = first; mode <= (warm ? kLpRetry : kLpPlain); ++mode) {
                 hipLaunchKernelGGL(k_lp_small, dim3(lp_grid_small(c, n)), dim3(kSmallBlock), 0, c->stream, c->perm, c->xs,
                                    c->ys, c->ids, c->srec, c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc,
-                                   lp, out, apply, c->counters, mode, c->q_retry);
+                                   lp, out, apply, c->counters, mode, c->q_retry, c->tuning.lp_small_lanes);
                 VRM_HIP(hipGetLastError());
             }
         }

@@ -427,7 +427,9 @@ def test_launch_shapes_do_not_change_results(vrm, name):
     P = vrm.params_of(wl)
     shapes = [None,
               {"lp_small_blocks": 1, "lp_full_blocks": 1, "full_stored_cost_n": -1, "infer_blocks": 1},
-              {"lp_small_blocks": 3, "lp_full_blocks": 5, "full_stored_cost_n": 1 << 30, "infer_blocks": 2}]
+              {"lp_small_blocks": 3, "lp_full_blocks": 5, "full_stored_cost_n": 1 << 30, "infer_blocks": 2,
+               "lp_small_lanes": 4},
+              {"lp_small_lanes": 16}]
     res = []
     for tuning in shapes:
         cloud = _gpu_cloud(vrm, wl, cap_factor=4)
