@@ -221,6 +221,17 @@ int vrm_verify(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params* p, const 
 /* Copy the device counters to *out_host.  Synchronises the stream. */
 int vrm_read_counters(vrm_ctx* ctx, vrm_counters* out_host);
 
+/* Sec. 3.4 eq. (nsode) with the regularised kernel of Sec. 5: the velocity
+ * the particles induce on themselves,
+ *   u_i = sum_j Gamma_j K_eps(x_i - x_j),
+ *   K_eps(d) = (-d_y, d_x) (1 - exp(-|d|^2 / eps^2)) / (2 pi |d|^2),  K_eps(0) = 0,
+ * by a direct sum over all N^2 pairs in FP32 (the paper evaluates it with a
+ * fast multipole method; the direct sum suits clouds up to ~10^5 particles).
+ * u_dev, v_dev: device floats [capacity], caller-owned; the first N entries
+ * are overwritten.  eps > 0 (the paper: eps = 3h).  Enqueued on the context's
+ * stream; no synchronisation. */
+int vrm_biot_savart(vrm_ctx* ctx, const vrm_cloud* cloud, double eps, float* u_dev, float* v_dev);
+
 /* Prescribed velocity of a sum of spreading Gaussian (Lamb-Oseen) vortices
  * at the current positions (test and benchmark harness, not part of the
  * method): for vortex k with centre (cx, cy), core sigma and strength G,

@@ -230,6 +230,29 @@ def step(state: OracleState, wl, insertion: bool = True, record: bool = True, st
     return out
 
 
+def biot_savart(x, y, gamma, eps, tx=None, ty=None, chunk=256):
+    """Velocity by the Biot-Savart law of the particles (Sec. 3.4, eq. nsode: dx_i/dt =
+    sum_j K(r_ij) Gamma_j with r_ij = x_j - x_i) with the regularised kernel of Sec. 5,
+    K_eps(d) = (-d_y, d_x) / (2 pi |d|^2) (1 - exp(-|d|^2 / eps^2)), d = x_i - x_j, and
+    K_eps(0) = 0; at the particles, or at the points (tx, ty).  FP64, direct sum."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    g = np.asarray(gamma, np.float64)
+    tx = x if tx is None else np.asarray(tx, np.float64)
+    ty = y if ty is None else np.asarray(ty, np.float64)
+    u = np.zeros(tx.shape[0])
+    v = np.zeros(tx.shape[0])
+    for a in range(0, tx.shape[0], chunk):
+        dx = tx[a:a + chunk, None] - x[None, :]
+        dy = ty[a:a + chunk, None] - y[None, :]
+        r2 = dx * dx + dy * dy
+        with np.errstate(divide="ignore", invalid="ignore"):
+            w = np.where(r2 > 0.0, -np.expm1(-r2 / (eps * eps)) / (2.0 * np.pi * r2), 0.0)
+        u[a:a + chunk] = (-dy * w) @ g
+        v[a:a + chunk] = (dx * w) @ g
+    return u, v
+
+
 def euler_step(state: OracleState, wl, record: bool = True) -> OracleState:
     """One step of Euler's method for the heat equation (Sec. 3.3; the case without
     convection of Sec. 5): diffused set and insertion at t^n, then

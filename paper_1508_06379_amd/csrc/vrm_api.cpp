@@ -817,4 +817,14 @@ int vrm_vortex_velocity(vrm_ctx* c, const vrm_cloud* cl, const float* vort_dev, 
     return vrm_velocity_run(c, cl, c->n, vort_dev, n_vort, nu, t, u_dev, v_dev);
 }
 
+int vrm_biot_savart(vrm_ctx* c, const vrm_cloud* cl, double eps, float* u_dev, float* v_dev)
+{
+    int r = check_cloud(c, cl);
+    if (!r && (!u_dev || !v_dev)) r = vrm_fail(VRM_E_ARG, "u and v are required");
+    if (!r && !(eps > 0.0)) r = vrm_fail(VRM_E_ARG, "eps must be positive (got %g)", eps);
+    if (!r && c->n_ptr != cl->n_dev) r = read_n(c, cl);
+    if (r) return r;
+    return vrm_biot_savart_run(c, cl, c->n, eps, u_dev, v_dev);
+}
+
 }  // extern "C"

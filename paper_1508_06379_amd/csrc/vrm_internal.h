@@ -243,6 +243,7 @@ int vrm_small_nbhd_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::La
 int vrm_combine_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const float* u, const float* v, double dt,
                     float lam, int stage);
 int vrm_save_base_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n);
+int vrm_biot_savart_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, double eps, float* u, float* v);
 int vrm_verify_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp,
                    const vrm_stencils* st, double* report);
 int vrm_velocity_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const float* vort, int32_t nv, double nu,

@@ -159,7 +159,102 @@ __global__ __launch_bounds__(256) void k_velocity(int n, const int32_t* __restri
 
 int blocks_for(int n) { return n > 0 ? (n + 255) / 256 : 1; }
 
+// ------------------------------------------------------------ Biot-Savart (direct sum)
+// u(x_i) = sum_j Gamma_j K_eps(x_i - x_j) with K_eps(d) = (-d_y, d_x) (1 - exp(-|d|^2 / eps^2))
+// / (2 pi |d|^2) and K_eps(0) = 0 (Sec. 3.4 eq. nsode, the regularised kernel of Sec. 5).
+// Each thread accumulates kBsT targets; a workgroup streams one chunk of the
+// sources (blockIdx.y) through LDS in tiles of kBsTile, and the chunks' partial
+// sums meet in u, v by atomics (distinct addresses: no contention).
+// Positions are scaled by s = sqrt(log2 e) / eps, so that with D = s d the
+// exponential is exp2(-|D|^2) and the pair term is s Gamma_j (-D_y, D_x)
+// (1 - 2^-|D|^2) / (2 pi |D|^2): per pair two differences, two FMAs for |D|^2,
+// exp2, a reciprocal, one product, one FMA for t - t e and two accumulating
+// FMAs; s multiplies the sums once.  The 1e-30 added to |D|^2 makes the self
+// term 0 * finite instead of a branch.
+constexpr int kBsBlock = 256;
+constexpr int kBsT = 2;
+constexpr int kBsTile = 512;
+
+__global__ __launch_bounds__(kBsBlock) void k_biot_savart(const int32_t* __restrict__ n_dev,
+                                                          const float* __restrict__ x, const float* __restrict__ y,
+                                                          const float* __restrict__ g, float sc, int chunk,
+                                                          float* u, float* v)
+{
+    __shared__ float4 s_src[kBsTile];
+    const int n = *n_dev;
+    const int tid = threadIdx.x;
+    float xt[kBsT], yt[kBsT], su[kBsT], sv[kBsT];
+#pragma unroll
+    for (int k = 0; k < kBsT; ++k) {
+        const int a = blockIdx.x * (kBsBlock * kBsT) + k * kBsBlock + tid;
+        xt[k] = a < n ? x[a] * sc : 0.0f;
+        yt[k] = a < n ? y[a] * sc : 0.0f;
+        su[k] = 0.0f;
+        sv[k] = 0.0f;
+    }
+    const float inv2pi = 0.15915494309189535f;
+    const int j0 = blockIdx.y * chunk, j1 = min(j0 + chunk, n);
+    for (int base = j0; base < j1; base += kBsTile) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kBsTile / kBsBlock; ++q) {
+            const int e = q * kBsBlock + tid, j = base + e;
+            s_src[e] = j < j1 ? make_float4(x[j] * sc, y[j] * sc, g[j] * inv2pi, 0.0f)
+                              : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int e = 0; e < kBsTile; ++e) {
+            const float4 s = s_src[e];
+#pragma unroll
+            for (int k = 0; k < kBsT; ++k) {
+                const float dx = xt[k] - s.x, dy = yt[k] - s.y;
+                const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1e-30f));
+                const float ex = __builtin_amdgcn_exp2f(-r2);
+                const float t = __builtin_amdgcn_rcpf(r2) * s.z;
+                const float f = __builtin_fmaf(-t, ex, t);
+                su[k] = __builtin_fmaf(-dy, f, su[k]);
+                sv[k] = __builtin_fmaf(dx, f, sv[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kBsT; ++k) {
+        const int a = blockIdx.x * (kBsBlock * kBsT) + k * kBsBlock + tid;
+        if (a < n) {
+            atomicAdd(&u[a], su[k] * sc);
+            atomicAdd(&v[a], sv[k] * sc);
+        }
+    }
+}
+
+__global__ void k_zero_uv(const int32_t* __restrict__ n_dev, float* u, float* v)
+{
+    const int n = *n_dev;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        u[i] = 0.0f;
+        v[i] = 0.0f;
+    }
+}
+
 }  // namespace
+
+int vrm_biot_savart_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, double eps, float* u, float* v)
+{
+    if (n <= 0) return VRM_OK;
+    hipLaunchKernelGGL(k_zero_uv, dim3(min(blocks_for(n), 1024)), dim3(256), 0, c->stream, cl->n_dev, u, v);
+    const int tx = (n + kBsBlock * kBsT - 1) / (kBsBlock * kBsT);
+    // source chunks: enough workgroups to fill the chip (>= 2048), whole tiles each
+    const int tiles = (n + kBsTile - 1) / kBsTile;
+    const int sy = max(1, min(tiles, (2048 + tx - 1) / tx));
+    const int chunk = ((tiles + sy - 1) / sy) * kBsTile;
+    const int ny = (n + chunk - 1) / chunk;
+    const float sc = (float)(sqrt(1.4426950408889634) / eps);
+    hipLaunchKernelGGL(k_biot_savart, dim3(tx, ny), dim3(kBsBlock), 0, c->stream, cl->n_dev, cl->x_dev, cl->y_dev,
+                       cl->gamma_dev, sc, chunk, u, v);
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
+}
 
 int vrm_combine_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const float* u, const float* v, double dt, float lam,
                     int stage)
