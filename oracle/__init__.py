@@ -196,8 +196,11 @@ def initial_state(wl) -> OracleState:
                        np.arange(wl.n, dtype=np.int32), wl.t0)
 
 
-def step(state: OracleState, wl, insertion: bool = True, record: bool = True, stages_cb=None) -> OracleState:
-    """One SSP-RK3 step: diffused set and insertion at t^n, then three stages."""
+def step(state: OracleState, wl, insertion: bool = True, record: bool = True, stages_cb=None,
+         velocity=None) -> OracleState:
+    """One SSP-RK3 step: diffused set and insertion at t^n, then three stages.
+    velocity(x, y, gamma, t) -> (u, v) replaces the workload's prescribed field
+    (for instance the particles' own Biot-Savart velocity, Sec. 3.4 eq. nsode)."""
     P = params_of(wl)
     t_start = time.perf_counter()
     mask, _, _ = diffused(state.gamma, state.ids, wl.h, wl.q, wl.c_diff)
@@ -211,7 +214,7 @@ def step(state: OracleState, wl, insertion: bool = True, record: bool = True, st
     counts = [0, 0, 0]
     for s in range(3):
         ts = state.t + RK3_C[s] * wl.dt
-        u, v = wl.velocity(x, y, ts)
+        u, v = wl.velocity(x, y, ts) if velocity is None else velocity(x, y, g, ts)
         st = stencils(x, y, ids, mask, P)
         if stages_cb is not None:
             stages_cb(s, x, y, g, ids, mask, st)
