@@ -189,6 +189,16 @@ int vrm_rk_stage(vrm_ctx* ctx, vrm_cloud* cloud, const float* u_dev, const float
  * floating-point atomic sums).  Synchronises once (insertion). */
 int vrm_step(vrm_ctx* ctx, vrm_cloud* cloud, const vrm_params* p, const float* vort_dev, int32_t n_vort, double t);
 
+/* Sec. 4.1: which non-negative solution of the moment conditions a stencil is.
+ * 0 (default): the canonical stencil, the minimiser of sum_j c_j f_j with
+ * c_j = |r_j/h|^(q+1) + 2^-10 rank(id_j) (both phases, exact certificate; the
+ * same result as any correct solver).  1: the first feasible vertex, as the
+ * paper's method stops after phase I (fewer pivots; the stencil depends on the
+ * pivoting rules, so results are checked by their moments, sign and
+ * conservation, not against another solver).  A phase-I basis whose refined
+ * values are not exactly feasible continues to the canonical stencil. */
+int vrm_set_lp_objective(vrm_ctx* ctx, int mode);
+
 /* Launch shapes (performance only; results do not depend on them).  A zero
  * field keeps the library's default.  The values are device-independent
  * numbers of workgroups; an autotuner (paper_1508_06379_amd/autotune.py)

@@ -76,7 +76,7 @@ EXPORTS = ["vrm_create", "vrm_destroy", "vrm_select_diffused", "vrm_set_diffused
            "vrm_insert_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_step", "vrm_set_graph", "vrm_set_tuning",
            "vrm_get_tuning", "vrm_verify",
            "vrm_read_counters",
-           "vrm_vortex_velocity", "vrm_biot_savart", "vrm_timing", "vrm_timing_groups", "vrm_read_timing", "vrm_mlp_load", "vrm_mlp_read",
+           "vrm_vortex_velocity", "vrm_biot_savart", "vrm_set_lp_objective", "vrm_timing", "vrm_timing_groups", "vrm_read_timing", "vrm_mlp_load", "vrm_mlp_read",
            "vrm_set_warm_start", "vrm_collect_training", "vrm_mlp_train_step", "vrm_mlp_infer", "vrm_gemm_bf16",
            "vrm_last_error", "vrm_status_string"]
 MLP_IN, MLP_OUT, MLP_PARAMS, MLP_SLOTS = 128, 64, 41280, 32
@@ -111,6 +111,7 @@ def lib():
                                  ctypes.POINTER(vrm_stencils), vp]
         L.vrm_read_counters.argtypes = [vp, ctypes.POINTER(vrm_counters)]
         L.vrm_biot_savart.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.c_double, vp, vp]
+        L.vrm_set_lp_objective.argtypes = [vp, ctypes.c_int]
         L.vrm_vortex_velocity.argtypes = [vp, ctypes.POINTER(vrm_cloud), vp, ctypes.c_int32, ctypes.c_double,
                                           ctypes.c_double, vp, vp]
         L.vrm_mlp_load.argtypes = [vp, vp]
@@ -292,6 +293,10 @@ class Context:
         c = vrm_counters()
         _check(lib().vrm_read_counters(self.handle, ctypes.byref(c)))
         return c.as_dict()
+
+    def vrm_set_lp_objective(self, mode: int):
+        """0: the canonical stencil (default); 1: the first feasible vertex (phase I only)."""
+        _check(lib().vrm_set_lp_objective(self.handle, int(mode)))
 
     def vrm_biot_savart(self, cloud: Cloud, eps, u, v):
         _check(lib().vrm_biot_savart(self.handle, ctypes.byref(cloud.c), ctypes.c_double(eps), _ptr(u), _ptr(v)))

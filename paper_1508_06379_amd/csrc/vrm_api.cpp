@@ -17,9 +17,10 @@ size_t vrm_sort_tmp_bytes(int32_t cap);
 namespace {
 thread_local std::string g_err;
 
-vrm::LaunchParams launch_params(const vrm_params* p)
+vrm::LaunchParams launch_params(const vrm_ctx* c, const vrm_params* p)
 {
     vrm::LaunchParams L{};
+    L.phase1 = c->lp_objective;
     const double h = p->h;
     L.h = (float)h;
     L.lo2 = (float)(p->r * p->r * h * h * (1.0 - 0x1p-20));
@@ -303,7 +304,7 @@ int vrm_build_neighbourhoods(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* 
     if (!r) r = check_params(p);
     if (!r) r = cached_n(c, cl);
     if (r) return r;
-    vrm::LaunchParams L = launch_params(p);
+    vrm::LaunchParams L = launch_params(c, p);
     r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
     if (r) return r;
     c->cells_valid = 1;
@@ -317,7 +318,7 @@ int vrm_insert_particles(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p)
     if (!r) r = check_params(p);
     if (!r) r = read_n(c, cl);
     if (r) return r;
-    vrm::LaunchParams L = launch_params(p);
+    vrm::LaunchParams L = launch_params(c, p);
     double factor = p->c_diff * std::pow(p->h, p->q + 1);
     {
         vrm::ScopedTimer tm(c, VRM_T_SELECT);
@@ -361,7 +362,7 @@ int vrm_solve_fractions(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, vr
                !out->full_k_dev || (!out->full_idx_dev) != (!out->full_f_dev)))
         r = vrm_fail(VRM_E_ARG, "stencil output arrays missing");
     if (r) return r;
-    vrm::LaunchParams L = launch_params(p);
+    vrm::LaunchParams L = launch_params(c, p);
     if (!c->cells_valid) {
         r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
         if (r) return r;
@@ -381,7 +382,7 @@ int stage_launch(vrm_ctx* c, vrm_cloud* cl, const float* u_dev, const float* v_d
                  int nb)
 {
     int r;
-    vrm::LaunchParams L = launch_params(p);
+    vrm::LaunchParams L = launch_params(c, p);
     if (stage == 0) {
         r = vrm_save_base_run(c, cl, nb);
         if (r) return r;
@@ -456,7 +457,7 @@ void drop_graph(vrm_ctx* c)
 
 // What a captured step depends on besides the device state it reads.
 void graph_key(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, const float* vort_dev, int32_t n_vort,
-               unsigned char (&key)[192])
+               unsigned char (&key)[256])
 {
     std::memset(key, 0, sizeof(key));
     size_t o = 0;
@@ -468,12 +469,16 @@ void graph_key(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, const float
     put(p, sizeof(vrm_params));
     put(&vort_dev, sizeof(vort_dev));
     put(&n_vort, sizeof(n_vort));
-    int flags[3] = {c->timing, c->warm, c->mlp ? c->mlp->loaded : 0};
+    int flags[4] = {c->timing, c->warm, c->mlp ? c->mlp->loaded : 0, c->lp_objective};
     put(flags, sizeof(flags));
     const void* mp = c->mlp;
     put(&mp, sizeof(mp));
     put(&c->tuning, sizeof(vrm_tuning));
 }
+static_assert(sizeof(vrm_cloud) + sizeof(vrm_params) + sizeof(void*) + sizeof(int32_t) + 4 * sizeof(int) +
+                      sizeof(void*) + sizeof(vrm_tuning) <=
+                  256,
+              "graph key buffer too small");
 
 }  // namespace
 
@@ -556,7 +561,7 @@ int vrm_step(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p, const float* vort_d
     if (!c->graph_enabled || c->timing || c->graph_failed[0] || n <= 0)
         return step_stages(c, cl, p, vort_dev, n_vort, t, nullptr, n);
 
-    unsigned char key[192];
+    unsigned char key[256];
     graph_key(c, cl, p, vort_dev, n_vort, key);
     const int f0[3] = {c->cells_valid, c->sorted, c->base_valid};
     if (!c->graph_exec || n > c->graph_nb || std::memcmp(key, c->graph_key, sizeof(key)) != 0 ||
@@ -620,7 +625,7 @@ int vrm_verify(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, const vrm_s
     if (!r && !report_dev) r = vrm_fail(VRM_E_ARG, "report is NULL");
     if (!r && c->n_ptr != cl->n_dev) r = read_n(c, cl);
     if (r) return r;
-    vrm::LaunchParams L = launch_params(p);
+    vrm::LaunchParams L = launch_params(c, p);
     return vrm_verify_run(c, cl, c->n, L, st, report_dev);
 }
 
@@ -704,7 +709,7 @@ int vrm_collect_training(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, u
     if (!r) r = cached_n(c, cl);
     if (!r && (!x || !y || !rows || max_rows <= 0)) r = vrm_fail(VRM_E_ARG, "training buffers");
     if (r) return r;
-    vrm::LaunchParams L = launch_params(p);
+    vrm::LaunchParams L = launch_params(c, p);
     if (!c->cells_valid) {
         r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
         if (r) return r;
@@ -825,6 +830,14 @@ int vrm_biot_savart(vrm_ctx* c, const vrm_cloud* cl, double eps, float* u_dev, f
     if (!r && c->n_ptr != cl->n_dev) r = read_n(c, cl);
     if (r) return r;
     return vrm_biot_savart_run(c, cl, c->n, eps, u_dev, v_dev);
+}
+
+int vrm_set_lp_objective(vrm_ctx* c, int mode)
+{
+    if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
+    if (mode != 0 && mode != 1) return vrm_fail(VRM_E_ARG, "lp objective must be 0 or 1 (got %d)", mode);
+    c->lp_objective = mode;
+    return VRM_OK;
 }
 
 }  // extern "C"

@@ -103,6 +103,7 @@ struct LaunchParams {
     float lam;                           // nu / h^2
     float sc;                            // 2^e / h: scaled offset -> offset / h
     int q, m;
+    int phase1;                          // 1: stop at the first feasible vertex (phase I only)
 };
 
 }  // namespace vrm
@@ -162,6 +163,7 @@ struct vrm_ctx {
     int32_t* tmp_i;       // [cap]
     uint8_t* tmp_u8;      // [cap]
     double* verify_buf;   // [8]
+    int lp_objective;     // 0 canonical stencil (phase II), 1 first feasible vertex (phase I only)
     // kernel timers
     int timing;
     uint32_t timing_groups;   // bit g: group g is timed
@@ -183,7 +185,7 @@ struct vrm_ctx {
     int graph_flags[3];          // cells_valid, sorted, base_valid after the stages
     hipGraph_t graph;
     hipGraphExec_t graph_exec;
-    unsigned char graph_key[192];
+    unsigned char graph_key[256];
     double* t_dev;               // step start time read by the graph's velocity kernels
     int32_t* prev;               // [cap][9] basis (column ids) of each particle's last stencil, by id
     vrm_tuning tuning;           // launch shapes in force (defaults filled in)

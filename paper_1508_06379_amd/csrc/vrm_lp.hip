@@ -335,6 +335,7 @@ struct SmallColsT : LdsColsT<BLK> {
 // the columns (column j = segment j) live in LDS.
 constexpr int kSmallBlock = 256;
 
+template <bool PH1>
 __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_lp_small(const int32_t* __restrict__ perm,
                                                           const float* __restrict__ xs, const float* __restrict__ ys,
                                                           const int32_t* __restrict__ ids, SmallRec rec,
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
                 cs.lg[4] = b.x, cs.lg[5] = b.y, cs.lg[6] = b.z, cs.lg[7] = b.w;
             }
             uint64_t basis = 0;
-            st = solve_lp<5>(cs, P, store, fii, piv, certified, warm_pass, nullptr, warm, basis,
+            st = solve_lp<5, PH1>(cs, P, store, fii, piv, certified, warm_pass, nullptr, warm, basis,
                              warm_pass && out.use_prev, pref);
             if (st == 0 && out.prev) record_basis(out.prev, own, basis, col_id);
             if (record) {
@@ -585,7 +586,7 @@ __device__ int collect_full(int t, float xi, float yi, const GridState& g, const
 // pricing, three resident blocks per CU) or computed from the offsets when
 // priced (36 KB: four blocks per CU).  Small clouds, whose launches are one
 // wave's latency, take the first; large ones, throughput-bound, the second.
-template <int M, bool SC>
+template <int M, bool SC, bool PH1>
 __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restrict__ perm,
                                                         const float* __restrict__ xs, const float* __restrict__ ys,
                                                         const int32_t* __restrict__ ids,
@@ -665,7 +666,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
             auto col_id = [&](int j) { return ids[(unsigned)s_meta[j * kFullBlock + tid] >> 6]; };
             const uint64_t pref = (warm_pass && out.use_prev) ? prev_mask(out.prev, own, k, col_id) : 0ull;
             uint64_t basis = 0;
-            st = k > 0 ? solve_lp<M>(cs, P, store, fii, piv, certified, warm_pass, logit, warm, basis,
+            st = k > 0 ? solve_lp<M, PH1>(cs, P, store, fii, piv, certified, warm_pass, logit, warm, basis,
                                      warm_pass && out.use_prev, pref)
                        : 1;
             if (st == 0 && out.prev) record_basis(out.prev, own, basis, col_id);
@@ -855,7 +856,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         {
             ScopedTimer tm(c, VRM_T_LP_SMALL);
             for (int mode = first; mode <= (warm ? kLpRetry : kLpPlain); ++mode) {
-                hipLaunchKernelGGL(k_lp_small, dim3(lp_grid_small(c, n)), dim3(kSmallBlock), 0, c->stream, c->perm, c->xs,
+                hipLaunchKernelGGL((lp.phase1 ? k_lp_small<true> : k_lp_small<false>), dim3(lp_grid_small(c, n)), dim3(kSmallBlock), 0, c->stream, c->perm, c->xs,
                                    c->ys, c->ids, c->srec, c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc,
                                    lp, out, apply, c->counters, mode, c->q_retry, c->tuning.lp_small_lanes);
                 VRM_HIP(hipGetLastError());
@@ -867,14 +868,20 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         o2.feat = nullptr;
         o2.lab = nullptr;
         ScopedTimer tm(c, VRM_T_LP_FULL);
-        hipLaunchKernelGGL((full_stored_costs(c, n) ? k_lp_full<5, true> : k_lp_full<5, false>), dim3(min(lp_grid_full(c, n), 64)), dim3(kFullBlock), 0, c->stream, c->perm,
+        const bool stored = full_stored_costs(c, n);
+        hipLaunchKernelGGL((lp.phase1 ? (stored ? k_lp_full<5, true, true> : k_lp_full<5, false, true>)
+                                      : (stored ? k_lp_full<5, true, false> : k_lp_full<5, false, false>)),
+                           dim3(min(lp_grid_full(c, n), 64)), dim3(kFullBlock), 0, c->stream, c->perm,
                            c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                            o2, apply, c->counters, kLpPlain, c->q_retry, 1);
     } else {
         ScopedTimer tm(c, VRM_T_LP_FULL);
         const int last = warm ? kLpRetry : kLpPlain;
         for (int mode = first; mode <= last; ++mode) {
-            hipLaunchKernelGGL((full_stored_costs(c, n) ? k_lp_full<9, true> : k_lp_full<9, false>), dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
+            const bool stored = full_stored_costs(c, n);
+            hipLaunchKernelGGL((lp.phase1 ? (stored ? k_lp_full<9, true, true> : k_lp_full<9, false, true>)
+                                          : (stored ? k_lp_full<9, true, false> : k_lp_full<9, false, false>)),
+                               dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
                                c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                                out, apply, c->counters, mode, c->q_retry, mode == last ? 1 : 0);
             VRM_HIP(hipGetLastError());

@@ -347,7 +347,11 @@ struct ThreadSimplex {
     // 2: phase II from a feasible basis).  0 optimal, 1 infeasible, 2 iteration
     // limit (cap >= 0: at most cap iterations per phase).  Both phases share one
     // loop, so the lanes of a wave step through their own phases together.
-    __device__ int run(const CS& cs, int& piv, int first, int cap = -1)
+    // With acc (phase I only): at the end of phase I the vertex is offered to
+    // accept_phase1 (refined basic values into *x); if taken, *accepted is set
+    // and run returns 0, else phase II continues.
+    __device__ int run(const CS& cs, int& piv, int first, int cap = -1, const LaunchParams* acc = nullptr,
+                       df* x = nullptr, bool* accepted = nullptr)
     {
         const int k = cs.k;
         const int bland_after = 3 * (k + M);
@@ -377,6 +381,10 @@ struct ThreadSimplex {
                 blk = 0;
                 p2 = true;
                 it = -1;
+                if (acc && accept_phase1(cs, *acc, *reinterpret_cast<df(*)[M]>(x))) {
+                    *accepted = true;
+                    return 0;
+                }
                 continue;
             }
             float rx, ry, ce;
@@ -449,31 +457,55 @@ struct ThreadSimplex {
         }
     }
 
+    // Basic solution of the current basis for the exact right-hand side, refined
+    // with double-float residuals; returns |first correction| / |x| (how far
+    // B^-1 is from the exact inverse).
+    __device__ float refine_primal(const CS& cs, const LaunchParams& P, df (&x)[M]) const
+    {
+#pragma unroll
+        for (int r = 0; r < M; ++r) x[r] = {(Bi[r][2] + Bi[r][4]) * P.bt_hi, 0.0f};
+        float first_corr = 1.0f;
+        for (int it = 0; it < kMaxRefine; ++it) {
+            float res[M];
+            primal_residual(cs, x, P, res);
+            float dmax = 0.0f, xmax = 0.0f;
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                float d = 0.0f;
+#pragma unroll
+                for (int a = 0; a < M; ++a) d = __builtin_fmaf(Bi[r][a], res[a], d);
+                x[r] = df_add(x[r], df{d, 0.0f});
+                dmax = fmaxf(dmax, fabsf(d));
+                xmax = fmaxf(xmax, fabsf(x[r].hi));
+            }
+            if (it == 0) first_corr = dmax / fmaxf(xmax, 1e-30f);
+            if (dmax <= 9.313225746154785e-10f * xmax) break;
+        }
+        return first_corr;
+    }
+
+    // Phase I only (Sec. 4.1: the first feasible vertex): the refined basic
+    // solution is accepted if every structural basic value is >= -1e-9 and
+    // every artificial one has vanished.
+    __device__ bool accept_phase1(const CS& cs, const LaunchParams& P, df (&x)[M]) const
+    {
+        refine_primal(cs, P, x);
+        bool ok = true;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const float v = x[r].hi + x[r].lo;
+            ok = ok && (bs[r] < ART ? !(v < -kCertX) : !(fabsf(v) > kCertX));
+        }
+        return ok;
+    }
+
     // Certify against the exact problem, repairing the basis if needed.
     // 0 optimal, 1 infeasible, 3 not certified.  x receives the basic values.
     __device__ int certify(const CS& cs, const LaunchParams& P, df (&x)[M], int& piv)
     {
         const int k = cs.k;
         for (int round = 0; round < kMaxCert; ++round) {
-#pragma unroll
-            for (int r = 0; r < M; ++r) x[r] = {(Bi[r][2] + Bi[r][4]) * P.bt_hi, 0.0f};
-            float first_corr = 1.0f;   // |first correction| / |x|: how far B^-1 is from the exact inverse
-            for (int it = 0; it < kMaxRefine; ++it) {
-                float res[M];
-                primal_residual(cs, x, P, res);
-                float dmax = 0.0f, xmax = 0.0f;
-#pragma unroll
-                for (int r = 0; r < M; ++r) {
-                    float d = 0.0f;
-#pragma unroll
-                    for (int a = 0; a < M; ++a) d = __builtin_fmaf(Bi[r][a], res[a], d);
-                    x[r] = df_add(x[r], df{d, 0.0f});
-                    dmax = fmaxf(dmax, fabsf(d));
-                    xmax = fmaxf(xmax, fabsf(x[r].hi));
-                }
-                if (it == 0) first_corr = dmax / fmaxf(xmax, 1e-30f);
-                if (dmax <= 9.313225746154785e-10f * xmax) break;
-            }
+            const float first_corr = refine_primal(cs, P, x);
             // Fast certificate: when B^-1 is accurate (the first correction is
             // tiny) and every FP32 reduced cost clears zero by a margin far above
             // its rounding error, the basis is optimal without the double-float
@@ -637,7 +669,9 @@ struct ThreadSimplex {
 template <int M>
 constexpr int warm_cap() { return M == 5 ? 3 : 12; }
 
-template <int M, class CS, class Store>
+// PH1: phase I only (the first feasible vertex, P.phase1) compiled in; the
+// canonical-only instantiation carries none of its code.
+template <int M, bool PH1, class CS, class Store>
 __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified,
                         bool warm_pass, const float* logit, int& warm, uint64_t& basis, bool use_pref = false,
                         uint64_t pref = 0)
@@ -661,13 +695,18 @@ __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float&
             return 4;
         }
         warm = piv == p1 ? 1 : 2;
-    } else {
-        st = lp.run(cs, piv, 1);
+    }
+    df x[M];
+    bool accepted = false;   // phase I only: the first feasible vertex, exact to the refinement
+    if (!warm_pass) {
+        if constexpr (PH1)
+            st = lp.run(cs, piv, 1, -1, &P, x, &accepted);
+        else
+            st = lp.run(cs, piv, 1);
     }
     certified = 1;
     if (st == 1) return 1;
-    df x[M];
-    int c = lp.certify(cs, P, x, piv);
+    const int c = accepted ? 0 : lp.certify(cs, P, x, piv);
     if (c == 1) return 1;
     certified = (c == 0 && st == 0) ? 1 : 0;
     float sum = 0.0f;
