@@ -45,7 +45,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(wl, steps, warmup, theta=None, warm_mode=0, tuning=None):
+def run_gpu(wl, steps, warmup, theta=None, warm_mode=0, tuning=None, lp_objective=0):
     import torch
     import paper_1508_06379_amd as vrm
 
@@ -56,6 +56,7 @@ def run_gpu(wl, steps, warmup, theta=None, warm_mode=0, tuning=None):
     ctx = vrm.Context(cap)
     if tuning:
         ctx.vrm_set_tuning(tuning)
+    ctx.vrm_set_lp_objective(lp_objective)
     if theta is not None:
         ctx.vrm_mlp_load(theta)
         ctx.vrm_set_warm_start(1)
@@ -236,9 +237,10 @@ def main():
     ap.add_argument("--workload", default="lamb_oseen_h0.01_q2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--solver", default="all", choices=["all", "both", "plain", "learned", "previous"],
-                    help="plain batched solver, learned warm start, previous-basis warm start; "
-                         "both = plain + learned, all = the three on the same workload")
+    ap.add_argument("--solver", default="all", choices=["all", "both", "plain", "learned", "previous", "phase1"],
+                    help="plain batched solver, learned warm start, previous-basis warm start, the first "
+                         "feasible vertex (phase I only); both = plain + learned, all = the four on the same "
+                         "workload")
     ap.add_argument("--train-snapshots", type=int, default=30)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -259,6 +261,8 @@ def main():
     train_info = None
     if args.solver in ("all", "previous"):
         runs["previous"] = run_gpu(wl, args.steps, args.warmup, warm_mode=2, tuning=tuning)
+    if args.solver in ("all", "phase1"):
+        runs["phase1"] = run_gpu(wl, args.steps, args.warmup, tuning=tuning, lp_objective=1)
     if args.solver in ("all", "both", "learned"):
         theta, train_info = train_network(args.workload, args.train_snapshots, args.epochs)
         log(f"network: {train_info}")
@@ -271,7 +275,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copy calibration: 5 copies of {src.numel() * 4} bytes")
-    main_solver = "plain" if "plain" in runs else ("learned" if "learned" in runs else "previous")
+    main_solver = next(k for k in ("plain", "learned", "previous", "phase1") if k in runs)
     res = runs[main_solver]
     c = res["counters"]
     value = c["redistributions"] / res["elapsed"]
@@ -304,6 +308,16 @@ def main():
                            "left_for_cold_solve": cp["warm_cold"] / nlp},
             "pivots": cp["pivots"], "uncertified": cp["n_uncertified"],
             "breakdown_ms_per_step": breakdown(r),
+        }
+    if "phase1" in runs and main_solver != "phase1":
+        r = runs["phase1"]
+        cp = r["counters"]
+        pv = cp["redistributions"] / r["elapsed"]
+        line["phase1_only"] = {
+            "value": pv, "ms_per_step": r["elapsed"] * 1e3 / args.steps, "vs_plain": pv / value,
+            "pivots": cp["pivots"], "pivots_per_lp": cp["pivots"] / max(1, cp["n_small"] + cp["n_full"]),
+            "uncertified": cp["n_uncertified"], "breakdown_ms_per_step": breakdown(r),
+            "note": "first feasible vertex (the paper's phase I); stencils differ from the canonical ones",
         }
     if "learned" in runs:
         r = runs["learned"]
