@@ -306,6 +306,31 @@ struct LdsColsT {
             cc = __builtin_fmaf(w, P->cs_hi, 0.0009765625f * (float)(smeta[j * BLK + tid] & 63));
         }
     }
+    // Raw column values, for loops that read column j + 1 while working on
+    // column j: the offsets, and the FP32 cost (STORED) or the meta word whose
+    // rank bits cost_of needs.
+    __device__ __forceinline__ void load(int j, float& x, float& y, uint32_t& aux) const
+    {
+        x = srx[j * BLK + tid];
+        y = sry[j * BLK + tid];
+        if constexpr (STORED)
+            aux = __float_as_uint(sc[j * BLK + tid]);
+        else
+            aux = (uint32_t)smeta[j * BLK + tid];
+    }
+    // FP32 cost of a column from load()'s values, for moment order Q (the
+    // value get() gives for P->q == Q)
+    template <int Q>
+    __device__ __forceinline__ float cost_of(float x, float y, uint32_t aux) const
+    {
+        if constexpr (STORED) {
+            return __uint_as_float(aux);
+        } else {
+            const float d2 = x * x + y * y;
+            const float w = Q == 2 ? d2 * __builtin_sqrtf(d2) : d2 * d2;
+            return __builtin_fmaf(w, P->cs_hi, 0.0009765625f * (float)(aux & 63u));
+        }
+    }
     __device__ __forceinline__ void exact_xy(int j, df& X, df& Y) const
     {
         if (sxlo) {
@@ -481,6 +506,42 @@ __device__ __forceinline__ uint64_t member_key(float d2, int id)
 // Complete neighbourhood of slot t within R_full (its VRM_KMAX nearest by (d2, id)
 // if larger), sorted nearest first.  Slots go to su[j * kFullBlock], keys to
 // sd2 / sid (same layout).  Returns the count.
+// Visit every member of the complete neighbourhood of slot t (within R_full,
+// not t itself): f(u, d2, id).  The three cells of a grid row are contiguous
+// in slot order; their positions and ids are loaded eight at a time, so one
+// memory latency covers eight candidates.
+template <class F>
+__device__ __forceinline__ void for_each_member(int t, float xi, float yi, int cx, int cy, const GridState& g,
+                                                const int32_t* __restrict__ cell_start, const float* __restrict__ xs,
+                                                const float* __restrict__ ys, const int32_t* __restrict__ ids,
+                                                const LaunchParams& P, F&& f)
+{
+    for (int oy = -1; oy <= 1; ++oy) {
+        const int yy = cy + oy;
+        if (yy < 0 || yy >= g.ny) continue;
+        const int c0 = yy * g.nx + max(cx - 1, 0), c1 = yy * g.nx + min(cx + 1, g.nx - 1);
+        const int u0 = cell_start[c0], u1 = cell_start[c1 + 1];
+        for (int u = u0; u < u1; u += 8) {
+            float bx[8], by[8];
+            int bi[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int v = min(u + e, u1 - 1);   // past the end: a repeat of the last slot, not visited
+                bx[e] = xs[v];
+                by[e] = ys[v];
+                bi[e] = ids[v];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                if (u + e >= u1 || u + e == t) continue;
+                const float d2 = d2_f32(bx[e] - xi, by[e] - yi);
+                if (d2 < P.lo2f || d2 > P.hi2f) continue;
+                f(u + e, d2, bi[e]);
+            }
+        }
+    }
+}
+
 __device__ int collect_full(int t, float xi, float yi, const GridState& g, const int32_t* __restrict__ cell_start,
                             const float* __restrict__ xs, const float* __restrict__ ys,
                             const int32_t* __restrict__ ids, const LaunchParams& P, int* su, float* sd2, int* sid,
@@ -489,74 +550,37 @@ __device__ int collect_full(int t, float xi, float yi, const GridState& g, const
     int cx, cy;
     cell_of_pos(g, xi, yi, cx, cy);
     int count = 0;
-    for (int oy = -1; oy <= 1; ++oy) {
-        int yy = cy + oy;
-        if (yy < 0 || yy >= g.ny) continue;
-        {
-            // the three cells of this row are contiguous in slot order
-            int c0 = yy * g.nx + max(cx - 1, 0), c1 = yy * g.nx + min(cx + 1, g.nx - 1);
-            int u0 = cell_start[c0], u1 = cell_start[c1 + 1];
-            for (int u = u0; u < u1; ++u) {
-                if (u == t) continue;
-                float d2 = d2_f32(xs[u] - xi, ys[u] - yi);
-                if (d2 < P.lo2f || d2 > P.hi2f) continue;
-                if (count < VRM_KMAX) {
-                    su[count * kFullBlock] = u;
-                    sd2[count * kFullBlock] = d2;
-                    sid[count * kFullBlock] = ids[u];
-                }
-                ++count;
-            }
+    for_each_member(t, xi, yi, cx, cy, g, cell_start, xs, ys, ids, P, [&](int u, float d2, int id) {
+        if (count < VRM_KMAX) {
+            su[count * kFullBlock] = u;
+            sd2[count * kFullBlock] = d2;
+            sid[count * kFullBlock] = id;
         }
-    }
+        ++count;
+    });
     truncated = count > VRM_KMAX;
     if (truncated) {
         // the VRM_KMAX-th smallest key, by bisection over the 64-bit keys
         uint64_t lo = 0, hi = ~0ull;
         while (lo < hi) {
-            uint64_t mid = lo + ((hi - lo) >> 1);
+            const uint64_t mid = lo + ((hi - lo) >> 1);
             int below = 0;
-            for (int oy = -1; oy <= 1; ++oy) {
-                int yy = cy + oy;
-                if (yy < 0 || yy >= g.ny) continue;
-                {
-                    // the three cells of this row are contiguous in slot order
-                    int c0 = yy * g.nx + max(cx - 1, 0), c1 = yy * g.nx + min(cx + 1, g.nx - 1);
-                    int u0 = cell_start[c0], u1 = cell_start[c1 + 1];
-                    for (int u = u0; u < u1; ++u) {
-                        if (u == t) continue;
-                        float d2 = d2_f32(xs[u] - xi, ys[u] - yi);
-                        if (d2 < P.lo2f || d2 > P.hi2f) continue;
-                        below += member_key(d2, ids[u]) <= mid ? 1 : 0;
-                    }
-                }
-            }
+            for_each_member(t, xi, yi, cx, cy, g, cell_start, xs, ys, ids, P,
+                            [&](int, float d2, int id) { below += member_key(d2, id) <= mid ? 1 : 0; });
             if (below >= VRM_KMAX)
                 hi = mid;
             else
                 lo = mid + 1;
         }
         int kk = 0;
-        for (int oy = -1; oy <= 1; ++oy) {
-            int yy = cy + oy;
-            if (yy < 0 || yy >= g.ny) continue;
-            {
-                // the three cells of this row are contiguous in slot order
-                int c0 = yy * g.nx + max(cx - 1, 0), c1 = yy * g.nx + min(cx + 1, g.nx - 1);
-                int u0 = cell_start[c0], u1 = cell_start[c1 + 1];
-                for (int u = u0; u < u1; ++u) {
-                    if (u == t) continue;
-                    float d2 = d2_f32(xs[u] - xi, ys[u] - yi);
-                    if (d2 < P.lo2f || d2 > P.hi2f) continue;
-                    if (member_key(d2, ids[u]) <= lo && kk < VRM_KMAX) {
-                        su[kk * kFullBlock] = u;
-                        sd2[kk * kFullBlock] = d2;
-                        sid[kk * kFullBlock] = ids[u];
-                        ++kk;
-                    }
-                }
+        for_each_member(t, xi, yi, cx, cy, g, cell_start, xs, ys, ids, P, [&](int u, float d2, int id) {
+            if (member_key(d2, id) <= lo && kk < VRM_KMAX) {
+                su[kk * kFullBlock] = u;
+                sd2[kk * kFullBlock] = d2;
+                sid[kk * kFullBlock] = id;
+                ++kk;
             }
-        }
+        });
         count = kk;
     }
     // insertion sort by (d2, id)
@@ -628,15 +652,29 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
             const bool rec = mode == kLpPlain && out.feat && item < out.max_rows;
             uint16_t* frow = rec ? out.feat + (size_t)item * kMlpIn : nullptr;
             if (rec) feature_zero(frow);
-            for (int j = 0; j < k; ++j) {
-                int meta = s_meta[j * kFullBlock + tid];
-                df X, Y;
-                int um = (int)((unsigned)meta >> 6);
-                exact_offset(xi, yi, xs[um], ys[um], P.scale2e, X, Y);
-                s_rx[j * kFullBlock + tid] = X.hi;
-                s_ry[j * kFullBlock + tid] = Y.hi;
-                if constexpr (SC) s_c[j * kFullBlock + tid] = add_rank(cost_df(X, Y, P), meta & 63).hi;
-                if (rec && j < kMlpSlots) feature_slot(frow, j, X.hi * P.sc, Y.hi * P.sc);
+            // exact offsets of the members, their positions loaded eight at a time
+            for (int j0 = 0; j0 < k; j0 += 8) {
+                int bm[8];
+                float bx[8], by[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bm[e] = s_meta[min(j0 + e, k - 1) * kFullBlock + tid];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int um = (int)((unsigned)bm[e] >> 6);
+                    bx[e] = xs[um];
+                    by[e] = ys[um];
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int j = j0 + e;
+                    if (j >= k) break;
+                    df X, Y;
+                    exact_offset(xi, yi, bx[e], by[e], P.scale2e, X, Y);
+                    s_rx[j * kFullBlock + tid] = X.hi;
+                    s_ry[j * kFullBlock + tid] = Y.hi;
+                    if constexpr (SC) s_c[j * kFullBlock + tid] = add_rank(cost_df(X, Y, P), bm[e] & 63).hi;
+                    if (rec && j < kMlpSlots) feature_slot(frow, j, X.hi * P.sc, Y.hi * P.sc);
+                }
             }
             if (rec) feature_q(frow, P.q);
             LdsColsT<kFullBlock, SC> cs{k, 0ull, s_rx, s_ry, s_c, s_meta, tid, xi, yi, xs, ys, &P, nullptr, nullptr};

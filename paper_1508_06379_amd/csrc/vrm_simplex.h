@@ -94,8 +94,13 @@ __device__ __forceinline__ df rhs_df(int a, const LaunchParams& P)
 //   void get(int j, float& rx, float& ry, float& c)  FP32 scaled offset and cost
 //   void exact(int j, df& X, df& Y, df& C)           exact offset and cost
 //   void exact_xy(int j, df& X, df& Y)               exact offset
+// and, for stores with a run-time column count (KC == 0),
+//   void load(int j, float& rx, float& ry, uint32_t& aux)  raw values of column j
+//   float cost_of<Q>(float rx, float ry, uint32_t aux)      its FP32 cost (order Q)
 template <int M, class CS>
 struct ThreadSimplex {
+    static_assert(M == 5 || M == 9, "5 rows for q = 2, 9 for q = 3");
+    static constexpr int kQ = M == 5 ? 2 : 3;   // moment order of an M-row LP
     float Bi[M][M];   // B^-1
     float xb[M];      // basic values (perturbed rhs)
     float cb[M];      // costs of the basic columns (0 for artificial ones)
@@ -329,15 +334,29 @@ struct ThreadSimplex {
                 if (consider(j, d, sc)) break;
             }
         } else {
-            for (int j = 0; j < cs.k; ++j) {
-                if ((excl >> j) & 1ull) continue;
-                float rx, ry, c;
-                cs.get(j, rx, ry, c);
-                float v[M];
-                mono<M>(rx, ry, v);
-                float d, sc;
-                reduced(v, c, y, p2, d, sc);
-                if (consider(j, d, sc)) break;
+            // Branch-free, four columns per iteration (their reads issued
+            // together); Bland's rule keeps the first qualifying column,
+            // Dantzig's the first of the most negative.
+            const int k = cs.k;
+            for (int j0 = 0; j0 < k; j0 += 4) {
+                float rx[4], ry[4];
+                uint32_t aux[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) cs.load(min(j0 + u, k - 1), rx[u], ry[u], aux[u]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = j0 + u;
+                    const float c = cs.template cost_of<kQ>(rx[u], ry[u], aux[u]);
+                    float v[M];
+                    mono<M>(rx[u], ry[u], v);
+                    float d, sc;
+                    reduced(v, c, y, p2, d, sc);
+                    const bool ok = j < k && !((excl >> j) & 1ull) && d < -kTolD * sc;
+                    if (ok && (e < 0 || (!bland && d < best))) {
+                        e = j;
+                        best = d;
+                    }
+                }
             }
         }
         return e;
@@ -533,15 +552,21 @@ struct ThreadSimplex {
                             dual_ok = dual_ok && !(d < kFastMargin * sc);
                         }
                     } else {
-                        for (int j = 0; j < k && dual_ok; ++j) {
-                            if ((excl >> j) & 1ull) continue;
-                            float rx, ry, c;
-                            cs.get(j, rx, ry, c);
-                            float v[M];
-                            mono<M>(rx, ry, v);
-                            float d, sc;
-                            reduced(v, c, yf, true, d, sc);
-                            if (d < kFastMargin * sc) dual_ok = false;
+                        for (int j0 = 0; j0 < k; j0 += 4) {
+                            float rx[4], ry[4];
+                            uint32_t aux[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) cs.load(min(j0 + u, k - 1), rx[u], ry[u], aux[u]);
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int j = j0 + u;
+                                const float c = cs.template cost_of<kQ>(rx[u], ry[u], aux[u]);
+                                float v[M];
+                                mono<M>(rx[u], ry[u], v);
+                                float d, sc;
+                                reduced(v, c, yf, true, d, sc);
+                                dual_ok = dual_ok && (j >= k || ((excl >> j) & 1ull) || !(d < kFastMargin * sc));
+                            }
                         }
                     }
                     if (dual_ok) return 0;
