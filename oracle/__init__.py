@@ -163,6 +163,44 @@ def insert(x, y, gamma, ids, mask, P: _Params, capacity=None):
     return X[:nn].copy(), Y[:nn].copy(), G[:nn].copy(), I[:nn].copy(), nc.value
 
 
+@dataclass
+class Removal:
+    x: np.ndarray        # the cloud after removal (kept particles, in input order)
+    y: np.ndarray
+    gamma: np.ndarray
+    ids: np.ndarray
+    removed_ids: np.ndarray
+    n_candidates: int
+    kcol: np.ndarray     # per input particle: columns of its identity LP (removed ones)
+    cols: np.ndarray     # [n, KMAX] input indices
+    g: np.ndarray        # [n, KMAX] fractions
+
+
+def remove(x, y, gamma, ids, P: _Params) -> Removal:
+    """Sec. 6 (Outlook) particle removal: particles closer than r h to another
+    are taken greedily in id order (none within R_full h of another taken one);
+    each gives its circulation to its neighbours by the first-order identity
+    LP (sum g = 1, sum g r = 0, g >= 0, min sum g (|r/h|^2 + 2^-16 rank^2)) and is
+    dropped; one whose LP is infeasible stays."""
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    G = np.array(gamma, np.float64)
+    ids = np.ascontiguousarray(ids, np.int32)
+    n = x.shape[0]
+    removed = np.zeros(n, np.uint8)
+    kcol = np.zeros(n, np.int32)
+    cols = np.full((n, KMAX), -1, np.int32)
+    g = np.zeros((n, KMAX))
+    nc = ctypes.c_int32(0)
+    nr = lib().orc_remove(n, _p(x), _p(y), _p(G), _p(ids), ctypes.byref(P), _p(removed), _p(kcol), _p(cols),
+                          _p(g), ctypes.byref(nc))
+    if nr < 0:
+        raise RuntimeError(f"orc_remove failed ({nr})")
+    keep = removed == 0
+    return Removal(x[keep].copy(), y[keep].copy(), G[keep].copy(), ids[keep].copy(), ids[~keep].copy(),
+                   nc.value, kcol, cols, g)
+
+
 def stencil_matrix_row(st: Stencils, i: int):
     """Column particle indices and fractions of particle i (incl. the self fraction)."""
     k = st.kcol[i]

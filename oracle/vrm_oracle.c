@@ -21,6 +21,8 @@
  *   operator apply    Sec. 3.4 eq. (nsode): dGamma_i/dt = nu sum_j f_ji Gamma_j
  *   time stepping     Sec. 3.3: Euler steps; SSP Runge-Kutta schemes are convex
  *                     combinations of Euler steps (Shu-Osher SSP-RK3 here)
+ *   removal           Sec. 6 (Outlook): the identity operator approximated by
+ *                     a particle's neighbours, its circulation given to them
  *
  * Readings where the paper is silent (the same readings bind the GPU path):
  *   - q is the highest moment order matched: q = 2 -> 5 rows (paper n = 1),
@@ -762,6 +764,144 @@ int orc_insert(int n, int cap, double* x, double* y, double* gamma, int32_t* id,
     free(acc);
     free(c);
     return n + na;
+}
+
+/* ------------------------------------------------------ particle removal */
+/* Particle removal (Sec. 6 "Outlook"): the same moment method, applied to the
+ * identity operator instead of the Laplacian, gives a particle's circulation
+ * to its neighbours so that the particle itself can be dropped.
+ *
+ * Readings (the passage gives the idea only):
+ *   - With non-negative fractions the identity can be matched to first order
+ *     only (a second moment sum_j g_j |r_j|^2 is positive), so the conditions
+ *     are sum_j g_j = 1 and sum_j g_j r_j = 0 (three rows: 1, x, y), g >= 0.
+ *     They keep I0 and I1 exactly; I2 grows by Gamma_i sum_j g_j |r_j|^2.
+ *   - Among those g, the one minimising sum_j c_j g_j with
+ *     c_j = |r_j/h|^2 + 2^-16 rank_j^2: the I2 change plus a tie-break.  The
+ *     tie-break is convex in the rank: on a lattice the ids of opposite
+ *     neighbours are symmetric about i, so every opposite pair has the same
+ *     rank sum and a tie-break linear in the rank would leave them tied.
+ *   - Columns: the complete neighbourhood r h <= |r_j| <= R_full h (its KMAX
+ *     nearest by (d2, id)).
+ *   - Candidates are particles closer than r h to another particle (the ones
+ *     the neighbourhood definition leaves out).  They are taken greedily in
+ *     id order; one is rejected when it lies within R_full h of a candidate
+ *     already taken, so that no removed particle receives circulation from
+ *     another.  A taken candidate whose LP is infeasible stays.
+ *   - Distances are decided in FP32 as for the neighbourhoods.
+ * Outputs: removed[i] = 1 for removed particles; gamma of the receivers is
+ * updated in place (removed entries keep their value; the caller drops them);
+ * for removed particles kcol/cols/g hold the columns and fractions (KMAX per
+ * particle).  Returns the number removed, or a negative error. */
+typedef struct { int32_t id; int idx; } orc_idk;
+
+static int idk_cmp(const void* pa, const void* pb)
+{
+    const orc_idk* a = (const orc_idk*)pa;
+    const orc_idk* b = (const orc_idk*)pb;
+    return (a->id > b->id) - (a->id < b->id);
+}
+
+int orc_remove(int n, const double* x, const double* y, double* gamma, const int32_t* id, const orc_params* P,
+               uint8_t* removed, int32_t* kcol, int32_t* cols, double* g, int32_t* n_candidates)
+{
+    orc_grid gr;
+    if (grid_build(&gr, n, x, y, P->R_full * P->h * 1.01) != 0) return -1;
+    float lo2, hi2;
+    annulus_bounds(P->h, P->r, P->R_full, &lo2, &hi2);
+    /* candidates: another particle closer than r h */
+    orc_idk* cand = (orc_idk*)malloc(sizeof(orc_idk) * (size_t)(n > 0 ? n : 1));
+    uint8_t* taken = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
+    double* delta = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    int nc = 0;
+    for (int i = 0; i < n; ++i) {
+        removed[i] = 0;
+        kcol[i] = 0;
+        float xi = (float)x[i], yi = (float)y[i];
+        int cx, cy, close = 0;
+        grid_cell(&gr, x[i], y[i], &cx, &cy);
+        for (int oy = -1; oy <= 1 && !close; ++oy)
+            for (int ox = -1; ox <= 1 && !close; ++ox) {
+                int xx = cx + ox, yy = cy + oy;
+                if (xx < 0 || yy < 0 || xx >= gr.nx || yy >= gr.ny) continue;
+                int c = yy * gr.nx + xx;
+                for (int t = gr.start[c]; t < gr.start[c + 1]; ++t) {
+                    int j = gr.items[t];
+                    if (j != i && f32_d2((float)x[j] - xi, (float)y[j] - yi) < lo2) {
+                        close = 1;
+                        break;
+                    }
+                }
+            }
+        if (close) {
+            cand[nc].id = id[i];
+            cand[nc].idx = i;
+            ++nc;
+        }
+    }
+    if (n_candidates) *n_candidates = nc;
+    /* greedy in id order, exclusion radius R_full h */
+    qsort(cand, (size_t)nc, sizeof(orc_idk), idk_cmp);
+    for (int a = 0; a < nc; ++a) {
+        int i = cand[a].idx;
+        float xi = (float)x[i], yi = (float)y[i];
+        int cx, cy, clash = 0;
+        grid_cell(&gr, x[i], y[i], &cx, &cy);
+        for (int oy = -1; oy <= 1 && !clash; ++oy)
+            for (int ox = -1; ox <= 1 && !clash; ++ox) {
+                int xx = cx + ox, yy = cy + oy;
+                if (xx < 0 || yy < 0 || xx >= gr.nx || yy >= gr.ny) continue;
+                int c = yy * gr.nx + xx;
+                for (int t = gr.start[c]; t < gr.start[c + 1]; ++t) {
+                    int j = gr.items[t];
+                    if (j != i && taken[j] && f32_d2((float)x[j] - xi, (float)y[j] - yi) <= hi2) {
+                        clash = 1;
+                        break;
+                    }
+                }
+            }
+        if (!clash) taken[i] = 1;
+    }
+    /* the identity LP of every taken candidate */
+    int nrem = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!taken[i]) continue;
+        orc_nb mem[512];
+        int cf = annulus_members(&gr, x, y, id, i, lo2, hi2, mem, 512);
+        if (cf > 512) { nrem = -3; break; }
+        qsort(mem, (size_t)cf, sizeof(orc_nb), nb_cmp_dist);
+        int k = cf < ORC_KMAX ? cf : ORC_KMAX;
+        if (k == 0) continue;
+        double A[3 * ORC_KMAX], b[3] = {1.0, 0.0, 0.0}, c[ORC_KMAX], f[ORC_KMAX];
+        for (int t = 0; t < k; ++t) {
+            int j = mem[t].idx;
+            double rx = (x[j] - x[i]) / P->h;
+            double ry = (y[j] - y[i]) / P->h;
+            int rank = 0;
+            for (int u = 0; u < k; ++u)
+                if (mem[u].id < mem[t].id) ++rank;
+            A[0 * k + t] = 1.0;
+            A[1 * k + t] = rx;
+            A[2 * k + t] = ry;
+            c[t] = rx * rx + ry * ry + 0x1p-16 * rank * rank;
+        }
+        if (orc_lp(3, k, A, b, c, f, NULL, NULL) != 0) continue;
+        removed[i] = 1;
+        kcol[i] = k;
+        for (int t = 0; t < k; ++t) {
+            cols[(size_t)i * ORC_KMAX + t] = mem[t].idx;
+            g[(size_t)i * ORC_KMAX + t] = f[t];
+            delta[mem[t].idx] += f[t] * gamma[i];
+        }
+        ++nrem;
+    }
+    if (nrem >= 0)
+        for (int i = 0; i < n; ++i) gamma[i] += delta[i];
+    free(cand);
+    free(taken);
+    free(delta);
+    grid_free(&gr);
+    return nrem;
 }
 
 int orc_kmax(void) { return ORC_KMAX; }

@@ -29,7 +29,7 @@ __all__ = [
     "Workload", "lattice", "lamb_oseen_omega", "lamb_oseen_velocity",
     "vortex_set", "vortices_gamma", "vortices_velocity",
     "config_lattice_small", "config_jittered", "config_vortices",
-    "config_scale", "training_snapshot", "lone_particle", "PRESETS", "make",
+    "config_scale", "config_close_pairs", "training_snapshot", "lone_particle", "PRESETS", "make",
 ]
 
 
@@ -181,6 +181,29 @@ def config_scale(h: float = 0.004, lo: float = -8.0, hi: float = 8.0, q: int = 3
     w = _vortex_cloud(f"vortices256_h{h}_q{q}", lo, hi, h, 256, 5, 51, 0, 0.0, q)
     w.steps = 50
     return w
+
+
+def config_close_pairs(h: float = 0.01, q: int = 2, frac: float = 0.05, seed: int = 4, lo: float = -1.0,
+                       hi: float = 1.0) -> Workload:
+    """Particle-removal input: the jittered Lamb-Oseen cloud (U(+-0.25h) per
+    coordinate) over [lo, hi]^2 plus, at a seeded fraction `frac` of the sites,
+    one more particle at distance U(0.05h, 0.45h) in a uniform direction (closer
+    than r h = 0.5h to its site).  The extra particles carry the field's
+    circulation density too and take the ids after the sites."""
+    nu, t0 = 0.01, 1.0
+    x, y = lattice(lo, hi, h)
+    rng = np.random.default_rng(seed)
+    x = x + rng.uniform(-0.25 * h, 0.25 * h, x.shape)
+    y = y + rng.uniform(-0.25 * h, 0.25 * h, y.shape)
+    pick = rng.random(x.shape) < frac
+    d = rng.uniform(0.05 * h, 0.45 * h, int(pick.sum()))
+    a = rng.uniform(0.0, 2.0 * np.pi, d.shape)
+    x = np.concatenate([x, x[pick] + d * np.cos(a)])
+    y = np.concatenate([y, y[pick] + d * np.sin(a)])
+    x32, y32 = _f32(x), _f32(y)
+    g = lamb_oseen_omega(x32.astype(np.float64), y32.astype(np.float64), t0, nu) * h * h
+    return Workload(f"close_pairs_h{h}_q{q}", x32, y32, _f32(g), h=h, nu=nu, q=q, dt=0.1 * h * h / nu,
+                    steps=0, t0=t0, R_full=2.0 if q == 2 else 3.0)
 
 
 def training_snapshot(seed: int, h: float = 0.01, q: int = 2, kind: str = "lamb_oseen") -> Workload:
