@@ -53,7 +53,8 @@ typedef struct vrm_ctx vrm_ctx;
 /* Particle cloud (Sec. 1, eq. vfield), structure of arrays, all device
  * pointers of `capacity` entries.  n_dev points to one int32 in device memory
  * holding the current count N; insertion increases it on the device.
- * vrm_insert_particles permutes the arrays (id travels with its particle). */
+ * vrm_insert_particles permutes the arrays (id travels with its particle);
+ * vrm_remove_particles drops entries and closes the gaps in order. */
 typedef struct {
     float* x_dev;
     float* y_dev;
@@ -156,6 +157,23 @@ int vrm_build_neighbourhoods(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_par
  * device; reported by the next vrm_read_counters as capacity_needed) the
  * cloud is left unchanged. */
 int vrm_insert_particles(vrm_ctx* ctx, vrm_cloud* cloud, const vrm_params* p);
+
+/* Sec. 6 (outlook): particle removal.  The moment method applied to the
+ * identity operator instead of the Laplacian gives a particle's circulation
+ * to its neighbours, after which the particle is dropped.  A particle is a
+ * candidate when another one lies closer than r h (inside the annulus the
+ * neighbourhoods leave out).  Candidates are taken greedily in id order,
+ * skipping any within R_full h of one already taken, so no removed particle
+ * receives circulation.  A taken particle i solves, over its complete
+ * neighbourhood r h <= |r_ij| <= R_full h (its VRM_KMAX nearest members),
+ *   sum_j g_j = 1,  sum_j g_j r_ij = 0,  g >= 0   (first order: with g >= 0 no
+ *   second moment can vanish), minimising sum_j g_j (|r_ij/h|^2 + 2^-16 rank(id_j)^2);
+ * then Gamma_j += g_j Gamma_i and i is removed.  A particle whose LP is
+ * infeasible stays.  I0 and I1 are kept; I2 grows by Gamma_i sum_j g_j |r_ij|^2.
+ * The kept particles keep their order; *n_dev is updated.  Synchronises.
+ * n_removed, n_candidates: host pointers (may be NULL) for the counts. */
+int vrm_remove_particles(vrm_ctx* ctx, vrm_cloud* cloud, const vrm_params* p, int32_t* n_removed,
+                         int32_t* n_candidates);
 
 /* Sec. 2 and 4.1-4.3: stencils of all diffused particles at the current
  * positions.  The small-neighbourhood LP is tried when it has at least as many

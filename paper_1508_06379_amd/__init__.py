@@ -73,7 +73,7 @@ class vrm_counters(ctypes.Structure):
 
 
 EXPORTS = ["vrm_create", "vrm_destroy", "vrm_select_diffused", "vrm_set_diffused", "vrm_build_neighbourhoods",
-           "vrm_insert_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_step", "vrm_set_graph", "vrm_set_tuning",
+           "vrm_insert_particles", "vrm_remove_particles", "vrm_solve_fractions", "vrm_rk_stage", "vrm_step", "vrm_set_graph", "vrm_set_tuning",
            "vrm_get_tuning", "vrm_verify",
            "vrm_read_counters",
            "vrm_vortex_velocity", "vrm_biot_savart", "vrm_set_lp_objective", "vrm_timing", "vrm_timing_groups", "vrm_read_timing", "vrm_mlp_load", "vrm_mlp_read",
@@ -99,6 +99,8 @@ def lib():
         L.vrm_set_diffused.argtypes = [vp, ctypes.POINTER(vrm_cloud), vp]
         L.vrm_build_neighbourhoods.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params), vp, vp]
         L.vrm_insert_particles.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params)]
+        L.vrm_remove_particles.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.vrm_solve_fractions.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params),
                                           ctypes.POINTER(vrm_stencils)]
         L.vrm_rk_stage.argtypes = [vp, ctypes.POINTER(vrm_cloud), vp, vp, ctypes.POINTER(vrm_params), ctypes.c_int]
@@ -252,6 +254,13 @@ class Context:
 
     def vrm_insert_particles(self, cloud: Cloud, p: vrm_params):
         _check(lib().vrm_insert_particles(self.handle, ctypes.byref(cloud.c), ctypes.byref(p)))
+
+    def vrm_remove_particles(self, cloud: Cloud, p: vrm_params):
+        """Particle removal (Sec. 6, outlook); returns (removed, candidates)."""
+        nr, nc = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().vrm_remove_particles(self.handle, ctypes.byref(cloud.c), ctypes.byref(p), ctypes.byref(nr),
+                                          ctypes.byref(nc)))
+        return nr.value, nc.value
 
     def vrm_solve_fractions(self, cloud: Cloud, p: vrm_params, out: Stencils):
         st = out.c()

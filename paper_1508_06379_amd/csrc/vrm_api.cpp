@@ -353,6 +353,43 @@ int vrm_insert_particles(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p)
     return VRM_OK;
 }
 
+int vrm_remove_particles(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p, int32_t* n_removed, int32_t* n_candidates)
+{
+    int r = check_cloud(c, cl);
+    if (!r) r = check_params(p);
+    if (!r) r = read_n(c, cl);
+    if (r) return r;
+    vrm::LaunchParams L = launch_params(c, p);
+    if (!(c->sorted && c->cells_valid)) {
+        r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
+        if (r) return r;
+        c->cells_valid = 1;
+        c->sorted = 0;
+    }
+    // the identity LP: rows 1, x, y; rhs e0 (scale-free); cost |r/h|^2 = |X|^2 (2^e / h)^2
+    vrm::LaunchParams R = L;
+    R.q = 1;
+    R.m = 3;
+    R.bt_hi = 1.0f;
+    R.bt_lo = 0.0f;
+    R.cs_hi = (float)((double)L.sc * (double)L.sc);
+    R.cs_lo = (float)((double)L.sc * (double)L.sc - (double)R.cs_hi);
+    R.phase1 = 0;
+    int32_t nc = 0;
+    const int m = vrm_remove_run(c, cl, c->n, R, &nc);
+    if (m < 0) return m;
+    if (n_candidates) *n_candidates = nc;
+    if (n_removed) *n_removed = c->n - m;
+    if (m != c->n) {
+        c->n = m;
+        c->cells_valid = 0;
+        c->sorted = 0;
+        c->n_diffused_valid = 0;
+        c->base_valid = 0;
+    }
+    return VRM_OK;
+}
+
 int vrm_solve_fractions(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, vrm_stencils* out)
 {
     int r = check_cloud(c, cl);

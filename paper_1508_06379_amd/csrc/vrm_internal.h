@@ -70,6 +70,8 @@ struct Queues {
     int32_t blocks_done;   // blocks of the last LP launch that have finished
     int32_t last_small;    // n_small and n_full of the last stencil run (the queues
     int32_t last_full;     // themselves are zero between runs)
+    int32_t n_removed;     // particle removal: particles removed by the last call
+    int32_t n_rm_uncertified;   // ... of which optimality was not certified
 };
 
 // Column records of the queued small-neighbourhood LPs, in queue order and
@@ -235,6 +237,7 @@ int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* i
 int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double bound_factor);
 int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp);
 int vrm_reorder_cloud(vrm_ctx* c, vrm_cloud* cl, int32_t n);
+int vrm_remove_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp, int32_t* n_candidates);
 // launchers (vrm_lp.hip)
 int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp,
                     const vrm_stencils* out, int apply, uint16_t* feat_out = nullptr, float* label_out = nullptr,

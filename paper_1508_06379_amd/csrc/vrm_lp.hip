@@ -5,11 +5,15 @@
 // (segments), Sec. 4.3 (small neighbourhoods first, complete ones as a
 // fallback), Sec. 3.4 eq. nsode (dGamma_i/dt = nu sum_j f_ji Gamma_j).
 //
+// Particle removal (Sec. 6, outlook) solves the identity operator's LP with
+// the same machinery.
+//
 // Small-neighbourhood LPs (5 rows, 8 columns) keep their columns in
 // registers; complete-neighbourhood LPs (up to 48 columns) keep them in LDS.
 // Each LP is solved by one thread (vrm_simplex.h).  The fractions are
 // scattered into sum_j fhat_ji Gamma_j with atomics.
 #include <hip/hip_runtime.h>
+#include <rocprim/device/device_scan.hpp>
 
 #include "vrm_device.h"
 #include "vrm_internal.h"
@@ -224,10 +228,19 @@ __device__ __forceinline__ void count_add(int* p, bool v)
     if (m && lane_id() == __ffsll((unsigned long long)m) - 1) atomicAdd(p, __popcll(m));
 }
 
-// add 2^-10 rank(id) to a double-float cost (exact at these magnitudes)
-__device__ __forceinline__ df add_rank(df C, int rank)
+// Tie-break of the canonical cost: 2^-10 rank(id); for the removal LP (q = 1)
+// 2^-16 rank^2, convex in the rank because on a lattice the id ranks of
+// opposite neighbours are symmetric and would tie under a linear weight.
+// Exact in FP32 for ranks < 64.
+__device__ __forceinline__ float tie_weight(unsigned rank, int q)
 {
-    df w = two_sum(C.hi, 0.0009765625f * (float)rank);
+    return q == 1 ? 0x1p-16f * (float)(rank * rank) : 0.0009765625f * (float)rank;
+}
+
+// add the tie-break to a double-float cost (exact at these magnitudes)
+__device__ __forceinline__ df add_rank(df C, int rank, int q)
+{
+    df w = two_sum(C.hi, tie_weight((unsigned)rank, q));
     w.lo += C.lo;
     return fast_two_sum(w.hi, w.lo);
 }
@@ -302,8 +315,8 @@ struct LdsColsT {
         } else {
             // FP32 cost from the FP32 offset (the exact cost is recomputed for certification)
             const float d2 = x * x + y * y;
-            const float w = P->q == 2 ? d2 * __builtin_sqrtf(d2) : d2 * d2;
-            cc = __builtin_fmaf(w, P->cs_hi, 0.0009765625f * (float)(smeta[j * BLK + tid] & 63));
+            const float w = P->q == 1 ? d2 : P->q == 2 ? d2 * __builtin_sqrtf(d2) : d2 * d2;
+            cc = __builtin_fmaf(w, P->cs_hi, tie_weight((unsigned)smeta[j * BLK + tid] & 63u, P->q));
         }
     }
     // Raw column values, for loops that read column j + 1 while working on
@@ -327,8 +340,8 @@ struct LdsColsT {
             return __uint_as_float(aux);
         } else {
             const float d2 = x * x + y * y;
-            const float w = Q == 2 ? d2 * __builtin_sqrtf(d2) : d2 * d2;
-            return __builtin_fmaf(w, P->cs_hi, 0.0009765625f * (float)(aux & 63u));
+            const float w = Q == 1 ? d2 : Q == 2 ? d2 * __builtin_sqrtf(d2) : d2 * d2;
+            return __builtin_fmaf(w, P->cs_hi, tie_weight(aux & 63u, Q));
         }
     }
     __device__ __forceinline__ void exact_xy(int j, df& X, df& Y) const
@@ -344,7 +357,7 @@ struct LdsColsT {
     __device__ __forceinline__ void exact(int j, df& X, df& Y, df& C) const
     {
         exact_xy(j, X, Y);
-        C = add_rank(cost_df(X, Y, *P), smeta[j * BLK + tid] & 63);
+        C = add_rank(cost_df(X, Y, *P), smeta[j * BLK + tid] & 63, P->q);
     }
 };
 
@@ -407,7 +420,7 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
                 int meta = 0;
                 if (pj >= 0) {
                     const int rank = (packed >> (3 * s)) & 7;
-                    df C = add_rank(cost_df(X, Y, P), rank);
+                    df C = add_rank(cost_df(X, Y, P), rank, P.q);
                     c = C.hi;
                     meta = (int)(((unsigned)pj << 6) | (unsigned)rank);
                     if (record) feature_slot(frow, s, X.hi * P.sc, Y.hi * P.sc);
@@ -672,7 +685,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
                     exact_offset(xi, yi, bx[e], by[e], P.scale2e, X, Y);
                     s_rx[j * kFullBlock + tid] = X.hi;
                     s_ry[j * kFullBlock + tid] = Y.hi;
-                    if constexpr (SC) s_c[j * kFullBlock + tid] = add_rank(cost_df(X, Y, P), bm[e] & 63).hi;
+                    if constexpr (SC) s_c[j * kFullBlock + tid] = add_rank(cost_df(X, Y, P), bm[e] & 63, P.q).hi;
                     if (rec && j < kMlpSlots) feature_slot(frow, j, X.hi * P.sc, Y.hi * P.sc);
                 }
             }
@@ -757,6 +770,209 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
         }
     }
 }
+
+// ------------------------------------------------------------ particle removal
+// Particle removal (Sec. 6, outlook): a particle closer than r h to another
+// gives its circulation to its complete neighbourhood (r h .. R_full h) by
+// the first-order identity LP -- sum g = 1, sum g r = 0, g >= 0, minimising
+// sum g (|r/h|^2 + 2^-16 rank^2) -- and is dropped.  Candidates are taken
+// greedily in id order, skipping one within R_full h of a taken candidate (so
+// no removed particle receives circulation); one whose LP is infeasible stays.
+constexpr uint8_t kRmNone = 0, kRmUndecided = 1, kRmIn = 2, kRmOut = 3;
+
+// candidates: a particle closer than r h to another (per slot)
+__global__ __launch_bounds__(256) void k_rm_candidates(int n, const float* __restrict__ xs,
+                                                       const float* __restrict__ ys,
+                                                       const int32_t* __restrict__ cell_start, const GridState* gs,
+                                                       LaunchParams P, uint8_t* state, Queues* qs)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    bool close = false;
+    if (t < n) {
+        const GridState g = *gs;
+        const float xi = xs[t], yi = ys[t];
+        int cx, cy;
+        cell_of_pos(g, xi, yi, cx, cy);
+        for (int oy = -1; oy <= 1 && !close; ++oy) {
+            const int yy = cy + oy;
+            if (yy < 0 || yy >= g.ny) continue;
+            const int u0 = cell_start[yy * g.nx + max(cx - 1, 0)];
+            const int u1 = cell_start[yy * g.nx + min(cx + 1, g.nx - 1) + 1];
+            for (int u = u0; u < u1 && !close; ++u) close = u != t && d2_f32(xs[u] - xi, ys[u] - yi) < P.lo2f;
+        }
+        state[t] = close ? kRmUndecided : kRmNone;
+    }
+    count_add(&qs->n_cand, close);
+}
+
+// One round of the greedy selection in id order: an undecided candidate with a
+// taken candidate within R_full h is out; one with no smaller-id candidate
+// still undecided there is taken.  States only go from undecided to taken or
+// out, so reading a neighbour's state while it changes is safe: both values
+// lead to a decision the sequential greedy pass also makes.
+__global__ __launch_bounds__(256) void k_rm_mis_round(int n, const float* __restrict__ xs,
+                                                      const float* __restrict__ ys, const int32_t* __restrict__ ids,
+                                                      const int32_t* __restrict__ cell_start, const GridState* gs,
+                                                      LaunchParams P, uint8_t* state, Queues* qs)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    volatile uint8_t* vstate = state;   // other threads change it during the round
+    if (t >= n || vstate[t] != kRmUndecided) return;
+    const GridState g = *gs;
+    const float xi = xs[t], yi = ys[t];
+    const int id = ids[t];
+    int cx, cy;
+    cell_of_pos(g, xi, yi, cx, cy);
+    bool in_near = false, smaller_open = false;
+    for (int oy = -1; oy <= 1; ++oy) {
+        const int yy = cy + oy;
+        if (yy < 0 || yy >= g.ny) continue;
+        const int u0 = cell_start[yy * g.nx + max(cx - 1, 0)];
+        const int u1 = cell_start[yy * g.nx + min(cx + 1, g.nx - 1) + 1];
+        for (int u = u0; u < u1; ++u) {
+            if (u == t) continue;
+            const uint8_t su = vstate[u];
+            if (su != kRmUndecided && su != kRmIn) continue;
+            if (d2_f32(xs[u] - xi, ys[u] - yi) > P.hi2f) continue;
+            if (su == kRmIn)
+                in_near = true;
+            else if (ids[u] < id)
+                smaller_open = true;
+        }
+    }
+    if (in_near)
+        vstate[t] = kRmOut;
+    else if (!smaller_open)
+        vstate[t] = kRmIn;
+    else
+        qs->n_undecided = 1;
+}
+
+// queue of the taken candidates
+__global__ __launch_bounds__(256) void k_rm_taken(int n, const uint8_t* __restrict__ state, Queues* qs,
+                                                  int32_t* queue)
+{
+    __shared__ int s_tmp[17];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool take = t < n && state[t] == kRmIn;
+    const int p = block_append_n(&qs->n_accepted, take ? 1 : 0, s_tmp);
+    if (take) queue[p] = t;
+}
+
+// The identity LP of every taken candidate, one thread each; the columns live
+// in LDS as for the complete-neighbourhood Laplacian LPs.
+template <bool SC>
+__global__ __launch_bounds__(kFullBlock) void k_rm_lp(const int32_t* __restrict__ perm, const float* __restrict__ xs,
+                                                      const float* __restrict__ ys, const int32_t* __restrict__ ids,
+                                                      const int32_t* __restrict__ cell_start, const GridState* gs,
+                                                      const int32_t* __restrict__ queue, Queues* qs,
+                                                      const float* __restrict__ gamma, float* acc, uint8_t* removed,
+                                                      LaunchParams P)
+{
+    __shared__ float s_rx[VRM_KMAX * kFullBlock];
+    __shared__ float s_ry[VRM_KMAX * kFullBlock];
+    __shared__ int s_meta[VRM_KMAX * kFullBlock];
+    __shared__ float s_c[SC ? VRM_KMAX * kFullBlock : 1];
+    const int tid = threadIdx.x;
+    const int nitems = qs->n_accepted;
+    const GridState g = *gs;
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x; base < nitems; base += stride) {
+        const int item = base + tid;
+        bool ok = false, unc = false;
+        if (item < nitems) {
+            const int t = queue[item];
+            const int i = perm[t];
+            const float xi = xs[t], yi = ys[t];
+            bool truncated;
+            const int k = collect_full(t, xi, yi, g, cell_start, xs, ys, ids, P, s_meta + tid, s_rx + tid,
+                                       reinterpret_cast<int*>(s_ry) + tid, truncated);
+            for (int j = 0; j < k; ++j) {
+                const int idj = __float_as_int(s_ry[j * kFullBlock + tid]);
+                int rank = 0;
+                for (int o = 0; o < k; ++o) rank += __float_as_int(s_ry[o * kFullBlock + tid]) < idj ? 1 : 0;
+                s_meta[j * kFullBlock + tid] = (int)(((unsigned)s_meta[j * kFullBlock + tid] << 6) | (unsigned)rank);
+            }
+            for (int j = 0; j < k; ++j) {
+                const int meta = s_meta[j * kFullBlock + tid];
+                const int um = (int)((unsigned)meta >> 6);
+                df X, Y;
+                exact_offset(xi, yi, xs[um], ys[um], P.scale2e, X, Y);
+                s_rx[j * kFullBlock + tid] = X.hi;
+                s_ry[j * kFullBlock + tid] = Y.hi;
+                if constexpr (SC) s_c[j * kFullBlock + tid] = add_rank(cost_df(X, Y, P), meta & 63, P.q).hi;
+            }
+            LdsColsT<kFullBlock, SC> cs{k, 0ull, s_rx, s_ry, s_c, s_meta, tid, xi, yi, xs, ys, &P, nullptr, nullptr};
+            const float g_i = gamma[i];
+            auto store = [&](int j, float v) {
+                const int pj = perm[(unsigned)s_meta[j * kFullBlock + tid] >> 6];
+                atomicAdd(&acc[pj], v * g_i);
+            };
+            float fii = 0.0f;
+            int piv = 0, certified = 1, warm = 0;
+            uint64_t basis = 0;
+            const int st = k > 0 ? solve_lp<3, false>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis)
+                                 : 1;
+            if (st == 0) {
+                removed[i] = 1;
+                ok = true;
+                unc = !certified;
+            }
+        }
+        count_add(&qs->n_removed, ok);
+        count_add(&qs->n_rm_uncertified, unc);
+    }
+}
+
+// received circulation, and the particles that stay
+__global__ __launch_bounds__(256) void k_rm_apply(int n, float* gamma, float* acc, const uint8_t* __restrict__ removed,
+                                                  int32_t* keep)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    gamma[i] += acc[i];
+    acc[i] = 0.0f;
+    keep[i] = removed[i] ? 0 : 1;
+}
+
+// the particles that stay, in their order, to the scratch arrays
+__global__ __launch_bounds__(256) void k_rm_gather(int n, const int32_t* __restrict__ keep,
+                                                   const int32_t* __restrict__ pos, const float* __restrict__ x,
+                                                   const float* __restrict__ y, const float* __restrict__ g,
+                                                   const int32_t* __restrict__ id, float* tx, float* ty, float* tg,
+                                                   int32_t* tid)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !keep[i]) return;
+    const int j = pos[i];
+    tx[j] = x[i];
+    ty[j] = y[i];
+    tg[j] = g[i];
+    tid[j] = id[i];
+}
+
+__global__ __launch_bounds__(256) void k_rm_copy(int m, const float* __restrict__ tx, const float* __restrict__ ty,
+                                                 const float* __restrict__ tg, const int32_t* __restrict__ tid, float* x,
+                                                 float* y, float* g, int32_t* id, int32_t* n_dev)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) *n_dev = m;
+    if (j >= m) return;
+    x[j] = tx[j];
+    y[j] = ty[j];
+    g[j] = tg[j];
+    id[j] = tid[j];
+}
+
+__global__ void k_rm_reset(Queues* q)
+{
+    q->n_cand = 0;
+    q->n_undecided = 0;
+    q->n_accepted = 0;
+    q->n_removed = 0;
+    q->n_rm_uncertified = 0;
+}
+__global__ void k_rm_reset_undecided(Queues* q) { q->n_undecided = 0; }
 
 // feature rows of the queued complete-neighbourhood LPs (warm start)
 __global__ __launch_bounds__(kFullBlock) void k_feat_full(const float* __restrict__ xs, const float* __restrict__ ys,
@@ -927,4 +1143,72 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
     }
     VRM_HIP(hipGetLastError());
     return VRM_OK;
+}
+
+// Particle removal over the current cell list (slot order); synchronises.
+// Returns the new particle count or a negative error; the removed count is in
+// the queues (n_removed).
+int vrm_remove_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp, int32_t* n_candidates)
+{
+    hipStream_t s = c->stream;
+    const int nb = n > 0 ? (n + 255) / 256 : 1;
+    hipLaunchKernelGGL(k_rm_reset, dim3(1), dim3(1), 0, s, c->queues);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_rm_candidates, dim3(nb), dim3(256), 0, s, n, c->xs, c->ys, c->cell_start, c->grid, lp,
+                           c->cstate, c->queues);
+        VRM_HIP(hipGetLastError());
+    }
+    Queues q;
+    VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
+    VRM_HIP(hipStreamSynchronize(s));
+    if (n_candidates) *n_candidates = q.n_cand;
+    if (q.n_cand == 0) return n;
+    for (int rounds = 0;;) {
+        const int batch = 4;
+        for (int k = 0; k < batch; ++k) {
+            hipLaunchKernelGGL(k_rm_reset_undecided, dim3(1), dim3(1), 0, s, c->queues);
+            hipLaunchKernelGGL(k_rm_mis_round, dim3(nb), dim3(256), 0, s, n, c->xs, c->ys, c->ids, c->cell_start,
+                               c->grid, lp, c->cstate, c->queues);
+        }
+        rounds += batch;
+        VRM_HIP(hipGetLastError());
+        VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
+        VRM_HIP(hipStreamSynchronize(s));
+        if (q.n_undecided == 0) break;
+        if (rounds > 4 * q.n_cand + 64) return vrm_fail(VRM_E_STATE, "removal: selection did not converge");
+    }
+    hipLaunchKernelGGL(k_rm_taken, dim3(nb), dim3(256), 0, s, n, c->cstate, c->queues, c->aidx);
+    VRM_HIP(hipGetLastError());
+    VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
+    VRM_HIP(hipStreamSynchronize(s));
+    const int na = q.n_accepted;
+    VRM_HIP(hipMemsetAsync(c->tmp_u8, 0, (size_t)n, s));
+    {
+        const bool stored = full_stored_costs(c, n);
+        hipLaunchKernelGGL((stored ? k_rm_lp<true> : k_rm_lp<false>), dim3(lp_grid_full(c, na)), dim3(kFullBlock), 0, s,
+                           c->perm, c->xs, c->ys, c->ids, c->cell_start, c->grid, c->aidx, c->queues, cl->gamma_dev,
+                           c->acc, c->tmp_u8, lp);
+        VRM_HIP(hipGetLastError());
+    }
+    int32_t* keep = c->ccell;
+    int32_t* pos = c->crank;
+    hipLaunchKernelGGL(k_rm_apply, dim3(nb), dim3(256), 0, s, n, cl->gamma_dev, c->acc, c->tmp_u8, keep);
+    VRM_HIP(hipGetLastError());
+    VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
+    VRM_HIP(hipStreamSynchronize(s));
+    const int m = n - q.n_removed;
+    if (q.n_removed == 0) return n;
+    size_t bytes = 0;
+    VRM_HIP(rocprim::exclusive_scan(nullptr, bytes, keep, pos, 0, (size_t)n, rocprim::plus<int32_t>(), s));
+    if (bytes > c->sort_tmp_bytes + 256)
+        return vrm_fail(VRM_E_STATE, "removal: scan needs %zu bytes of scratch, %zu held", bytes, c->sort_tmp_bytes);
+    VRM_HIP(rocprim::exclusive_scan(c->sort_tmp, bytes, keep, pos, 0, (size_t)n, rocprim::plus<int32_t>(), s));
+    const size_t cap = (size_t)c->capacity;
+    hipLaunchKernelGGL(k_rm_gather, dim3(nb), dim3(256), 0, s, n, keep, pos, cl->x_dev, cl->y_dev, cl->gamma_dev,
+                       cl->id_dev, c->tmp_f, c->tmp_f + cap, c->tmp_f + 2 * cap, c->tmp_i);
+    VRM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_rm_copy, dim3(m > 0 ? (m + 255) / 256 : 1), dim3(256), 0, s, m, c->tmp_f, c->tmp_f + cap,
+                       c->tmp_f + 2 * cap, c->tmp_i, cl->x_dev, cl->y_dev, cl->gamma_dev, cl->id_dev, cl->n_dev);
+    VRM_HIP(hipGetLastError());
+    return m;
 }

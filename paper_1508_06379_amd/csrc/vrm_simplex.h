@@ -4,7 +4,8 @@
 //   minimise  sum_j c_j f_j   subject to  V f = b,  f >= 0,
 //
 // V has M rows (the monomials r^alpha, 1 <= |alpha| <= q, of the scaled
-// offsets) and k <= 64 columns.  As the paper describes, every iteration works
+// offsets; or 1, x, y when the identity operator is approximated for
+// particle removal, Sec. 6) and k <= 64 columns.  As the paper describes, every iteration works
 // with the m x m matrix of the current basic columns; here its inverse B^-1
 // is kept explicitly in registers and updated by one elementary row
 // operation per pivot.  Phase I starts from the artificial basis with a
@@ -32,45 +33,59 @@ constexpr int kMaxCert = 8;
 constexpr int kMaxRefine = 6;
 constexpr float kFastMargin = 1e-3f;              // FP32 reduced-cost margin of the fast certificate
 
+// Rows of a column: the monomials r^alpha, 1 <= |alpha| <= q (M = 5, 9), or
+// for the identity operator of particle removal (M = 3) 1, x, y.
 template <int M>
 __device__ __forceinline__ void mono(float x, float y, float (&v)[M])
 {
-    v[0] = x;
-    v[1] = y;
-    v[2] = x * x;
-    v[3] = x * y;
-    v[4] = y * y;
-    if constexpr (M == 9) {
-        v[5] = v[2] * x;
-        v[6] = v[2] * y;
-        v[7] = x * v[4];
-        v[8] = v[4] * y;
+    if constexpr (M == 3) {
+        v[0] = 1.0f;
+        v[1] = x;
+        v[2] = y;
+    } else {
+        v[0] = x;
+        v[1] = y;
+        v[2] = x * x;
+        v[3] = x * y;
+        v[4] = y * y;
+        if constexpr (M == 9) {
+            v[5] = v[2] * x;
+            v[6] = v[2] * y;
+            v[7] = x * v[4];
+            v[8] = v[4] * y;
+        }
     }
 }
 
 template <int M>
 __device__ __forceinline__ void mono_df(df X, df Y, df (&v)[M])
 {
-    df XX = df_mul(X, X), XY = df_mul(X, Y), YY = df_mul(Y, Y);
-    v[0] = X;
-    v[1] = Y;
-    v[2] = XX;
-    v[3] = XY;
-    v[4] = YY;
-    if constexpr (M == 9) {
-        v[5] = df_mul(XX, X);
-        v[6] = df_mul(XX, Y);
-        v[7] = df_mul(X, YY);
-        v[8] = df_mul(YY, Y);
+    if constexpr (M == 3) {
+        v[0] = {1.0f, 0.0f};
+        v[1] = X;
+        v[2] = Y;
+    } else {
+        df XX = df_mul(X, X), XY = df_mul(X, Y), YY = df_mul(Y, Y);
+        v[0] = X;
+        v[1] = Y;
+        v[2] = XX;
+        v[3] = XY;
+        v[4] = YY;
+        if constexpr (M == 9) {
+            v[5] = df_mul(XX, X);
+            v[6] = df_mul(XX, Y);
+            v[7] = df_mul(X, YY);
+            v[8] = df_mul(YY, Y);
+        }
     }
 }
 
 // |r|^(q+1) of the scaled exact offset, times (2^e/h)^(q+1): the canonical
-// cost in units of h, double-float
+// cost in units of h, double-float (q = 1: |r|^2, the removal LP's cost)
 __device__ __forceinline__ df cost_df(df X, df Y, const LaunchParams& P)
 {
     df d2 = df_add(df_mul(X, X), df_mul(Y, Y));
-    df w = (P.q == 2) ? df_mul(d2, df_sqrt(d2)) : df_mul(d2, d2);
+    df w = P.q == 1 ? d2 : (P.q == 2) ? df_mul(d2, df_sqrt(d2)) : df_mul(d2, d2);
     return df_mul(w, df{P.cs_hi, P.cs_lo});
 }
 
@@ -83,10 +98,19 @@ __device__ __forceinline__ void exact_offset(float xi, float yi, float xj, float
     Y = {dy.hi * s, dy.lo * s};
 }
 
-__device__ __forceinline__ float rhs_hi(int a, const LaunchParams& P) { return (a == 2 || a == 4) ? P.bt_hi : 0.0f; }
+// Right-hand side: 2 h^2 / 4^e at (2,0) and (0,2) for the Laplacian (eq.
+// cond_two); the unit vector e0 for the identity (removal, M = 3)
+template <int M>
+__device__ __forceinline__ bool rhs_row(int a)
+{
+    return M == 3 ? a == 0 : (a == 2 || a == 4);
+}
+template <int M>
+__device__ __forceinline__ float rhs_hi(int a, const LaunchParams& P) { return rhs_row<M>(a) ? P.bt_hi : 0.0f; }
+template <int M>
 __device__ __forceinline__ df rhs_df(int a, const LaunchParams& P)
 {
-    return (a == 2 || a == 4) ? df{P.bt_hi, P.bt_lo} : df{0.0f, 0.0f};
+    return rhs_row<M>(a) ? df{P.bt_hi, P.bt_lo} : df{0.0f, 0.0f};
 }
 
 // Column store interface (CS):
@@ -99,8 +123,8 @@ __device__ __forceinline__ df rhs_df(int a, const LaunchParams& P)
 //   float cost_of<Q>(float rx, float ry, uint32_t aux)      its FP32 cost (order Q)
 template <int M, class CS>
 struct ThreadSimplex {
-    static_assert(M == 5 || M == 9, "5 rows for q = 2, 9 for q = 3");
-    static constexpr int kQ = M == 5 ? 2 : 3;   // moment order of an M-row LP
+    static_assert(M == 3 || M == 5 || M == 9, "3 rows: identity, 5: q = 2, 9: q = 3");
+    static constexpr int kQ = M == 3 ? 1 : M == 5 ? 2 : 3;   // order of the cost |r|^(kQ+1)
     float Bi[M][M];   // B^-1
     float xb[M];      // basic values (perturbed rhs)
     float cb[M];      // costs of the basic columns (0 for artificial ones)
@@ -117,7 +141,7 @@ struct ThreadSimplex {
         for (int r = 0; r < M; ++r) {
 #pragma unroll
             for (int a = 0; a < M; ++a) Bi[r][a] = (r == a) ? 1.0f : 0.0f;
-            xb[r] = rhs_hi(r, P) + kPerturb * P.bt_hi * (1.0f + 0.618f * (float)r);
+            xb[r] = rhs_hi<M>(r, P) + kPerturb * P.bt_hi * (1.0f + 0.618f * (float)r);
             cb[r] = 0.0f;
             bs[r] = ART + r;
         }
@@ -447,7 +471,7 @@ struct ThreadSimplex {
         }
 #pragma unroll
         for (int a = 0; a < M; ++a) {
-            df rr = df_add(rhs_df(a, P), df_neg(acc[a]));
+            df rr = df_add(rhs_df<M>(a, P), df_neg(acc[a]));
             res[a] = rr.hi + rr.lo;
         }
     }
@@ -482,7 +506,12 @@ struct ThreadSimplex {
     __device__ float refine_primal(const CS& cs, const LaunchParams& P, df (&x)[M]) const
     {
 #pragma unroll
-        for (int r = 0; r < M; ++r) x[r] = {(Bi[r][2] + Bi[r][4]) * P.bt_hi, 0.0f};
+        for (int r = 0; r < M; ++r) {
+            float v = 0.0f;
+#pragma unroll
+            for (int a = 0; a < M; ++a) v += rhs_row<M>(a) ? Bi[r][a] : 0.0f;
+            x[r] = {v * P.bt_hi, 0.0f};
+        }
         float first_corr = 1.0f;
         for (int it = 0; it < kMaxRefine; ++it) {
             float res[M];
@@ -525,6 +554,13 @@ struct ThreadSimplex {
         const int k = cs.k;
         for (int round = 0; round < kMaxCert; ++round) {
             const float first_corr = refine_primal(cs, P, x);
+            // An artificial variable still basic must vanish in the exact basic
+            // solution; one that does not means phase I ended, within its FP32
+            // tolerance, on a vertex that is not feasible: the LP is taken as
+            // infeasible (its exact phase-I optimum is positive).
+#pragma unroll
+            for (int r = 0; r < M; ++r)
+                if (bs[r] >= ART && fabsf(x[r].hi + x[r].lo) > kCertX) return 1;
             // Fast certificate: when B^-1 is accurate (the first correction is
             // tiny) and every FP32 reduced cost clears zero by a margin far above
             // its rounding error, the basis is optimal without the double-float

@@ -177,3 +177,22 @@ def test_one_sided_neighbourhood_stays(orc):
     r = orc.remove(np.array([0.0, 0.1 * h]), np.zeros(2), np.ones(2), np.arange(2, dtype=np.int32),
                    orc.params(h, q=2))
     assert r.n_candidates == 2 and r.removed_ids.size == 0
+
+
+def near_infeasible_cloud(h=0.05, delta=5e-4):
+    """A candidate (id 0) whose neighbours (1, -delta) h, (-1, -delta) h, (0, -1) h
+    leave the origin delta h outside their hull, and its close partner (id 1)."""
+    x = h * np.array([0.0, 0.0, 1.0, -1.0, 0.0])
+    y = h * np.array([0.0, 0.3, -delta, -delta, -1.0])
+    return x.astype(np.float32).astype(np.float64), y.astype(np.float32).astype(np.float64)
+
+
+def test_near_infeasible_candidate_stays(orc):
+    """Infeasible by delta = 5e-4 h (sum g r_y = 0 needs weight above the line):
+    the candidate stays; a phase I stopped within an FP32 tolerance must not
+    take it."""
+    h = 0.05
+    x, y = near_infeasible_cloud(h)
+    r = orc.remove(x, y, np.ones(5), np.arange(5, dtype=np.int32), orc.params(h, q=2))
+    assert r.n_candidates == 2 and r.removed_ids.size == 0
+
