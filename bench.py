@@ -229,6 +229,41 @@ def cpu_baseline(wl, budget_s=15.0, max_steps=10000):
                       f"({el:.1f} s; LPs and neighbourhoods OpenMP-parallel, insertion and apply serial)"}
 
 
+def run_removal(reps=3, oracle_too=True):
+    """Particle removal (Sec. 6, outlook) on the close-pair cloud over [-4, 4]^2 at
+    h = 0.005: 2.56 M jittered sites plus 5 % planted particles closer than r h
+    (2.69 M).  Wall time of vrm_remove_particles (it synchronises) on a fresh copy
+    of the cloud per call, median of `reps` after one untimed call; the oracle
+    does the same removal once on the host for comparison."""
+    import torch
+    import paper_1508_06379_amd as vrm
+    wl = workloads.config_close_pairs(h=0.005, q=2, lo=-4.0, hi=4.0, seed=21)
+    P = vrm.params_of(wl)
+    ctx = vrm.Context(wl.n + 1024)
+    times = []
+    for rep in range(reps + 1):
+        cloud = vrm.Cloud(wl.x, wl.y, wl.gamma, capacity=wl.n + 1024)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nr, nc = ctx.vrm_remove_particles(cloud, P)
+        torch.cuda.synchronize()
+        if rep:
+            times.append(time.perf_counter() - t0)
+        del cloud
+    el = float(np.median(times))
+    out = {"workload": f"close_pairs_h0.005_[-4,4]^2", "n": wl.n, "candidates": nc, "removed": nr,
+           "ms": el * 1e3, "removed_per_s": nr / el, "particles_per_s": wl.n / el}
+    if oracle_too:
+        import oracle
+        x, y, g = (a.astype(np.float64) for a in (wl.x, wl.y, wl.gamma))
+        t0 = time.perf_counter()
+        ref = oracle.remove(x, y, g, wl.ids, oracle.params_of(wl))
+        ot = time.perf_counter() - t0
+        out["oracle"] = {"s": ot, "removed": int(ref.removed_ids.size), "cores": 1}
+    log(f"removal: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +278,9 @@ def main():
                          "workload")
     ap.add_argument("--train-snapshots", type=int, default=30)
     ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--no-removal", action="store_true", help="skip the particle-removal measurement")
+    ap.add_argument("--removal-only", action="store_true",
+                    help="only the particle-removal measurement (one JSON object)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also copy a 256 MiB buffer five times (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
@@ -250,6 +288,9 @@ def main():
         print(f"bench.py runs on one GPU only: the redistribution path has no multi-GPU mode "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
+    if args.removal_only:
+        print(json.dumps({"removal": run_removal(oracle_too=not args.no_cpu_baseline)}), flush=True)
+        return
     wl = WORKLOADS[args.workload]()
     log(f"workload {args.workload}: N={wl.n} h={wl.h} q={wl.q} dt={wl.dt}")
     from paper_1508_06379_amd import autotune
@@ -333,6 +374,8 @@ def main():
             "breakdown_ms_per_step": breakdown(r),
             "network": train_info,
         }
+    if not args.no_removal:
+        line["removal"] = run_removal(oracle_too=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, budget_s=args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -206,7 +206,7 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
     A(verify_buf, 8);
 #undef A
     if (r == VRM_OK) {
-        c->sort_tmp_bytes = vrm_sort_tmp_bytes(capacity);
+        c->sort_tmp_bytes = std::max(vrm_sort_tmp_bytes(capacity), vrm_remove_tmp_bytes(capacity));
         void* p = nullptr;
         hipError_t e = hipMalloc(&p, c->sort_tmp_bytes + 256);
         if (e != hipSuccess) r = vrm_hip_check(e, "hipMalloc(sort)");

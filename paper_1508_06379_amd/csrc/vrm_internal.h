@@ -238,6 +238,7 @@ int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double bound_facto
 int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp);
 int vrm_reorder_cloud(vrm_ctx* c, vrm_cloud* cl, int32_t n);
 int vrm_remove_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp, int32_t* n_candidates);
+size_t vrm_remove_tmp_bytes(int32_t cap);
 // launchers (vrm_lp.hip)
 int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp,
                     const vrm_stencils* out, int apply, uint16_t* feat_out = nullptr, float* label_out = nullptr,

@@ -13,7 +13,11 @@
 // Each LP is solved by one thread (vrm_simplex.h).  The fractions are
 // scattered into sum_j fhat_ji Gamma_j with atomics.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_select.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
 
 #include "vrm_device.h"
 #include "vrm_internal.h"
@@ -780,44 +784,64 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
 // no removed particle receives circulation); one whose LP is infeasible stays.
 constexpr uint8_t kRmNone = 0, kRmUndecided = 1, kRmIn = 2, kRmOut = 3;
 
-// candidates: a particle closer than r h to another (per slot)
+// candidates: a particle closer than r h to another (per slot); the
+// positions of a row's three cells are read eight at a time
 __global__ __launch_bounds__(256) void k_rm_candidates(int n, const float* __restrict__ xs,
                                                        const float* __restrict__ ys,
                                                        const int32_t* __restrict__ cell_start, const GridState* gs,
-                                                       LaunchParams P, uint8_t* state, Queues* qs)
+                                                       LaunchParams P, uint8_t* state)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const GridState g = *gs;
+    const float xi = xs[t], yi = ys[t];
+    int cx, cy;
+    cell_of_pos(g, xi, yi, cx, cy);
     bool close = false;
-    if (t < n) {
-        const GridState g = *gs;
-        const float xi = xs[t], yi = ys[t];
-        int cx, cy;
-        cell_of_pos(g, xi, yi, cx, cy);
-        for (int oy = -1; oy <= 1 && !close; ++oy) {
-            const int yy = cy + oy;
-            if (yy < 0 || yy >= g.ny) continue;
-            const int u0 = cell_start[yy * g.nx + max(cx - 1, 0)];
-            const int u1 = cell_start[yy * g.nx + min(cx + 1, g.nx - 1) + 1];
-            for (int u = u0; u < u1 && !close; ++u) close = u != t && d2_f32(xs[u] - xi, ys[u] - yi) < P.lo2f;
+    for (int oy = -1; oy <= 1 && !close; ++oy) {
+        const int yy = cy + oy;
+        if (yy < 0 || yy >= g.ny) continue;
+        const int u0 = cell_start[yy * g.nx + max(cx - 1, 0)];
+        const int u1 = cell_start[yy * g.nx + min(cx + 1, g.nx - 1) + 1];
+        for (int u = u0; u < u1 && !close; u += 8) {
+            float bx[8], by[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int v = min(u + e, u1 - 1);
+                bx[e] = xs[v];
+                by[e] = ys[v];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                close = close || (u + e < u1 && u + e != t && d2_f32(bx[e] - xi, by[e] - yi) < P.lo2f);
         }
-        state[t] = close ? kRmUndecided : kRmNone;
     }
-    count_add(&qs->n_cand, close);
+    state[t] = close ? kRmUndecided : kRmNone;
 }
+
+// selection predicate: the slot's state
+struct RmStateIs {
+    const uint8_t* state;
+    uint8_t want;
+    __device__ bool operator()(int t) const { return state[t] == want; }
+};
 
 // One round of the greedy selection in id order: an undecided candidate with a
 // taken candidate within R_full h is out; one with no smaller-id candidate
 // still undecided there is taken.  States only go from undecided to taken or
 // out, so reading a neighbour's state while it changes is safe: both values
 // lead to a decision the sequential greedy pass also makes.
-__global__ __launch_bounds__(256) void k_rm_mis_round(int n, const float* __restrict__ xs,
-                                                      const float* __restrict__ ys, const int32_t* __restrict__ ids,
+__global__ __launch_bounds__(256) void k_rm_mis_round(int nc, const int32_t* __restrict__ cand,
+                                                      const float* __restrict__ xs, const float* __restrict__ ys,
+                                                      const int32_t* __restrict__ ids,
                                                       const int32_t* __restrict__ cell_start, const GridState* gs,
                                                       LaunchParams P, uint8_t* state, Queues* qs)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    const int t = cand[k];
     volatile uint8_t* vstate = state;   // other threads change it during the round
-    if (t >= n || vstate[t] != kRmUndecided) return;
+    if (vstate[t] != kRmUndecided) return;
     const GridState g = *gs;
     const float xi = xs[t], yi = ys[t];
     const int id = ids[t];
@@ -846,17 +870,6 @@ __global__ __launch_bounds__(256) void k_rm_mis_round(int n, const float* __rest
         vstate[t] = kRmIn;
     else
         qs->n_undecided = 1;
-}
-
-// queue of the taken candidates
-__global__ __launch_bounds__(256) void k_rm_taken(int n, const uint8_t* __restrict__ state, Queues* qs,
-                                                  int32_t* queue)
-{
-    __shared__ int s_tmp[17];
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool take = t < n && state[t] == kRmIn;
-    const int p = block_append_n(&qs->n_accepted, take ? 1 : 0, s_tmp);
-    if (take) queue[p] = t;
 }
 
 // The identity LP of every taken candidate, one thread each; the columns live
@@ -1145,6 +1158,19 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
     return VRM_OK;
 }
 
+// Scratch bytes of the removal's device-wide selections and scan for up to
+// cap particles (the context's sort scratch is sized to hold them too).
+size_t vrm_remove_tmp_bytes(int32_t cap)
+{
+    size_t a = 0, b = 0, d = 0;
+    int32_t* p = nullptr;
+    (void)rocprim::select(nullptr, a, rocprim::counting_iterator<int32_t>(0), p, p, (size_t)cap,
+                          RmStateIs{nullptr, kRmUndecided}, (hipStream_t)0);
+    (void)rocprim::select(nullptr, b, p, p, p, (size_t)cap, RmStateIs{nullptr, kRmIn}, (hipStream_t)0);
+    (void)rocprim::exclusive_scan(nullptr, d, p, p, 0, (size_t)cap, rocprim::plus<int32_t>(), (hipStream_t)0);
+    return std::max(a, std::max(b, d));
+}
+
 // Particle removal over the current cell list (slot order); synchronises.
 // Returns the new particle count or a negative error; the removed count is in
 // the queues (n_removed).
@@ -1153,32 +1179,54 @@ int vrm_remove_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp,
     hipStream_t s = c->stream;
     const int nb = n > 0 ? (n + 255) / 256 : 1;
     hipLaunchKernelGGL(k_rm_reset, dim3(1), dim3(1), 0, s, c->queues);
-    if (n > 0) {
-        hipLaunchKernelGGL(k_rm_candidates, dim3(nb), dim3(256), 0, s, n, c->xs, c->ys, c->cell_start, c->grid, lp,
-                           c->cstate, c->queues);
-        VRM_HIP(hipGetLastError());
+    if (n == 0) {
+        if (n_candidates) *n_candidates = 0;
+        return n;
+    }
+    hipLaunchKernelGGL(k_rm_candidates, dim3(nb), dim3(256), 0, s, n, c->xs, c->ys, c->cell_start, c->grid, lp,
+                       c->cstate);
+    VRM_HIP(hipGetLastError());
+    // queue of the candidates (slots), then of the taken ones: device-wide selections
+    int32_t* cand = c->cperm;
+    {
+        size_t bytes = 0;
+        VRM_HIP(rocprim::select(nullptr, bytes, rocprim::counting_iterator<int32_t>(0), cand, &c->queues->n_cand,
+                                (size_t)n, RmStateIs{c->cstate, kRmUndecided}, s));
+        if (bytes > c->sort_tmp_bytes + 256)
+            return vrm_fail(VRM_E_STATE, "removal: selection needs %zu bytes of scratch", bytes);
+        VRM_HIP(rocprim::select(c->sort_tmp, bytes, rocprim::counting_iterator<int32_t>(0), cand,
+                                &c->queues->n_cand, (size_t)n, RmStateIs{c->cstate, kRmUndecided}, s));
     }
     Queues q;
     VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
     VRM_HIP(hipStreamSynchronize(s));
-    if (n_candidates) *n_candidates = q.n_cand;
-    if (q.n_cand == 0) return n;
+    const int nc = q.n_cand;
+    if (n_candidates) *n_candidates = nc;
+    if (nc == 0) return n;
+    const int nbc = (nc + 255) / 256;
     for (int rounds = 0;;) {
         const int batch = 4;
         for (int k = 0; k < batch; ++k) {
             hipLaunchKernelGGL(k_rm_reset_undecided, dim3(1), dim3(1), 0, s, c->queues);
-            hipLaunchKernelGGL(k_rm_mis_round, dim3(nb), dim3(256), 0, s, n, c->xs, c->ys, c->ids, c->cell_start,
-                               c->grid, lp, c->cstate, c->queues);
+            hipLaunchKernelGGL(k_rm_mis_round, dim3(nbc), dim3(256), 0, s, nc, cand, c->xs, c->ys, c->ids,
+                               c->cell_start, c->grid, lp, c->cstate, c->queues);
         }
         rounds += batch;
         VRM_HIP(hipGetLastError());
         VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
         VRM_HIP(hipStreamSynchronize(s));
         if (q.n_undecided == 0) break;
-        if (rounds > 4 * q.n_cand + 64) return vrm_fail(VRM_E_STATE, "removal: selection did not converge");
+        if (rounds > 4 * nc + 64) return vrm_fail(VRM_E_STATE, "removal: selection did not converge");
     }
-    hipLaunchKernelGGL(k_rm_taken, dim3(nb), dim3(256), 0, s, n, c->cstate, c->queues, c->aidx);
-    VRM_HIP(hipGetLastError());
+    {
+        size_t bytes = 0;
+        VRM_HIP(rocprim::select(nullptr, bytes, cand, c->aidx, &c->queues->n_accepted, (size_t)nc,
+                                RmStateIs{c->cstate, kRmIn}, s));
+        if (bytes > c->sort_tmp_bytes + 256)
+            return vrm_fail(VRM_E_STATE, "removal: selection needs %zu bytes of scratch", bytes);
+        VRM_HIP(rocprim::select(c->sort_tmp, bytes, cand, c->aidx, &c->queues->n_accepted, (size_t)nc,
+                                RmStateIs{c->cstate, kRmIn}, s));
+    }
     VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
     VRM_HIP(hipStreamSynchronize(s));
     const int na = q.n_accepted;
