@@ -298,3 +298,36 @@ def test_sampled_stencils_at_full_size(vrm, orc, name):
          "worst rel diff", worst)
     assert not bad, f"{len(bad)} stencils with a different support, e.g. ids {bad[:5]}"
     assert worst <= 1e-6
+
+
+@pytest.mark.timeout(400)
+def test_infeasible_lps_are_infeasible_in_the_oracle(vrm, orc):
+    """The 16 M-particle q = 3 cloud after one whole step (the particles have
+    moved): every particle whose complete-neighbourhood LP the GPU declares
+    infeasible (an FP32 phase I can end within its tolerance on a vertex whose
+    artificial variable does not vanish; the certification rejects it) is
+    infeasible for the FP64 oracle on the same FP32 positions too."""
+    name = "vortices256_h0.004_q3"
+    _say("case", name, "generating the cloud")
+    wl = FULL[name]()
+    cloud, ctx = _context(vrm, name, wl)
+    P = vrm.params_of(wl)
+    ctx.vrm_step(cloud, P, vrm.vortex_table(wl.vortices), wl.t0)
+    st = vrm.Stencils.alloc(cloud.capacity)
+    ctx.vrm_solve_fractions(cloud, P, st)
+    torch.cuda.synchronize()
+    n = cloud.n
+    status = st.status[:n].cpu().numpy()
+    x, y, g, ids = cloud.numpy()
+    inf = np.flatnonzero(status == 2)
+    _say(name, "N", n, "infeasible on the GPU", inf.size, "full", int((status == 1).sum()))
+    del st, cloud, ctx
+    torch.cuda.empty_cache()
+    if inf.size == 0:
+        pytest.skip("no infeasible LP in this state")
+    mask = np.zeros(n, np.uint8)
+    mask[inf[:200]] = 1
+    ref = orc.stencils(x.astype(np.float64), y.astype(np.float64), ids, mask, orc.params_of(wl))
+    st_ref = ref.status[inf[:200]]
+    _say("oracle status of those", np.bincount(st_ref, minlength=4))
+    assert (st_ref == 2).all()
