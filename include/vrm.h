@@ -228,7 +228,11 @@ typedef struct vrm_tuning {
                                     -1: never */
     int32_t infer_blocks;        /* most workgroups (256 threads) of the network's inference; default 512 */
     int32_t lp_small_lanes;      /* small LPs per wave of the small-LP launch (1, 2, 4, ..., 64); default 64 */
-    int32_t reserved[3];
+    int32_t lp_small_coop;       /* 1: the plain and phase-I small-LP passes give each LP eight lanes, one
+                                    column each (shorter chains for latency-bound launches); 0 (default):
+                                    one thread per LP.  Warm-start and training-collection passes always use
+                                    one thread per LP.  Results are the same either way. */
+    int32_t reserved[2];
 } vrm_tuning;
 /* Set (t = NULL: restore the defaults) or read the launch shapes. */
 int vrm_set_tuning(vrm_ctx* ctx, const vrm_tuning* t);

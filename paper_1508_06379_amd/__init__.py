@@ -43,8 +43,9 @@ class vrm_params(ctypes.Structure):
 class vrm_tuning(ctypes.Structure):
     _fields_ = [("lp_small_blocks", ctypes.c_int32), ("lp_full_blocks", ctypes.c_int32),
                 ("full_stored_cost_n", ctypes.c_int32), ("infer_blocks", ctypes.c_int32),
-                ("lp_small_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
-    FIELDS = ("lp_small_blocks", "lp_full_blocks", "full_stored_cost_n", "infer_blocks", "lp_small_lanes")
+                ("lp_small_lanes", ctypes.c_int32), ("lp_small_coop", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+    FIELDS = ("lp_small_blocks", "lp_full_blocks", "full_stored_cost_n", "infer_blocks", "lp_small_lanes",
+              "lp_small_coop")
 
 
 class vrm_cloud(ctypes.Structure):

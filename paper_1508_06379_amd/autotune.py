@@ -27,6 +27,7 @@ CANDIDATES = {
     "lp_full_blocks": [256, 512, 768, 1024, 2048, 4096],
     "full_stored_cost_n": [-1, 200000, 1 << 30],
     "lp_small_lanes": [8, 16, 32, 64],
+    "lp_small_coop": [1],
 }
 
 
@@ -71,7 +72,8 @@ def time_steps(wl, tuning: dict, steps: int, warm_mode: int = 0) -> float:
 
 def relevant_fields(wl):
     """Fields that act on the workload's launches."""
-    return ["lp_small_lanes", "lp_small_blocks"] if wl.q == 2 else ["lp_full_blocks", "full_stored_cost_n"]
+    return ["lp_small_coop", "lp_small_lanes", "lp_small_blocks"] if wl.q == 2 else ["lp_full_blocks",
+                                                                                     "full_stored_cost_n"]
 
 
 def tune(name: str, wl, steps: int, sweeps: int = 2, warm_mode: int = 0, log=print) -> dict:

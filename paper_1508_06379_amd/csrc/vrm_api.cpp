@@ -554,6 +554,9 @@ int vrm_set_tuning(vrm_ctx* c, const vrm_tuning* t)
         if (t->full_stored_cost_n) d.full_stored_cost_n = t->full_stored_cost_n;
         if (t->infer_blocks) d.infer_blocks = t->infer_blocks;
         if (t->lp_small_lanes) d.lp_small_lanes = t->lp_small_lanes;
+        if (t->lp_small_coop != 0 && t->lp_small_coop != 1)
+            return vrm_fail(VRM_E_ARG, "lp_small_coop must be 0 or 1 (got %d)", t->lp_small_coop);
+        d.lp_small_coop = t->lp_small_coop;
     }
     c->tuning = d;
     return VRM_OK;

@@ -297,6 +297,7 @@ constexpr int kLpRetry = 2;
 template <int BLK, bool STORED = true>
 struct LdsColsT {
     static constexpr int KC = 0;   // column count known at run time only
+    static constexpr bool kCoop = false;
     int k;
     uint64_t dead;
     float* srx;
@@ -371,6 +372,94 @@ template <int BLK>
 struct SmallColsT : LdsColsT<BLK> {
     static constexpr int KC = VRM_NSEG;
     float lg[VRM_NSEG];
+};
+
+// Small-neighbourhood columns spread over an aligned group of eight lanes,
+// one column (segment) per lane.  Every lane of the group runs the same
+// simplex on replicated state; another lane's column is read with a lane
+// permute, and reductions over the group use DPP within the 8 lanes.
+struct CoopCols {
+    static constexpr int KC = VRM_NSEG;
+    static constexpr bool kCoop = true;
+    int k;
+    uint64_t dead;
+    int own, base;                 // this lane's column; the group's first lane
+    float x, y, c;                 // this lane's column: FP32 scaled offset, cost
+    float xlo, ylo;                // low parts of the exact scaled offset
+    int meta;                      // (slot << 6) | id rank
+    const LaunchParams* P;
+    float lg[VRM_NSEG];            // not used (no warm pass in this layout)
+    mutable int cj;                // column whose values the last pick left in cx, cy, cc
+    mutable float cx, cy, cc;
+
+    __device__ __forceinline__ static float lane_f(float v, int src) { return __shfl(v, src, 64); }
+    __device__ __forceinline__ static int lane_i(int v, int src) { return __shfl(v, src, 64); }
+    __device__ __forceinline__ void get(int j, float& rx, float& ry, float& cost) const
+    {
+        if (j == cj) {
+            rx = cx, ry = cy, cost = cc;
+            return;
+        }
+        rx = lane_f(x, base + j);
+        ry = lane_f(y, base + j);
+        cost = lane_f(c, base + j);
+    }
+    __device__ __forceinline__ void exact_xy(int j, df& X, df& Y) const
+    {
+        X = {lane_f(x, base + j), lane_f(xlo, base + j)};
+        Y = {lane_f(y, base + j), lane_f(ylo, base + j)};
+    }
+    __device__ __forceinline__ void exact(int j, df& X, df& Y, df& C) const
+    {
+        exact_xy(j, X, Y);
+        C = add_rank(cost_df(X, Y, *P), lane_i(meta, base + j) & 63, P->q);
+    }
+    __device__ __forceinline__ void exact_own(df& X, df& Y, df& C) const
+    {
+        X = {x, xlo};
+        Y = {y, ylo};
+        C = add_rank(cost_df(X, Y, *P), meta & 63, P->q);
+    }
+    // value of the lane whose index differs by the DPP pattern: quad_perm
+    // [1,0,3,2] (xor 1), [2,3,0,1] (xor 2), and the mirror within 8 lanes
+    template <int CTRL>
+    __device__ __forceinline__ static int dpp(int v)
+    {
+        return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+    }
+    template <int CTRL>
+    __device__ __forceinline__ static void pick_step(float& key, int& j, float& px, float& py, float& pc)
+    {
+        const float k2 = __int_as_float(dpp<CTRL>(__float_as_int(key)));
+        const int j2 = dpp<CTRL>(j);
+        const float x2 = __int_as_float(dpp<CTRL>(__float_as_int(px)));
+        const float y2 = __int_as_float(dpp<CTRL>(__float_as_int(py)));
+        const float c2 = __int_as_float(dpp<CTRL>(__float_as_int(pc)));
+        const bool take = k2 < key || (k2 == key && j2 < j);
+        key = take ? k2 : key;
+        j = take ? j2 : j;
+        px = take ? x2 : px;
+        py = take ? y2 : py;
+        pc = take ? c2 : pc;
+    }
+    __device__ __forceinline__ int pick(bool ok, float key) const
+    {
+        float k = ok ? key : __builtin_huge_valf();
+        int j = ok ? own : 64;
+        float px = x, py = y, pc = c;
+        pick_step<0xB1>(k, j, px, py, pc);
+        pick_step<0x4E>(k, j, px, py, pc);
+        pick_step<0x141>(k, j, px, py, pc);
+        cj = j < 64 ? j : -1;
+        cx = px, cy = py, cc = pc;
+        return cj;
+    }
+    __device__ __forceinline__ int first(bool ok) const
+    {
+        const uint64_t g = (__ballot(ok) >> base) & 0xFFull;
+        return g ? __ffsll((unsigned long long)g) - 1 : -1;
+    }
+    __device__ __forceinline__ bool all(bool ok) const { return ((__ballot(!ok) >> base) & 0xFFull) == 0; }
 };
 
 // Small-neighbourhood LPs (5 rows, up to 8 columns), one thread per particle;
@@ -512,6 +601,86 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
         bool retry = live && st == 4;
         int pr = wave_append(&qs->n_retry, retry);
         if (retry) q_retry[pr] = r;
+    }
+}
+
+// Small-neighbourhood LPs with eight lanes each (CoopCols): the same LPs, the
+// same pivots and results as k_lp_small, in one eighth of its dependent chain
+// per pivot (one column priced per lane).  Plain and phase-I passes only.
+template <bool PH1>
+__global__ __launch_bounds__(kSmallBlock) void k_lp_small_coop(const float* __restrict__ gamma,
+                                                               SmallRec rec, const int32_t* __restrict__ q_small,
+                                                               Queues* qs, int32_t* q_full, float* acc,
+                                                               LaunchParams P, StencilOut out, int apply,
+                                                               vrm_counters* cnt)
+{
+    cnt = counter_stripe(cnt);
+    const int lane = threadIdx.x & 63;
+    const int s = lane & 7, base = lane & ~7;
+    const bool lead = s == 0;
+    const int nitems = qs->n_small;
+    const size_t cap = (size_t)rec.cap;
+    const int group = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int ngroups = (gridDim.x * blockDim.x) >> 3;
+    const int loops = (nitems + ngroups - 1) / ngroups;
+    for (int it = 0; it < loops; ++it) {
+        const int item = group + it * ngroups;
+        const bool live = item < nitems;   // the same for the eight lanes of a group
+        int st = 1, piv = 0, certified = 1, t = 0;
+        if (live) {
+            t = q_small[item];
+            const int i = rec.i[item];
+            const int pj = rec.pj[s * cap + item];
+            const bool alive = pj >= 0;
+            df X{rec.off[(4 * s + 0) * cap + item], rec.off[(4 * s + 1) * cap + item]};
+            df Y{rec.off[(4 * s + 2) * cap + item], rec.off[(4 * s + 3) * cap + item]};
+            const int rank = (rec.rank[item] >> (3 * s)) & 7;
+            CoopCols cs;
+            cs.k = VRM_NSEG;
+            cs.dead = (__ballot(!alive) >> base) & 0xFFull;
+            cs.own = s;
+            cs.base = base;
+            cs.x = X.hi;
+            cs.y = Y.hi;
+            cs.xlo = X.lo;
+            cs.ylo = Y.lo;
+            cs.c = alive ? add_rank(cost_df(X, Y, P), rank, P.q).hi : 0.0f;
+            cs.meta = alive ? (int)(((unsigned)pj << 6) | (unsigned)rank) : 0;
+            cs.P = &P;
+            cs.cj = -1;
+            float fv = 0.0f, fii = 0.0f;
+            auto store = [&](int j, float v) {
+                if (j == s) fv = v;
+            };
+            int warm = 0;
+            uint64_t basis = 0;
+            st = solve_lp<5, PH1>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false, 0ull);
+            if (st == 0) {
+                const float g = gamma[i];
+                if (apply && fv != 0.0f) atomicAdd(&acc[pj], fv * g);
+                if (apply && lead) atomicAdd(&acc[i], fii * g);
+                if (out.small_f) {
+                    out.small_idx[(size_t)i * VRM_NSEG + s] = alive ? pj : -1;
+                    out.small_f[(size_t)i * VRM_NSEG + s] = fv;
+                    if (lead) {
+                        out.fii[i] = fii;
+                        out.status[i] = VRM_ST_SMALL;
+                    }
+                }
+            }
+        }
+        const bool ok = live && lead && st == 0;
+        if (lead && piv) atomicAdd((unsigned long long*)&cnt->pivots, (unsigned long long)piv);
+        count_add(&cnt->n_small, ok);
+        count_add(&cnt->n_uncertified, ok && !certified);
+        if (apply) {
+            uint64_t m = __ballot(ok);
+            if (m && lane_id() == __ffsll((unsigned long long)m) - 1)
+                atomicAdd((unsigned long long*)&cnt->redistributions, (unsigned long long)__popcll(m));
+        }
+        const bool fail = live && lead && st == 1;
+        const int p = wave_append(&qs->n_full, fail);
+        if (fail) q_full[p] = t;
     }
 }
 
@@ -1122,11 +1291,22 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
     if (lp.m == 5) {
         {
             ScopedTimer tm(c, VRM_T_LP_SMALL);
-            for (int mode = first; mode <= (warm ? kLpRetry : kLpPlain); ++mode) {
-                hipLaunchKernelGGL((lp.phase1 ? k_lp_small<true> : k_lp_small<false>), dim3(lp_grid_small(c, n)), dim3(kSmallBlock), 0, c->stream, c->perm, c->xs,
-                                   c->ys, c->ids, c->srec, c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc,
-                                   lp, out, apply, c->counters, mode, c->q_retry, c->tuning.lp_small_lanes);
+            if (!warm && c->tuning.lp_small_coop && !feat_out) {
+                // eight lanes per LP (plain or phase-I pass)
+                const int per_block = kSmallBlock / 8;
+                const int grid = min((n + per_block - 1) / per_block, c->tuning.lp_small_blocks);
+                hipLaunchKernelGGL((lp.phase1 ? k_lp_small_coop<true> : k_lp_small_coop<false>), dim3(max(grid, 1)),
+                                   dim3(kSmallBlock), 0, c->stream, cl->gamma_dev, c->srec, c->q_small, c->queues,
+                                   c->q_full, c->acc, lp, out, apply, c->counters);
                 VRM_HIP(hipGetLastError());
+            } else {
+                for (int mode = first; mode <= (warm ? kLpRetry : kLpPlain); ++mode) {
+                    hipLaunchKernelGGL((lp.phase1 ? k_lp_small<true> : k_lp_small<false>), dim3(lp_grid_small(c, n)),
+                                       dim3(kSmallBlock), 0, c->stream, c->perm, c->xs, c->ys, c->ids, c->srec,
+                                       c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc, lp, out, apply,
+                                       c->counters, mode, c->q_retry, c->tuning.lp_small_lanes);
+                    VRM_HIP(hipGetLastError());
+                }
             }
         }
         // fallbacks of the small LPs: no network input for them

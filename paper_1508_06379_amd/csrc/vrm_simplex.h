@@ -121,6 +121,14 @@ __device__ __forceinline__ df rhs_df(int a, const LaunchParams& P)
 // and, for stores with a run-time column count (KC == 0),
 //   void load(int j, float& rx, float& ry, uint32_t& aux)  raw values of column j
 //   float cost_of<Q>(float rx, float ry, uint32_t aux)      its FP32 cost (order Q)
+// A store with kCoop spreads the columns over a group of lanes, one each
+// (own, x, y, c: this lane's column); every lane of the group runs this
+// simplex on the same, replicated state, and the loops over columns become
+// one column per lane plus a group reduction:
+//   int pick(bool ok, float key)  lowest (key, column) among the lanes with ok, or -1
+//   int first(bool ok)            lowest column among the lanes with ok, or -1
+//   bool all(bool ok)             every lane of the group has ok
+//   void exact_own(df& X, df& Y, df& C)  this lane's exact offset and cost
 template <int M, class CS>
 struct ThreadSimplex {
     static_assert(M == 3 || M == 5 || M == 9, "3 rows: identity, 5: q = 2, 9: q = 3");
@@ -344,7 +352,16 @@ struct ThreadSimplex {
             }
             return false;
         };
-        if constexpr (CS::KC > 0) {
+        if constexpr (CS::kCoop) {
+            // this lane's column, then the group's choice: Bland's first
+            // qualifying column, or Dantzig's first of the most negative
+            float v[M];
+            mono<M>(cs.x, cs.y, v);
+            float d, sc;
+            reduced(v, cs.c, y, p2, d, sc);
+            const bool ok = !((excl >> cs.own) & 1ull) && d < -kTolD * sc;
+            return cs.pick(ok, bland ? 0.0f : d);
+        } else if constexpr (CS::KC > 0) {
             // compile-time column count: the loop is unrolled
 #pragma unroll
             for (int j = 0; j < CS::KC; ++j) {
@@ -575,7 +592,13 @@ struct ThreadSimplex {
                     prices(true, yf);
                     bool dual_ok = true;
                     const uint64_t excl = isb | dead;
-                    if constexpr (CS::KC > 0) {
+                    if constexpr (CS::kCoop) {
+                        float v[M];
+                        mono<M>(cs.x, cs.y, v);
+                        float d, sc;
+                        reduced(v, cs.c, yf, true, d, sc);
+                        dual_ok = cs.all(((excl >> cs.own) & 1ull) || !(d < kFastMargin * sc));
+                    } else if constexpr (CS::KC > 0) {
 #pragma unroll
                         for (int j = 0; j < CS::KC; ++j) {
                             if ((excl >> j) & 1ull) continue;
@@ -651,10 +674,8 @@ struct ThreadSimplex {
                 }
                 int e = -1;
                 float best = 0.0f;
-                for (int j = 0; j < k; ++j) {
-                    if (((isb | dead) >> j) & 1ull) continue;
-                    df X, Y, C;
-                    cs.exact(j, X, Y, C);
+                // the dual ratio of column j (w: its entry in row lrow of B^-1 V)
+                auto dual_ratio = [&](const df& X, const df& Y, const df& C, float& ratio) -> bool {
                     df v[M];
                     mono_df<M>(X, Y, v);
                     float w = 0.0f;
@@ -664,9 +685,22 @@ struct ThreadSimplex {
                         w = __builtin_fmaf(wrow[a], v[a].hi, w);
                         s = df_add(s, df_neg(df_mul(v[a], y[a])));
                     }
-                    if (w < -kTolPiv) {
-                        float ratio = fmaxf(s.hi + s.lo, 0.0f) / (-w);
-                        if (e < 0 || ratio < best) {
+                    ratio = w < -kTolPiv ? fmaxf(s.hi + s.lo, 0.0f) / (-w) : 0.0f;
+                    return w < -kTolPiv;
+                };
+                if constexpr (CS::kCoop) {
+                    df X, Y, C;
+                    cs.exact_own(X, Y, C);
+                    float ratio;
+                    const bool ok = dual_ratio(X, Y, C, ratio) && !(((isb | dead) >> cs.own) & 1ull);
+                    e = cs.pick(ok, ratio);
+                } else {
+                    for (int j = 0; j < k; ++j) {
+                        if (((isb | dead) >> j) & 1ull) continue;
+                        df X, Y, C;
+                        cs.exact(j, X, Y, C);
+                        float ratio;
+                        if (dual_ratio(X, Y, C, ratio) && (e < 0 || ratio < best)) {
                             e = j;
                             best = ratio;
                         }
@@ -683,10 +717,8 @@ struct ThreadSimplex {
             }
             // exact reduced costs; Bland's entering column
             int e = -1;
-            for (int j = 0; j < k && e < 0; ++j) {
-                if (((isb | dead) >> j) & 1ull) continue;
-                df X, Y, C;
-                cs.exact(j, X, Y, C);
+            // exact reduced cost of column j below its tolerance
+            auto negative = [&](const df& X, const df& Y, const df& C) -> bool {
                 df v[M];
                 mono_df<M>(X, Y, v);
                 df s = C;
@@ -697,7 +729,19 @@ struct ThreadSimplex {
                     s = df_add(s, df_neg(p));
                     sc += fabsf(p.hi);
                 }
-                if (s.hi + s.lo < -kCertD * sc) e = j;
+                return s.hi + s.lo < -kCertD * sc;
+            };
+            if constexpr (CS::kCoop) {
+                df X, Y, C;
+                cs.exact_own(X, Y, C);
+                e = cs.first(!(((isb | dead) >> cs.own) & 1ull) && negative(X, Y, C));
+            } else {
+                for (int j = 0; j < k && e < 0; ++j) {
+                    if (((isb | dead) >> j) & 1ull) continue;
+                    df X, Y, C;
+                    cs.exact(j, X, Y, C);
+                    if (negative(X, Y, C)) e = j;
+                }
             }
             if (e < 0) return 0;
             float rx, ry, ce;

@@ -62,7 +62,7 @@ int main(void) {
   printf("vrm_tuning %zu\\n", sizeof(vrm_tuning));
   P(vrm_params, q) P(vrm_cloud, capacity) P(vrm_stencils, full_f_dev)
   P(vrm_counters, pivots) P(vrm_counters, redistributions) P(vrm_counters, mis_rounds) P(vrm_counters, full_cols)
-  P(vrm_counters, graph_replays) P(vrm_tuning, infer_blocks) P(vrm_tuning, lp_small_lanes)
+  P(vrm_counters, graph_replays) P(vrm_tuning, infer_blocks) P(vrm_tuning, lp_small_lanes) P(vrm_tuning, lp_small_coop)
   return 0;
 }
 """)
@@ -84,6 +84,7 @@ int main(void) {
     assert int(out["vrm_tuning"]) == ctypes.sizeof(vrm.vrm_tuning)
     assert int(out["vrm_tuning.infer_blocks"]) == vrm.vrm_tuning.infer_blocks.offset
     assert int(out["vrm_tuning.lp_small_lanes"]) == vrm.vrm_tuning.lp_small_lanes.offset
+    assert int(out["vrm_tuning.lp_small_coop"]) == vrm.vrm_tuning.lp_small_coop.offset
 
 
 def test_product_path_has_no_cpu_fallback():

@@ -429,7 +429,9 @@ def test_launch_shapes_do_not_change_results(vrm, name):
               {"lp_small_blocks": 1, "lp_full_blocks": 1, "full_stored_cost_n": -1, "infer_blocks": 1},
               {"lp_small_blocks": 3, "lp_full_blocks": 5, "full_stored_cost_n": 1 << 30, "infer_blocks": 2,
                "lp_small_lanes": 4},
-              {"lp_small_lanes": 16}]
+              {"lp_small_lanes": 16},
+              {"lp_small_coop": 1},
+              {"lp_small_coop": 1, "lp_small_blocks": 1}]
     res = []
     for tuning in shapes:
         cloud = _gpu_cloud(vrm, wl, cap_factor=4)
@@ -451,3 +453,39 @@ def test_launch_shapes_do_not_change_results(vrm, name):
         # particle across the selection threshold
         assert cnt["n_infeasible"] == ca["n_infeasible"]
         assert abs(cnt["pivots"] - ca["pivots"]) <= 0.01 * ca["pivots"]
+
+
+@pytest.mark.parametrize("objective", [0, 1])
+@pytest.mark.parametrize("name", ["lattice", "jittered_q2_h0.02", "vortices_h0.02"])
+def test_cooperative_small_lps_give_identical_stencils(vrm, name, objective):
+    """Eight lanes per small LP (lp_small_coop) take the same pivots as one
+    thread per LP: stencils, statuses and pivot counts identical, bit for bit
+    (canonical objective and phase I only)."""
+    wl = CONFIGS[name]
+    P = vrm.params_of(wl)
+    out = []
+    for coop in (0, 1):
+        cloud = _gpu_cloud(vrm, wl, cap_factor=4)
+        ctx = vrm.Context(cloud.capacity)
+        ctx.vrm_set_tuning({"lp_small_coop": coop})
+        ctx.vrm_set_lp_objective(objective)
+        ctx.vrm_insert_particles(cloud, P)
+        st = vrm.Stencils.alloc(cloud.capacity)
+        c0 = ctx.vrm_read_counters()
+        ctx.vrm_solve_fractions(cloud, P, st)
+        torch.cuda.synchronize()
+        c1 = ctx.vrm_read_counters()
+        n = cloud.n
+        o = np.argsort(cloud.id[:n].cpu().numpy())
+        ids = cloud.id[:n].cpu().numpy()
+        S = {k: getattr(st, k)[:n].cpu().numpy()[o] for k in ("small_f", "fii", "status", "full_k", "full_f")}
+        # column particles by id (each context orders its cloud on its own)
+        si = st.small_idx[:n].cpu().numpy()[o]
+        S["small_id"] = np.where(si >= 0, ids[np.maximum(si, 0)], -1)
+        out.append((S, c1["pivots"] - c0["pivots"], c1["n_small"] - c0["n_small"]))
+    (a, pa, na), (b, pb, nb) = out
+    _say("case coop", name, objective, "pivots", pa, pb, "small LPs", na, nb)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    assert pa == pb and na == nb
+
