@@ -373,13 +373,25 @@ __global__ __launch_bounds__(256) void k_candidates(int n, const int32_t* __rest
                 // the three cells of this row are contiguous in slot order
                 int c0 = yy * g.nx + max(cxi - 1, 0), c1 = yy * g.nx + min(cxi + 1, g.nx - 1);
                 int u0 = cell_start[c0], u1 = cell_start[c1 + 1];
-                for (int u = u0; u < u1; ++u) {
-                    if (u == t) continue;
-                    float dx = xs[u] - xi;
-                    float dy = ys[u] - yi;
-                    float d2 = d2_f32(dx, dy);
-                    if (d2 < P.lo2 || d2 > P.hi2) continue;
-                    occupied |= 1 << segment_f32(dx, dy);
+                // positions read eight at a time: one memory latency per eight candidates
+                for (int ub = u0; ub < u1; ub += 8) {
+                    float bx[8], by[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int v = min(ub + e, u1 - 1);   // past the end: a repeat, not visited
+                        bx[e] = xs[v];
+                        by[e] = ys[v];
+                    }
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int u = ub + e;
+                        if (u >= u1 || u == t) continue;
+                        float dx = bx[e] - xi;
+                        float dy = by[e] - yi;
+                        float d2 = d2_f32(dx, dy);
+                        if (d2 < P.lo2 || d2 > P.hi2) continue;
+                        occupied |= 1 << segment_f32(dx, dy);
+                    }
                 }
             }
         }
