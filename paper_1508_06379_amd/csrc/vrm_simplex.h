@@ -319,6 +319,51 @@ struct ThreadSimplex {
         return true;
     }
 
+    // Guided phase I from a prediction: from the artificial basis the columns
+    // of the M largest logits enter in decreasing order by ordinary phase-I
+    // pivots (the ratio test chooses the leaving row), so the basis stays
+    // primal feasible whatever the prediction; run(…, 1) then finishes
+    // phase I and phase II from it without pricing the entered columns.
+    __device__ void guided(const CS& cs, const float* logit, int& piv)
+    {
+        const int kk = cs.k < 32 ? cs.k : 32;
+        uint64_t chosen = dead;
+        for (int t = 0; t < M && t < kk; ++t) {
+            int best = -1;
+            float bl = 0.0f;
+            if constexpr (CS::KC > 0) {
+#pragma unroll
+                for (int j = 0; j < CS::KC; ++j) {
+                    if ((chosen >> j) & 1ull) continue;
+                    const float z = cs.lg[j];
+                    if (best < 0 || z > bl) {
+                        best = j;
+                        bl = z;
+                    }
+                }
+            } else {
+                for (int j = 0; j < kk; ++j) {
+                    if ((chosen >> j) & 1ull) continue;
+                    const float z = logit[j];
+                    if (best < 0 || z > bl) {
+                        best = j;
+                        bl = z;
+                    }
+                }
+            }
+            if (best < 0) break;
+            chosen |= 1ull << best;
+            float rx, ry, c;
+            cs.get(best, rx, ry, c);
+            float alpha[M];
+            column_alpha(rx, ry, alpha);
+            const int l = ratio_test(alpha, xb, false);
+            if (l < 0) continue;
+            pivot(l, best, alpha, c);
+            ++piv;
+        }
+    }
+
     // Reduced cost d_j = c_j - y . v_j (phase II; 0 - y . v_j in phase I) and
     // the scale sum |c_j| + sum |y_a v_ja| its tolerance is relative to.
     __device__ __forceinline__ static void reduced(const float (&v)[M], float c, const float (&y)[M], bool p2,
@@ -766,9 +811,11 @@ struct ThreadSimplex {
 // Warm pass (warm_pass): the simplex starts from the crash basis of the
 // prediction (logits of the first 32 columns, or the column set pref with
 // use_pref); a rejected crash basis, or one that needs more than warm_cap<M>()
-// phase-II pivots, is given up (status 4).  basis: the final basic columns.
-// warm = 0 cold, 1 the predicted basis was optimal, 2 phase II from it,
-// 3 given up.
+// phase-II pivots, is given up (status 4) -- except a network's prediction
+// for a 9-row LP, which is always finished in the pass (a rejected crash
+// basis becomes a guided phase I, no pivot cap).  basis: the final basic
+// columns.  warm = 0 cold, 1 the predicted basis was optimal, 2 phase I/II
+// from it, 3 given up.
 // phase-II pivots allowed from a predicted basis in the warm pass: a few for
 // 5-row LPs (a cold solve takes ~8), more for 9-row ones (~30)
 template <int M>
@@ -788,18 +835,28 @@ __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float&
     int st;
     warm = 0;
     basis = 0;
+    // a network's prediction for a 9-row LP is finished in this pass, whatever
+    // it is worth: a rejected crash basis turns into a guided phase I, and no
+    // pivot cap applies (a cold retry of these long LPs would redo the work)
+    const bool finish = M == 9 && warm_pass && !use_pref;
+    bool guided = false;
     if (warm_pass) {
         if (!lp.crash(cs, logit, piv, use_pref, pref)) {
-            warm = 3;
-            return 4;
+            if (!finish) {
+                warm = 3;
+                return 4;
+            }
+            lp.init(P);
+            lp.guided(cs, logit, piv);
+            guided = true;
         }
         const int p1 = piv;
-        st = lp.run(cs, piv, 2, warm_cap<M>());
-        if (st == 2) {
+        st = guided ? lp.run(cs, piv, 1) : lp.run(cs, piv, 2, finish ? -1 : warm_cap<M>());
+        if (st == 2 && !finish) {
             warm = 3;
             return 4;
         }
-        warm = piv == p1 ? 1 : 2;
+        warm = (!guided && piv == p1) ? 1 : 2;
     }
     df x[M];
     bool accepted = false;   // phase I only: the first feasible vertex, exact to the refinement
