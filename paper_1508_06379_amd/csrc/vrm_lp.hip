@@ -808,7 +808,7 @@ __device__ int collect_full(int t, float xi, float yi, const GridState& g, const
 // pricing, three resident blocks per CU) or computed from the offsets when
 // priced (36 KB: four blocks per CU).  Small clouds, whose launches are one
 // wave's latency, take the first; large ones, throughput-bound, the second.
-template <int M, bool SC, bool PH1>
+template <int M, bool SC, bool PH1, bool WARM>
 __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restrict__ perm,
                                                         const float* __restrict__ xs, const float* __restrict__ ys,
                                                         const int32_t* __restrict__ ids,
@@ -902,7 +902,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
             auto col_id = [&](int j) { return ids[(unsigned)s_meta[j * kFullBlock + tid] >> 6]; };
             const uint64_t pref = (warm_pass && out.use_prev) ? prev_mask(out.prev, own, k, col_id) : 0ull;
             uint64_t basis = 0;
-            st = k > 0 ? solve_lp<M, PH1>(cs, P, store, fii, piv, certified, warm_pass, logit, warm, basis,
+            st = k > 0 ? solve_lp<M, PH1, WARM>(cs, P, store, fii, piv, certified, warm_pass, logit, warm, basis,
                                      warm_pass && out.use_prev, pref)
                        : 1;
             if (st == 0 && out.prev) record_basis(out.prev, own, basis, col_id);
@@ -1328,8 +1328,8 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         o2.lab = nullptr;
         ScopedTimer tm(c, VRM_T_LP_FULL);
         const bool stored = full_stored_costs(c, n);
-        hipLaunchKernelGGL((lp.phase1 ? (stored ? k_lp_full<5, true, true> : k_lp_full<5, false, true>)
-                                      : (stored ? k_lp_full<5, true, false> : k_lp_full<5, false, false>)),
+        hipLaunchKernelGGL((lp.phase1 ? (stored ? k_lp_full<5, true, true, false> : k_lp_full<5, false, true, false>)
+                                      : (stored ? k_lp_full<5, true, false, false> : k_lp_full<5, false, false, false>)),
                            dim3(min(lp_grid_full(c, n), 64)), dim3(kFullBlock), 0, c->stream, c->perm,
                            c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                            o2, apply, c->counters, kLpPlain, c->q_retry, 1);
@@ -1338,8 +1338,12 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         const int last = warm ? kLpRetry : kLpPlain;
         for (int mode = first; mode <= last; ++mode) {
             const bool stored = full_stored_costs(c, n);
-            hipLaunchKernelGGL((lp.phase1 ? (stored ? k_lp_full<9, true, true> : k_lp_full<9, false, true>)
-                                          : (stored ? k_lp_full<9, true, false> : k_lp_full<9, false, false>)),
+            // the warm pass carries the crash code; plain and retry launches do not
+            const bool w = mode == kLpWarm;
+            hipLaunchKernelGGL((lp.phase1 ? (stored ? (w ? k_lp_full<9, true, true, true> : k_lp_full<9, true, true, false>)
+                                                    : (w ? k_lp_full<9, false, true, true> : k_lp_full<9, false, true, false>))
+                                          : (stored ? (w ? k_lp_full<9, true, false, true> : k_lp_full<9, true, false, false>)
+                                                    : (w ? k_lp_full<9, false, false, true> : k_lp_full<9, false, false, false>))),
                                dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
                                c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                                out, apply, c->counters, mode, c->q_retry, mode == last ? 1 : 0);

@@ -823,11 +823,14 @@ constexpr int warm_cap() { return M == 5 ? 3 : 12; }
 
 // PH1: phase I only (the first feasible vertex, P.phase1) compiled in; the
 // canonical-only instantiation carries none of its code.
-template <int M, bool PH1, class CS, class Store>
+// WARM: the warm-pass code compiled in (a kernel that never runs a warm pass
+// leaves it out, and with it its registers).
+template <int M, bool PH1, bool WARM = true, class CS, class Store>
 __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified,
-                        bool warm_pass, const float* logit, int& warm, uint64_t& basis, bool use_pref = false,
+                        bool warm_pass_arg, const float* logit, int& warm, uint64_t& basis, bool use_pref = false,
                         uint64_t pref = 0)
 {
+    const bool warm_pass = WARM && warm_pass_arg;
     ThreadSimplex<M, CS> lp;
     lp.bt_ = P.bt_hi;
     lp.init(P);
@@ -840,7 +843,7 @@ __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float&
     // pivot cap applies (a cold retry of these long LPs would redo the work)
     const bool finish = M == 9 && warm_pass && !use_pref;
     bool guided = false;
-    if (warm_pass) {
+    if constexpr (WARM) if (warm_pass) {
         if (!lp.crash(cs, logit, piv, use_pref, pref)) {
             if (!finish) {
                 warm = 3;
