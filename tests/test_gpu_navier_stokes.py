@@ -11,6 +11,8 @@ the C ABI, against the oracle doing the same in FP64.
   is compared on the particle count, I0, I1 and the I2 error; and, as the
   paper observes, convection inserts more particles than the heat equation by
   a roughly constant factor (the paper: about 1.6).
+* The paper's velocity error e_u of those runs at h = 0.08, 0.04, 0.02: second
+  order, dominated by the smoothing of K_eps.
 """
 import numpy as np
 import pytest
@@ -104,3 +106,53 @@ def test_ns_dirac_run_matches_oracle_statistics(vrm, orc):
     assert max(abs(gi[1]), abs(gi[2])) <= 1e-5
     assert abs((exact - gi[3]) - (exact - ri[3])) <= 0.1 * abs(exact - ri[3])
     assert 1.3 <= x.size / heat.x.size <= 2.0
+
+
+def _velocity_error(orc, x, y, g, eps, nu, t=1.0, n=150):
+    """Sec. 5 velocity error e_u: relative L2 error over A = [-1.5, 1.5]^2 (midpoint
+    rule, n^2 points) of the particle velocity (K_eps) against the Lamb-Oseen
+    velocity of the Dirac start (Gamma = 2 pi) at time t."""
+    q = -1.5 + (np.arange(n) + 0.5) * 3.0 / n
+    qx, qy = (a.ravel() for a in np.meshgrid(q, q))
+    u, v = orc.biot_savart(np.asarray(x, np.float64), np.asarray(y, np.float64), np.asarray(g, np.float64),
+                           eps, qx, qy)
+    ue, ve = workloads.lamb_oseen_velocity(qx, qy, t, nu, 2.0 * np.pi)
+    return float(np.sqrt(np.sum((u - ue) ** 2 + (v - ve) ** 2) / np.sum(ue ** 2 + ve ** 2)))
+
+
+def _smoothing_error(eps, nu, t=1.0, n=150):
+    """e_u of the exact particle field: with the Gaussian kernel K_eps the
+    Lamb-Oseen vortex of spread 4 nu t is seen with spread 4 nu t + eps^2."""
+    q = -1.5 + (np.arange(n) + 0.5) * 3.0 / n
+    qx, qy = (a.ravel() for a in np.meshgrid(q, q))
+    ue, ve = workloads.lamb_oseen_velocity(qx, qy, t, nu, 2.0 * np.pi)
+    us, vs = workloads.lamb_oseen_velocity(qx, qy, t + eps * eps / (4.0 * nu), nu, 2.0 * np.pi)
+    return float(np.sqrt(np.sum((us - ue) ** 2 + (vs - ve) ** 2) / np.sum(ue ** 2 + ve ** 2)))
+
+
+@pytest.mark.timeout(600)
+def test_ns_velocity_error_converges_at_second_order(vrm, orc):
+    """Sec. 5: the velocity error e_u of the Dirac start with convection at t = 1
+    falls at second order over h = 0.08, 0.04, 0.02 (the paper observes second
+    order and attributes the error to the smoothing, eps = 3h); each e_u is within
+    10 % of the smoothing error of the exact field, and at h = 0.08 within 2 % of
+    the FP64 oracle's run."""
+    errs = []
+    for h in (0.08, 0.04, 0.02):
+        wl = workloads.dirac_lamb_oseen(h)
+        eps = 3.0 * h
+        _say("case ns velocity error h", h, "steps", wl.steps)
+        (x, y, g, ids), cnt = gpu_ns(vrm, wl, eps, wl.steps, int(10.0 / h ** 2) + 1024)
+        e = _velocity_error(orc, x, y, g, eps, wl.nu)
+        es = _smoothing_error(eps, wl.nu)
+        _say("h", h, "N", x.size, "e_u", e, "smoothing alone", es)
+        assert abs(e - es) <= 0.1 * es
+        if h == 0.08:
+            ref = oracle_ns(orc, wl, eps, wl.steps)
+            er = _velocity_error(orc, ref.x, ref.y, ref.gamma, eps, wl.nu)
+            _say("oracle e_u", er)
+            assert abs(e - er) <= 0.02 * er
+        errs.append(e)
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    _say("orders", orders)
+    assert ((orders > 1.5) & (orders < 2.3)).all()
