@@ -21,7 +21,8 @@ sys.path.insert(0, ROOT)
 
 import workloads  # noqa: E402
 
-# MI355X published peaks and the VALU peak of non-packed FP32 (the design doc derives it)
+# MI355X published HBM peak; FP32 VALU peak without packed math: 256 CUs x 4 SIMDs
+# x 16 lanes x 2 FLOP (FMA) x 2.4 GHz (the library emits no packed FP32)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
 
