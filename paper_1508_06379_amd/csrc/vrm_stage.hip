@@ -129,32 +129,60 @@ __global__ void k_verify_init(unsigned long long* out)
     out[3] = 0ull;
 }
 
-// time = t, or *t_dev + t when t_dev is given (graph replays)
+// Prescribed velocity of Lamb-Oseen vortices (centre, core sigma, circulation G):
+// u(x) = sum_k G_k (-d_y, d_x) (1 - exp(-|d|^2 / (sigma_k^2 + 4 nu t))) / (2 pi |d|^2),
+// d = x - centre_k, and 0 at a centre.  Time = t, or *t_dev + t when t_dev is
+// given (graph replays).  Each thread holds kVelT targets, so the per-vortex
+// constants a = G / (2 pi) and b = log2(e) / (sigma^2 + 4 nu t) (one hardware
+// reciprocal) are paid once per kVelT pairs; a pair costs two differences, two
+// FMAs for |d|^2, exp2(-b |d|^2), a reciprocal of |d|^2, one product, one FMA
+// for t - t e, a select and two accumulating FMAs, with no IEEE division.
+// A pair with |d|^2 <= 1e-30 (a target on a centre) contributes 0.
+constexpr int kVelT = 4;
+
 __global__ __launch_bounds__(256) void k_velocity(int n, const int32_t* __restrict__ n_dev,
                                                   const float* __restrict__ x, const float* __restrict__ y,
                                                   const float* __restrict__ vort, int nv, double nu, double t,
                                                   const double* __restrict__ t_dev, float* u, float* v)
 {
     if (n_dev) n = *n_dev;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int base = blockIdx.x * (256 * kVelT) + threadIdx.x;
+    if (base >= n) return;
     const double tt = t_dev ? *t_dev + t : t;
     const float four_nu_t = (float)(4.0 * nu * tt);
-    float xi = x[i], yi = y[i];
-    float su = 0.0f, sv = 0.0f;
-    const float inv2pi = 0.15915494309189535f;
-    for (int k = 0; k < nv; ++k) {
-        float dx = xi - vort[4 * k], dy = yi - vort[4 * k + 1];
-        float s = vort[4 * k + 2];
-        float G = vort[4 * k + 3];
-        float r2 = dx * dx + dy * dy;
-        float s2 = s * s + four_nu_t;
-        float fac = r2 > 0.0f ? G * inv2pi / r2 * (1.0f - __expf(-r2 / s2)) : 0.0f;
-        su -= fac * dy;
-        sv += fac * dx;
+    const float inv2pi = 0.15915494309189535f, log2e = 1.4426950408889634f;
+    float xi[kVelT], yi[kVelT], su[kVelT], sv[kVelT];
+#pragma unroll
+    for (int j = 0; j < kVelT; ++j) {
+        const int i = min(base + 256 * j, n - 1);
+        xi[j] = x[i];
+        yi[j] = y[i];
+        su[j] = 0.0f;
+        sv[j] = 0.0f;
     }
-    u[i] = su;
-    v[i] = sv;
+    for (int k = 0; k < nv; ++k) {
+        const float cx = vort[4 * k], cy = vort[4 * k + 1], s = vort[4 * k + 2];
+        const float a = vort[4 * k + 3] * inv2pi;
+        const float b = -log2e * __builtin_amdgcn_rcpf(__builtin_fmaf(s, s, four_nu_t));
+#pragma unroll
+        for (int j = 0; j < kVelT; ++j) {
+            const float dx = xi[j] - cx, dy = yi[j] - cy;
+            const float r2 = __builtin_fmaf(dx, dx, dy * dy);
+            const float ex = __builtin_amdgcn_exp2f(b * r2);
+            const float tr = __builtin_amdgcn_rcpf(r2) * a;
+            const float f = r2 > 1e-30f ? __builtin_fmaf(-tr, ex, tr) : 0.0f;
+            su[j] = __builtin_fmaf(-f, dy, su[j]);
+            sv[j] = __builtin_fmaf(f, dx, sv[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kVelT; ++j) {
+        const int i = base + 256 * j;
+        if (i < n) {
+            u[i] = su[j];
+            v[i] = sv[j];
+        }
+    }
 }
 
 int blocks_for(int n) { return n > 0 ? (n + 255) / 256 : 1; }
@@ -297,7 +325,7 @@ int vrm_velocity_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const float* vo
                      float* u, float* v, const double* t_dev)
 {
     if (n <= 0) return VRM_OK;
-    hipLaunchKernelGGL(k_velocity, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, cl->n_dev, cl->x_dev, cl->y_dev,
+    hipLaunchKernelGGL(k_velocity, dim3((n + 256 * kVelT - 1) / (256 * kVelT)), dim3(256), 0, c->stream, n, cl->n_dev, cl->x_dev, cl->y_dev,
                        vort, nv, nu, t, t_dev, u, v);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
