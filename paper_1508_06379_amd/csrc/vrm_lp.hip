@@ -187,6 +187,165 @@ __global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __rest
     }
 }
 
+// Small neighbourhoods with kNbL lanes per particle (aligned lane groups), for
+// clouds too small to fill the chip with one lane per particle, where the chain
+// of loads of one particle's scan sets the time.  The lanes of a group scan
+// interleaved candidates of the 3 x 3 cells, each keeps its closest candidate
+// per segment (ties to the smaller id), and the group takes the minimum of
+// (distance, id) per segment: the candidate the one-lane scan keeps, since that
+// scan also keeps the lexicographic minimum.  Same outputs and queue records as
+// k_small_nbhd; the lead lane of a group appends, the others write their share
+// of the segments.
+constexpr int kNbL = 4;
+constexpr int kNbhdCoopMaxN = 1 << 18;
+
+__global__ __launch_bounds__(256) void k_small_nbhd_coop(int n, const int32_t* __restrict__ n_dev,
+                                                         const int32_t* __restrict__ perm,
+                                                         const float* __restrict__ xs, const float* __restrict__ ys,
+                                                         const int32_t* __restrict__ ids,
+                                                         const int32_t* __restrict__ cell_start,
+                                                         const uint8_t* __restrict__ diffused, const GridState* gs,
+                                                         LaunchParams P, SmallRec rec, int32_t* q_small,
+                                                         int32_t* q_full, Queues* qs,
+                                                         int32_t* out_small_idx, int32_t* out_kfull, int want_kfull)
+{
+    __shared__ float s_bd[VRM_NSEG * 256];
+    __shared__ int s_best[VRM_NSEG * 256];
+    if (n_dev) n = *n_dev;
+    const int tid = threadIdx.x, sub = tid & (kNbL - 1);
+    const int t = blockIdx.x * (256 / kNbL) + tid / kNbL;
+    const bool active = t < n;
+    const int i = active ? perm[t] : 0;
+    const bool dif = active && diffused[i];
+    int kfull = 0;
+#pragma unroll
+    for (int s = 0; s < VRM_NSEG; ++s) {
+        s_bd[s * 256 + tid] = INFINITY;
+        s_best[s * 256 + tid] = -1;
+    }
+    if (dif && (P.m <= VRM_NSEG || want_kfull)) {
+        GridState g = *gs;
+        const float xi = xs[t], yi = ys[t];
+        int cx, cy;
+        cell_of_pos(g, xi, yi, cx, cy);
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int yy = cy + oy;
+            if (yy < 0 || yy >= g.ny) continue;
+            const int c0 = yy * g.nx + max(cx - 1, 0), c1 = yy * g.nx + min(cx + 1, g.nx - 1);
+            const int u0 = cell_start[c0], u1 = cell_start[c1 + 1];
+            for (int ub = u0 + sub; ub < u1; ub += 8 * kNbL) {
+                float bx[8], by[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int v = min(ub + kNbL * e, u1 - 1);
+                    bx[e] = xs[v];
+                    by[e] = ys[v];
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int u = ub + kNbL * e;
+                    if (u >= u1 || u == t) continue;
+                    const float dx = bx[e] - xi, dy = by[e] - yi;
+                    const float d2 = d2_f32(dx, dy);
+                    if (d2 < P.lo2) continue;
+                    if (d2 <= P.hi2f) ++kfull;
+                    if (d2 > P.hi2) continue;
+                    const int at = segment_f32(dx, dy) * 256 + tid;
+                    const float cur = s_bd[at];
+                    if (d2 <= cur) {
+                        bool take = d2 < cur;
+                        if (!take) {
+                            const int cb = s_best[at];
+                            take = cb >= 0 && ids[u] < ids[cb];
+                        }
+                        if (take) {
+                            s_bd[at] = d2;
+                            s_best[at] = u;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // group minimum of (distance, id) per segment; empty = (inf, INT_MAX, -1)
+    float bd[VRM_NSEG];
+    int bu[VRM_NSEG], bid[VRM_NSEG];
+#pragma unroll
+    for (int s = 0; s < VRM_NSEG; ++s) {
+        bd[s] = s_bd[s * 256 + tid];
+        bu[s] = s_best[s * 256 + tid];
+        bid[s] = bu[s] >= 0 ? ids[bu[s]] : 0x7fffffff;
+    }
+#pragma unroll
+    for (int o = 1; o < kNbL; o <<= 1) {
+        kfull += __shfl_xor(kfull, o, VRM_WAVE);
+#pragma unroll
+        for (int s = 0; s < VRM_NSEG; ++s) {
+            const float od = __shfl_xor(bd[s], o, VRM_WAVE);
+            const int ou = __shfl_xor(bu[s], o, VRM_WAVE), oid = __shfl_xor(bid[s], o, VRM_WAVE);
+            if (od < bd[s] || (od == bd[s] && oid < bid[s])) {
+                bd[s] = od;
+                bu[s] = ou;
+                bid[s] = oid;
+            }
+        }
+    }
+    int ksmall = 0;
+#pragma unroll
+    for (int s = 0; s < VRM_NSEG; ++s) ksmall += bu[s] >= 0 ? 1 : 0;
+    const bool lead = sub == 0;
+    if (active) {
+        if (out_small_idx) {
+#pragma unroll
+            for (int s = 0; s < VRM_NSEG; ++s)
+                if ((s & (kNbL - 1)) == sub) out_small_idx[(size_t)i * VRM_NSEG + s] = bu[s] >= 0 ? perm[bu[s]] : -1;
+        }
+        if (out_kfull && lead) out_kfull[i] = dif ? kfull : 0;
+    }
+    if (q_small) {
+        __shared__ int s_app[17];
+        const bool small_ok = dif && P.m <= VRM_NSEG && ksmall >= P.m;
+        int p1 = block_append_n(&qs->n_small, small_ok && lead ? 1 : 0, s_app);
+        p1 = __shfl(p1, lane_id() & ~(kNbL - 1), VRM_WAVE);
+        if (small_ok) {
+            const size_t cap = (size_t)rec.cap;
+            const float xi = xs[t], yi = ys[t];
+            if (lead) {
+                int packed = 0;
+#pragma unroll
+                for (int s = 0; s < VRM_NSEG; ++s) {
+                    int rank = 0;
+#pragma unroll
+                    for (int o = 0; o < VRM_NSEG; ++o) rank += bid[o] < bid[s] ? 1 : 0;
+                    packed |= rank << (3 * s);
+                }
+                q_small[p1] = t;
+                rec.i[p1] = i;
+                rec.rank[p1] = packed;
+            }
+#pragma unroll
+            for (int s = 0; s < VRM_NSEG; ++s) {
+                if ((s & (kNbL - 1)) != sub) continue;
+                const int u = bu[s];
+                df X{0.0f, 0.0f}, Y{0.0f, 0.0f};
+                int pj = -1;
+                if (u >= 0) {
+                    exact_offset(xi, yi, xs[u], ys[u], P.scale2e, X, Y);
+                    pj = perm[u];
+                }
+                rec.pj[s * cap + p1] = pj;
+                rec.off[(4 * s + 0) * cap + p1] = X.hi;
+                rec.off[(4 * s + 1) * cap + p1] = X.lo;
+                rec.off[(4 * s + 2) * cap + p1] = Y.hi;
+                rec.off[(4 * s + 3) * cap + p1] = Y.lo;
+            }
+        }
+        const bool full = dif && !small_ok;
+        const int p2 = block_append_n(&qs->n_full, full && lead ? 1 : 0, s_app);
+        if (full && lead) q_full[p2] = t;
+    }
+}
+
 struct StencilOut {
     int32_t* small_idx;
     float* small_f;
@@ -1230,6 +1389,9 @@ int lp_grid_full(const vrm_ctx* c, int n)
 {
     return n > 0 ? min((n + kFullBlock - 1) / kFullBlock, c->tuning.lp_full_blocks) : 1;
 }
+// workgroups of the neighbourhood kernel: 256 particles each, or 256 / kNbL
+// with kNbL lanes per particle up to kNbhdCoopMaxN particles
+int nbhd_blocks(int n) { return n <= kNbhdCoopMaxN ? (n + 256 / kNbL - 1) / (256 / kNbL) : (n + 255) / 256; }
 // clouds up to the tuned size launch the complete-LP kernel with stored costs
 bool full_stored_costs(const vrm_ctx* c, int n) { return n <= c->tuning.full_stored_cost_n; }
 
@@ -1240,10 +1402,10 @@ int vrm_small_nbhd_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchP
 {
     (void)cl;
     if (n <= 0) return VRM_OK;
-    int nb = (n + 255) / 256;
-    hipLaunchKernelGGL(k_small_nbhd, dim3(nb), dim3(256), 0, c->stream, n, cl->n_dev, c->perm, c->xs, c->ys, c->ids,
-                       c->cell_start, c->diffused, c->grid, lp, SmallRec{}, (int32_t*)nullptr, (int32_t*)nullptr,
-                       c->queues, small_idx, kfull, kfull != nullptr ? 1 : 0);
+    const bool coop = n <= kNbhdCoopMaxN;
+    hipLaunchKernelGGL(coop ? k_small_nbhd_coop : k_small_nbhd, dim3(nbhd_blocks(n)), dim3(256), 0, c->stream, n,
+                       cl->n_dev, c->perm, c->xs, c->ys, c->ids, c->cell_start, c->diffused, c->grid, lp, SmallRec{},
+                       (int32_t*)nullptr, (int32_t*)nullptr, c->queues, small_idx, kfull, kfull != nullptr ? 1 : 0);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }
@@ -1268,12 +1430,12 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
     out.lab = label_out;
     out.max_rows = max_rows;
     // the LP queues are empty here: the last LP launch of every run empties them
-    int nb = (n + 255) / 256;
     {
         ScopedTimer tm(c, VRM_T_NBHD);
-        hipLaunchKernelGGL(k_small_nbhd, dim3(nb), dim3(256), 0, c->stream, n, cl->n_dev, c->perm, c->xs, c->ys, c->ids,
-                           c->cell_start, c->diffused, c->grid, lp, c->srec, c->q_small, c->q_full, c->queues,
-                           (int32_t*)nullptr, (int32_t*)nullptr, 0);
+        const bool coop = n <= kNbhdCoopMaxN;
+        hipLaunchKernelGGL(coop ? k_small_nbhd_coop : k_small_nbhd, dim3(nbhd_blocks(n)), dim3(256), 0, c->stream, n,
+                           cl->n_dev, c->perm, c->xs, c->ys, c->ids, c->cell_start, c->diffused, c->grid, lp, c->srec,
+                           c->q_small, c->q_full, c->queues, (int32_t*)nullptr, (int32_t*)nullptr, 0);
     }
     VRM_HIP(hipGetLastError());
     const bool net = c->warm == 1 && c->mlp && c->mlp->loaded && !feat_out;
