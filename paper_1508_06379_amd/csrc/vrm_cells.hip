@@ -348,6 +348,13 @@ __global__ void k_zero_diffused_count(vrm_counters* cnt)
 
 // ------------------------------------------------------------ insertion
 // Candidates: every empty segment of a diffused particle (slot order).
+// L lanes per particle (aligned groups; L = 4 for clouds up to kCandCoopMaxN
+// particles, where one lane per particle leaves the chip mostly idle and the
+// chain of loads of one scan sets the time): the lanes scan interleaved
+// candidates and OR their occupied segments; the group's lead lane appends.
+constexpr int kCandCoopMaxN = 1 << 18;
+
+template <int L>
 __global__ __launch_bounds__(256) void k_candidates(int n, const int32_t* __restrict__ perm,
                                                     const float* __restrict__ xs, const float* __restrict__ ys,
                                                     const int32_t* __restrict__ ids,
@@ -356,7 +363,8 @@ __global__ __launch_bounds__(256) void k_candidates(int n, const int32_t* __rest
                                                     LaunchParams P, Queues* qs, int cand_cap, float* cx, float* cy,
                                                     uint64_t* ckey, uint8_t* cstate)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sub = threadIdx.x & (L - 1);
+    const int t = blockIdx.x * (256 / L) + threadIdx.x / L;
     int occupied = 0xff;
     float xi = 0.0f, yi = 0.0f;
     if (t < n && diffused[perm[t]]) {
@@ -374,17 +382,17 @@ __global__ __launch_bounds__(256) void k_candidates(int n, const int32_t* __rest
                 int c0 = yy * g.nx + max(cxi - 1, 0), c1 = yy * g.nx + min(cxi + 1, g.nx - 1);
                 int u0 = cell_start[c0], u1 = cell_start[c1 + 1];
                 // positions read eight at a time: one memory latency per eight candidates
-                for (int ub = u0; ub < u1; ub += 8) {
+                for (int ub = u0 + sub; ub < u1; ub += 8 * L) {
                     float bx[8], by[8];
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        const int v = min(ub + e, u1 - 1);   // past the end: a repeat, not visited
+                        const int v = min(ub + L * e, u1 - 1);   // past the end: a repeat, not visited
                         bx[e] = xs[v];
                         by[e] = ys[v];
                     }
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        const int u = ub + e;
+                        const int u = ub + L * e;
                         if (u >= u1 || u == t) continue;
                         float dx = bx[e] - xi;
                         float dy = by[e] - yi;
@@ -396,9 +404,11 @@ __global__ __launch_bounds__(256) void k_candidates(int n, const int32_t* __rest
             }
         }
     }
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) occupied |= __shfl_xor(occupied, o, VRM_WAVE);
     __shared__ int s_app[17];
     int empty = (~occupied) & 0xff;
-    int want = __popc(empty);
+    int want = sub == 0 ? __popc(empty) : 0;
     int base = block_append_n(&qs->n_cand, want, s_app);
     if (want) {
         int id = ids[t];
@@ -705,7 +715,9 @@ int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp)
     const int cand_cap = 2 * c->capacity;
     hipLaunchKernelGGL(k_reset_insert, dim3(1), dim3(1), 0, s, c->queues);
     if (n > 0)
-        hipLaunchKernelGGL(k_candidates, dim3(blocks_for(n)), dim3(256), 0, s, n, c->perm, c->xs, c->ys, c->ids,
+        hipLaunchKernelGGL(n <= kCandCoopMaxN ? k_candidates<4> : k_candidates<1>,
+                           dim3(n <= kCandCoopMaxN ? (n + 63) / 64 : blocks_for(n)), dim3(256), 0, s, n, c->perm,
+                           c->xs, c->ys, c->ids,
                            c->cell_start, c->diffused, c->grid, lp, c->queues, cand_cap, c->cx, c->cy, c->ckey,
                            c->cstate);
     if (n > 0)
