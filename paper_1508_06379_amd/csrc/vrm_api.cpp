@@ -213,6 +213,13 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
         c->sort_tmp = p;
     }
     if (r == VRM_OK) {
+        void* p = nullptr;
+        hipError_t e = hipHostMalloc(&p, sizeof(vrm::HostQueues), hipHostMallocCoherent);
+        if (e != hipSuccess) r = vrm_hip_check(e, "hipHostMalloc(queue record)");
+        c->q_host = static_cast<vrm::HostQueues*>(p);
+        if (c->q_host) std::memset(c->q_host, 0, sizeof(vrm::HostQueues));
+    }
+    if (r == VRM_OK) {
         hipError_t e = hipMemsetAsync(c->acc, 0, cap * sizeof(float), c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->counters, 0, vrm::kCounterStripes * vrm::kCounterStride, c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->queues, 0, sizeof(vrm::Queues), c->stream);
@@ -241,6 +248,7 @@ int vrm_destroy(vrm_ctx* c)
                     c->akey, c->aidx, c->tmp_f, c->tmp_i, c->tmp_u8, c->verify_buf, c->sort_tmp};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    if (c->q_host) (void)hipHostFree(c->q_host);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->t_dev) (void)hipFree(c->t_dev);

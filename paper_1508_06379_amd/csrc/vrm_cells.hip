@@ -661,7 +661,40 @@ __global__ void k_insert_counters(const Queues* q, vrm_counters* cnt, int rounds
 
 int blocks_for(int n) { return n > 0 ? (n + 255) / 256 : 1; }
 
+// One thread copies the queue record to the host copy, then writes the
+// sequence number with a system-scope release (after a system fence).
+__global__ void k_publish_queues(const Queues* q, HostQueues* h, int32_t seq)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        h->q = *q;
+        __threadfence_system();
+        __hip_atomic_store(&h->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 }  // namespace
+
+// The host spins on the sequence number; every 256 polls it asks the stream:
+// an error ends the wait with that error, and a finished stream without the
+// record is a state error (so a wait cannot outlast the stream's work).
+int vrm_read_queues(vrm_ctx* c, Queues& q)
+{
+    const int32_t seq = ++c->q_seq;
+    hipLaunchKernelGGL(k_publish_queues, dim3(1), dim3(64), 0, c->stream, c->queues, c->q_host, seq);
+    VRM_HIP(hipGetLastError());
+    for (uint64_t k = 1;; ++k) {
+        if (__atomic_load_n(&c->q_host->seq, __ATOMIC_ACQUIRE) == seq) break;
+        if ((k & 255) == 0) {
+            const hipError_t e = hipStreamQuery(c->stream);
+            if (e == hipErrorNotReady) continue;
+            VRM_HIP(e);
+            if (__atomic_load_n(&c->q_host->seq, __ATOMIC_ACQUIRE) == seq) break;
+            return vrm_fail(VRM_E_STATE, "queue record not published");
+        }
+    }
+    std::memcpy(&q, const_cast<const Queues*>(&c->q_host->q), sizeof(Queues));
+    return VRM_OK;
+}
 
 // Cell list of (x, y) into ctx->cell_start / perm / xs, ys, ids (slot order).
 int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* id, int32_t n, const LaunchParams& lp,
@@ -708,7 +741,8 @@ int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double factor)
     return VRM_OK;
 }
 
-// Insertion; the cell list of the cloud must be current.  Synchronises.
+// Insertion; the cell list of the cloud must be current.  Returns once the
+// stream has run the work enqueued here (the host reads the queue record).
 int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp)
 {
     hipStream_t s = c->stream;
@@ -726,8 +760,7 @@ int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp)
                            c->counters);
     VRM_HIP(hipGetLastError());
     Queues q;
-    VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
-    VRM_HIP(hipStreamSynchronize(s));
+    if (int r = vrm_read_queues(c, q)) return r;
     if (q.small_state == 2)
         return vrm_fail(VRM_E_CAPACITY, "insertion needs %d particles, capacity is %d", n + q.n_accepted,
                         cl->capacity);
@@ -757,8 +790,7 @@ int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp)
             }
             rounds += batch;
             VRM_HIP(hipGetLastError());
-            VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
-            VRM_HIP(hipStreamSynchronize(s));
+            if (int e = vrm_read_queues(c, q)) return e;
             if (q.n_undecided == 0) break;
             if (rounds > 4 * nc + 64)
                 return vrm_fail(VRM_E_STATE, "insertion: conflict resolution did not converge");
@@ -766,8 +798,7 @@ int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp)
         hipLaunchKernelGGL(k_accepted, dim3(blocks_for(nc)), dim3(256), 0, s, nc, c->ckey, c->cstate, c->queues,
                            c->akey, c->aidx);
         VRM_HIP(hipGetLastError());
-        VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
-        VRM_HIP(hipStreamSynchronize(s));
+        if (int e = vrm_read_queues(c, q)) return e;
         na = q.n_accepted;
         if (n + na > cl->capacity) {
             int need = n + na;

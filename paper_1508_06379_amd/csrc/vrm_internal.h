@@ -74,6 +74,14 @@ struct Queues {
     int32_t n_rm_uncertified;   // ... of which optimality was not certified
 };
 
+// Queue record published to pinned, coherent host memory: the kernel writes q,
+// then seq last with a system-scope release; the host reads q once it sees the
+// sequence number it asked for.
+struct HostQueues {
+    Queues q;
+    int32_t seq;
+};
+
 // Column records of the queued small-neighbourhood LPs, in queue order and
 // plane-major (plane p of item r at p * cap + r) so that the LP and network
 // kernels read them coalesced instead of gathering neighbours.
@@ -128,6 +136,8 @@ struct vrm_ctx {
     // device buffers
     vrm::GridState* grid;
     vrm::Queues* queues;
+    vrm::HostQueues* q_host;    // pinned, coherent host copy of *queues (vrm_read_queues)
+    int32_t q_seq;              // last sequence number asked of it
     vrm::SelectState* sel;
     vrm_counters* counters;
     int32_t* cell_of;     // [cap] cell of particle
@@ -236,6 +246,9 @@ int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* i
                     const vrm::LaunchParams& lp, const int32_t* n_dev = nullptr);
 int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double bound_factor);
 int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp);
+// the queue record after the work enqueued so far on the context's stream,
+// read from the pinned host copy (no stream synchronisation)
+int vrm_read_queues(vrm_ctx* c, vrm::Queues& q);
 int vrm_reorder_cloud(vrm_ctx* c, vrm_cloud* cl, int32_t n);
 int vrm_remove_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp, int32_t* n_candidates);
 size_t vrm_remove_tmp_bytes(int32_t cap);
