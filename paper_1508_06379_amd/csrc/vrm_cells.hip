@@ -227,9 +227,12 @@ int scan_cells(vrm_ctx* c, int32_t* start)
 // are equal up to round-off form one group (whole groups are left out).
 __device__ __forceinline__ uint32_t selection_key(float a) { return __float_as_uint(a) & 0xffffff00u; }
 
-__global__ void k_sel_init(SelectState* s)
+// also zeroes the diffused count of every counter copy (k_sel_mask adds to it)
+__global__ void k_sel_init(SelectState* s, vrm_counters* cnt)
 {
     int t = threadIdx.x;
+    if (t < kCounterStripes)
+        reinterpret_cast<vrm_counters*>(reinterpret_cast<char*>(cnt) + t * kCounterStride)->n_diffused = 0;
     if (t == 0) {
         s->norm1 = 0.0;
         s->bound = 0.0;
@@ -341,11 +344,6 @@ __global__ __launch_bounds__(256) void k_sel_mask(const float* __restrict__ g, i
 }
 
 // one thread per counter copy
-__global__ void k_zero_diffused_count(vrm_counters* cnt)
-{
-    reinterpret_cast<vrm_counters*>(reinterpret_cast<char*>(cnt) + threadIdx.x * kCounterStride)->n_diffused = 0;
-}
-
 // ------------------------------------------------------------ insertion
 // Candidates: every empty segment of a diffused particle (slot order).
 // L lanes per particle (aligned groups; L = 4 for clouds up to kCandCoopMaxN
@@ -727,13 +725,13 @@ int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* i
 int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double factor)
 {
     hipStream_t s = c->stream;
-    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c->sel);
+    static_assert(kCounterStripes <= 256, "k_sel_init zeroes one counter copy per thread");
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c->sel, c->counters);
     int nb = min(2048, blocks_for(n));
     for (int shift = 24; shift >= 8; shift -= 8) {   // the ranking key has no bits below 8
         if (n > 0) hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, s, gamma, n, c->sel, shift);
         hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, c->sel, shift, factor);
     }
-    hipLaunchKernelGGL(k_zero_diffused_count, dim3(1), dim3(kCounterStripes), 0, s, c->counters);
     if (n > 0)
         hipLaunchKernelGGL(k_sel_mask, dim3(blocks_for(n)), dim3(256), 0, s, gamma, n, c->sel, c->diffused,
                            (uint8_t*)nullptr, c->counters);
