@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __rest
 // k_small_nbhd; the lead lane of a group appends, the others write their share
 // of the segments.
 constexpr int kNbL = 4;
-constexpr int kNbhdCoopMaxN = 1 << 18;
+constexpr int kNbhdCoopMaxN = 1 << 16;
 
 __global__ __launch_bounds__(256) void k_small_nbhd_coop(int n, const int32_t* __restrict__ n_dev,
                                                          const int32_t* __restrict__ perm,
