@@ -2,15 +2,27 @@
 
 A step is one SSP-RK3 step of the whole path: reduced-operator selection,
 insertion and reordering (once per step), then for each of the three stages
-the cell list, the small neighbourhoods, the moment LPs (small, then complete
-neighbourhood fallback), the scatter of nu sum_j f_ji Gamma_j and the stage
-combination.  The metric counts the stencils found and applied per second.
+the cell list, the neighbourhoods, the moment LPs (small ones, then the
+complete neighbourhoods: column lists, size bins, LPs), the scatter of
+nu sum_j f_ji Gamma_j and the stage combination.  The metric counts the
+stencils found and applied per second.
+
+Default workload: 256 vortices on [-8, 8]^2 at h = 0.004 (16.0 M particles,
+q = 3), the largest configuration on one GPU.  Timing, per solver:
+  * the timed region: `--steps` whole steps replayed from the step's HIP graph,
+    wall time between two device synchronisations, no events;
+  * a breakdown pass (3 steps, every kernel group timed with HIP events, direct
+    launches) that names the dominant group;
+  * a roofline pass (`--roofline-steps` steps, only the dominant group timed with
+    HIP events on the context's stream) for its average launch duration.
 
 Prints ONE JSON line on stdout (everything else goes to stderr).
 """
 import argparse
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -21,9 +33,11 @@ sys.path.insert(0, ROOT)
 
 import workloads  # noqa: E402
 
-# MI355X published HBM peak; FP32 VALU peak without packed math: 256 CUs x 4 SIMDs
-# x 16 lanes x 2 FLOP (FMA) x 2.4 GHz (the library emits no packed FP32)
+# MI355X published peaks: HBM 8 TB/s; FP32 vector 157.3 TFLOP/s (packed FP32,
+# which this library never emits: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA)
+# x 2.4 GHz = 78.6 TFLOP/s without it); BF16 dense matrix cores 2.5 PFLOP/s
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
 
 # algorithmic bytes per particle of the memory-bound kernel groups
@@ -32,21 +46,19 @@ BYTES_PER_PARTICLE = {
     "nbhd": 42.0,      # own x, y, id, diffused; small neighbourhood (8 x 4 B) and a queue entry
     "combine": 40.0,   # read x0, y0, g0, x, y, g, u, v, acc; write x, y, g, acc (heat: no x/u traffic)
     "select": 20.0,    # four passes over |Gamma| and the mask
+    "full_cols": 44.0,  # own x, y; the record row (37.5 x 4 B would be the columns: 150 B) -- see DESIGN
 }
 
-WORKLOADS = {
-    "lamb_oseen_h0.01_q2": lambda: workloads.config_jittered(h=0.01, q=2, seed=2),
-    "lamb_oseen_h0.01_q3": lambda: workloads.config_jittered(h=0.01, q=3, seed=2),
-    "vortices64_h0.005": lambda: workloads.config_vortices(),
-    "vortices256_h0.004_q3": lambda: workloads.config_scale(),
-}
+WORKLOADS = workloads.BENCH
+DEFAULT_WORKLOAD = "vortices256_h0.004_q3"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(wl, steps, warmup, theta=None, warm_mode=0, tuning=None, lp_objective=0):
+def run_gpu(wl, steps, warmup, theta=None, warm_mode=0, tuning=None, lp_objective=0, roofline_steps=10,
+            profile=True):
     import torch
     import paper_1508_06379_amd as vrm
 
@@ -66,23 +78,13 @@ def run_gpu(wl, steps, warmup, theta=None, warm_mode=0, tuning=None, lp_objectiv
     vt = vrm.vortex_table(wl.vortices) if wl.vortices is not None else None
 
     t = wl.t0
-    # warmup; its last step has every kernel group timed, to find the dominant
-    # one (the first step carries first-launch costs)
-    for k in range(warmup):
-        if k == warmup - 1:
-            torch.cuda.synchronize()
-            ctx.vrm_timing(True)
+    for _ in range(warmup):
         ctx.vrm_step(cloud, P, vt, t)
         t += wl.dt
     torch.cuda.synchronize()
-    warm_timers, _ = ctx.vrm_read_timing()
-    ctx.vrm_timing(False)
-    dom = dominant_group(warm_timers, wl.q)
     c0 = ctx.vrm_read_counters()
     n0 = cloud.n
-    # timed region: HIP events around the dominant group's launches only (the
-    # other launches carry no events)
-    ctx.vrm_timing_groups([dom])
+    # the timed region: graph replays, no events
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -90,22 +92,37 @@ def run_gpu(wl, steps, warmup, theta=None, warm_mode=0, tuning=None, lp_objectiv
         t += wl.dt
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    timers, overflow = ctx.vrm_read_timing()
-    ctx.vrm_timing(False)
     c1 = ctx.vrm_read_counters()
-    d = {k: c1[k] - c0[k] for k in ("redistributions", "pivots", "n_small", "n_full", "n_infeasible",
-                                     "n_uncertified", "full_cols", "warm_hit", "warm_phase2", "warm_cold")}
-    # breakdown over every group, from a few further steps (outside the timed region)
+    keys = ("redistributions", "pivots", "n_small", "n_full", "n_infeasible", "n_uncertified", "full_cols",
+            "warm_hit", "warm_phase2", "warm_cold", "graph_replays")
+    d = {k: c1[k] - c0[k] for k in keys}
+    out = dict(elapsed=elapsed, counters=d, n_start=n0, n_end=cloud.n, final=c1)
+    if not profile:
+        return out
+    # breakdown: every group timed (direct launches) over a few steps
+    nb = 3
     ctx.vrm_timing(True)
-    nb = min(steps, 10)
     for _ in range(nb):
         ctx.vrm_step(cloud, P, vt, t)
         t += wl.dt
     torch.cuda.synchronize()
-    breakdown, _ = ctx.vrm_read_timing()
+    bd, _ = ctx.vrm_read_timing()
     ctx.vrm_timing(False)
-    return dict(elapsed=elapsed, counters=d, timers=timers, timer_overflow=overflow, n_start=n0, n_end=cloud.n,
-                final=c1, dominant=dom, breakdown=breakdown, breakdown_steps=nb)
+    dom = dominant_group(bd, wl.q)
+    # roofline pass: only the dominant group's launches bracketed by events
+    ctx.vrm_timing_groups([dom])
+    r0 = ctx.vrm_read_counters()
+    for _ in range(roofline_steps):
+        ctx.vrm_step(cloud, P, vt, t)
+        t += wl.dt
+    torch.cuda.synchronize()
+    timers, overflow = ctx.vrm_read_timing()
+    ctx.vrm_timing(False)
+    r1 = ctx.vrm_read_counters()
+    rc = {k: r1[k] - r0[k] for k in keys}
+    out.update(breakdown=bd, breakdown_steps=nb, dominant=dom, roofline_timers=timers, roofline_counters=rc,
+               roofline_steps=roofline_steps, timer_overflow=overflow)
+    return out
 
 
 def breakdown(res):
@@ -184,50 +201,88 @@ def measured_traffic(workload, group):
 
 
 def roofline(wl, res, workload):
-    """Roofline of the dominant kernel group, timed by HIP events in the timed region."""
+    """Roofline of the dominant kernel group: algorithmic work per launch (counters of
+    the roofline pass) over the average launch duration (HIP events of that pass)."""
     dom = res["dominant"]
-    ms, launches = res["timers"][dom]
-    avg_s = ms / 1e3 / launches
-    c = res["counters"]
+    ms, launches = res["roofline_timers"][dom]
+    avg_s = ms / 1e3 / max(1, launches)
+    c = res["roofline_counters"]
     m = 5 if wl.q == 2 else 9
     if dom in ("lp_small", "lp_full"):
-        # revised simplex with an explicit m x m inverse, per pivot: reduced costs of
-        # the k columns (2 m k), prices, entering column and rank-one update of the
-        # inverse (2 m^2 each); k = 8 (small) or the mean complete-neighbourhood size
+        # simplex work per pivot: 2 m (k + 1) FLOP (pricing of the k columns and the
+        # update of the m x (k + 1) tableau it stands for); k = 8 (small) or the mean
+        # complete-neighbourhood size; pivots and k measured by the counters
         nlp = c["n_small"] if dom == "lp_small" else max(1, c["n_full"])
         k = 8.0 if dom == "lp_small" else c["full_cols"] / max(1, c["n_full"])
-        flops = c["pivots"] * (2.0 * m * k + 6.0 * m * m)
-        per_launch = flops / launches
+        flops = c["pivots"] * 2.0 * m * (k + 1.0)
+        per_launch = flops / max(1, launches)
         ach = per_launch / avg_s / 1e12
-        return {"kernel": dom, "bound": "alu", "achieved": ach, "peak": PEAK_FP32_NONPACKED_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_NONPACKED_TFLOPS, "traffic": measured_traffic(workload, dom),
-                "avg_launch_ms": avg_s * 1e3, "launches": launches,
-                "flop_model": f"pivots x (2 m k + 6 m^2), m={m}, k={k:.2f}, {c['pivots'] / max(1, nlp):.2f} pivots/LP"}
+        traffic = measured_traffic(workload, dom)
+        return {"kernel": dom, "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
+                "frac_of_nonpacked_peak": ach / PEAK_FP32_NONPACKED_TFLOPS, "traffic": traffic,
+                "avg_launch_ms": avg_s * 1e3, "launches": launches, "lps_per_launch": nlp / max(1, launches),
+                "flop_model": f"pivots x 2 m (k + 1), m={m}, k={k:.2f}, {c['pivots'] / max(1, nlp):.2f} pivots/LP",
+                "timing": "HIP events on the context's stream around every launch of the group, "
+                          f"{res['roofline_steps']} steps after the timed region"}
     npart = 0.5 * (res["n_start"] + res["n_end"])
     per_launch = BYTES_PER_PARTICLE[dom] * npart
     ach = per_launch / avg_s / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic(workload, dom), "avg_launch_ms": avg_s * 1e3, "launches": launches}
+            "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic(workload, dom), "avg_launch_ms": avg_s * 1e3,
+            "launches": launches}
 
 
-def cpu_baseline(wl, budget_s=15.0, max_steps=10000):
-    """The FP64 oracle on the host cores, on the first steps of the same run."""
+def host_info():
+    model = platform.processor() or ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
+def cpu_baseline(wl, name, budget_s=15.0):
+    """The FP64 oracle on the host cores: whole SSP-RK3 steps of a bounded sample of
+    the same workload (the small clouds from their initial state; the vortex clouds
+    on a square window of the same generated cloud, its size chosen for about
+    `budget_s` of work), as redistributions per second."""
     import oracle
     oracle.build()
-    st = oracle.initial_state(wl)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    if wl.n > 200000:
+        # a window with about budget_s of LP work: calibrate on a small one
+        probe = workloads.c5_window(wl, 0.3)
+        t0 = time.perf_counter()
+        st = oracle.step(oracle.initial_state(probe), probe)
+        rate = (time.perf_counter() - t0) / max(1, probe.n)
+        half = float(np.clip(0.3 * np.sqrt(budget_s / max(1e-9, rate * probe.n)), 0.3, 8.0))
+        sample = workloads.c5_window(wl, half)
+        desc = (f"one SSP-RK3 step (insertion and three stages) of the particles of the same cloud in "
+                f"[-{half:.2f}, {half:.2f}]^2 ({sample.n} of {wl.n}; the window's edge adds insertions)")
+        steps_max = 1
+    else:
+        sample = wl
+        desc = "the first SSP-RK3 steps of the same workload from its initial state"
+        steps_max = 10000
+    st = oracle.initial_state(sample)
     red = 0
-    t0 = time.perf_counter()
     steps = 0
-    while steps < max_steps and time.perf_counter() - t0 < budget_s:
-        st = oracle.step(st, wl)
+    t0 = time.perf_counter()
+    while steps < steps_max and (steps == 0 or time.perf_counter() - t0 < budget_s):
+        st = oracle.step(st, sample)
         h = st.history[-1]
         red += h.status_counts[0] + h.status_counts[1]
         steps += 1
     el = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": red / el, "unit": "redistributions/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {steps} SSP-RK3 steps of the same workload from its initial state "
-                      f"({el:.1f} s; LPs and neighbourhoods OpenMP-parallel, insertion and apply serial)"}
+    return {"value": red / el, "unit": "redistributions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{desc}; {steps} step(s), {red} redistributions in {el:.1f} s; LPs and neighbourhoods "
+                      f"OpenMP-parallel over {threads} threads, insertion, selection and the apply scatter serial "
+                      f"(the apply in a fixed order)",
+            "host": host_info()}
 
 
 def run_removal(reps=3, oracle_too=True):
@@ -252,7 +307,7 @@ def run_removal(reps=3, oracle_too=True):
             times.append(time.perf_counter() - t0)
         del cloud
     el = float(np.median(times))
-    out = {"workload": f"close_pairs_h0.005_[-4,4]^2", "n": wl.n, "candidates": nc, "removed": nr,
+    out = {"workload": "close_pairs_h0.005_[-4,4]^2", "n": wl.n, "candidates": nc, "removed": nr,
            "ms": el * 1e3, "removed_per_s": nr / el, "particles_per_s": wl.n / el}
     if oracle_too:
         import oracle
@@ -265,18 +320,35 @@ def run_removal(reps=3, oracle_too=True):
     return out
 
 
+def solver_summary(r, steps, value_plain):
+    c = r["counters"]
+    v = c["redistributions"] / r["elapsed"]
+    nlp = max(1, c["warm_hit"] + c["warm_phase2"] + c["warm_cold"])
+    out = {"value": v, "ms_per_step": r["elapsed"] * 1e3 / steps,
+           "vs_plain": v / value_plain if value_plain else None,
+           "pivots": c["pivots"], "pivots_per_lp": c["pivots"] / max(1, c["n_small"] + c["n_full"]),
+           "uncertified": c["n_uncertified"], "infeasible": c["n_infeasible"]}
+    if c["warm_hit"] + c["warm_phase2"] + c["warm_cold"]:
+        out["warm_start"] = {"optimal_from_start": c["warm_hit"] / nlp, "phase2_from_start": c["warm_phase2"] / nlp,
+                             "left_for_cold_solve": c["warm_cold"] / nlp}
+    if "breakdown" in r:
+        out["breakdown_ms_per_step"] = breakdown(r)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lamb_oseen_h0.01_q2", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--solver", default="all", choices=["all", "both", "plain", "learned", "previous", "phase1"],
                     help="plain batched solver, learned warm start, previous-basis warm start, the first "
                          "feasible vertex (phase I only); both = plain + learned, all = the four on the same "
                          "workload")
+    ap.add_argument("--roofline-steps", type=int, default=5)
     ap.add_argument("--train-snapshots", type=int, default=30)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--no-removal", action="store_true", help="skip the particle-removal measurement")
@@ -292,23 +364,30 @@ def main():
     if args.removal_only:
         print(json.dumps({"removal": run_removal(oracle_too=not args.no_cpu_baseline)}), flush=True)
         return
+    t_gen = time.perf_counter()
     wl = WORKLOADS[args.workload]()
-    log(f"workload {args.workload}: N={wl.n} h={wl.h} q={wl.q} dt={wl.dt}")
+    log(f"workload {args.workload}: N={wl.n} h={wl.h} q={wl.q} dt={wl.dt} (generated in "
+        f"{time.perf_counter() - t_gen:.1f} s)")
     from paper_1508_06379_amd import autotune
     tuning = autotune.load(args.workload)   # launch shapes chosen by the autotuner, if any
     log(f"tuning: {tuning}")
     runs = {}
+    kw = dict(roofline_steps=args.roofline_steps)
     if args.solver in ("all", "both", "plain"):
-        runs["plain"] = run_gpu(wl, args.steps, args.warmup, tuning=tuning)
+        runs["plain"] = run_gpu(wl, args.steps, args.warmup, tuning=tuning, **kw)
+        log(f"plain: {runs['plain']['elapsed']:.3f} s, {runs['plain']['counters']}")
     train_info = None
     if args.solver in ("all", "previous"):
-        runs["previous"] = run_gpu(wl, args.steps, args.warmup, warm_mode=2, tuning=tuning)
+        runs["previous"] = run_gpu(wl, args.steps, args.warmup, warm_mode=2, tuning=tuning, **kw)
+        log(f"previous: {runs['previous']['elapsed']:.3f} s")
     if args.solver in ("all", "phase1"):
-        runs["phase1"] = run_gpu(wl, args.steps, args.warmup, tuning=tuning, lp_objective=1)
+        runs["phase1"] = run_gpu(wl, args.steps, args.warmup, tuning=tuning, lp_objective=1, **kw)
+        log(f"phase1: {runs['phase1']['elapsed']:.3f} s")
     if args.solver in ("all", "both", "learned"):
         theta, train_info = train_network(args.workload, args.train_snapshots, args.epochs)
         log(f"network: {train_info}")
-        runs["learned"] = run_gpu(wl, args.steps, args.warmup, theta=theta, tuning=tuning)
+        runs["learned"] = run_gpu(wl, args.steps, args.warmup, theta=theta, tuning=tuning, **kw)
+        log(f"learned: {runs['learned']['elapsed']:.3f} s")
     if args.calibrate_copy:
         import torch
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -322,8 +401,8 @@ def main():
     c = res["counters"]
     value = c["redistributions"] / res["elapsed"]
     for k, r in runs.items():
-        log(f"{k}: elapsed {r['elapsed']:.4f} s, counters {r['counters']}, timed group {r['dominant']} "
-            f"{r['timers'][r['dominant']]}, breakdown {r['breakdown']}")
+        log(f"{k}: elapsed {r['elapsed']:.4f} s, counters {r['counters']}, dominant {r.get('dominant')}, "
+            f"breakdown {r.get('breakdown')}")
     rl = roofline(wl, res, args.workload)
     line = {
         "metric": "particle redistributions/s (learned warm start vs plain), FP32, moments <= 1e-6",
@@ -331,54 +410,28 @@ def main():
         "ms_per_step": res["elapsed"] * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "h": wl.h, "q": wl.q, "n_start": res["n_start"],
-                   "n_end": res["n_end"], "dt": wl.dt, "solver": main_solver},
+                   "n_end": res["n_end"], "dt": wl.dt, "solver": main_solver,
+                   "timed": "graph-replayed steps, wall time between device synchronisations"},
         "roofline": rl,
         "tuning": tuning,
         # kernel time per step and group, from steps after the timed region with every group timed
         "breakdown_ms_per_step": breakdown(res),
         "lp": {"small": c["n_small"], "full": c["n_full"], "infeasible": c["n_infeasible"],
-               "uncertified": c["n_uncertified"], "pivots": c["pivots"]},
+               "uncertified": c["n_uncertified"], "pivots": c["pivots"],
+               "mean_complete_columns": c["full_cols"] / max(1, c["n_full"])},
     }
-    if "previous" in runs and main_solver != "previous":
-        r = runs["previous"]
-        cp = r["counters"]
-        pv = cp["redistributions"] / r["elapsed"]
-        nlp = max(1, cp["warm_hit"] + cp["warm_phase2"] + cp["warm_cold"])
-        line["previous_basis"] = {
-            "value": pv, "ms_per_step": r["elapsed"] * 1e3 / args.steps, "vs_plain": pv / value,
-            "warm_start": {"optimal_from_previous": cp["warm_hit"] / nlp, "phase2_from_previous": cp["warm_phase2"] / nlp,
-                           "left_for_cold_solve": cp["warm_cold"] / nlp},
-            "pivots": cp["pivots"], "uncertified": cp["n_uncertified"],
-            "breakdown_ms_per_step": breakdown(r),
-        }
-    if "phase1" in runs and main_solver != "phase1":
-        r = runs["phase1"]
-        cp = r["counters"]
-        pv = cp["redistributions"] / r["elapsed"]
-        line["phase1_only"] = {
-            "value": pv, "ms_per_step": r["elapsed"] * 1e3 / args.steps, "vs_plain": pv / value,
-            "pivots": cp["pivots"], "pivots_per_lp": cp["pivots"] / max(1, cp["n_small"] + cp["n_full"]),
-            "uncertified": cp["n_uncertified"], "breakdown_ms_per_step": breakdown(r),
-            "note": "first feasible vertex (the paper's phase I); stencils differ from the canonical ones",
-        }
-    if "learned" in runs:
-        r = runs["learned"]
-        cl = r["counters"]
-        lv = cl["redistributions"] / r["elapsed"]
-        nlp = max(1, cl["warm_hit"] + cl["warm_phase2"] + cl["warm_cold"])
-        line["learned"] = {
-            "value": lv, "ms_per_step": r["elapsed"] * 1e3 / args.steps,
-            "vs_plain": lv / value if main_solver == "plain" else None,
-            "warm_start": {"optimal_from_prediction": cl["warm_hit"] / nlp, "phase2_from_prediction": cl["warm_phase2"] / nlp,
-                           "left_for_cold_solve": cl["warm_cold"] / nlp},
-            "pivots": cl["pivots"], "uncertified": cl["n_uncertified"],
-            "breakdown_ms_per_step": breakdown(r),
-            "network": train_info,
-        }
+    names = {"previous": "previous_basis", "phase1": "phase1_only", "learned": "learned"}
+    for k, key in names.items():
+        if k in runs and k != main_solver:
+            line[key] = solver_summary(runs[k], args.steps, value if main_solver == "plain" else None)
+    if "phase1_only" in line:
+        line["phase1_only"]["note"] = "first feasible vertex (the paper's phase I); stencils differ from the canonical ones"
+    if "learned" in line:
+        line["learned"]["network"] = train_info
     if not args.no_removal:
         line["removal"] = run_removal(oracle_too=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl, budget_s=args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline(wl, args.workload, budget_s=args.cpu_budget)
     print(json.dumps(line), flush=True)
 
 

@@ -22,6 +22,15 @@
  *   - Fractions are normalised: f_ij = fhat_ij / h^2 (Sec. 2, last paragraph).
  *   - Floating point: FP32 state and fractions; FP64 only in the verification
  *     sums (moment residual, circulation).
+ *   - Non-finite input: the first kernel that reads the positions (the cell
+ *     list's bounding box) or the circulations (the diffused-set selection,
+ *     the stage-0 copy of vrm_rk_stage, the removal's candidate scan) flags a
+ *     NaN or infinite value on the device.  From then on no cell index is
+ *     formed from it and no kernel changes the cloud: the calls of the step
+ *     become no-ops.  The next synchronising call (vrm_insert_particles,
+ *     vrm_step, vrm_remove_particles, vrm_read_counters) returns
+ *     VRM_E_NONFINITE, clears the flag and drops the context's cached cell
+ *     list and diffused set.
  */
 #ifndef VRM_H
 #define VRM_H
@@ -38,6 +47,7 @@ extern "C" {
 #define VRM_E_CAPACITY (-2)   /* insertion would exceed cloud capacity; nothing appended */
 #define VRM_E_HIP (-3)        /* a HIP runtime call failed */
 #define VRM_E_STATE (-4)      /* call order violated (e.g. no diffused set yet) */
+#define VRM_E_NONFINITE (-5)  /* a position or circulation is NaN or infinite; the cloud is unchanged */
 
 #define VRM_NSEG 8            /* 45-degree segments of a neighbourhood (Sec. 4.2) */
 #define VRM_KMAX 48           /* max columns of a complete-neighbourhood LP */
@@ -47,6 +57,9 @@ extern "C" {
 #define VRM_ST_FULL 1         /* complete neighbourhood LP solved (fallback) */
 #define VRM_ST_INFEASIBLE 2   /* no non-negative stencil: not diffused this stage */
 #define VRM_ST_SKIPPED 3      /* not in the diffused set (Sec. 3.5) */
+#define VRM_ST_WARM 4         /* solved from the warm start's basis (vrm_set_warm_start), certified like
+                                 the cold solve: the same stencil; full_k_dev > 0 marks a complete
+                                 neighbourhood */
 
 typedef struct vrm_ctx vrm_ctx;
 
@@ -73,11 +86,16 @@ typedef struct {
  *   c_diff  reduced-operator constant (Sec. 3.5, eq. reduced_bound)
  *   dt      time step of vrm_rk_stage
  *   q       highest moment order matched: 2 (5 conditions, paper n = 1) or
- *           3 (9 conditions, paper n = 2) */
+ *           3 (9 conditions, paper n = 2)
+ *   deterministic  0: the update sum_j f_ji Gamma_j is accumulated with FP32
+ *           atomics (fastest; the last bits depend on their order).  1: each
+ *           contribution is rounded to a multiple of 2^(e - 46), max|Gamma^n| <
+ *           2^e, and summed as a 64-bit integer: results are bit-reproducible
+ *           whatever the launch shapes and the order of the atomics. */
 typedef struct {
     double h, nu, r, R, R_full, c_diff, dt;
     int32_t q;
-    int32_t reserved;
+    int32_t deterministic;
 } vrm_params;
 
 /* Stencil output of vrm_solve_fractions, device arrays indexed by particle
@@ -115,6 +133,9 @@ typedef struct {
     int64_t warm_cold;        /* predictions given up by the warm pass (rejected crash basis or more than a
                                  few phase-II pivots): solved by the cold pass (cumulative) */
     int64_t graph_replays;    /* vrm_step stage sequences replayed from the recorded graph (cumulative; host count) */
+    int64_t cert_rounds;      /* certification rounds of the solved LPs (cumulative; 1 per LP when the first
+                                 refinement already proves optimality) */
+    int64_t cert_exact;       /* LPs whose certification needed the double-float dual check (cumulative) */
 } vrm_counters;
 
 /* Create a context on `device` that enqueues on `stream` (a hipStream_t; NULL
@@ -127,10 +148,12 @@ int vrm_destroy(vrm_ctx* ctx);
 /* Sec. 3.5, eq. reduced_bound: choose the diffused set of the step from the
  * current circulations: leave out the particles of smallest |Gamma| while the
  * l1 norm of the left-out ones stays <= c_diff h^(q+1) ||Gamma||_1.  Particles
- * are ranked by |Gamma| truncated to 16 significant bits and whole groups of
- * equal rank are left out together (values equal up to round-off form one
- * group); the sums use the exact |Gamma| in FP64.  Kept in the context (and written to
- * mask_dev[N] as 0/1 when mask_dev != NULL). */
+ * are ranked by their FP32 |Gamma| (the whole 32-bit key; equal keys are left out
+ * together or not at all); the sums are exact FP64 sums of |Gamma|.  With T the
+ * first |Gamma| that does not fit, every particle with |Gamma| >= fl32(T (1 -
+ * 2^-16)) is diffused: circulations equal in exact arithmetic but apart by
+ * round-off stay together (the left-out set only shrinks, so the bound holds).
+ * Kept in the context (and written to mask_dev[N] as 0/1 when mask_dev != NULL). */
 int vrm_select_diffused(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params* p, uint8_t* mask_dev);
 
 /* Replace the context's diffused set with mask_dev[N] (0/1), e.g. to solve
@@ -151,11 +174,11 @@ int vrm_build_neighbourhoods(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_par
  * vrm_select_diffused), inserts a Gamma = 0 particle on the centre line of
  * every empty segment of every diffused particle at radius 1.5 h, resolving
  * conflicts between candidates closer than 0.5 h greedily in (id, segment)
- * order, appends the new particles with ids N, N+1, ... in that order (the
- * cloud's ids are expected to be 0..N-1 in some order), and
- * reorders the whole cloud by cell.  On VRM_E_CAPACITY (detected on the
- * device; reported by the next vrm_read_counters as capacity_needed) the
- * cloud is left unchanged. */
+ * order, appends the new particles with ids M+1, M+2, ... in that order, where
+ * M is the largest id of the cloud (ids must be distinct and non-negative),
+ * and reorders the whole cloud by cell.  On VRM_E_CAPACITY (detected on the
+ * device; reported by the next vrm_read_counters as capacity_needed) or
+ * VRM_E_NONFINITE the cloud is left unchanged.  Synchronises once. */
 int vrm_insert_particles(vrm_ctx* ctx, vrm_cloud* cloud, const vrm_params* p);
 
 /* Sec. 6 (outlook): particle removal.  The moment method applied to the
@@ -223,7 +246,7 @@ int vrm_set_lp_objective(vrm_ctx* ctx, int mode);
  * picks them per workload by timing steps. */
 typedef struct vrm_tuning {
     int32_t lp_small_blocks;     /* most workgroups (256 threads) of the small-LP launch; default 2048 */
-    int32_t lp_full_blocks;      /* most workgroups (64 threads) of the complete-LP launch; default 1024 */
+    int32_t lp_full_blocks;      /* most workgroups (64 threads) of the complete-LP launches; default 2048 */
     int32_t full_stored_cost_n;  /* clouds with N up to this keep complete-LP costs in LDS; default 200000;
                                     -1: never */
     int32_t infer_blocks;        /* most workgroups (256 threads) of the network's inference; default 512 */
@@ -232,7 +255,12 @@ typedef struct vrm_tuning {
                                     column each (shorter chains for latency-bound launches); 0 (default):
                                     one thread per LP.  Warm-start and training-collection passes always use
                                     one thread per LP.  Results are the same either way. */
-    int32_t reserved[2];
+    int32_t cert_rounds;         /* test hook, not a launch shape: repair rounds of an LP's exact
+                                    certification (default 8, at most 64).  An LP still not certified
+                                    after them keeps its basis only if the basis's exact values satisfy
+                                    the moment and sign conditions (counted in n_uncertified); otherwise
+                                    it is handled as infeasible. */
+    int32_t reserved;
 } vrm_tuning;
 /* Set (t = NULL: restore the defaults) or read the launch shapes. */
 int vrm_set_tuning(vrm_ctx* ctx, const vrm_tuning* t);
@@ -250,7 +278,8 @@ int vrm_set_graph(vrm_ctx* ctx, int enable);
 int vrm_verify(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params* p, const vrm_stencils* st,
                double* report_dev);
 
-/* Copy the device counters to *out_host.  Synchronises the stream. */
+/* Copy the device counters to *out_host.  Synchronises the stream.  Returns
+ * VRM_E_NONFINITE (after filling *out_host) if a non-finite value was flagged. */
 int vrm_read_counters(vrm_ctx* ctx, vrm_counters* out_host);
 
 /* Sec. 3.4 eq. (nsode) with the regularised kernel of Sec. 5: the velocity
@@ -338,7 +367,8 @@ int vrm_gemm_bf16(vrm_ctx* ctx, const uint16_t* a_dev, const uint16_t* b_dev, fl
 #define VRM_T_INSERT 5      /* insertion (Sec. 4.2), including its host synchronisations */
 #define VRM_T_COMBINE 6     /* Runge-Kutta stage combination */
 #define VRM_T_MLP 7         /* warm-start network */
-#define VRM_NTIMER 8
+#define VRM_T_FULL_COLS 8   /* complete-neighbourhood column lists and their size bins (q = 3) */
+#define VRM_NTIMER 9
 int vrm_timing(vrm_ctx* ctx, int enable);
 /* The same for the groups whose bit (1 << VRM_T_*) is set in `groups` only:
  * the other groups launch without events (0: timers off). */

@@ -24,8 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libvrm.so")
 
 NSEG = 8
 KMAX = 48
-ST_SMALL, ST_FULL, ST_INFEASIBLE, ST_SKIPPED = 0, 1, 2, 3
-E_ARG, E_CAPACITY, E_HIP, E_STATE = -1, -2, -3, -4
+ST_SMALL, ST_FULL, ST_INFEASIBLE, ST_SKIPPED, ST_WARM = 0, 1, 2, 3, 4
+E_ARG, E_CAPACITY, E_HIP, E_STATE, E_NONFINITE = -1, -2, -3, -4, -5
 
 
 class VrmError(RuntimeError):
@@ -37,15 +37,16 @@ class VrmError(RuntimeError):
 class vrm_params(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("nu", ctypes.c_double), ("r", ctypes.c_double), ("R", ctypes.c_double),
                 ("R_full", ctypes.c_double), ("c_diff", ctypes.c_double), ("dt", ctypes.c_double),
-                ("q", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("q", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 class vrm_tuning(ctypes.Structure):
     _fields_ = [("lp_small_blocks", ctypes.c_int32), ("lp_full_blocks", ctypes.c_int32),
                 ("full_stored_cost_n", ctypes.c_int32), ("infer_blocks", ctypes.c_int32),
-                ("lp_small_lanes", ctypes.c_int32), ("lp_small_coop", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("lp_small_lanes", ctypes.c_int32), ("lp_small_coop", ctypes.c_int32), ("cert_rounds", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
     FIELDS = ("lp_small_blocks", "lp_full_blocks", "full_stored_cost_n", "infer_blocks", "lp_small_lanes",
-              "lp_small_coop")
+              "lp_small_coop", "cert_rounds")
 
 
 class vrm_cloud(ctypes.Structure):
@@ -67,7 +68,7 @@ class vrm_counters(ctypes.Structure):
                 ("pivots", ctypes.c_int64), ("redistributions", ctypes.c_int64),
                 ("capacity_needed", ctypes.c_int32), ("mis_rounds", ctypes.c_int32), ("full_cols", ctypes.c_int64),
                 ("warm_hit", ctypes.c_int64), ("warm_phase2", ctypes.c_int64), ("warm_cold", ctypes.c_int64),
-                ("graph_replays", ctypes.c_int64)]
+                ("graph_replays", ctypes.c_int64), ("cert_rounds", ctypes.c_int64), ("cert_exact", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -81,7 +82,7 @@ EXPORTS = ["vrm_create", "vrm_destroy", "vrm_select_diffused", "vrm_set_diffused
            "vrm_set_warm_start", "vrm_collect_training", "vrm_mlp_train_step", "vrm_mlp_infer", "vrm_gemm_bf16",
            "vrm_last_error", "vrm_status_string"]
 MLP_IN, MLP_OUT, MLP_PARAMS, MLP_SLOTS = 128, 64, 41280, 32
-TIMERS = ["select", "cells", "nbhd", "lp_small", "lp_full", "insert", "combine", "mlp"]
+TIMERS = ["select", "cells", "nbhd", "lp_small", "lp_full", "insert", "combine", "mlp", "full_cols"]
 
 _lib = None
 
@@ -150,14 +151,14 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def make_params(h, nu=0.01, q=2, dt=0.0, r=0.5, R=2.0, R_full=None, c_diff=1.0) -> vrm_params:
+def make_params(h, nu=0.01, q=2, dt=0.0, r=0.5, R=2.0, R_full=None, c_diff=1.0, deterministic=0) -> vrm_params:
     if R_full is None:
         R_full = R if q == 2 else 3.0
-    return vrm_params(h, nu, r, R, R_full, c_diff, dt, q, 0)
+    return vrm_params(h, nu, r, R, R_full, c_diff, dt, q, int(deterministic))
 
 
-def params_of(wl) -> vrm_params:
-    return vrm_params(wl.h, wl.nu, wl.r, wl.R, wl.R_full, wl.c_diff, wl.dt, wl.q, 0)
+def params_of(wl, deterministic=0) -> vrm_params:
+    return vrm_params(wl.h, wl.nu, wl.r, wl.R, wl.R_full, wl.c_diff, wl.dt, wl.q, int(deterministic))
 
 
 class Cloud:

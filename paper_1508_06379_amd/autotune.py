@@ -102,14 +102,14 @@ def tune(name: str, wl, steps: int, sweeps: int = 2, warm_mode: int = 0, log=pri
 
 def main():
     sys.path.insert(0, os.path.dirname(HERE))
-    import bench
+    import workloads
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", required=True, choices=sorted(bench.WORKLOADS))
+    ap.add_argument("--workload", required=True, choices=sorted(workloads.BENCH))
     ap.add_argument("--steps", type=int, default=0, help="timed steps per candidate (0: by workload size)")
     ap.add_argument("--sweeps", type=int, default=2)
     ap.add_argument("--out", default=None, help="output file (default tuning/<workload>.json)")
     args = ap.parse_args()
-    wl = bench.WORKLOADS[args.workload]()
+    wl = workloads.BENCH[args.workload]()
     steps = args.steps or (20 if wl.n < 200000 else (4 if wl.n < 5_000_000 else 1))
     res = tune(args.workload, wl, steps, args.sweeps, log=lambda m: print(m, flush=True))
     out = args.out or tuning_path(args.workload)

@@ -44,6 +44,8 @@ vrm::LaunchParams launch_params(const vrm_ctx* c, const vrm_params* p)
     L.sc = (float)s;
     L.q = p->q;
     L.m = p->q == 2 ? 5 : 9;
+    L.det = p->deterministic;
+    L.max_cert = c->tuning.cert_rounds > 0 ? c->tuning.cert_rounds : vrm::kMaxCert;
     return L;
 }
 
@@ -59,6 +61,8 @@ int check_params(const vrm_params* p)
     if (!(p->nu >= 0.0) || !std::isfinite(p->nu)) return vrm_fail(VRM_E_ARG, "nu must be >= 0");
     if (!(p->c_diff >= 0.0) || !std::isfinite(p->c_diff)) return vrm_fail(VRM_E_ARG, "c_diff must be >= 0");
     if (!(p->dt >= 0.0) || !std::isfinite(p->dt)) return vrm_fail(VRM_E_ARG, "dt must be >= 0");
+    if (p->deterministic != 0 && p->deterministic != 1)
+        return vrm_fail(VRM_E_ARG, "deterministic must be 0 or 1 (got %d)", p->deterministic);
     return VRM_OK;
 }
 
@@ -112,7 +116,22 @@ __global__ void k_copy_mask(int n, const uint8_t* in, uint8_t* out)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = in[i] ? 1 : 0;
 }
+
+__global__ void k_clear_bad(vrm::GridState* g) { g->bad = 0; }
 }  // namespace
+
+int vrm_nonfinite(vrm_ctx* c, int32_t bits)
+{
+    hipLaunchKernelGGL(k_clear_bad, dim3(1), dim3(1), 0, c->stream, c->grid);
+    c->cells_valid = 0;
+    c->sorted = 0;
+    c->n_diffused_valid = 0;
+    c->base_valid = 0;
+    (void)hipGetLastError();
+    return vrm_fail(VRM_E_NONFINITE, "non-finite %s%s%s in the cloud; it was left unchanged",
+                    (bits & vrm::kBadPos) ? "position" : "", (bits & vrm::kBadPos) && (bits & vrm::kBadGamma) ? " and " : "",
+                    (bits & vrm::kBadGamma) ? "circulation" : "");
+}
 
 int vrm_fail(int code, const char* fmt, ...)
 {
@@ -142,6 +161,7 @@ const char* vrm_status_string(int code)
     case VRM_E_CAPACITY: return "capacity exceeded";
     case VRM_E_HIP: return "HIP runtime error";
     case VRM_E_STATE: return "invalid call order";
+    case VRM_E_NONFINITE: return "non-finite position or circulation";
     default: return "unknown";
     }
 }
@@ -178,7 +198,7 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
     A(ys, cap);
     A(ids, cap);
     A(diffused, cap);
-    A(acc, cap);
+    A(acc, 2 * cap);
     A(x0, cap);
     A(y0, cap);
     A(g0, cap);
@@ -204,6 +224,10 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
     A(tmp_i, cap);
     A(tmp_u8, cap);
     A(verify_buf, 8);
+    A(full_cols, cap * VRM_KMAX);
+    A(full_k, cap);
+    A(full_order, cap);
+    A(khist, 2 * (VRM_KMAX + 1));
 #undef A
     if (r == VRM_OK) {
         c->sort_tmp_bytes = std::max(vrm_sort_tmp_bytes(capacity), vrm_remove_tmp_bytes(capacity));
@@ -220,10 +244,12 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
         if (c->q_host) std::memset(c->q_host, 0, sizeof(vrm::HostQueues));
     }
     if (r == VRM_OK) {
-        hipError_t e = hipMemsetAsync(c->acc, 0, cap * sizeof(float), c->stream);
+        hipError_t e = hipMemsetAsync(c->acc, 0, 2 * cap * sizeof(float), c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->counters, 0, vrm::kCounterStripes * vrm::kCounterStride, c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->queues, 0, sizeof(vrm::Queues), c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->sel, 0, sizeof(vrm::SelectState), c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->grid, 0, sizeof(vrm::GridState), c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->khist, 0, 2 * (VRM_KMAX + 1) * sizeof(int32_t), c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) r = vrm_hip_check(e, "initialisation");
     }
@@ -245,7 +271,8 @@ int vrm_destroy(vrm_ctx* c)
     void* ptrs[] = {c->grid, c->queues, c->sel, c->counters, c->cell_of, c->rank, c->cell_start, c->scan_part,
                     c->perm, c->xs, c->ys, c->ids, c->diffused, c->acc, c->x0, c->y0, c->g0, c->q_small, c->q_full, c->q_retry,
                     c->srec.i, c->srec.rank, c->srec.pj, c->srec.off, c->cx, c->cy, c->ckey, c->cstate, c->ccell, c->crank, c->cstart, c->cperm,
-                    c->akey, c->aidx, c->tmp_f, c->tmp_i, c->tmp_u8, c->verify_buf, c->sort_tmp};
+                    c->akey, c->aidx, c->tmp_f, c->tmp_i, c->tmp_u8, c->verify_buf, c->sort_tmp, c->full_cols,
+                    c->full_k, c->full_order, c->khist};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->q_host) (void)hipHostFree(c->q_host);
@@ -280,7 +307,7 @@ int vrm_select_diffused(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, ui
     double factor = p->c_diff * std::pow(p->h, p->q + 1);
     {
         vrm::ScopedTimer tm(c, VRM_T_SELECT);
-        r = vrm_select_run(c, cl->gamma_dev, c->n, factor);
+        r = vrm_select_run(c, cl->gamma_dev, cl->id_dev, c->n, factor);
     }
     if (r) return r;
     if (mask_dev && c->n > 0) {
@@ -330,7 +357,7 @@ int vrm_insert_particles(vrm_ctx* c, vrm_cloud* cl, const vrm_params* p)
     double factor = p->c_diff * std::pow(p->h, p->q + 1);
     {
         vrm::ScopedTimer tm(c, VRM_T_SELECT);
-        r = vrm_select_run(c, cl->gamma_dev, c->n, factor);
+        r = vrm_select_run(c, cl->gamma_dev, cl->id_dev, c->n, factor);
     }
     if (r) return r;
     // the cell list of the last reorder is still valid if nothing moved since
@@ -429,7 +456,7 @@ int stage_launch(vrm_ctx* c, vrm_cloud* cl, const float* u_dev, const float* v_d
     int r;
     vrm::LaunchParams L = launch_params(c, p);
     if (stage == 0) {
-        r = vrm_save_base_run(c, cl, nb);
+        r = vrm_save_base_run(c, cl, nb, L.det);
         if (r) return r;
         c->base_valid = 1;
     }
@@ -441,7 +468,7 @@ int stage_launch(vrm_ctx* c, vrm_cloud* cl, const float* u_dev, const float* v_d
     r = vrm_stencil_run(c, cl, nb, L, nullptr, 1);
     if (!r) {
         vrm::ScopedTimer tm(c, VRM_T_COMBINE);
-        r = vrm_combine_run(c, cl, nb, u_dev, v_dev, p->dt, L.lam, stage);
+        r = vrm_combine_run(c, cl, nb, u_dev, v_dev, p->dt, L.lam, stage, L.det);
     }
     if (r) return r;
     if (u_dev) {
@@ -546,7 +573,7 @@ int vrm_set_tuning(vrm_ctx* c, const vrm_tuning* t)
     if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
     vrm_tuning d{};
     d.lp_small_blocks = 2048;
-    d.lp_full_blocks = 1024;
+    d.lp_full_blocks = 2048;
     d.full_stored_cost_n = 200000;
     d.infer_blocks = 512;
     d.lp_small_lanes = 64;
@@ -565,6 +592,9 @@ int vrm_set_tuning(vrm_ctx* c, const vrm_tuning* t)
         if (t->lp_small_coop != 0 && t->lp_small_coop != 1)
             return vrm_fail(VRM_E_ARG, "lp_small_coop must be 0 or 1 (got %d)", t->lp_small_coop);
         d.lp_small_coop = t->lp_small_coop;
+        if (t->cert_rounds < 0 || t->cert_rounds > 64)
+            return vrm_fail(VRM_E_ARG, "cert_rounds must be in [0, 64] (got %d)", t->cert_rounds);
+        d.cert_rounds = t->cert_rounds;
     }
     c->tuning = d;
     return VRM_OK;
@@ -674,7 +704,7 @@ int vrm_verify(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, const vrm_s
     if (!r && c->n_ptr != cl->n_dev) r = read_n(c, cl);
     if (r) return r;
     vrm::LaunchParams L = launch_params(c, p);
-    return vrm_verify_run(c, cl, c->n, L, st, report_dev);
+    return vrm_verify_run(c, cl, c->n, L, p->h, st, report_dev);
 }
 
 int vrm_read_counters(vrm_ctx* c, vrm_counters* out)
@@ -682,7 +712,9 @@ int vrm_read_counters(vrm_ctx* c, vrm_counters* out)
     if (!c || !out) return vrm_fail(VRM_E_ARG, "NULL argument");
     // the copies of the counters: accumulated fields are summed, assigned ones are in copy 0
     static thread_local char buf[vrm::kCounterStripes * vrm::kCounterStride];
+    int32_t bad = 0;
     VRM_HIP(hipMemcpyAsync(buf, c->counters, sizeof(buf), hipMemcpyDeviceToHost, c->stream));
+    VRM_HIP(hipMemcpyAsync(&bad, &c->grid->bad, sizeof(bad), hipMemcpyDeviceToHost, c->stream));
     VRM_HIP(hipStreamSynchronize(c->stream));
     *out = *reinterpret_cast<const vrm_counters*>(buf);
     for (int k = 1; k < vrm::kCounterStripes; ++k) {
@@ -700,9 +732,12 @@ int vrm_read_counters(vrm_ctx* c, vrm_counters* out)
         out->warm_hit += s.warm_hit;
         out->warm_phase2 += s.warm_phase2;
         out->warm_cold += s.warm_cold;
+        out->cert_rounds += s.cert_rounds;
+        out->cert_exact += s.cert_exact;
     }
     out->n = c->n;
     out->graph_replays = c->graph_replays;
+    if (bad) return vrm_nonfinite(c, bad);
     return VRM_OK;
 }
 

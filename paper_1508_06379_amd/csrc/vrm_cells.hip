@@ -22,6 +22,7 @@ constexpr int kScanBlocks = 512;
 
 __global__ void k_grid_reset(GridState* g)
 {
+    g->bad &= ~kBadPos;
     g->bbox[0] = 0xffffffffu;
     g->bbox[1] = 0xffffffffu;
     g->bbox[2] = 0u;
@@ -33,9 +34,13 @@ __global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ x, const
 {
     if (n_dev) n = *n_dev;
     uint32_t mnx = 0xffffffffu, mny = 0xffffffffu, mxx = 0u, mxy = 0u;
+    bool bad = false;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float xv = x[i], yv = y[i];
-        if (!(fabsf(xv) <= 3.0e38f) || !(fabsf(yv) <= 3.0e38f)) continue;   // skip non-finite
+        if (!(fabsf(xv) <= 3.4028235e38f) || !(fabsf(yv) <= 3.4028235e38f)) {
+            bad = true;   // NaN or infinite: reported, never given a cell
+            continue;
+        }
         uint32_t kx = ordered_key(xv), ky = ordered_key(yv);
         mnx = min(mnx, kx);
         mny = min(mny, ky);
@@ -70,6 +75,7 @@ __global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ x, const
         atomicMax(&g->bbox[2], mxx);
         atomicMax(&g->bbox[3], mxy);
     }
+    if (__any(bad) && lane_id() == 0) atomicOr(&g->bad, kBadPos);
 }
 
 __global__ void k_grid_params(GridState* g, float cs, int ncell_cap, vrm_counters* cnt)
@@ -127,6 +133,7 @@ __global__ __launch_bounds__(256) void k_count(const float* __restrict__ x, cons
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     GridState g = *gs;
+    if (g.bad & kBadPos) return;   // a non-finite position: no cell indices
     int c = cell_index(g, x[i], y[i]);
     cell_of[i] = c;
     rank[i] = atomicAdd(&start[c], 1);
@@ -199,11 +206,11 @@ __global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ x, co
                                                  const int32_t* __restrict__ n_dev,
                                                  const int32_t* __restrict__ start, const int32_t* __restrict__ cell_of,
                                                  const int32_t* __restrict__ rank, int32_t* perm, float* xs, float* ys,
-                                                 int32_t* ids)
+                                                 int32_t* ids, const GridState* gs)
 {
     if (n_dev) n = *n_dev;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (gs->bad & kBadPos)) return;
     int t = start[cell_of[i]] + rank[i];
     perm[t] = i;
     if (xs) {
@@ -223,15 +230,16 @@ int scan_cells(vrm_ctx* c, int32_t* start)
 }
 
 // ------------------------------------------------------ reduced operator
-// Ranking key: |Gamma| truncated to 16 significant bits, so circulations that
-// are equal up to round-off form one group (whole groups are left out).
-__device__ __forceinline__ uint32_t selection_key(float a) { return __float_as_uint(a) & 0xffffff00u; }
+// Ranking key (Sec. 3.5): the bits of |Gamma| in FP32, monotone in the value
+// for non-negative floats; particles with equal keys form one group, left out
+// together.  Four 8-bit radix passes resolve the whole key.
+__device__ __forceinline__ uint32_t selection_key(float a) { return __float_as_uint(a); }
 
 // also zeroes the diffused count of every counter copy (k_sel_mask adds to it)
-__global__ void k_sel_init(SelectState* s, vrm_counters* cnt)
+__global__ void k_sel_init(SelectState* s, vrm_counters* cnt, GridState* gs)
 {
     int t = threadIdx.x;
-    if (t < kCounterStripes)
+    if (cnt && t < kCounterStripes)
         reinterpret_cast<vrm_counters*>(reinterpret_cast<char*>(cnt) + t * kCounterStride)->n_diffused = 0;
     if (t == 0) {
         s->norm1 = 0.0;
@@ -240,28 +248,48 @@ __global__ void k_sel_init(SelectState* s, vrm_counters* cnt)
         s->key_prefix = 0u;
         s->done = 0u;
         s->threshold = 0u;
+        s->max_id = -1;
+        gs->bad &= ~kBadGamma;
     }
     s->bin_sum[t] = 0.0;
     s->bin_cnt[t] = 0u;
 }
 
-__global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ g, int n, SelectState* s, int shift)
+// One radix pass.  A bin holds FP32 values that share at least the top seven
+// bits of their exponent, i.e. values in [2^E, 2^(E+2)) that are multiples of
+// 2^(E-23); up to 2^26 of them sum to below 2^(E+28), a multiple of 2^(E-23)
+// with at most 51 significant bits, so every FP64 bin sum is exact and does
+// not depend on the order of the atomics.  The first pass also finds non-finite
+// circulations (kBadGamma) and the largest id.
+__global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ g, const int32_t* __restrict__ ids, int n,
+                                                  SelectState* s, int shift, GridState* gs)
 {
     __shared__ double h_sum[256];
     __shared__ uint32_t h_cnt[256];
     h_sum[threadIdx.x] = 0.0;
     h_cnt[threadIdx.x] = 0u;
     __syncthreads();
+    bool bad = false;
+    int mid = -1;
     if (!s->done) {
         uint32_t pre = s->key_prefix;
         for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
             float a = fabsf(g[i]);
             uint32_t key = selection_key(a);
+            if (shift == 24) {
+                bad = bad || key >= 0x7f800000u;
+                if (ids) mid = max(mid, ids[i]);
+            }
             if (shift < 24 && (key >> (shift + 8)) != (pre >> (shift + 8))) continue;
             int b = (key >> shift) & 255u;
             atomicAdd(&h_sum[b], (double)a);
             atomicAdd(&h_cnt[b], 1u);
         }
+    }
+    if (shift == 24) {
+        for (int o = 32; o > 0; o >>= 1) mid = max(mid, __shfl_xor(mid, o, VRM_WAVE));
+        if (lane_id() == 0 && mid >= 0) atomicMax(&s->max_id, mid);
+        if (__any(bad) && lane_id() == 0) atomicOr(&gs->bad, kBadGamma);
     }
     __syncthreads();
     if (h_cnt[threadIdx.x]) {
@@ -314,7 +342,7 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelectState* s, int shift, dou
             s->done = top > 0xffffffffull ? 2u : 1u;
         } else {
             s->key_prefix |= (uint32_t)b << shift;
-            if (shift == 8) {
+            if (shift == 0) {
                 s->threshold = s->key_prefix;
                 s->done = 1u;
             }
@@ -327,20 +355,27 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelectState* s, int shift, dou
     s->bin_cnt[t] = 0u;
 }
 
+// Diffused: |Gamma| >= fl32(T (1 - 2^-16)), T the first key that does not fit:
+// the particle that reaches the bound and every particle within a relative
+// 2^-16 below it are diffused (circulations equal in exact arithmetic differ by
+// round-off once computed: 2^-16 covers the stated 1e-5 per-value bound and the
+// random-walk round-off of FP32 circulations over 10^2 SSP-RK3 steps).
+constexpr float kTieBand = 0.9999847412109375f;   // 1 - 2^-16
+
 __global__ __launch_bounds__(256) void k_sel_mask(const float* __restrict__ g, int n, const SelectState* s,
                                                   uint8_t* diffused, uint8_t* mask_out, vrm_counters* cnt)
 {
-    cnt = counter_stripe(cnt);
+    if (cnt) cnt = counter_stripe(cnt);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool d = false;
+    const float band = __uint_as_float(s->threshold) * kTieBand;
     if (i < n) {
-        uint32_t key = selection_key(fabsf(g[i]));
-        d = s->done == 2u ? false : key >= s->threshold;
+        d = s->done == 2u ? false : fabsf(g[i]) >= band;
         diffused[i] = d ? 1 : 0;
         if (mask_out) mask_out[i] = d ? 1 : 0;
     }
     uint64_t m = __ballot(d);
-    if (lane_id() == 0 && m) atomicAdd(&cnt->n_diffused, __popcll(m));
+    if (cnt && lane_id() == 0 && m) atomicAdd(&cnt->n_diffused, __popcll(m));
 }
 
 // one thread per counter copy
@@ -365,7 +400,7 @@ __global__ __launch_bounds__(256) void k_candidates(int n, const int32_t* __rest
     const int t = blockIdx.x * (256 / L) + threadIdx.x / L;
     int occupied = 0xff;
     float xi = 0.0f, yi = 0.0f;
-    if (t < n && diffused[perm[t]]) {
+    if (t < n && !gs->bad && diffused[perm[t]]) {
         occupied = 0;
         GridState g = *gs;
         xi = xs[t];
@@ -489,9 +524,13 @@ __global__ __launch_bounds__(256) void k_accepted(int nc, const uint64_t* __rest
     }
 }
 
+// New particles get ids max_id + 1, max_id + 2, ... in key order (the largest
+// id of the cloud is found by the selection's first pass), so ids stay unique
+// after particles were removed.
 __global__ __launch_bounds__(256) void k_append(int n0, int na, const int32_t* __restrict__ aidx_sorted,
                                                 const float* __restrict__ cx, const float* __restrict__ cy, float* x,
-                                                float* y, float* gamma, int32_t* id, uint8_t* diffused, int32_t* n_dev)
+                                                float* y, float* gamma, int32_t* id, uint8_t* diffused, int32_t* n_dev,
+                                                const SelectState* sel)
 {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r == 0) *n_dev = n0 + na;
@@ -500,7 +539,7 @@ __global__ __launch_bounds__(256) void k_append(int n0, int na, const int32_t* _
     x[n0 + r] = cx[a];
     y[n0 + r] = cy[a];
     gamma[n0 + r] = 0.0f;
-    id[n0 + r] = n0 + r;
+    id[n0 + r] = sel->max_id + 1 + r;
     diffused[n0 + r] = 0;
 }
 
@@ -515,7 +554,7 @@ __global__ __launch_bounds__(1024) void k_insert_small(int n0, int capacity, int
                                                        const float* __restrict__ cx, const float* __restrict__ cy,
                                                        const uint64_t* __restrict__ ckey, float ex2, float* x, float* y,
                                                        float* gamma, int32_t* id, uint8_t* diffused, int32_t* n_dev,
-                                                       Queues* qs, vrm_counters* cnt)
+                                                       Queues* qs, vrm_counters* cnt, const SelectState* sel)
 {
     __shared__ uint64_t key[kInsSmallMax];
     __shared__ int32_t src[kInsSmallMax];
@@ -593,12 +632,13 @@ __global__ __launch_bounds__(1024) void k_insert_small(int n0, int capacity, int
         }
         return;
     }
+    const int id0 = sel->max_id + 1;
     for (int r = t; r < na; r += blockDim.x) {
         int a = asrc[r];
         x[n0 + r] = cx[a];
         y[n0 + r] = cy[a];
         gamma[n0 + r] = 0.0f;
-        id[n0 + r] = n0 + r;
+        id[n0 + r] = id0 + r;
         diffused[n0 + r] = 0;
     }
     if (t == 0) {
@@ -661,10 +701,11 @@ int blocks_for(int n) { return n > 0 ? (n + 255) / 256 : 1; }
 
 // One thread copies the queue record to the host copy, then writes the
 // sequence number with a system-scope release (after a system fence).
-__global__ void k_publish_queues(const Queues* q, HostQueues* h, int32_t seq)
+__global__ void k_publish_queues(const Queues* q, const GridState* g, HostQueues* h, int32_t seq)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         h->q = *q;
+        h->q.nonfinite = g->bad;
         __threadfence_system();
         __hip_atomic_store(&h->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
@@ -678,7 +719,7 @@ __global__ void k_publish_queues(const Queues* q, HostQueues* h, int32_t seq)
 int vrm_read_queues(vrm_ctx* c, Queues& q)
 {
     const int32_t seq = ++c->q_seq;
-    hipLaunchKernelGGL(k_publish_queues, dim3(1), dim3(64), 0, c->stream, c->queues, c->q_host, seq);
+    hipLaunchKernelGGL(k_publish_queues, dim3(1), dim3(64), 0, c->stream, c->queues, c->grid, c->q_host, seq);
     VRM_HIP(hipGetLastError());
     for (uint64_t k = 1;; ++k) {
         if (__atomic_load_n(&c->q_host->seq, __ATOMIC_ACQUIRE) == seq) break;
@@ -716,20 +757,20 @@ int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* i
     if (r) return r;
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(256), 0, s, x, y, id, n, n_dev, c->cell_start,
-                           c->cell_of, c->rank, c->perm, c->xs, c->ys, c->ids);
+                           c->cell_of, c->rank, c->perm, c->xs, c->ys, c->ids, c->grid);
     }
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }
 
-int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double factor)
+int vrm_select_run(vrm_ctx* c, const float* gamma, const int32_t* ids, int32_t n, double factor)
 {
     hipStream_t s = c->stream;
     static_assert(kCounterStripes <= 256, "k_sel_init zeroes one counter copy per thread");
-    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c->sel, c->counters);
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c->sel, c->counters, c->grid);
     int nb = min(2048, blocks_for(n));
-    for (int shift = 24; shift >= 8; shift -= 8) {   // the ranking key has no bits below 8
-        if (n > 0) hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, s, gamma, n, c->sel, shift);
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        if (n > 0) hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, s, gamma, ids, n, c->sel, shift, c->grid);
         hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, c->sel, shift, factor);
     }
     if (n > 0)
@@ -755,10 +796,11 @@ int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp)
     if (n > 0)
         hipLaunchKernelGGL(k_insert_small, dim3(1), dim3(1024), 0, s, n, cl->capacity, cand_cap, c->cx, c->cy, c->ckey,
                            lp.ex2, cl->x_dev, cl->y_dev, cl->gamma_dev, cl->id_dev, c->diffused, cl->n_dev, c->queues,
-                           c->counters);
+                           c->counters, c->sel);
     VRM_HIP(hipGetLastError());
     Queues q;
     if (int r = vrm_read_queues(c, q)) return r;
+    if (q.nonfinite) return vrm_nonfinite(c, q.nonfinite);
     if (q.small_state == 2)
         return vrm_fail(VRM_E_CAPACITY, "insertion needs %d particles, capacity is %d", n + q.n_accepted,
                         cl->capacity);
@@ -777,7 +819,7 @@ int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp)
         if (r) return r;
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nc)), dim3(256), 0, s, c->cx, c->cy, (const int32_t*)nullptr,
                            nc, (const int32_t*)nullptr, c->cstart, c->ccell, c->crank, c->cperm, (float*)nullptr,
-                           (float*)nullptr, (int32_t*)nullptr);
+                           (float*)nullptr, (int32_t*)nullptr, c->grid);
         VRM_HIP(hipGetLastError());
         for (;;) {
             const int batch = 4;
@@ -813,7 +855,7 @@ int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp)
             int32_t* vsorted = c->tmp_i;
             VRM_HIP(rocprim::radix_sort_pairs(c->sort_tmp, bytes, kin, ksorted, vin, vsorted, (size_t)na, 0, 35, s));
             hipLaunchKernelGGL(k_append, dim3(blocks_for(na)), dim3(256), 0, s, n, na, vsorted, c->cx, c->cy, cl->x_dev,
-                               cl->y_dev, cl->gamma_dev, cl->id_dev, c->diffused, cl->n_dev);
+                               cl->y_dev, cl->gamma_dev, cl->id_dev, c->diffused, cl->n_dev, c->sel);
             VRM_HIP(hipGetLastError());
         }
     }

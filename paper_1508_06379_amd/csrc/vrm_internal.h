@@ -56,7 +56,15 @@ struct GridState {
     uint32_t bbox[4];      // ordered keys: min x, min y, max x, max y
     float x0, y0, cs, inv_cs;
     int32_t nx, ny, ncells, clamped;
+    // kBadPos: a position the last cell build read was not finite; kBadGamma: a
+    // circulation the last selection or stage-0 copy read was not finite.  While
+    // either bit is set no cell index is formed and no kernel changes the cloud.
+    int32_t bad;
+    // bits of max |Gamma^n| (stage 0): scale of the fixed-point accumulation
+    uint32_t gmax_bits;
 };
+constexpr int32_t kBadPos = 1;
+constexpr int32_t kBadGamma = 2;
 
 // Queue counters of a stage (device side).
 struct Queues {
@@ -72,6 +80,8 @@ struct Queues {
     int32_t last_full;     // themselves are zero between runs)
     int32_t n_removed;     // particle removal: particles removed by the last call
     int32_t n_rm_uncertified;   // ... of which optimality was not certified
+    int32_t nonfinite;     // copy of GridState::bad taken when the record is published
+    int32_t pad;
 };
 
 // Queue record published to pinned, coherent host memory: the kernel writes q,
@@ -99,7 +109,7 @@ struct SelectState {
     uint32_t key_prefix;   // resolved high bits of the threshold key
     uint32_t done;         // 1 once the threshold is known
     uint32_t threshold;    // particles with key < threshold are left out
-    uint32_t pad;
+    int32_t max_id;        // largest id of the cloud (new particles get max_id + 1, ...)
     double bin_sum[256];
     uint32_t bin_cnt[256];
 };
@@ -114,7 +124,31 @@ struct LaunchParams {
     float sc;                            // 2^e / h: scaled offset -> offset / h
     int q, m;
     int phase1;                          // 1: stop at the first feasible vertex (phase I only)
+    int det;                             // 1: order-independent fixed-point accumulation of the update
+    int max_cert;                        // certification rounds of one LP (kMaxCert unless tuned)
 };
+constexpr int kMaxCert = 8;              // certification rounds: primal / dual repairs of one LP
+
+// Fixed-point accumulation (deterministic mode): every contribution f Gamma is
+// rounded to a multiple of 2^(e - 46), where max |Gamma^n| < 2^e, and summed as
+// a 64-bit integer, so the sum does not depend on the order of the atomics and
+// particles with equal contributions get bit-identical sums.  A fraction is at
+// most 16 (Sec. 3.2 lemma: sum_{j != i} fhat_ij <= 4 / r^2), a stage value at
+// most 4 max|Gamma^n|, and a particle receives at most 2^10 contributions, so
+// every scaled sum stays below 2^62 in magnitude.
+__device__ __forceinline__ double det_scale(uint32_t gmax_bits)
+{
+    const int e = (int)((gmax_bits >> 23) & 255u) - 126;   // max|Gamma| < 2^e
+    return __builtin_ldexp(1.0, 46 - e);
+}
+__device__ __forceinline__ void acc_add(float* acc, int j, float f, float g, double dsc)
+{
+    if (dsc != 0.0)
+        atomicAdd(reinterpret_cast<unsigned long long*>(acc) + j,
+                  (unsigned long long)(long long)__builtin_rint((double)f * (double)g * dsc));
+    else
+        atomicAdd(acc + j, f * g);
+}
 
 }  // namespace vrm
 
@@ -149,7 +183,7 @@ struct vrm_ctx {
     float* ys;
     int32_t* ids;         // [cap] ids in slot order
     uint8_t* diffused;    // [cap] per particle
-    float* acc;           // [cap] sum_j fhat_ji Gamma_j
+    float* acc;           // [2 cap] sum_j fhat_ji Gamma_j (FP32, or int64 fixed point when deterministic)
     float* x0;            // [cap] stage-0 state
     float* y0;
     float* g0;
@@ -208,7 +242,10 @@ struct vrm_ctx {
     uint16_t* feat;       // [cap][128] feature rows of the queued LPs (warm start / collection)
     float* pred;          // [cap][64] network outputs
     float* labels;        // [cap][64] collection targets
-    int32_t* full_cols;   // [cap][48] complete-neighbourhood columns sorted by (d2, id)
+    int32_t* full_cols;   // [cap][48] complete-neighbourhood columns nearest first: (slot << 6) | id rank
+    int32_t* full_k;      // [cap] their counts, by queue item
+    int32_t* full_order;  // [cap] queue items grouped by decreasing count
+    int32_t* khist;       // [2 (VRM_KMAX + 1)] histogram of the counts, then the bins' fill pointers
     int32_t feat_cap;
 };
 
@@ -244,7 +281,7 @@ struct ScopedTimer {
 // launchers (vrm_cells.hip)
 int vrm_build_cells(vrm_ctx* c, const float* x, const float* y, const int32_t* id, int32_t n,
                     const vrm::LaunchParams& lp, const int32_t* n_dev = nullptr);
-int vrm_select_run(vrm_ctx* c, const float* gamma, int32_t n, double bound_factor);
+int vrm_select_run(vrm_ctx* c, const float* gamma, const int32_t* ids, int32_t n, double bound_factor);
 int vrm_insert_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp);
 // the queue record after the work enqueued so far on the context's stream,
 // read from the pinned host copy (no stream synchronisation)
@@ -260,10 +297,10 @@ int vrm_small_nbhd_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::La
                        int32_t* small_idx, int32_t* kfull);
 // launchers (vrm_stage.hip)
 int vrm_combine_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const float* u, const float* v, double dt,
-                    float lam, int stage);
-int vrm_save_base_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n);
+                    float lam, int stage, int det);
+int vrm_save_base_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, int det);
 int vrm_biot_savart_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, double eps, float* u, float* v);
-int vrm_verify_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp,
+int vrm_verify_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp, double h,
                    const vrm_stencils* st, double* report);
 int vrm_velocity_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const float* vort, int32_t nv, double nu,
                      double t, float* u, float* v, const double* t_dev = nullptr);
@@ -285,6 +322,9 @@ int vrm_gemm_test(vrm_ctx* c, const uint16_t* A, const uint16_t* B, float* C, in
 
 // error helpers (vrm_api.cpp)
 int vrm_fail(int code, const char* fmt, ...);
+// report a non-finite input (GridState::bad bits): clears the device flag and
+// drops the context's cached cell list and diffused set; returns VRM_E_NONFINITE
+int vrm_nonfinite(vrm_ctx* c, int32_t bits);
 int vrm_hip_check(hipError_t e, const char* what);
 #define VRM_HIP(call)                                                    \
     do {                                                                 \

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_small_nbhd(int n, const int32_t* __rest
     if (n_dev) n = *n_dev;
     const int tid = threadIdx.x;
     int t = blockIdx.x * blockDim.x + tid;
-    bool active = t < n;
+    bool active = t < n && !gs->bad;   // no cell list while a value is not finite
     int i = active ? perm[t] : 0;
     bool dif = active && diffused[i];
     int best[VRM_NSEG];
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_small_nbhd_coop(int n, const int32_t* _
     if (n_dev) n = *n_dev;
     const int tid = threadIdx.x, sub = tid & (kNbL - 1);
     const int t = blockIdx.x * (256 / kNbL) + tid / kNbL;
-    const bool active = t < n;
+    const bool active = t < n && !gs->bad;   // no cell list while a value is not finite
     const int i = active ? perm[t] : 0;
     const bool dif = active && diffused[i];
     int kfull = 0;
@@ -359,6 +359,7 @@ struct StencilOut {
     int max_rows;
     const float* pred;   // warm start: small LPs 8 logits, complete ones kMlpOut outputs per queue item; or NULL
     int32_t* prev;       // basis (column ids) of each particle's last stencil, [id][kPrevIds]: recorded if non-NULL
+    int prev_cap;        // rows of prev: particles with larger ids keep no basis (they start cold)
     int use_prev;        // warm start from prev instead of pred
     const int32_t* cloud_id;   // ids by cloud index
 };
@@ -482,6 +483,10 @@ struct LdsColsT {
     const LaunchParams* P;
     float* sxlo;   // low parts of the exact scaled offsets (hi parts are srx, sry), or NULL:
     float* sylo;   // then the exact offsets are recomputed from the positions
+    static constexpr int kLds = 64;
+    __device__ __forceinline__ int active() const { return k; }
+    __device__ __forceinline__ bool widen() const { return false; }
+    __device__ __forceinline__ void load_lds(int j, float& x, float& y, uint32_t& aux) const { load(j, x, y, aux); }
     __device__ __forceinline__ void get(int j, float& x, float& y, float& cc) const
     {
         x = srx[j * BLK + tid];
@@ -563,6 +568,8 @@ struct CoopCols {
     mutable int cj;                // column whose values the last pick left in cx, cy, cc
     mutable float cx, cy, cc;
 
+    __device__ __forceinline__ int active() const { return k; }
+    __device__ __forceinline__ bool widen() const { return false; }
     __device__ __forceinline__ static float lane_f(float v, int src) { return __shfl(v, src, 64); }
     __device__ __forceinline__ static int lane_i(int v, int src) { return __shfl(v, src, 64); }
     __device__ __forceinline__ void get(int j, float& rx, float& ry, float& cost) const
@@ -644,7 +651,8 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
                                                           const int32_t* __restrict__ q_small, Queues* qs,
                                                           int32_t* q_full, const float* __restrict__ gamma,
                                                           float* acc, LaunchParams P, StencilOut out, int apply,
-                                                          vrm_counters* cnt, int mode, int32_t* q_retry, int lanes)
+                                                          vrm_counters* cnt, int mode, int32_t* q_retry, int lanes,
+                                                          const GridState* gs)
 {
     __shared__ float s_rx[8 * kSmallBlock];
     __shared__ float s_ry[8 * kSmallBlock];
@@ -661,6 +669,7 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
     const int wave = (blockIdx.x * blockDim.x + tid) >> 6, lane = tid & 63;
     const int stride = ((gridDim.x * blockDim.x) >> 6) * lanes;
     const int loops = (nitems + stride - 1) / stride;
+    const double dsc = P.det && apply ? det_scale(gs->gmax_bits) : 0.0;
     for (int it = 0; it < loops; ++it) {
         const int item = wave * lanes + lane + it * stride;
         const bool live = lane < lanes && item < nitems;
@@ -717,7 +726,7 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
             };
             uint64_t pref = 0;
             if (warm_pass && out.use_prev) {
-                pref = prev_mask(out.prev, own, 8, col_id);
+                pref = (unsigned)own < (unsigned)out.prev_cap ? prev_mask(out.prev, own, 8, col_id) : 0ull;
             } else if (warm_pass) {
                 const float4* lg4 = reinterpret_cast<const float4*>(out.pred + (size_t)r * VRM_NSEG);
                 const float4 a = lg4[0], b = lg4[1];
@@ -727,7 +736,7 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
             uint64_t basis = 0;
             st = solve_lp<5, PH1>(cs, P, store, fii, piv, certified, warm_pass, nullptr, warm, basis,
                              warm_pass && out.use_prev, pref);
-            if (st == 0 && out.prev) record_basis(out.prev, own, basis, col_id);
+            if (st == 0 && out.prev && (unsigned)own < (unsigned)out.prev_cap) record_basis(out.prev, own, basis, col_id);
             if (record) {
                 float* lab = out.lab + (size_t)item * kMlpOut;
 #pragma unroll
@@ -743,16 +752,16 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
                 for (int s = 0; s < 8; ++s) {
                     bool alive = !((dead >> s) & 1ull);
                     int pj = alive ? (int)((unsigned)s_meta[s * kSmallBlock + tid] >> 6) : -1;
-                    if (apply && fv[s] != 0.0f) atomicAdd(&acc[pj], fv[s] * g);
+                    if (apply && fv[s] != 0.0f) acc_add(acc, pj, fv[s], g, dsc);
                     if (out.small_f) {
                         out.small_idx[(size_t)i * VRM_NSEG + s] = pj;
                         out.small_f[(size_t)i * VRM_NSEG + s] = fv[s];
                     }
                 }
-                if (apply) atomicAdd(&acc[i], fii * g);
+                if (apply) acc_add(acc, i, fii, g, dsc);
                 if (out.small_f) {
                     out.fii[i] = fii;
-                    out.status[i] = VRM_ST_SMALL;
+                    out.status[i] = (warm == 1 || warm == 2) ? VRM_ST_WARM : VRM_ST_SMALL;
                 }
             }
         }
@@ -783,9 +792,10 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small_coop(const float* __re
                                                                SmallRec rec, const int32_t* __restrict__ q_small,
                                                                Queues* qs, int32_t* q_full, float* acc,
                                                                LaunchParams P, StencilOut out, int apply,
-                                                               vrm_counters* cnt)
+                                                               vrm_counters* cnt, const GridState* gs)
 {
     cnt = counter_stripe(cnt);
+    const double dsc = P.det && apply ? det_scale(gs->gmax_bits) : 0.0;
     const int lane = threadIdx.x & 63;
     const int s = lane & 7, base = lane & ~7;
     const bool lead = s == 0;
@@ -828,8 +838,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small_coop(const float* __re
             st = solve_lp<5, PH1>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false, 0ull);
             if (st == 0) {
                 const float g = gamma[i];
-                if (apply && fv != 0.0f) atomicAdd(&acc[pj], fv * g);
-                if (apply && lead) atomicAdd(&acc[i], fii * g);
+                if (apply && fv != 0.0f) acc_add(acc, pj, fv, g, dsc);
+                if (apply && lead) acc_add(acc, i, fii, g, dsc);
                 if (out.small_f) {
                     out.small_idx[(size_t)i * VRM_NSEG + s] = alive ? pj : -1;
                     out.small_f[(size_t)i * VRM_NSEG + s] = fv;
@@ -988,6 +998,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
     const GridState g = *gs;
     const int stride = gridDim.x * blockDim.x;
     const int loops = (nitems + stride - 1) / stride;
+    const double dsc = P.det && apply ? det_scale(g.gmax_bits) : 0.0;
     for (int it = 0; it < loops; ++it) {
         const int item = blockIdx.x * blockDim.x + tid + it * stride;
         const bool live = item < nitems;
@@ -1044,7 +1055,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
             auto store = [&](int j, float v) {
                 int u = (int)((unsigned)s_meta[j * kFullBlock + tid] >> 6);
                 int pj = perm[u];
-                if (apply) atomicAdd(&acc[pj], v * g_i);
+                if (apply) acc_add(acc, pj, v, g_i, dsc);
                 if (out.full_idx) {
                     out.full_idx[(size_t)i * VRM_KMAX + nz] = pj;
                     out.full_f[(size_t)i * VRM_KMAX + nz] = v;
@@ -1059,18 +1070,20 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
             const float* logit = (warm_pass && !out.use_prev) ? out.pred + (size_t)item * kMlpOut : nullptr;
             const int own = ids[t];
             auto col_id = [&](int j) { return ids[(unsigned)s_meta[j * kFullBlock + tid] >> 6]; };
-            const uint64_t pref = (warm_pass && out.use_prev) ? prev_mask(out.prev, own, k, col_id) : 0ull;
+            const uint64_t pref = (warm_pass && out.use_prev && (unsigned)own < (unsigned)out.prev_cap)
+                                      ? prev_mask(out.prev, own, k, col_id)
+                                      : 0ull;
             uint64_t basis = 0;
             st = k > 0 ? solve_lp<M, PH1, WARM>(cs, P, store, fii, piv, certified, warm_pass, logit, warm, basis,
                                      warm_pass && out.use_prev, pref)
                        : 1;
-            if (st == 0 && out.prev) record_basis(out.prev, own, basis, col_id);
+            if (st == 0 && out.prev && (unsigned)own < (unsigned)out.prev_cap) record_basis(out.prev, own, basis, col_id);
             if (st == 0) {
-                if (apply) atomicAdd(&acc[i], fii * g_i);
+                if (apply) acc_add(acc, i, fii, g_i, dsc);
                 if (out.full_k) {
                     out.full_k[i] = nz;
                     out.fii[i] = fii;
-                    out.status[i] = VRM_ST_FULL;
+                    out.status[i] = (warm == 1 || warm == 2) ? VRM_ST_WARM : VRM_ST_FULL;
                 }
             } else if (st == 1) {
                 if (out.status) out.status[i] = VRM_ST_INFEASIBLE;
@@ -1115,6 +1128,396 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
     }
 }
 
+// ------------------------------------------------ complete LPs, size-binned
+// The complete-neighbourhood LPs of q = 3 (9 rows, k = 9..48 columns) in three
+// launches: the column lists (k_full_collect: every member within R_full h,
+// the VRM_KMAX nearest by (d2, id), nearest first, with their id ranks) go to
+// HBM with a histogram of k; a counting sort orders the LPs by decreasing k
+// (k_full_bin_starts, k_full_bin_scatter), so the 64 lanes of a wave solve LPs
+// of similar size; k_lp_sift solves them with the nearest kSiftW columns in LDS
+// as the working set (Sec. 4.3: the closer particles carry the stencil; the
+// canonical cost grows like |r|^4), pricing the others from HBM only once the
+// working set is exhausted -- the optimum is certified over all k columns.
+constexpr int kSiftW = 24;
+constexpr int kKBins = VRM_KMAX + 1;
+// a record row: (slot << 6) | id rank per column, nearest first
+constexpr int kRecRow = VRM_KMAX;
+
+// Column lists with kCollL lanes per LP (aligned lane groups, four LPs per
+// wave): the lanes scan interleaved candidates of the three rows of cells and
+// append the members (within R_full h) to the group's list in LDS; then every
+// lane places its members at once: position = number of members with a
+// smaller (d2, id), id rank = number with a smaller id (among the VRM_KMAX
+// nearest if there are more).  No sort, no rescans; a list longer than
+// kMemCap (a density the method never produces) goes to the retry queue and
+// is solved by the one-thread kernel, which collects on its own.
+constexpr int kCollL = 16;
+constexpr int kMemCap = 96;
+constexpr int kCollBlock = 256;
+constexpr int kCollGroups = kCollBlock / kCollL;
+constexpr int kMemPerLane = kMemCap / kCollL;
+
+__global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __restrict__ xs,
+                                                             const float* __restrict__ ys,
+                                                             const int32_t* __restrict__ ids,
+                                                             const int32_t* __restrict__ cell_start,
+                                                             const GridState* gs, const int32_t* __restrict__ q_full,
+                                                             Queues* qs, LaunchParams P, int32_t* rec, int32_t* kcol,
+                                                             int32_t* khist, int32_t* q_retry, vrm_counters* cnt)
+{
+    __shared__ float s_d2[kCollGroups][kMemCap];
+    __shared__ int s_id[kCollGroups][kMemCap];
+    __shared__ int s_u[kCollGroups][kMemCap];
+    __shared__ int s_pos[kCollGroups][kMemCap];
+    __shared__ int s_hist[kKBins];
+    cnt = counter_stripe(cnt);
+    const int tid = threadIdx.x, sub = tid & (kCollL - 1), grp = tid / kCollL;
+    const int lane = lane_id(), gbase = lane & ~(kCollL - 1);
+    for (int b = tid; b < kKBins; b += blockDim.x) s_hist[b] = 0;
+    __syncthreads();
+    const int nitems = qs->n_full;
+    const GridState g = *gs;
+    const int ngroups = gridDim.x * kCollGroups;
+    const int loops = (nitems + ngroups - 1) / ngroups;
+    for (int it = 0; it < loops; ++it) {
+        const int r = blockIdx.x * kCollGroups + grp + it * ngroups;
+        const bool live = r < nitems;   // the same for the lanes of a group
+        int t = 0, cx = 0, cy = 0;
+        float xi = 0.0f, yi = 0.0f;
+        if (live) {
+            t = q_full[r];
+            xi = xs[t];
+            yi = ys[t];
+            cell_of_pos(g, xi, yi, cx, cy);
+        }
+        int count = 0;
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int yy = cy + oy;
+            int u0 = 0, u1 = 0;
+            if (live && yy >= 0 && yy < g.ny) {
+                u0 = cell_start[yy * g.nx + max(cx - 1, 0)];
+                u1 = cell_start[yy * g.nx + min(cx + 1, g.nx - 1) + 1];
+            }
+            for (int ub = u0;; ub += kCollL) {
+                const bool act = ub < u1;   // group-uniform
+                if (!__any(act)) break;
+                const int u = ub + sub;
+                bool mem = false;
+                float d2 = 0.0f;
+                if (act && u < u1 && u != t) {
+                    d2 = d2_f32(xs[u] - xi, ys[u] - yi);
+                    mem = !(d2 < P.lo2f) && !(d2 > P.hi2f);
+                }
+                const uint32_t m = (uint32_t)(__ballot(mem) >> gbase) & 0xFFFFu;
+                if (mem) {
+                    const int at = count + __popc(m & ((1u << sub) - 1u));
+                    if (at < kMemCap) {
+                        s_d2[grp][at] = d2;
+                        s_id[grp][at] = ids[u];
+                        s_u[grp][at] = u;
+                    }
+                }
+                count += __popc(m);
+            }
+        }
+        // the group's appends are read by its other lanes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const bool over = live && count > kMemCap;
+        const int nm = over ? 0 : count;
+        // this lane's members: e = sub + kCollL q
+        float md[kMemPerLane];
+        int mi[kMemPerLane], pos[kMemPerLane], rk[kMemPerLane];
+#pragma unroll
+        for (int q = 0; q < kMemPerLane; ++q) {
+            const int e = sub + kCollL * q;
+            md[q] = e < nm ? s_d2[grp][e] : 0.0f;
+            mi[q] = e < nm ? s_id[grp][e] : 0;
+            pos[q] = 0;
+            rk[q] = 0;
+        }
+        for (int o = 0; o < nm; ++o) {
+            const float d = s_d2[grp][o];
+            const int id = s_id[grp][o];
+#pragma unroll
+            for (int q = 0; q < kMemPerLane; ++q) {
+                pos[q] += (d < md[q] || (d == md[q] && id < mi[q])) ? 1 : 0;
+                rk[q] += id < mi[q] ? 1 : 0;
+            }
+        }
+        const int k = min(nm, VRM_KMAX);
+        if (nm > VRM_KMAX) {
+            // ranks among the VRM_KMAX nearest only
+#pragma unroll
+            for (int q = 0; q < kMemPerLane; ++q)
+                if (sub + kCollL * q < nm) s_pos[grp][sub + kCollL * q] = pos[q];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int q = 0; q < kMemPerLane; ++q) rk[q] = 0;
+            for (int o = 0; o < nm; ++o) {
+                const int id = s_id[grp][o];
+                const bool kept = s_pos[grp][o] < VRM_KMAX;
+#pragma unroll
+                for (int q = 0; q < kMemPerLane; ++q) rk[q] += (kept && id < mi[q]) ? 1 : 0;
+            }
+        }
+        if (live && !over) {
+            int32_t* row = rec + (size_t)r * kRecRow;
+#pragma unroll
+            for (int q = 0; q < kMemPerLane; ++q) {
+                const int e = sub + kCollL * q;
+                if (e < nm && pos[q] < VRM_KMAX)
+                    row[pos[q]] = (int)(((unsigned)s_u[grp][e] << 6) | (unsigned)rk[q]);
+            }
+            if (sub == 0) {
+                kcol[r] = k;
+                atomicAdd(&s_hist[k], 1);
+            }
+        }
+        if (over && sub == 0) kcol[r] = -1;
+        // lists too long for the group: the one-thread kernel solves them from the retry queue
+        const int pr = wave_append(&qs->n_retry, over && sub == 0);
+        if (over && sub == 0) q_retry[pr] = t;
+        count_add(&cnt->n_truncated, live && sub == 0 && nm > VRM_KMAX);
+        // the next item's appends must not overwrite the list before every lane is done with it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __syncthreads();
+    for (int b = tid; b < kKBins; b += blockDim.x)
+        if (s_hist[b]) atomicAdd(&khist[b], s_hist[b]);
+}
+
+// start of each size bin in decreasing k; khist[kKBins .. 2 kKBins) becomes the fill
+// pointers, and the histogram is cleared for the next run
+__global__ void k_full_bin_starts(int32_t* khist)
+{
+    if (threadIdx.x == 0) {
+        int at = 0;
+        for (int k = kKBins - 1; k >= 0; --k) {
+            khist[kKBins + k] = at;
+            at += khist[k];
+            khist[k] = 0;
+        }
+    }
+}
+
+// order[pos] = queue item, grouped by k (decreasing); one atomic per bin and workgroup
+__global__ __launch_bounds__(256) void k_full_bin_scatter(const int32_t* __restrict__ kcol, const Queues* qs,
+                                                          int32_t* khist, int32_t* order)
+{
+    __shared__ int s_cnt[kKBins], s_base[kKBins];
+    const int tid = threadIdx.x;
+    for (int b = tid; b < kKBins; b += blockDim.x) s_cnt[b] = 0;
+    __syncthreads();
+    const int nitems = qs->n_full;
+    const int r = blockIdx.x * blockDim.x + tid;
+    int k = -1, local = 0;
+    if (r < nitems) {
+        k = kcol[r];   // -1: left for the one-thread kernel
+        if (k >= 0) local = atomicAdd(&s_cnt[k], 1);
+    }
+    __syncthreads();
+    for (int b = tid; b < kKBins; b += blockDim.x)
+        s_base[b] = s_cnt[b] ? atomicAdd(&khist[kKBins + b], s_cnt[b]) : 0;
+    __syncthreads();
+    if (k >= 0) order[s_base[k] + local] = r;
+}
+
+// Working-set column store: the nearest W columns' FP32 scaled offsets and costs
+// in LDS (planes of kFullBlock), the others computed from the record row and the
+// positions when priced (only after widen()).  Exact offsets always come from the
+// positions.
+template <int W>
+struct SiftCols {
+    static constexpr int KC = 0;
+    static constexpr bool kCoop = false;
+    int k;
+    mutable int kw;                 // columns priced: the working set, then all
+    uint64_t dead;
+    const float* sx;                // LDS planes, this thread's column 0
+    const float* sy;
+    const float* sc;
+    const int32_t* __restrict__ row;   // record row: (slot << 6) | rank
+    float xi, yi;
+    const float* __restrict__ xs;
+    const float* __restrict__ ys;
+    const LaunchParams* P;
+    static constexpr int kLds = W;
+    __device__ __forceinline__ void load_lds(int j, float& x, float& y, uint32_t& aux) const
+    {
+        x = sx[j * kFullBlock];
+        y = sy[j * kFullBlock];
+        aux = __float_as_uint(sc[j * kFullBlock]);
+    }
+    __device__ __forceinline__ int active() const { return kw; }
+    __device__ __forceinline__ bool widen() const
+    {
+        if (kw >= k) return false;
+        kw = k;
+        return true;
+    }
+    __device__ __forceinline__ void exact_xy(int j, df& X, df& Y) const
+    {
+        const int u = (int)((unsigned)row[j] >> 6);
+        exact_offset(xi, yi, xs[u], ys[u], P->scale2e, X, Y);
+    }
+    __device__ __forceinline__ void exact(int j, df& X, df& Y, df& C) const
+    {
+        const int m = row[j];
+        const int u = (int)((unsigned)m >> 6);
+        exact_offset(xi, yi, xs[u], ys[u], P->scale2e, X, Y);
+        C = add_rank(cost_df(X, Y, *P), m & 63, P->q);
+    }
+    __device__ __forceinline__ void get(int j, float& x, float& y, float& c) const
+    {
+        if (j < W) {
+            x = sx[j * kFullBlock];
+            y = sy[j * kFullBlock];
+            c = sc[j * kFullBlock];
+        } else {
+            df X, Y, C;
+            exact(j, X, Y, C);
+            x = X.hi;
+            y = Y.hi;
+            c = C.hi;
+        }
+    }
+    __device__ __forceinline__ void load(int j, float& x, float& y, uint32_t& aux) const
+    {
+        float c;
+        get(j, x, y, c);
+        aux = __float_as_uint(c);
+    }
+    template <int Q>
+    __device__ __forceinline__ float cost_of(float, float, uint32_t aux) const
+    {
+        return __uint_as_float(aux);
+    }
+};
+
+template <int M, int W, bool PH1>
+__global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_lp_sift(
+    const int32_t* __restrict__ perm, const float* __restrict__ xs, const float* __restrict__ ys,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ kcol, const int32_t* __restrict__ rec,
+    const int32_t* __restrict__ q_full, Queues* qs, const float* __restrict__ gamma, float* acc, LaunchParams P,
+    StencilOut out, int apply, vrm_counters* cnt, int last_launch, const GridState* gs)
+{
+    __shared__ float s_x[W * kFullBlock];
+    __shared__ float s_y[W * kFullBlock];
+    __shared__ float s_c[W * kFullBlock];
+    cnt = counter_stripe(cnt);
+    const int tid = threadIdx.x;
+    const int nitems = qs->n_full - qs->n_retry;   // the binned ones
+    const int stride = gridDim.x * blockDim.x;
+    const int loops = (nitems + stride - 1) / stride;
+    const double dsc = P.det && apply ? det_scale(gs->gmax_bits) : 0.0;
+    for (int it = 0; it < loops; ++it) {
+        const int p = blockIdx.x * blockDim.x + tid + it * stride;
+        const bool live = p < nitems;
+        int st = 1, piv = 0, certified = 1, k = 0;
+        int cstat[2] = {0, 0};
+        if (live) {
+            const int r = order[p];
+            const int t = q_full[r];
+            const int i = perm[t];
+            k = kcol[r];
+            const int32_t* row = rec + (size_t)r * kRecRow;
+            const float xi = xs[t], yi = ys[t];
+            const int kw = min(k, W);
+            // the working set: offsets and costs of the nearest columns, slots read eight at a time
+            for (int j0 = 0; j0 < kw; j0 += 8) {
+                int bm[8];
+                float bx[8], by[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bm[e] = row[min(j0 + e, kw - 1)];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int u = (int)((unsigned)bm[e] >> 6);
+                    bx[e] = xs[u];
+                    by[e] = ys[u];
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int j = j0 + e;
+                    if (j >= kw) break;
+                    df X, Y;
+                    exact_offset(xi, yi, bx[e], by[e], P.scale2e, X, Y);
+                    s_x[j * kFullBlock + tid] = X.hi;
+                    s_y[j * kFullBlock + tid] = Y.hi;
+                    s_c[j * kFullBlock + tid] = add_rank(cost_df(X, Y, P), bm[e] & 63, P.q).hi;
+                }
+            }
+            SiftCols<W> cs{k, kw, 0ull, s_x + tid, s_y + tid, s_c + tid, row, xi, yi, xs, ys, &P};
+            float fii = 0.0f;
+            const float g_i = gamma[i];
+            int nz = 0;
+            auto store = [&](int j, float v) {
+                const int pj = perm[(unsigned)row[j] >> 6];
+                if (apply) acc_add(acc, pj, v, g_i, dsc);
+                if (out.full_idx) {
+                    out.full_idx[(size_t)i * VRM_KMAX + nz] = pj;
+                    out.full_f[(size_t)i * VRM_KMAX + nz] = v;
+                }
+                ++nz;
+            };
+            int warm = 0;
+            uint64_t basis = 0;
+            st = solve_lp<M, PH1, false>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false, 0ull,
+                                         cstat);
+            if (st == 0) {
+                if (apply) acc_add(acc, i, fii, g_i, dsc);
+                if (out.full_k) {
+                    out.full_k[i] = nz;
+                    out.fii[i] = fii;
+                    out.status[i] = VRM_ST_FULL;
+                }
+            } else if (out.status) {
+                out.status[i] = VRM_ST_INFEASIBLE;
+            }
+        }
+        const bool ok = live && st == 0;
+        if (piv) atomicAdd((unsigned long long*)&cnt->pivots, (unsigned long long)piv);
+        if (ok) atomicAdd((unsigned long long*)&cnt->full_cols, (unsigned long long)k);
+        if (cstat[0]) atomicAdd((unsigned long long*)&cnt->cert_rounds, (unsigned long long)cstat[0]);
+        count_add(&cnt->n_full, ok);
+        count_add(&cnt->n_infeasible, live && st == 1);
+        count_add(&cnt->n_uncertified, ok && !certified);
+        {
+            const uint64_t m = __ballot(live && cstat[1]);
+            if (m && lane_id() == __ffsll((unsigned long long)m) - 1)
+                atomicAdd((unsigned long long*)&cnt->cert_exact, (unsigned long long)__popcll(m));
+        }
+        if (apply) {
+            uint64_t m = __ballot(ok);
+            if (m && lane_id() == __ffsll((unsigned long long)m) - 1)
+                atomicAdd((unsigned long long*)&cnt->redistributions, (unsigned long long)__popcll(m));
+        }
+    }
+    if (last_launch) {
+        // the last LP launch of a stencil run: its last block to finish empties the
+        // queues for the next run (keeping the counts for the host)
+        __shared__ int last;
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) last = atomicAdd(&qs->blocks_done, 1) == (int)gridDim.x - 1;
+        __syncthreads();
+        if (last && threadIdx.x == 0) {
+            __threadfence();
+            qs->last_small = qs->n_small;
+            qs->last_full = qs->n_full;
+            qs->n_small = 0;
+            qs->n_full = 0;
+            qs->n_retry = 0;
+            qs->blocks_done = 0;
+        }
+    }
+}
+
 // ------------------------------------------------------------ particle removal
 // Particle removal (Sec. 6, outlook): a particle closer than r h to another
 // gives its circulation to its complete neighbourhood (r h .. R_full h) by
@@ -1126,14 +1529,24 @@ constexpr uint8_t kRmNone = 0, kRmUndecided = 1, kRmIn = 2, kRmOut = 3;
 
 // candidates: a particle closer than r h to another (per slot); the
 // positions of a row's three cells are read eight at a time
+// (a non-finite circulation sets kBadGamma; with a non-finite value no slot is a
+// candidate)
 __global__ __launch_bounds__(256) void k_rm_candidates(int n, const float* __restrict__ xs,
                                                        const float* __restrict__ ys,
-                                                       const int32_t* __restrict__ cell_start, const GridState* gs,
-                                                       LaunchParams P, uint8_t* state)
+                                                       const int32_t* __restrict__ cell_start, GridState* gs,
+                                                       LaunchParams P, uint8_t* state, const int32_t* __restrict__ perm,
+                                                       const float* __restrict__ gamma)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    // slots exist only for finite positions
+    const bool nf = t < n && !(gs->bad & kBadPos) && !(fabsf(gamma[perm[t]]) <= 3.4028235e38f);
+    if (__any(nf) && lane_id() == 0) atomicOr(&gs->bad, kBadGamma);
     if (t >= n) return;
     const GridState g = *gs;
+    if (g.bad) {
+        state[t] = kRmNone;
+        return;
+    }
     const float xi = xs[t], yi = ys[t];
     int cx, cy;
     cell_of_pos(g, xi, yi, cx, cy);
@@ -1443,6 +1856,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
     out.cloud_id = cl->id_dev;
     if (c->warm == 2 && c->prev && !feat_out) {
         out.prev = c->prev;
+        out.prev_cap = c->capacity;
         out.use_prev = 1;
     }
     if (net) {
@@ -1471,14 +1885,14 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
                 const int grid = min((n + per_block - 1) / per_block, c->tuning.lp_small_blocks);
                 hipLaunchKernelGGL((lp.phase1 ? k_lp_small_coop<true> : k_lp_small_coop<false>), dim3(max(grid, 1)),
                                    dim3(kSmallBlock), 0, c->stream, cl->gamma_dev, c->srec, c->q_small, c->queues,
-                                   c->q_full, c->acc, lp, out, apply, c->counters);
+                                   c->q_full, c->acc, lp, out, apply, c->counters, c->grid);
                 VRM_HIP(hipGetLastError());
             } else {
                 for (int mode = first; mode <= (warm ? kLpRetry : kLpPlain); ++mode) {
                     hipLaunchKernelGGL((lp.phase1 ? k_lp_small<true> : k_lp_small<false>), dim3(lp_grid_small(c, n)),
                                        dim3(kSmallBlock), 0, c->stream, c->perm, c->xs, c->ys, c->ids, c->srec,
                                        c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc, lp, out, apply,
-                                       c->counters, mode, c->q_retry, c->tuning.lp_small_lanes);
+                                       c->counters, mode, c->q_retry, c->tuning.lp_small_lanes, c->grid);
                     VRM_HIP(hipGetLastError());
                 }
             }
@@ -1495,6 +1909,30 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
                            dim3(min(lp_grid_full(c, n), 64)), dim3(kFullBlock), 0, c->stream, c->perm,
                            c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                            o2, apply, c->counters, kLpPlain, c->q_retry, 1);
+    } else if (!warm && !feat_out) {
+        // size-binned working-set path: column lists, counting sort by k, LPs
+        {
+            ScopedTimer tm(c, VRM_T_FULL_COLS);
+            hipLaunchKernelGGL(k_full_collect, dim3(min((n + kCollGroups - 1) / kCollGroups, 4096)), dim3(kCollBlock), 0,
+                               c->stream, c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, lp,
+                               c->full_cols, c->full_k, c->khist, c->q_retry, c->counters);
+            hipLaunchKernelGGL(k_full_bin_starts, dim3(1), dim3(64), 0, c->stream, c->khist);
+            hipLaunchKernelGGL(k_full_bin_scatter, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->full_k,
+                               c->queues, c->khist, c->full_order);
+            VRM_HIP(hipGetLastError());
+        }
+        ScopedTimer tm(c, VRM_T_LP_FULL);
+        hipLaunchKernelGGL((lp.phase1 ? k_lp_sift<9, kSiftW, true> : k_lp_sift<9, kSiftW, false>),
+                           dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
+                           c->full_order, c->full_k, c->full_cols, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, out,
+                           apply, c->counters, 0, c->grid);
+        // lists too long for the collection groups (none in practice): the one-thread
+        // kernel from the retry queue; as the run's last LP launch it empties the queues
+        hipLaunchKernelGGL((lp.phase1 ? k_lp_full<9, false, true, false> : k_lp_full<9, false, false, false>),
+                           dim3(1), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys, c->ids, c->cell_start,
+                           c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, out, apply, c->counters, kLpRetry,
+                           c->q_retry, 1);
+        VRM_HIP(hipGetLastError());
     } else {
         ScopedTimer tm(c, VRM_T_LP_FULL);
         const int last = warm ? kLpRetry : kLpPlain;
@@ -1542,7 +1980,7 @@ int vrm_remove_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp,
         return n;
     }
     hipLaunchKernelGGL(k_rm_candidates, dim3(nb), dim3(256), 0, s, n, c->xs, c->ys, c->cell_start, c->grid, lp,
-                       c->cstate);
+                       c->cstate, c->perm, cl->gamma_dev);
     VRM_HIP(hipGetLastError());
     // queue of the candidates (slots), then of the taken ones: device-wide selections
     int32_t* cand = c->cperm;
@@ -1556,8 +1994,11 @@ int vrm_remove_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const LaunchParams& lp,
                                 &c->queues->n_cand, (size_t)n, RmStateIs{c->cstate, kRmUndecided}, s));
     }
     Queues q;
+    int32_t bad = 0;
     VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(Queues), hipMemcpyDeviceToHost, s));
+    VRM_HIP(hipMemcpyAsync(&bad, &c->grid->bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     VRM_HIP(hipStreamSynchronize(s));
+    if (bad) return vrm_nonfinite(c, bad);   // nothing changed yet
     const int nc = q.n_cand;
     if (n_candidates) *n_candidates = nc;
     if (nc == 0) return n;

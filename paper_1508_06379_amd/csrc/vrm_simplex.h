@@ -29,7 +29,6 @@ constexpr float kTolPiv = 1e-6f;                  // FP32 pivot tolerance (relat
 constexpr float kTolFeas = 1e-3f;                 // phase-I infeasibility (relative to the rhs)
 constexpr float kCertD = 1e-9f;                   // certified reduced-cost tolerance (relative)
 constexpr float kCertX = 1e-9f;                   // certified primal tolerance (absolute, fhat units)
-constexpr int kMaxCert = 8;
 constexpr int kMaxRefine = 6;
 constexpr float kFastMargin = 1e-3f;              // FP32 reduced-cost margin of the fast certificate
 
@@ -121,6 +120,12 @@ __device__ __forceinline__ df rhs_df(int a, const LaunchParams& P)
 // and, for stores with a run-time column count (KC == 0),
 //   void load(int j, float& rx, float& ry, uint32_t& aux)  raw values of column j
 //   float cost_of<Q>(float rx, float ry, uint32_t aux)      its FP32 cost (order Q)
+//   int active()     columns the simplex prices (a prefix of the k; k by default)
+//   kLds, load_lds(j, ...)  columns j < kLds are in LDS: load without the general path
+//   bool widen()     price every column from now on; false if that is already so
+// The simplex declares a phase finished only after widen() returned false, so
+// a store whose working set is the nearest columns (most optimal stencils use
+// only those) gives the same certified optimum as pricing all of them.
 // A store with kCoop spreads the columns over a group of lanes, one each
 // (own, x, y, c: this lane's column); every lane of the group runs this
 // simplex on the same, replicated state, and the loops over columns become
@@ -140,6 +145,8 @@ struct ThreadSimplex {
     uint64_t isb;     // basic structural columns
     uint64_t blk;     // columns blocked until the next pivot (no positive pivot element)
     uint64_t dead;    // columns that do not exist
+    int cert_rounds;  // certification rounds taken
+    int cert_exact;   // 1 once the double-float dual check ran
 
     static constexpr int ART = 64;
 
@@ -378,6 +385,30 @@ struct ThreadSimplex {
         }
     }
 
+    // The same for the nine rows of q = 3 by Horner's scheme on the cubic
+    // y . v(x, y) = x (y0 + y3 Y + x (y2 + y6 Y + y5 x)) + Y (y1 + Y (y4 + y7 x + y8 Y))
+    // (9 operations instead of 7 monomials and 9 products), and its scale from
+    // |y| and |x|, |Y| (the |monomials| are the monomials of |x|, |Y|).
+    __device__ __forceinline__ static void reduced_horner(float x, float Y, float c, const float (&y)[M],
+                                                          const float (&ya)[M], bool p2, float& d, float& sc)
+    {
+        static_assert(M == 9, "cubic rows");
+        const float a = __builtin_fmaf(x, y[5], __builtin_fmaf(Y, y[6], y[2]));
+        const float b = __builtin_fmaf(x, a, __builtin_fmaf(Y, y[3], y[0]));
+        const float e = __builtin_fmaf(Y, y[8], __builtin_fmaf(x, y[7], y[4]));
+        const float g = __builtin_fmaf(Y, e, y[1]);
+        const float p = __builtin_fmaf(x, b, Y * g);
+        const float ax = fabsf(x), ay = fabsf(Y);
+        const float aa = __builtin_fmaf(ax, ya[5], __builtin_fmaf(ay, ya[6], ya[2]));
+        const float ab = __builtin_fmaf(ax, aa, __builtin_fmaf(ay, ya[3], ya[0]));
+        const float ae = __builtin_fmaf(ay, ya[8], __builtin_fmaf(ax, ya[7], ya[4]));
+        const float ag = __builtin_fmaf(ay, ae, ya[1]);
+        const float ap = __builtin_fmaf(ax, ab, ay * ag);
+        const float cc = p2 ? c : 0.0f;
+        d = cc - p;
+        sc = fabsf(cc) + ap;
+    }
+
     // Entering column: Dantzig (most negative reduced cost), Bland (lowest
     // index) after many iterations.
     __device__ __forceinline__ int price(const CS& cs, const float (&y)[M], bool p2, bool bland) const
@@ -423,26 +454,43 @@ struct ThreadSimplex {
             // Branch-free, four columns per iteration (their reads issued
             // together); Bland's rule keeps the first qualifying column,
             // Dantzig's the first of the most negative.
-            const int k = cs.k;
-            for (int j0 = 0; j0 < k; j0 += 4) {
+            const int k = cs.active();
+            float ya[M];
+#pragma unroll
+            for (int a = 0; a < M; ++a) ya[a] = fabsf(y[a]);
+            auto column = [&](int j, bool in, float rx, float ry, uint32_t aux) {
+                const float c = cs.template cost_of<kQ>(rx, ry, aux);
+                float d, sc;
+                if constexpr (M == 9) {
+                    reduced_horner(rx, ry, c, y, ya, p2, d, sc);
+                } else {
+                    float v[M];
+                    mono<M>(rx, ry, v);
+                    reduced(v, c, y, p2, d, sc);
+                }
+                const bool ok = in && !((excl >> j) & 1ull) && d < -kTolD * sc;
+                if (ok && (e < 0 || (!bland && d < best))) {
+                    e = j;
+                    best = d;
+                }
+            };
+            // the columns a store keeps in LDS (all, or its working set), then the rest
+            const int k1 = min(k, CS::kLds);
+            for (int j0 = 0; j0 < k1; j0 += 4) {
+                float rx[4], ry[4];
+                uint32_t aux[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) cs.load_lds(min(j0 + u, k1 - 1), rx[u], ry[u], aux[u]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) column(j0 + u, j0 + u < k1, rx[u], ry[u], aux[u]);
+            }
+            for (int j0 = k1; j0 < k; j0 += 4) {
                 float rx[4], ry[4];
                 uint32_t aux[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) cs.load(min(j0 + u, k - 1), rx[u], ry[u], aux[u]);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int j = j0 + u;
-                    const float c = cs.template cost_of<kQ>(rx[u], ry[u], aux[u]);
-                    float v[M];
-                    mono<M>(rx[u], ry[u], v);
-                    float d, sc;
-                    reduced(v, c, y, p2, d, sc);
-                    const bool ok = j < k && !((excl >> j) & 1ull) && d < -kTolD * sc;
-                    if (ok && (e < 0 || (!bland && d < best))) {
-                        e = j;
-                        best = d;
-                    }
-                }
+                for (int u = 0; u < 4; ++u) column(j0 + u, j0 + u < k, rx[u], ry[u], aux[u]);
             }
         }
         return e;
@@ -468,6 +516,7 @@ struct ThreadSimplex {
             prices(p2, y);
             const int e = price(cs, y, p2, it >= bland_after);
             if (e < 0) {
+                if (cs.widen()) continue;   // the working set is done: price every column
                 if (p2) return 0;
                 // end of phase I: feasible iff the artificial variables vanished
                 float art = 0.0f;
@@ -610,11 +659,13 @@ struct ThreadSimplex {
     }
 
     // Certify against the exact problem, repairing the basis if needed.
-    // 0 optimal, 1 infeasible, 3 not certified.  x receives the basic values.
+    // 0 optimal, 1 infeasible, 3 not certified.  x receives the basic values
+    // of the final basis (refined for it, also after a last repair pivot).
     __device__ int certify(const CS& cs, const LaunchParams& P, df (&x)[M], int& piv)
     {
         const int k = cs.k;
-        for (int round = 0; round < kMaxCert; ++round) {
+        for (int round = 0; round < P.max_cert; ++round) {
+            ++cert_rounds;
             const float first_corr = refine_primal(cs, P, x);
             // An artificial variable still basic must vanish in the exact basic
             // solution; one that does not means phase I ended, within its FP32
@@ -656,26 +707,36 @@ struct ThreadSimplex {
                             dual_ok = dual_ok && !(d < kFastMargin * sc);
                         }
                     } else {
-                        for (int j0 = 0; j0 < k; j0 += 4) {
+                        auto column = [&](int j, bool in, float rx, float ry, uint32_t aux) {
+                            const float c = cs.template cost_of<kQ>(rx, ry, aux);
+                            float v[M];
+                            mono<M>(rx, ry, v);
+                            float d, sc;
+                            reduced(v, c, yf, true, d, sc);
+                            dual_ok = dual_ok && (!in || ((excl >> j) & 1ull) || !(d < kFastMargin * sc));
+                        };
+                        const int k1 = min(k, CS::kLds);
+                        for (int j0 = 0; j0 < k1; j0 += 4) {
+                            float rx[4], ry[4];
+                            uint32_t aux[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) cs.load_lds(min(j0 + u, k1 - 1), rx[u], ry[u], aux[u]);
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) column(j0 + u, j0 + u < k1, rx[u], ry[u], aux[u]);
+                        }
+                        for (int j0 = k1; j0 < k; j0 += 4) {
                             float rx[4], ry[4];
                             uint32_t aux[4];
 #pragma unroll
                             for (int u = 0; u < 4; ++u) cs.load(min(j0 + u, k - 1), rx[u], ry[u], aux[u]);
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int j = j0 + u;
-                                const float c = cs.template cost_of<kQ>(rx[u], ry[u], aux[u]);
-                                float v[M];
-                                mono<M>(rx[u], ry[u], v);
-                                float d, sc;
-                                reduced(v, c, yf, true, d, sc);
-                                dual_ok = dual_ok && (j >= k || ((excl >> j) & 1ull) || !(d < kFastMargin * sc));
-                            }
+                            for (int u = 0; u < 4; ++u) column(j0 + u, j0 + u < k, rx[u], ry[u], aux[u]);
                         }
                     }
                     if (dual_ok) return 0;
                 }
             }
+            cert_exact = 1;
             float yf[M];
             prices(true, yf);
             df y[M];
@@ -800,7 +861,23 @@ struct ThreadSimplex {
             pivot(l, e, alpha, ce);
             ++piv;
         }
+        // out of rounds right after a repair pivot: the values of the basis now held
+        refine_primal(cs, P, x);
         return 3;
+    }
+
+    // The refined basic solution satisfies the constraints: every structural
+    // value >= -kCertX and every artificial one vanished (a basis whose
+    // optimality could not be certified is kept only then).
+    __device__ bool primal_feasible(const df (&x)[M]) const
+    {
+        bool ok = true;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const float v = x[r].hi + x[r].lo;
+            ok = ok && (bs[r] < ART ? !(v < -kCertX) : !(fabsf(v) > kCertX));
+        }
+        return ok;
     }
 };
 
@@ -828,13 +905,16 @@ constexpr int warm_cap() { return M == 5 ? 3 : 12; }
 template <int M, bool PH1, bool WARM = true, class CS, class Store>
 __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified,
                         bool warm_pass_arg, const float* logit, int& warm, uint64_t& basis, bool use_pref = false,
-                        uint64_t pref = 0)
+                        uint64_t pref = 0, int* stats = nullptr)
 {
     const bool warm_pass = WARM && warm_pass_arg;
     ThreadSimplex<M, CS> lp;
     lp.bt_ = P.bt_hi;
     lp.init(P);
     lp.dead = cs.dead;
+    lp.cert_rounds = 0;
+    lp.cert_exact = 0;
+    if (stats) stats[0] = stats[1] = 0;
     int st;
     warm = 0;
     basis = 0;
@@ -872,8 +952,15 @@ __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float&
     certified = 1;
     if (st == 1) return 1;
     const int c = accepted ? 0 : lp.certify(cs, P, x, piv);
+    if (stats) {
+        stats[0] = lp.cert_rounds;
+        stats[1] = lp.cert_exact;
+    }
     if (c == 1) return 1;
-    certified = (c == 0 && st == 0) ? 1 : 0;
+    // not certified optimal: kept only if its exact values meet the moment
+    // conditions and the sign condition, else treated as infeasible
+    if (c == 3 && !lp.primal_feasible(x)) return 1;
+    certified = c == 0 ? 1 : 0;
     float sum = 0.0f;
     float v[M];
 #pragma unroll

@@ -14,21 +14,35 @@ using namespace vrm;
 
 namespace {
 
-// n_dev (optional): the particle count read on the device (graph replays), else n
+// n_dev (optional): the particle count read on the device (graph replays), else n.
+// det: the accumulator holds 64-bit fixed-point sums (scale det_scale).  While a
+// non-finite value is flagged the accumulator is cleared and the cloud is left
+// as it is.
 __global__ __launch_bounds__(256) void k_combine(int n, const int32_t* __restrict__ n_dev, float a, float b, float dt,
                                                  float lam, const float* __restrict__ x0, const float* __restrict__ y0,
                                                  const float* __restrict__ g0, float* x, float* y, float* g,
-                                                 const float* __restrict__ u, const float* __restrict__ v, float* acc)
+                                                 const float* __restrict__ u, const float* __restrict__ v, float* acc,
+                                                 const GridState* gs, int det)
 {
     if (n_dev) n = *n_dev;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float dg = lam * acc[i];
-    acc[i] = 0.0f;
+    float sum;
+    if (det) {
+        unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(acc);
+        const long long w = (long long)acc64[i];
+        acc64[i] = 0ull;
+        sum = (float)((double)w * (1.0 / det_scale(gs->gmax_bits)));
+    } else {
+        sum = acc[i];
+        acc[i] = 0.0f;
+    }
+    if (gs->bad) return;
+    float dg = lam * sum;
     float gn = __builtin_fmaf(dt, dg, g[i]);
-    float gs = b * gn;
-    if (a != 0.0f) gs = __builtin_fmaf(a, g0[i], gs);
-    g[i] = gs;
+    float gst = b * gn;
+    if (a != 0.0f) gst = __builtin_fmaf(a, g0[i], gst);
+    g[i] = gst;
     if (u) {
         float xn = __builtin_fmaf(dt, u[i], x[i]);
         float yn = __builtin_fmaf(dt, v[i], y[i]);
@@ -62,6 +76,7 @@ __global__ __launch_bounds__(256) void k_verify(int n, const float* __restrict__
         i0 = gi;
         l1 = fabs(gi);
         int st = status ? status[i] : 3;
+        if (st == VRM_ST_WARM) st = (fk && fk[i] > 0) ? 1 : 0;   // warm-started: small or complete
         if (st <= 1) {
             double m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
             double xi = (double)x[i], yi = (double)y[i];
@@ -109,17 +124,31 @@ __global__ __launch_bounds__(256) void k_verify(int n, const float* __restrict__
     }
 }
 
+// y^n of the step; also flags a non-finite circulation (kBadGamma) and, for the
+// fixed-point accumulation (det), finds max |Gamma^n| (k_gmax_reset first)
 __global__ __launch_bounds__(256) void k_save_base(int n, const int32_t* __restrict__ n_dev,
                                                    const float* __restrict__ x, const float* __restrict__ y,
-                                                   const float* __restrict__ g, float* x0, float* y0, float* g0)
+                                                   const float* __restrict__ g, float* x0, float* y0, float* g0,
+                                                   GridState* gs, int det)
 {
     if (n_dev) n = *n_dev;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    x0[i] = x[i];
-    y0[i] = y[i];
-    g0[i] = g[i];
+    uint32_t bits = 0u;
+    if (i < n) {
+        const float gi = g[i];
+        x0[i] = x[i];
+        y0[i] = y[i];
+        g0[i] = gi;
+        bits = __float_as_uint(fabsf(gi));
+    }
+    if (__any(bits >= 0x7f800000u) && lane_id() == 0) atomicOr(&gs->bad, kBadGamma);
+    if (det) {
+        for (int o = 32; o > 0; o >>= 1) bits = max(bits, (uint32_t)__shfl_xor((int)bits, o, VRM_WAVE));
+        if (lane_id() == 0 && bits < 0x7f800000u) atomicMax(&gs->gmax_bits, bits);
+    }
 }
+
+__global__ void k_gmax_reset(GridState* gs) { gs->gmax_bits = 0u; }
 
 __global__ void k_verify_init(unsigned long long* out)
 {
@@ -285,34 +314,36 @@ int vrm_biot_savart_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, double eps, 
 }
 
 int vrm_combine_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const float* u, const float* v, double dt, float lam,
-                    int stage)
+                    int stage, int det)
 {
     static const float A[3] = {0.0f, 0.75f, 1.0f / 3.0f};
     static const float B[3] = {1.0f, 0.25f, 2.0f / 3.0f};
     if (n <= 0) return VRM_OK;
     hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, cl->n_dev, A[stage], B[stage],
-                       (float)dt, lam, c->x0, c->y0, c->g0, cl->x_dev, cl->y_dev, cl->gamma_dev, u, v, c->acc);
+                       (float)dt, lam, c->x0, c->y0, c->g0, cl->x_dev, cl->y_dev, cl->gamma_dev, u, v, c->acc, c->grid,
+                       det);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }
 
-int vrm_save_base_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n)
+int vrm_save_base_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, int det)
 {
     if (n <= 0) return VRM_OK;
+    if (det) hipLaunchKernelGGL(k_gmax_reset, dim3(1), dim3(1), 0, c->stream, c->grid);
     hipLaunchKernelGGL(k_save_base, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, cl->n_dev, cl->x_dev, cl->y_dev,
-                       cl->gamma_dev, c->x0, c->y0, c->g0);
+                       cl->gamma_dev, c->x0, c->y0, c->g0, c->grid, det);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }
 
-int vrm_verify_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchParams& lp, const vrm_stencils* st,
-                   double* report)
+int vrm_verify_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchParams& lp, double h,
+                   const vrm_stencils* st, double* report)
 {
     unsigned long long* out = reinterpret_cast<unsigned long long*>(report);
     hipLaunchKernelGGL(k_verify_init, dim3(1), dim3(1), 0, c->stream, out);
     if (n > 0) {
         hipLaunchKernelGGL(k_verify, dim3(blocks_for(n)), dim3(256), 0, c->stream, n, cl->x_dev, cl->y_dev,
-                           cl->gamma_dev, (double)lp.h, lp.q, st ? st->small_idx_dev : nullptr,
+                           cl->gamma_dev, h, lp.q, st ? st->small_idx_dev : nullptr,
                            st ? st->small_f_dev : nullptr, st ? st->status_dev : nullptr,
                            st ? st->full_k_dev : nullptr, st ? st->full_idx_dev : nullptr,
                            st ? st->full_f_dev : nullptr, out);

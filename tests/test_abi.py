@@ -38,6 +38,7 @@ def test_status_strings(lib):
     lib.vrm_status_string.restype = ctypes.c_char_p
     assert lib.vrm_status_string(0) == b"ok"
     assert lib.vrm_status_string(-2) == b"capacity exceeded"
+    assert b"non-finite" in lib.vrm_status_string(-5)
 
 
 def test_create_rejects_bad_capacity(lib):
@@ -60,9 +61,12 @@ int main(void) {
   printf("vrm_stencils %zu\\n", sizeof(vrm_stencils));
   printf("vrm_counters %zu\\n", sizeof(vrm_counters));
   printf("vrm_tuning %zu\\n", sizeof(vrm_tuning));
-  P(vrm_params, q) P(vrm_cloud, capacity) P(vrm_stencils, full_f_dev)
+  P(vrm_params, q) P(vrm_params, deterministic) P(vrm_tuning, cert_rounds)
+  printf("VRM_E_NONFINITE %d\\n", VRM_E_NONFINITE);
+  printf("VRM_ST_WARM %d\\n", VRM_ST_WARM);
+  P(vrm_cloud, capacity) P(vrm_stencils, full_f_dev)
   P(vrm_counters, pivots) P(vrm_counters, redistributions) P(vrm_counters, mis_rounds) P(vrm_counters, full_cols)
-  P(vrm_counters, graph_replays) P(vrm_tuning, infer_blocks) P(vrm_tuning, lp_small_lanes) P(vrm_tuning, lp_small_coop)
+  P(vrm_counters, graph_replays) P(vrm_counters, cert_exact) P(vrm_tuning, infer_blocks) P(vrm_tuning, lp_small_lanes) P(vrm_tuning, lp_small_coop)
   return 0;
 }
 """)
@@ -74,6 +78,10 @@ int main(void) {
     assert int(out["vrm_stencils"]) == ctypes.sizeof(vrm.vrm_stencils)
     assert int(out["vrm_counters"]) == ctypes.sizeof(vrm.vrm_counters)
     assert int(out["vrm_params.q"]) == vrm.vrm_params.q.offset
+    assert int(out["vrm_params.deterministic"]) == vrm.vrm_params.deterministic.offset
+    assert int(out["vrm_tuning.cert_rounds"]) == vrm.vrm_tuning.cert_rounds.offset
+    assert int(out["VRM_E_NONFINITE"]) == vrm.E_NONFINITE
+    assert int(out["VRM_ST_WARM"]) == vrm.ST_WARM
     assert int(out["vrm_cloud.capacity"]) == vrm.vrm_cloud.capacity.offset
     assert int(out["vrm_stencils.full_f_dev"]) == vrm.vrm_stencils.full_f_dev.offset
     assert int(out["vrm_counters.pivots"]) == vrm.vrm_counters.pivots.offset
@@ -81,6 +89,7 @@ int main(void) {
     assert int(out["vrm_counters.mis_rounds"]) == vrm.vrm_counters.mis_rounds.offset
     assert int(out["vrm_counters.full_cols"]) == vrm.vrm_counters.full_cols.offset
     assert int(out["vrm_counters.graph_replays"]) == vrm.vrm_counters.graph_replays.offset
+    assert int(out["vrm_counters.cert_exact"]) == vrm.vrm_counters.cert_exact.offset
     assert int(out["vrm_tuning"]) == ctypes.sizeof(vrm.vrm_tuning)
     assert int(out["vrm_tuning.infer_blocks"]) == vrm.vrm_tuning.infer_blocks.offset
     assert int(out["vrm_tuning.lp_small_lanes"]) == vrm.vrm_tuning.lp_small_lanes.offset

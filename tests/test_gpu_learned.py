@@ -138,6 +138,10 @@ def _stencil_dicts(vrm, ctx, cloud, P):
     S = {k: getattr(st, k)[:n].cpu().numpy() for k in ("small_idx", "small_f", "fii", "status", "full_k", "full_idx",
                                                        "full_f")}
     out = {}
+    # a stencil solved from the warm start's basis (status 4) is a small or a complete one
+    warm = S["status"] == 4
+    S["status"] = np.where(warm, np.where(S["full_k"] > 0, 1, 0), S["status"])
+    out["_warm"] = int(warm.sum())
     for i in range(n):
         s = S["status"][i]
         if s == 0:
@@ -168,6 +172,9 @@ def test_warm_start_gives_the_plain_results(vrm, trained, q):
         res.append((_stencil_dicts(vrm, ctx, cloud, P), ctx.vrm_read_counters()))
     (a, ca), (b, cb) = res
     print("plain", ca, "\nwarm", cb, flush=True)
+    assert a.pop("_warm") == 0
+    # every LP settled in the warm pass is marked as such (status 4)
+    assert b.pop("_warm") == cb["warm_hit"] + cb["warm_phase2"] > 0
     assert a.keys() == b.keys()
     worst = 0.0
     for pid in a:

@@ -9,6 +9,7 @@ residuals <= 1e-6 relative, Gamma within 1e-5 relative L2 after whole runs
 import numpy as np
 import pytest
 
+import moments
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -192,14 +193,19 @@ def test_fractions_match_oracle(vrm, orc, name):
     rep = torch.zeros(4, dtype=torch.float64, device="cuda")
     ctx.vrm_verify(cloud, P, st, rep)
     res, i0, l1, fmax = rep.cpu().numpy()
-    _say(name, "max moment residual", res, "max sum f", fmax)
-    assert res <= 1e-6
+    # the verification kernel against the residual recomputed on the host
+    rows, cols, f = moments.stencil_columns(S)
+    host = moments.residuals(x, y, wl.h, wl.q, rows, cols, f)
+    _say(name, "max moment residual", res, "host", host.max(), "max sum f", fmax)
+    assert rows.size == len(R)
+    assert host.max() <= 1e-6
+    assert abs(res - host.max()) <= 1e-13
     assert abs(i0 - rg.sum()) <= 1e-6 * np.abs(rg).sum()
 
 
 # ------------------------------------------------------------------ a7: runs
-def _run_parity(vrm, orc, wl, steps):
-    P = vrm.params_of(wl)
+def _run_parity(vrm, orc, wl, steps, det=0):
+    P = vrm.params_of(wl, deterministic=det)
     cloud = _gpu_cloud(vrm, wl, cap_factor=4)
     ctx = vrm.Context(cloud.capacity)
     vt = vrm.vortex_table(wl.vortices) if wl.vortices is not None else None
@@ -230,13 +236,15 @@ def _rel_l2_by_id(ids, g, rids, rg):
     return np.linalg.norm(d) / np.linalg.norm(rg)
 
 
-@pytest.mark.parametrize("name,steps", [("lattice", 10), ("jittered_q2_h0.02", 25), ("jittered_q3_h0.02", 10)])
-def test_run_gamma_matches_oracle(vrm, orc, name, steps):
+@pytest.mark.parametrize("name,steps,det", [("lattice", 10, 0), ("lattice", 10, 1), ("jittered_q2_h0.02", 25, 0),
+                                           ("jittered_q2_h0.02", 25, 1), ("jittered_q3_h0.02", 10, 0)])
+def test_run_gamma_matches_oracle(vrm, orc, name, steps, det):
     """Sec. 3.3-3.4: whole SSP-RK3 runs; Gamma within 1e-5 relative L2 of the oracle,
-    circulation kept to 1e-5 of ||Gamma||_1."""
+    circulation kept to 1e-5 of ||Gamma||_1, with the FP32 atomic sums and with the
+    deterministic fixed-point sums."""
     wl = CONFIGS[name]
-    _say("case", name, steps)
-    ctx, (x, y, g, ids), ref = _run_parity(vrm, orc, wl, steps)
+    _say("case", name, steps, "deterministic", det)
+    ctx, (x, y, g, ids), ref = _run_parity(vrm, orc, wl, steps, det)
     err = _rel_l2_by_id(ids, g, ref.ids, ref.gamma)
     cnt = ctx.vrm_read_counters()
     _say(name, "N", x.size, ref.x.size, "rel L2", err, cnt)
@@ -489,3 +497,98 @@ def test_cooperative_small_lps_give_identical_stencils(vrm, name, objective):
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
     assert pa == pb and na == nb
 
+
+
+# ------------------------------------------------------------------ deterministic accumulation
+@pytest.mark.parametrize("name", ["lattice", "jittered_q3_h0.02", "vortices_h0.02"])
+def test_deterministic_runs_are_bit_identical(vrm, name):
+    """vrm_params.deterministic: the update is summed in 64-bit fixed point, so runs
+    whose atomics arrive in another order (other launch shapes) give bit-identical
+    circulations and positions."""
+    wl = CONFIGS[name]
+    P = vrm.params_of(wl, deterministic=1)
+    vt = vrm.vortex_table(wl.vortices) if wl.vortices is not None else None
+    out = []
+    for tuning in (None, {"lp_small_blocks": 1, "lp_full_blocks": 3, "lp_small_lanes": 8}, {"lp_small_coop": 1}):
+        cloud = _gpu_cloud(vrm, wl, cap_factor=4)
+        ctx = vrm.Context(cloud.capacity)
+        ctx.vrm_set_tuning(tuning)
+        t = wl.t0
+        for _ in range(4):
+            ctx.vrm_step(cloud, P, vt, t)
+            t += wl.dt
+        torch.cuda.synchronize()
+        x, y, g, ids = cloud.numpy()
+        o = np.argsort(ids)
+        out.append((ids[o], x[o], y[o], g[o]))
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            np.testing.assert_array_equal(a, b)
+
+
+# ------------------------------------------------------------------ non-finite input
+def test_nonfinite_input_is_reported_and_leaves_the_cloud(vrm):
+    """Sec. 2's problem has finite positions and circulations: a NaN or infinite
+    one is flagged by the first kernel that reads it; vrm_step then returns
+    VRM_E_NONFINITE with the cloud unchanged, and works again once the value is
+    finite.  The asynchronous stage entry reports it through vrm_read_counters,
+    also without changing the cloud."""
+    wl = CONFIGS["jittered_q2_h0.02"]
+    P = vrm.params_of(wl)
+    for what, value in (("x", float("nan")), ("gamma", float("inf")), ("y", float("-inf"))):
+        cloud = _gpu_cloud(vrm, wl)
+        vrm.Context(cloud.capacity).vrm_step(cloud, P, None, wl.t0)
+        orig = float(getattr(cloud, what)[17].item())
+        getattr(cloud, what)[17] = value
+        before = [a.copy() for a in cloud.numpy()]
+        # a context that has not cached this cloud's cell list (a caller that
+        # edits the cloud between steps must not reuse one that has)
+        ctx = vrm.Context(cloud.capacity)
+        with pytest.raises(vrm.VrmError) as e:
+            ctx.vrm_step(cloud, P, None, wl.t0)
+        assert e.value.code == vrm.E_NONFINITE, e.value
+        after = cloud.numpy()
+        for a, b in zip(before, after):
+            np.testing.assert_array_equal(a, b)
+        # the asynchronous stages: no change, reported by the counters
+        ctx.vrm_set_diffused(cloud, torch.ones(cloud.capacity, dtype=torch.uint8, device="cuda"))
+        ctx.vrm_rk_stage(cloud, P, 0)
+        with pytest.raises(vrm.VrmError) as e:
+            ctx.vrm_read_counters()
+        assert e.value.code == vrm.E_NONFINITE
+        for a, b in zip(before, cloud.numpy()):
+            np.testing.assert_array_equal(a, b)
+        getattr(cloud, what)[17] = orig   # finite again
+        ctx.vrm_step(cloud, P, None, wl.t0)
+        assert np.isfinite(cloud.numpy()[2]).all()
+        _say("non-finite", what, "reported; step after repair ok, N", cloud.n)
+
+
+# ------------------------------------------------------------------ uncertified LPs
+def test_uncertified_lps_still_meet_the_moment_conditions(vrm):
+    """With a single certification round (test hook cert_rounds = 1) many 9-row LPs
+    end uncertified; each kept stencil must still satisfy the moment conditions and
+    the sign condition in FP64 (recomputed on the host), and the rest count as
+    infeasible."""
+    wl = CONFIGS["jittered_q3_h0.02"]
+    P = vrm.params_of(wl)
+    res = {}
+    for rounds in (0, 1):
+        cloud = _gpu_cloud(vrm, wl)
+        ctx = vrm.Context(cloud.capacity)
+        ctx.vrm_set_tuning({"cert_rounds": rounds})
+        ctx.vrm_insert_particles(cloud, P)
+        S, st = _gpu_stencils(vrm, ctx, cloud, P)
+        cnt = ctx.vrm_read_counters()
+        x, y, g, ids = cloud.numpy()
+        rows, cols, f = moments.stencil_columns(S)
+        host = moments.residuals(x, y, wl.h, wl.q, rows, cols, f)
+        rep = torch.zeros(4, dtype=torch.float64, device="cuda")
+        ctx.vrm_verify(cloud, P, st, rep)
+        _say("cert rounds", rounds or "default", "uncertified", cnt["n_uncertified"], "infeasible",
+             cnt["n_infeasible"], "solved", rows.size, "max residual host", host.max(), "kernel", float(rep[0]))
+        assert host.max() <= 1e-6 and abs(host.max() - float(rep[0])) <= 1e-13
+        assert (f >= 0.0).all()
+        res[rounds] = cnt
+    assert res[0]["n_uncertified"] == 0
+    assert res[1]["n_uncertified"] > 0

@@ -15,6 +15,7 @@ solver reproduces it: these tests check what any correct stencil satisfies.
 import numpy as np
 import pytest
 
+import moments
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -56,9 +57,16 @@ def _stencils(vrm, wl, mode):
     torch.cuda.synchronize()
     c1 = ctx.vrm_read_counters()
     n = cloud.n
+    # the FP64 moment residual recomputed on the host from the returned stencils
+    x, y, _, _ = cloud.numpy()
+    A = {k: getattr(st, k)[:n].cpu().numpy() for k in ("small_idx", "small_f", "status", "full_k", "full_idx",
+                                                      "full_f")}
+    rows, cols, f = moments.stencil_columns(A)
+    host = moments.residuals(x, y, wl.h, wl.q, rows, cols, f).max() if rows.size else 0.0
     # by particle id (each context orders its cloud by cell on its own)
     o = np.argsort(cloud.id[:n].cpu().numpy())
-    S = {k: getattr(st, k)[:n].cpu().numpy()[o] for k in ("small_f", "status", "full_k", "full_f")}
+    S = {k: A[k][o] for k in ("small_f", "status", "full_k", "full_f")}
+    S["host_residual"] = host
     return S, rep.cpu().numpy(), c1["pivots"] - c0["pivots"], c1["n_uncertified"] - c0["n_uncertified"]
 
 
@@ -68,9 +76,11 @@ def test_phase1_stencils_are_valid(vrm, name):
     m = 5 if wl.q == 2 else 9
     ref, rref, piv_ref, _ = _stencils(vrm, wl, 0)
     S, rep, piv, unc = _stencils(vrm, wl, 1)
-    _say(name, "moment residual", rep[0], "pivots", piv, "canonical", piv_ref, "uncertified", unc)
+    _say(name, "moment residual", rep[0], "host", S["host_residual"], "pivots", piv, "canonical", piv_ref,
+         "uncertified", unc)
     np.testing.assert_array_equal(S["status"], ref["status"])
-    assert rep[0] <= 1e-6
+    assert rep[0] <= 1e-6 and S["host_residual"] <= 1e-6
+    assert abs(rep[0] - S["host_residual"]) <= 1e-13
     assert abs(rep[1] - rref[1]) <= 1e-6 * rep[2]
     small = S["status"] == 0
     full = S["status"] == 1

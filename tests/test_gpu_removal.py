@@ -127,13 +127,27 @@ def test_repeated_removal_until_nothing_is_close_then_step(vrm, orc):
             break
     _say("calls", calls, "removed", total, "left candidates", nc)
     assert total > 0
-    # the context's cached state follows the compaction: a step still conserves I0
+    # the context's cached state follows the compaction: a step still conserves I0,
+    # and the particles it inserts get ids above every surviving one (Sec. 4.2 as
+    # the oracle does it: max id + 1, ...), so all ids stay distinct
     x, y, g, ids = cloud.numpy()
     s0 = g.astype(np.float64).sum()
+    mask, _, _ = orc.diffused(g.astype(np.float64), ids, wl.h, wl.q, wl.c_diff)
+    rx, ry, rg, rids, _ = orc.insert(x.astype(np.float64), y.astype(np.float64), g.astype(np.float64), ids, mask,
+                                     orc.params_of(wl))
     ctx.vrm_step(cloud, P, None, wl.t0)
     torch.cuda.synchronize()
-    g2 = cloud.numpy()[2]
+    x2, y2, g2, ids2 = cloud.numpy()
     assert abs(g2.astype(np.float64).sum() - s0) <= 1e-5 * np.abs(g).sum()
+    _say("after the removals: N", x.size, "max id", ids.max(), "inserted by the step", x2.size - x.size,
+         "oracle", rx.size - x.size)
+    assert x2.size > x.size and x.size > 0
+    assert np.unique(ids2).size == ids2.size
+    o, ro = np.argsort(ids2), np.argsort(rids)
+    np.testing.assert_array_equal(ids2[o], rids[ro])
+    # the new particles sit where the oracle put them (the stage moves nothing: u = 0)
+    np.testing.assert_array_equal(x2[o], rx[ro].astype(np.float32))
+    np.testing.assert_array_equal(y2[o], ry[ro].astype(np.float32))
 
 
 def test_removal_edges(vrm, orc):

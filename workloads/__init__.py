@@ -29,7 +29,8 @@ __all__ = [
     "Workload", "lattice", "lamb_oseen_omega", "lamb_oseen_velocity",
     "vortex_set", "vortices_gamma", "vortices_velocity",
     "config_lattice_small", "config_jittered", "config_vortices",
-    "config_scale", "config_close_pairs", "training_snapshot", "lone_particle", "PRESETS", "make",
+    "config_scale", "config_close_pairs", "training_snapshot", "lone_particle", "PRESETS", "make", "BENCH",
+    "c5_window",
 ]
 
 
@@ -102,29 +103,52 @@ def vortex_set(n_vortex: int, lo: float, hi: float, seed: int) -> dict:
     return {"cx": cx, "cy": cy, "sigma": sigma, "gamma": g}
 
 
+_CHUNK = 1 << 20
+
+
+def _chunked(fn, n, *arrays):
+    """fn over consecutive chunks of the particle arrays on a few threads (numpy
+    releases the interpreter lock in its loops); each particle's arithmetic, and
+    so every result bit, is the same as in one pass."""
+    if n <= _CHUNK:
+        return fn(*arrays)
+    from concurrent.futures import ThreadPoolExecutor
+    import os
+    bounds = [(a, min(a + _CHUNK, n)) for a in range(0, n, _CHUNK)]
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        parts = list(ex.map(lambda b: fn(*(arr[b[0]:b[1]] for arr in arrays)), bounds))
+    if isinstance(parts[0], tuple):
+        return tuple(np.concatenate([p[k] for p in parts]) for k in range(len(parts[0])))
+    return np.concatenate(parts)
+
+
 def vortices_gamma(v: dict, x, y, h: float, t: float = 0.0, nu: float = 0.0):
     """Particle circulations Gamma_i = omega(t, x_i) h^2 for a sum of Gaussian vortices."""
-    out = np.zeros_like(x, dtype=np.float64)
-    for cx, cy, s, g in zip(v["cx"], v["cy"], v["sigma"], v["gamma"]):
-        s2 = s * s + 4.0 * nu * t
-        out += g / (math.pi * s2) * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / s2)
-    return out * h * h
+    def part(x, y):
+        out = np.zeros_like(x, dtype=np.float64)
+        for cx, cy, s, g in zip(v["cx"], v["cy"], v["sigma"], v["gamma"]):
+            s2 = s * s + 4.0 * nu * t
+            out += g / (math.pi * s2) * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / s2)
+        return out * h * h
+    return _chunked(part, np.asarray(x).shape[0], np.asarray(x), np.asarray(y))
 
 
 def vortices_velocity(v: dict, x, y, t: float, nu: float):
     """Superposed Lamb-Oseen velocities of the spreading Gaussian vortices (prescribed field)."""
-    u = np.zeros_like(x, dtype=np.float64)
-    w = np.zeros_like(y, dtype=np.float64)
-    for cx, cy, s, g in zip(v["cx"], v["cy"], v["sigma"], v["gamma"]):
-        dx = x - cx
-        dy = y - cy
-        r2 = dx * dx + dy * dy
-        s2 = s * s + 4.0 * nu * t
-        with np.errstate(divide="ignore", invalid="ignore"):
-            fac = np.where(r2 > 0, g / (2 * math.pi * r2) * (1 - np.exp(-r2 / s2)), 0.0)
-        u -= fac * dy
-        w += fac * dx
-    return u, w
+    def part(x, y):
+        u = np.zeros_like(x, dtype=np.float64)
+        w = np.zeros_like(y, dtype=np.float64)
+        for cx, cy, s, g in zip(v["cx"], v["cy"], v["sigma"], v["gamma"]):
+            dx = x - cx
+            dy = y - cy
+            r2 = dx * dx + dy * dy
+            s2 = s * s + 4.0 * nu * t
+            with np.errstate(divide="ignore", invalid="ignore"):
+                fac = np.where(r2 > 0, g / (2 * math.pi * r2) * (1 - np.exp(-r2 / s2)), 0.0)
+            u -= fac * dy
+            w += fac * dx
+        return u, w
+    return _chunked(part, np.asarray(x).shape[0], np.asarray(x, np.float64), np.asarray(y, np.float64))
 
 
 def _f32(a):
@@ -233,6 +257,24 @@ def dirac_lamb_oseen(h: float) -> Workload:
     z = np.zeros(1, np.float32)
     return Workload(f"dirac_h{h}", z.copy(), z.copy(), np.array([2.0 * np.pi], np.float32), h=h, nu=nu, q=2,
                     dt=dt, steps=int(round(1.0 / dt)), t0=0.0)
+
+
+# the benchmark's workloads by name (bench.py, the autotuner, the full-size tests)
+BENCH = {
+    "lamb_oseen_h0.01_q2": lambda: config_jittered(h=0.01, q=2, seed=2),
+    "lamb_oseen_h0.01_q3": lambda: config_jittered(h=0.01, q=3, seed=2),
+    "vortices64_h0.005": lambda: config_vortices(),
+    "vortices256_h0.004_q3": lambda: config_scale(),
+}
+
+
+def c5_window(wl: Workload, half: float) -> Workload:
+    """The particles of a vortex-cloud workload inside [-half, half]^2, with their
+    circulations and the same prescribed velocity field (a bounded sample of the
+    workload for the host-side reference timing)."""
+    sel = (np.abs(wl.x) <= half) & (np.abs(wl.y) <= half)
+    return dataclasses.replace(wl, name=f"{wl.name}_window{half}", x=wl.x[sel].copy(), y=wl.y[sel].copy(),
+                               gamma=wl.gamma[sel].copy())
 
 
 PRESETS = {
