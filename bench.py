@@ -336,6 +336,42 @@ def solver_summary(r, steps, value_plain):
     return out
 
 
+def solver_accuracy(q=3, h=0.02, T=0.16):
+    """Accuracy of the stencil solvers on the Lamb-Oseen case (Sec. 5.1): for the
+    canonical LP, the first feasible vertex and non-negative least squares, the
+    weak error at T against the closed form, the largest moment residual of the
+    last stencils (verification kernel, FP64) and the time per step."""
+    import torch
+    import paper_1508_06379_amd as vrm
+    out = {"workload": f"lamb_oseen jittered lattice h={h} q={q}, SSP-RK3 to T={T}"}
+    for name, obj in (("canonical", 0), ("phase1_only", 1), ("nnls", 2)):
+        wl = workloads.config_jittered(h=h, q=q, seed=2)
+        steps = int(round(T / wl.dt))
+        cloud = vrm.Cloud(wl.x, wl.y, wl.gamma, capacity=4 * wl.n + 64)
+        ctx = vrm.Context(cloud.capacity)
+        ctx.vrm_set_lp_objective(obj)
+        P = vrm.params_of(wl)
+        t = wl.t0
+        ctx.vrm_step(cloud, P, None, t)
+        t += wl.dt
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps - 1):
+            ctx.vrm_step(cloud, P, None, t)
+            t += wl.dt
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / max(1, steps - 1)
+        x, y, g, _ = cloud.numpy()
+        st = vrm.Stencils.alloc(cloud.capacity)
+        ctx.vrm_solve_fractions(cloud, P, st)
+        rep = torch.zeros(4, dtype=torch.float64, device="cuda")
+        ctx.vrm_verify(cloud, P, st, rep)
+        torch.cuda.synchronize()
+        out[name] = {"weak_error": workloads.lamb_oseen_weak_error(x, y, g, t, wl.nu),
+                     "max_moment_residual": float(rep[0]), "ms_per_step": ms, "steps": steps}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,10 +380,11 @@ def main():
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--solver", default="all", choices=["all", "both", "plain", "learned", "previous", "phase1"],
+    ap.add_argument("--solver", default="all",
+                    choices=["all", "both", "plain", "learned", "previous", "phase1", "nnls"],
                     help="plain batched solver, learned warm start, previous-basis warm start, the first "
-                         "feasible vertex (phase I only); both = plain + learned, all = the four on the same "
-                         "workload")
+                         "feasible vertex (phase I only), non-negative least squares; both = plain + learned, "
+                         "all = the five on the same workload")
     ap.add_argument("--roofline-steps", type=int, default=5)
     ap.add_argument("--train-snapshots", type=int, default=30)
     ap.add_argument("--epochs", type=int, default=6)
@@ -383,6 +420,9 @@ def main():
     if args.solver in ("all", "phase1"):
         runs["phase1"] = run_gpu(wl, args.steps, args.warmup, tuning=tuning, lp_objective=1, **kw)
         log(f"phase1: {runs['phase1']['elapsed']:.3f} s")
+    if args.solver in ("all", "nnls"):
+        runs["nnls"] = run_gpu(wl, args.steps, args.warmup, tuning=tuning, lp_objective=2, **kw)
+        log(f"nnls: {runs['nnls']['elapsed']:.3f} s")
     if args.solver in ("all", "both", "learned"):
         theta, train_info = train_network(args.workload, args.train_snapshots, args.epochs)
         log(f"network: {train_info}")
@@ -396,7 +436,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copy calibration: 5 copies of {src.numel() * 4} bytes")
-    main_solver = next(k for k in ("plain", "learned", "previous", "phase1") if k in runs)
+    main_solver = next(k for k in ("plain", "learned", "previous", "phase1", "nnls") if k in runs)
     res = runs[main_solver]
     c = res["counters"]
     value = c["redistributions"] / res["elapsed"]
@@ -420,14 +460,19 @@ def main():
                "uncertified": c["n_uncertified"], "pivots": c["pivots"],
                "mean_complete_columns": c["full_cols"] / max(1, c["n_full"])},
     }
-    names = {"previous": "previous_basis", "phase1": "phase1_only", "learned": "learned"}
+    names = {"previous": "previous_basis", "phase1": "phase1_only", "nnls": "nnls", "learned": "learned"}
     for k, key in names.items():
         if k in runs and k != main_solver:
             line[key] = solver_summary(runs[k], args.steps, value if main_solver == "plain" else None)
     if "phase1_only" in line:
         line["phase1_only"]["note"] = "first feasible vertex (the paper's phase I); stencils differ from the canonical ones"
+    if "nnls" in line:
+        line["nnls"]["note"] = ("non-negative least squares (Lawson-Hanson, Sec. 4.1's alternative); pivots "
+                                "count the columns freed")
     if "learned" in line:
         line["learned"]["network"] = train_info
+    if args.solver == "all":
+        line["solver_accuracy"] = solver_accuracy()
     if not args.no_removal:
         line["removal"] = run_removal(oracle_too=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:

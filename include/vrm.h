@@ -237,7 +237,16 @@ int vrm_step(vrm_ctx* ctx, vrm_cloud* cloud, const vrm_params* p, const float* v
  * paper's method stops after phase I (fewer pivots; the stencil depends on the
  * pivoting rules, so results are checked by their moments, sign and
  * conservation, not against another solver).  A phase-I basis whose refined
- * values are not exactly feasible continues to the canonical stencil. */
+ * values are not exactly feasible continues to the canonical stencil.
+ * 2: non-negative least squares, min_{f >= 0} |V f - b|^2 (the alternative the
+ * paper discusses and sets aside in Sec. 4.1), by Lawson and Hanson's
+ * active-set method in FP32; the support it ends on gets its exact values from
+ * the same double-float refinement as a simplex basis, and a stencil whose
+ * refined values are not a non-negative solution of the moment conditions is
+ * reported infeasible.  Another non-negative solution than the canonical one
+ * (the method's path decides which).  Modes 1 and 2 leave counters' pivots as
+ * pivots or freed columns.  Mode 2 excludes warm starts (VRM_E_STATE from
+ * either setter while the other is on).  Errors: VRM_E_ARG for another mode. */
 int vrm_set_lp_objective(vrm_ctx* ctx, int mode);
 
 /* Launch shapes (performance only; results do not depend on them).  A zero
@@ -344,6 +353,15 @@ int vrm_collect_training(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params*
  * loss and gradient only. */
 int vrm_mlp_train_step(vrm_ctx* ctx, const uint16_t* x_dev, const float* y_dev, int32_t rows, float lr,
                        float weight_decay, float frac_weight, double* loss_dev, float* grad_dev);
+/* Test hook of the learned warm start: the network outputs the warm pass would use
+ * for the LPs queued at the current positions and diffused set (small LPs for
+ * q = 2: their 8 logits in columns 0..7, zeros after; complete LPs for q = 3: all
+ * 64 outputs), computed by the same fused kernels (input rows built on the device
+ * from the LPs' columns).  out_dev[max_rows][64] FP32, particle_dev[max_rows]: the
+ * cloud index of each row's particle; *rows_host = rows written.  Needs
+ * vrm_set_warm_start(ctx, 1).  Synchronises. */
+int vrm_warm_predictions(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params* p, float* out_dev,
+                         int32_t* particle_dev, int32_t max_rows, int32_t* rows_host);
 /* Forward pass: y_dev[rows][64] from x_dev[rows][128]. */
 int vrm_mlp_infer(vrm_ctx* ctx, const uint16_t* x_dev, int32_t rows, float* y_dev);
 /* Matrix product on the BF16 matrix cores (test hook): C[M][N] (FP32, zeroed

@@ -45,7 +45,7 @@ def build(force: bool = False) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("nu", ctypes.c_double), ("r", ctypes.c_double),
                 ("R", ctypes.c_double), ("R_full", ctypes.c_double), ("c_diff", ctypes.c_double),
-                ("dt", ctypes.c_double), ("q", ctypes.c_int)]
+                ("dt", ctypes.c_double), ("q", ctypes.c_int), ("solver", ctypes.c_int)]
 
 
 _lib = None
@@ -62,14 +62,26 @@ def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def params(h, nu=0.01, q=2, r=0.5, R=2.0, R_full=None, c_diff=1.0, dt=0.0) -> _Params:
+def params(h, nu=0.01, q=2, r=0.5, R=2.0, R_full=None, c_diff=1.0, dt=0.0, solver=0) -> _Params:
+    """solver 0: the canonical LP stencil; 1: non-negative least squares (Lawson-Hanson)."""
     if R_full is None:
         R_full = R if q == 2 else 3.0
-    return _Params(h, nu, r, R, R_full, c_diff, dt, q)
+    return _Params(h, nu, r, R, R_full, c_diff, dt, q, solver)
 
 
-def params_of(wl) -> _Params:
-    return _Params(wl.h, wl.nu, wl.r, wl.R, wl.R_full, wl.c_diff, wl.dt, wl.q)
+def params_of(wl, solver=0) -> _Params:
+    return _Params(wl.h, wl.nu, wl.r, wl.R, wl.R_full, wl.c_diff, wl.dt, wl.q, solver)
+
+
+def nnls(A: np.ndarray, b: np.ndarray):
+    """min_{f >= 0} |A f - b|^2 (Lawson-Hanson) -> (f, additions) or raises on a rank-deficient subproblem."""
+    A = np.ascontiguousarray(A, np.float64)
+    m, k = A.shape
+    f = np.zeros(k)
+    adds = lib().orc_nnls(m, k, _p(A), _p(np.ascontiguousarray(b, np.float64)), _p(f))
+    if adds < 0:
+        raise RuntimeError("orc_nnls: rank-deficient subproblem")
+    return f, adds
 
 
 def rows(q: int) -> int:
@@ -235,11 +247,12 @@ def initial_state(wl) -> OracleState:
 
 
 def step(state: OracleState, wl, insertion: bool = True, record: bool = True, stages_cb=None,
-         velocity=None) -> OracleState:
+         velocity=None, params=None) -> OracleState:
     """One SSP-RK3 step: diffused set and insertion at t^n, then three stages.
     velocity(x, y, gamma, t) -> (u, v) replaces the workload's prescribed field
-    (for instance the particles' own Biot-Savart velocity, Sec. 3.4 eq. nsode)."""
-    P = params_of(wl)
+    (for instance the particles' own Biot-Savart velocity, Sec. 3.4 eq. nsode);
+    params (default params_of(wl)) selects the stencil solver."""
+    P = params_of(wl) if params is None else params
     t_start = time.perf_counter()
     mask, _, _ = diffused(state.gamma, state.ids, wl.h, wl.q, wl.c_diff)
     n_before = state.x.shape[0]
@@ -322,10 +335,12 @@ def run_euler(wl, steps=None) -> OracleState:
     return st
 
 
-def run(wl, steps=None, insertion=True) -> OracleState:
+def run(wl, steps=None, insertion=True, solver=0) -> OracleState:
+    """steps of SSP-RK3 from the workload's cloud; solver as in params()."""
+    P = params_of(wl, solver=solver)
     st = initial_state(wl)
     for _ in range(wl.steps if steps is None else steps):
-        st = step(st, wl, insertion=insertion)
+        st = step(st, wl, insertion=insertion, params=P)
     return st
 
 

@@ -18,6 +18,8 @@
  *                     empty segment at radius 1.5 h
  *   moment LP         Sec. 2 eqs. (cond_two), (cond_alpha), (fii), (momcondmv);
  *                     Sec. 4.1: dense simplex on V f = b, f >= 0
+ *   NNLS              Sec. 4.1: the alternative min_{f >= 0} |V f - b|^2 by
+ *                     Lawson and Hanson's active-set method
  *   operator apply    Sec. 3.4 eq. (nsode): dGamma_i/dt = nu sum_j f_ji Gamma_j
  *   time stepping     Sec. 3.3: Euler steps; SSP Runge-Kutta schemes are convex
  *                     combinations of Euler steps (Shu-Osher SSP-RK3 here)
@@ -60,6 +62,7 @@
 typedef struct {
     double h, nu, r, R, R_full, c_diff, dt;
     int q;
+    int solver;   /* 0: the canonical LP (Sec. 4.1 simplex); 1: non-negative least squares (Lawson-Hanson) */
 } orc_params;
 
 static int rows_for_q(int q) { return q == 2 ? 5 : 9; }
@@ -259,14 +262,6 @@ static int nb_cmp_dist(const void* pa, const void* pb)
     if (a->d2 < b->d2) return -1;
     if (a->d2 > b->d2) return 1;
     return (a->id > b->id) - (a->id < b->id);
-}
-
-static int nb_cmp_seg(const void* pa, const void* pb)
-{
-    const orc_nb* a = (const orc_nb*)pa;
-    const orc_nb* b = (const orc_nb*)pb;
-    if (a->seg != b->seg) return a->seg - b->seg;
-    return nb_cmp_dist(pa, pb);
 }
 
 /* All j != i with lo2 <= d2 <= hi2 (FP32), written to out (capacity cap).
@@ -543,6 +538,130 @@ void orc_moment_rhs(int q, double* b)
 
 /* Solve the canonical LP over the given columns (particle indices cols[0..k)).
  * Returns LP status; f (k entries) normalised fractions. */
+/* ------------------------------------------------------------- NNLS */
+/* Least squares on the columns in set[0..p): z = argmin |A_set z - b| by Householder
+ * QR (m rows, p <= m columns).  Returns 0, or -1 if A_set is rank deficient. */
+static int ls_solve(int m, int k, const double* A, const double* b, const int* set, int p, double* z)
+{
+    double Q[ORC_MMAX][ORC_MMAX], c[ORC_MMAX];
+    if (p > m) return -1;
+    for (int a = 0; a < m; ++a) {
+        c[a] = b[a];
+        for (int t = 0; t < p; ++t) Q[a][t] = A[a * k + set[t]];
+    }
+    double scale = 0.0;
+    for (int a = 0; a < m; ++a)
+        for (int t = 0; t < p; ++t) scale = fmax(scale, fabs(Q[a][t]));
+    for (int t = 0; t < p; ++t) {
+        /* reflect column t below the diagonal onto e_t */
+        double nrm = 0.0;
+        for (int a = t; a < m; ++a) nrm += Q[a][t] * Q[a][t];
+        nrm = sqrt(nrm);
+        if (nrm <= 1e-13 * scale) return -1;
+        double alpha = Q[t][t] > 0.0 ? -nrm : nrm;
+        double v[ORC_MMAX];
+        for (int a = 0; a < m; ++a) v[a] = a < t ? 0.0 : Q[a][t];
+        v[t] -= alpha;
+        double vv = 0.0;
+        for (int a = t; a < m; ++a) vv += v[a] * v[a];
+        for (int u = t; u < p; ++u) {
+            double s = 0.0;
+            for (int a = t; a < m; ++a) s += v[a] * Q[a][u];
+            s = 2.0 * s / vv;
+            for (int a = t; a < m; ++a) Q[a][u] -= s * v[a];
+        }
+        double s = 0.0;
+        for (int a = t; a < m; ++a) s += v[a] * c[a];
+        s = 2.0 * s / vv;
+        for (int a = t; a < m; ++a) c[a] -= s * v[a];
+    }
+    for (int t = p - 1; t >= 0; --t) {
+        double s = c[t];
+        for (int u = t + 1; u < p; ++u) s -= Q[t][u] * z[u];
+        z[t] = s / Q[t][t];
+    }
+    return 0;
+}
+
+/* Non-negative least squares min_{f >= 0} |A f - b|^2 (the alternative of Sec. 4.1,
+ * solved as Lawson and Hanson do): start with every column at zero; repeatedly
+ * free the column whose negative gradient w_j = a_j . (b - A f) is largest (the
+ * lowest index among equal ones), solve the unconstrained least-squares problem on
+ * the free columns, and while that solution has a non-positive entry step back
+ * from the current point towards it until the first entry reaches zero and fix
+ * the entries at zero again.  Stops when no fixed column has w_j above a relative
+ * 1e-12.  Returns the number of free-column additions, or -1 on a rank-deficient
+ * subproblem. */
+int orc_nnls(int m, int k, const double* A, const double* b, double* f)
+{
+    int set[ORC_MMAX + 1], p = 0;
+    int inset[ORC_KMAX];
+    double z[ORC_MMAX + 1], xs[ORC_MMAX + 1];
+    double anorm = 0.0, bnorm = 0.0;
+    for (int j = 0; j < k; ++j) {
+        f[j] = 0.0;
+        inset[j] = 0;
+        for (int a = 0; a < m; ++a) anorm = fmax(anorm, fabs(A[a * k + j]));
+    }
+    for (int a = 0; a < m; ++a) bnorm = fmax(bnorm, fabs(b[a]));
+    const double tol = 1e-12 * anorm * bnorm * m;
+    int adds = 0;
+    for (int outer = 0; outer < 4 * k + 16; ++outer) {
+        double r[ORC_MMAX];
+        for (int a = 0; a < m; ++a) {
+            double s = b[a];
+            for (int t = 0; t < p; ++t) s -= A[a * k + set[t]] * f[set[t]];
+            r[a] = s;
+        }
+        int best = -1;
+        double wbest = tol;
+        for (int j = 0; j < k; ++j) {
+            if (inset[j]) continue;
+            double w = 0.0;
+            for (int a = 0; a < m; ++a) w += A[a * k + j] * r[a];
+            if (w > wbest) {
+                wbest = w;
+                best = j;
+            }
+        }
+        if (best < 0 || p == m) return adds;
+        set[p++] = best;
+        inset[best] = 1;
+        ++adds;
+        for (;;) {
+            if (ls_solve(m, k, A, b, set, p, z) != 0) return -1;
+            int allpos = 1;
+            for (int t = 0; t < p; ++t) allpos = allpos && z[t] > 0.0;
+            if (allpos) {
+                for (int t = 0; t < p; ++t) f[set[t]] = z[t];
+                break;
+            }
+            double alpha = 1.0;
+            for (int t = 0; t < p; ++t) {
+                xs[t] = f[set[t]];
+                if (z[t] <= 0.0) {
+                    double q = xs[t] / (xs[t] - z[t]);
+                    if (q < alpha) alpha = q;
+                }
+            }
+            int q2 = 0;
+            for (int t = 0; t < p; ++t) {
+                double v = xs[t] + alpha * (z[t] - xs[t]);
+                if (v <= 1e-15 * bnorm) {
+                    f[set[t]] = 0.0;
+                    inset[set[t]] = 0;
+                } else {
+                    f[set[t]] = v;
+                    set[q2++] = set[t];
+                }
+            }
+            p = q2;
+            if (p == 0) break;
+        }
+    }
+    return adds;
+}
+
 static int solve_columns(const double* x, const double* y, const int32_t* id, int i, const int* cols,
                          int k, const orc_params* P, double* f, int* pivots)
 {
@@ -562,6 +681,19 @@ static int solve_columns(const double* x, const double* y, const int32_t* id, in
         c[t] = pow(d, P->q + 1) + 0x1p-10 * rank;
     }
     orc_moment_rhs(P->q, b);
+    if (P->solver == 1) {
+        /* NNLS: a stencil when the least-squares residual vanishes (moments to 1e-10 of b) */
+        int adds = orc_nnls(m, k, A, b, f);
+        if (pivots) *pivots = adds > 0 ? adds : 0;
+        if (adds < 0) return 1;
+        double res = 0.0;
+        for (int a = 0; a < m; ++a) {
+            double s = -b[a];
+            for (int t = 0; t < k; ++t) s += A[a * k + t] * f[t];
+            res = fmax(res, fabs(s));
+        }
+        return res <= 2e-10 ? 0 : 1;
+    }
     return orc_lp(m, k, A, b, c, f, NULL, pivots);
 }
 
@@ -618,13 +750,12 @@ int orc_stencils(int n, const double* x, const double* y, const int32_t* id, con
         if (st == 0) {
             status[i] = 0;
         } else {
-            /* complete neighbourhood within R_full: KMAX nearest, ordered (segment, d2, id) */
+            /* complete neighbourhood within R_full: KMAX nearest, nearest first by (d2, id) */
             int cf = annulus_members(&g, x, y, id, i, lo2f, hi2f, mem, 512);
             if (cf > 512) { err = -3; continue; }
             kfull[i] = cf;
             qsort(mem, (size_t)cf, sizeof(orc_nb), nb_cmp_dist);
             k = cf < ORC_KMAX ? cf : ORC_KMAX;
-            qsort(mem, (size_t)k, sizeof(orc_nb), nb_cmp_seg);
             for (int t = 0; t < k; ++t) cl[t] = mem[t].idx;
             st = k >= 1 ? solve_columns(x, y, id, i, cl, k, P, fl, &piv) : 1;
             piv_sum += piv;

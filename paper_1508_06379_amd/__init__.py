@@ -80,7 +80,7 @@ EXPORTS = ["vrm_create", "vrm_destroy", "vrm_select_diffused", "vrm_set_diffused
            "vrm_read_counters",
            "vrm_vortex_velocity", "vrm_biot_savart", "vrm_set_lp_objective", "vrm_timing", "vrm_timing_groups", "vrm_read_timing", "vrm_mlp_load", "vrm_mlp_read",
            "vrm_set_warm_start", "vrm_collect_training", "vrm_mlp_train_step", "vrm_mlp_infer", "vrm_gemm_bf16",
-           "vrm_last_error", "vrm_status_string"]
+           "vrm_warm_predictions", "vrm_last_error", "vrm_status_string"]
 MLP_IN, MLP_OUT, MLP_PARAMS, MLP_SLOTS = 128, 64, 41280, 32
 TIMERS = ["select", "cells", "nbhd", "lp_small", "lp_full", "insert", "combine", "mlp", "full_cols"]
 
@@ -126,6 +126,8 @@ def lib():
         L.vrm_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                          vp, vp]
         L.vrm_mlp_infer.argtypes = [vp, vp, ctypes.c_int32, vp]
+        L.vrm_warm_predictions.argtypes = [vp, ctypes.POINTER(vrm_cloud), ctypes.POINTER(vrm_params), vp, vp,
+                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.vrm_gemm_bf16.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
                                     ctypes.c_int]
         L.vrm_timing.argtypes = [vp, ctypes.c_int]
@@ -358,6 +360,12 @@ class Context:
 
     def vrm_mlp_infer(self, x, rows, y):
         _check(lib().vrm_mlp_infer(self.handle, _ptr(x), int(rows), _ptr(y)))
+
+    def vrm_warm_predictions(self, cloud: Cloud, p: vrm_params, out, particle) -> int:
+        rows = ctypes.c_int32(0)
+        _check(lib().vrm_warm_predictions(self.handle, ctypes.byref(cloud.c), ctypes.byref(p), _ptr(out),
+                                          _ptr(particle), int(out.shape[0]), ctypes.byref(rows)))
+        return rows.value
 
     def vrm_gemm_bf16(self, a, b, c, M, N, K, trans_a=False, trans_b=False):
         _check(lib().vrm_gemm_bf16(self.handle, _ptr(a), _ptr(b), _ptr(c), M, N, K, int(trans_a), int(trans_b)))

@@ -760,6 +760,7 @@ int vrm_set_warm_start(vrm_ctx* c, int enable)
 {
     if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
     if (enable < 0 || enable > 2) return vrm_fail(VRM_E_ARG, "warm start mode %d (0, 1 or 2)", enable);
+    if (enable && c->lp_objective == 2) return vrm_fail(VRM_E_STATE, "the least-squares objective has no warm start");
     if (enable == 2) {
         if (!c->prev) {
             void* p = nullptr;
@@ -805,6 +806,32 @@ int vrm_collect_training(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, u
     VRM_HIP(hipStreamSynchronize(c->stream));
     int got = L.m == 5 ? q.last_small : q.last_full;
     *rows = got < max_rows ? got : max_rows;
+    return VRM_OK;
+}
+
+int vrm_warm_predictions(vrm_ctx* c, const vrm_cloud* cl, const vrm_params* p, float* out_dev, int32_t* particle_dev,
+                         int32_t max_rows, int32_t* rows_host)
+{
+    int r = check_cloud(c, cl);
+    if (!r) r = check_params(p);
+    if (!r) r = cached_n(c, cl);
+    if (!r && (!out_dev || !particle_dev || !rows_host || max_rows <= 0)) r = vrm_fail(VRM_E_ARG, "prediction buffers");
+    if (!r && (c->warm != 1 || !c->feat || !c->mlp || !c->mlp->loaded))
+        r = vrm_fail(VRM_E_STATE, "needs the learned warm start (vrm_mlp_load, vrm_set_warm_start(ctx, 1))");
+    if (r) return r;
+    vrm::LaunchParams L = launch_params(c, p);
+    if (!c->cells_valid) {
+        r = vrm_build_cells(c, cl->x_dev, cl->y_dev, cl->id_dev, c->n, L);
+        if (r) return r;
+        c->cells_valid = 1;
+    }
+    r = vrm_warm_predict_run(c, cl, c->n, L, out_dev, particle_dev, max_rows);
+    if (r) return r;
+    vrm::Queues q;
+    VRM_HIP(hipMemcpyAsync(&q, c->queues, sizeof(q), hipMemcpyDeviceToHost, c->stream));
+    VRM_HIP(hipStreamSynchronize(c->stream));
+    const int got = L.m == 5 ? q.last_small : q.last_full;
+    *rows_host = got < max_rows ? got : max_rows;
     return VRM_OK;
 }
 
@@ -918,7 +945,8 @@ int vrm_biot_savart(vrm_ctx* c, const vrm_cloud* cl, double eps, float* u_dev, f
 int vrm_set_lp_objective(vrm_ctx* c, int mode)
 {
     if (!c) return vrm_fail(VRM_E_ARG, "context is NULL");
-    if (mode != 0 && mode != 1) return vrm_fail(VRM_E_ARG, "lp objective must be 0 or 1 (got %d)", mode);
+    if (mode < 0 || mode > 2) return vrm_fail(VRM_E_ARG, "lp objective must be 0, 1 or 2 (got %d)", mode);
+    if (mode == 2 && c->warm) return vrm_fail(VRM_E_STATE, "the least-squares objective has no warm start (warm mode %d)", c->warm);
     c->lp_objective = mode;
     return VRM_OK;
 }

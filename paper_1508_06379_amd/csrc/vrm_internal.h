@@ -295,6 +295,8 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::Launc
                     int max_rows = 0);
 int vrm_small_nbhd_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp,
                        int32_t* small_idx, int32_t* kfull);
+int vrm_warm_predict_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const vrm::LaunchParams& lp, float* out,
+                         int32_t* particle, int max_rows);
 // launchers (vrm_stage.hip)
 int vrm_combine_run(vrm_ctx* c, vrm_cloud* cl, int32_t n, const float* u, const float* v, double dt,
                     float lam, int stage, int det);

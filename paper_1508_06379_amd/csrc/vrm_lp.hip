@@ -644,7 +644,7 @@ struct CoopCols {
 // the columns (column j = segment j) live in LDS.
 constexpr int kSmallBlock = 256;
 
-template <bool PH1>
+template <int OBJ>
 __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_lp_small(const int32_t* __restrict__ perm,
                                                           const float* __restrict__ xs, const float* __restrict__ ys,
                                                           const int32_t* __restrict__ ids, SmallRec rec,
@@ -734,7 +734,7 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
                 cs.lg[4] = b.x, cs.lg[5] = b.y, cs.lg[6] = b.z, cs.lg[7] = b.w;
             }
             uint64_t basis = 0;
-            st = solve_lp<5, PH1>(cs, P, store, fii, piv, certified, warm_pass, nullptr, warm, basis,
+            st = solve_lp<5, OBJ>(cs, P, store, fii, piv, certified, warm_pass, nullptr, warm, basis,
                              warm_pass && out.use_prev, pref);
             if (st == 0 && out.prev && (unsigned)own < (unsigned)out.prev_cap) record_basis(out.prev, own, basis, col_id);
             if (record) {
@@ -787,7 +787,7 @@ __global__ __launch_bounds__(kSmallBlock) __attribute__((amdgpu_waves_per_eu(3))
 // Small-neighbourhood LPs with eight lanes each (CoopCols): the same LPs, the
 // same pivots and results as k_lp_small, in one eighth of its dependent chain
 // per pivot (one column priced per lane).  Plain and phase-I passes only.
-template <bool PH1>
+template <int OBJ>
 __global__ __launch_bounds__(kSmallBlock) void k_lp_small_coop(const float* __restrict__ gamma,
                                                                SmallRec rec, const int32_t* __restrict__ q_small,
                                                                Queues* qs, int32_t* q_full, float* acc,
@@ -835,7 +835,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small_coop(const float* __re
             };
             int warm = 0;
             uint64_t basis = 0;
-            st = solve_lp<5, PH1>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false, 0ull);
+            st = solve_lp<5, OBJ>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false, 0ull);
             if (st == 0) {
                 const float g = gamma[i];
                 if (apply && fv != 0.0f) acc_add(acc, pj, fv, g, dsc);
@@ -977,7 +977,7 @@ __device__ int collect_full(int t, float xi, float yi, const GridState& g, const
 // pricing, three resident blocks per CU) or computed from the offsets when
 // priced (36 KB: four blocks per CU).  Small clouds, whose launches are one
 // wave's latency, take the first; large ones, throughput-bound, the second.
-template <int M, bool SC, bool PH1, bool WARM>
+template <int M, bool SC, int OBJ, bool WARM>
 __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restrict__ perm,
                                                         const float* __restrict__ xs, const float* __restrict__ ys,
                                                         const int32_t* __restrict__ ids,
@@ -1074,7 +1074,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
                                       ? prev_mask(out.prev, own, k, col_id)
                                       : 0ull;
             uint64_t basis = 0;
-            st = k > 0 ? solve_lp<M, PH1, WARM>(cs, P, store, fii, piv, certified, warm_pass, logit, warm, basis,
+            st = k > 0 ? solve_lp<M, OBJ, WARM>(cs, P, store, fii, piv, certified, warm_pass, logit, warm, basis,
                                      warm_pass && out.use_prev, pref)
                        : 1;
             if (st == 0 && out.prev && (unsigned)own < (unsigned)out.prev_cap) record_basis(out.prev, own, basis, col_id);
@@ -1380,11 +1380,15 @@ struct SiftCols {
             y = sy[j * kFullBlock];
             c = sc[j * kFullBlock];
         } else {
-            df X, Y, C;
-            exact(j, X, Y, C);
-            x = X.hi;
-            y = Y.hi;
-            c = C.hi;
+            // FP32 offset (the high part of the exact one: the scale is a power
+            // of two) and FP32 cost; the exact ones are recomputed for certification
+            const int m = row[j];
+            const int u = (int)((unsigned)m >> 6);
+            x = (xs[u] - xi) * P->scale2e;
+            y = (ys[u] - yi) * P->scale2e;
+            const float d2 = x * x + y * y;
+            const float w = P->q == 2 ? d2 * __builtin_sqrtf(d2) : d2 * d2;
+            c = __builtin_fmaf(w, P->cs_hi, tie_weight((unsigned)m & 63u, P->q));
         }
     }
     __device__ __forceinline__ void load(int j, float& x, float& y, uint32_t& aux) const
@@ -1400,7 +1404,7 @@ struct SiftCols {
     }
 };
 
-template <int M, int W, bool PH1>
+template <int M, int W, int OBJ>
 __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_lp_sift(
     const int32_t* __restrict__ perm, const float* __restrict__ xs, const float* __restrict__ ys,
     const int32_t* __restrict__ order, const int32_t* __restrict__ kcol, const int32_t* __restrict__ rec,
@@ -1467,7 +1471,7 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
             };
             int warm = 0;
             uint64_t basis = 0;
-            st = solve_lp<M, PH1, false>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false, 0ull,
+            st = solve_lp<M, OBJ, false>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false, 0ull,
                                          cstat);
             if (st == 0) {
                 if (apply) acc_add(acc, i, fii, g_i, dsc);
@@ -1808,6 +1812,26 @@ int nbhd_blocks(int n) { return n <= kNbhdCoopMaxN ? (n + 256 / kNbL - 1) / (256
 // clouds up to the tuned size launch the complete-LP kernel with stored costs
 bool full_stored_costs(const vrm_ctx* c, int n) { return n <= c->tuning.full_stored_cost_n; }
 
+// the instantiation of an LP kernel for the context's objective (0 canonical,
+// 1 phase I only, 2 non-negative least squares)
+template <class F>
+F by_objective(int obj, F canonical, F phase1, F nnls)
+{
+    return obj == 2 ? nnls : obj == 1 ? phase1 : canonical;
+}
+template <int M, bool SC>
+auto full_kernel(int obj) -> decltype(&k_lp_full<M, SC, 0, false>)
+{
+    return by_objective(obj, k_lp_full<M, SC, 0, false>, k_lp_full<M, SC, 1, false>, k_lp_full<M, SC, 2, false>);
+}
+// warm passes exist for the simplex objectives only (the setters keep warm
+// starts and the least-squares objective apart)
+template <bool SC>
+auto full_warm_kernel(int obj) -> decltype(&k_lp_full<9, SC, 0, true>)
+{
+    return obj == 1 ? k_lp_full<9, SC, 1, true> : k_lp_full<9, SC, 0, true>;
+}
+
 }  // namespace
 
 int vrm_small_nbhd_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchParams& lp, int32_t* small_idx,
@@ -1879,17 +1903,17 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
     if (lp.m == 5) {
         {
             ScopedTimer tm(c, VRM_T_LP_SMALL);
-            if (!warm && c->tuning.lp_small_coop && !feat_out) {
+            if (!warm && c->tuning.lp_small_coop && !feat_out && lp.phase1 != 2) {
                 // eight lanes per LP (plain or phase-I pass)
                 const int per_block = kSmallBlock / 8;
                 const int grid = min((n + per_block - 1) / per_block, c->tuning.lp_small_blocks);
-                hipLaunchKernelGGL((lp.phase1 ? k_lp_small_coop<true> : k_lp_small_coop<false>), dim3(max(grid, 1)),
+                hipLaunchKernelGGL((lp.phase1 == 1 ? k_lp_small_coop<1> : k_lp_small_coop<0>), dim3(max(grid, 1)),
                                    dim3(kSmallBlock), 0, c->stream, cl->gamma_dev, c->srec, c->q_small, c->queues,
                                    c->q_full, c->acc, lp, out, apply, c->counters, c->grid);
                 VRM_HIP(hipGetLastError());
             } else {
                 for (int mode = first; mode <= (warm ? kLpRetry : kLpPlain); ++mode) {
-                    hipLaunchKernelGGL((lp.phase1 ? k_lp_small<true> : k_lp_small<false>), dim3(lp_grid_small(c, n)),
+                    hipLaunchKernelGGL((by_objective(lp.phase1, k_lp_small<0>, k_lp_small<1>, k_lp_small<2>)), dim3(lp_grid_small(c, n)),
                                        dim3(kSmallBlock), 0, c->stream, c->perm, c->xs, c->ys, c->ids, c->srec,
                                        c->q_small, c->queues, c->q_full, cl->gamma_dev, c->acc, lp, out, apply,
                                        c->counters, mode, c->q_retry, c->tuning.lp_small_lanes, c->grid);
@@ -1904,8 +1928,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         o2.lab = nullptr;
         ScopedTimer tm(c, VRM_T_LP_FULL);
         const bool stored = full_stored_costs(c, n);
-        hipLaunchKernelGGL((lp.phase1 ? (stored ? k_lp_full<5, true, true, false> : k_lp_full<5, false, true, false>)
-                                      : (stored ? k_lp_full<5, true, false, false> : k_lp_full<5, false, false, false>)),
+        hipLaunchKernelGGL((stored ? full_kernel<5, true>(lp.phase1) : full_kernel<5, false>(lp.phase1)),
                            dim3(min(lp_grid_full(c, n), 64)), dim3(kFullBlock), 0, c->stream, c->perm,
                            c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                            o2, apply, c->counters, kLpPlain, c->q_retry, 1);
@@ -1922,13 +1945,13 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
             VRM_HIP(hipGetLastError());
         }
         ScopedTimer tm(c, VRM_T_LP_FULL);
-        hipLaunchKernelGGL((lp.phase1 ? k_lp_sift<9, kSiftW, true> : k_lp_sift<9, kSiftW, false>),
+        hipLaunchKernelGGL((by_objective(lp.phase1, k_lp_sift<9, kSiftW, 0>, k_lp_sift<9, kSiftW, 1>, k_lp_sift<9, kSiftW, 2>)),
                            dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
                            c->full_order, c->full_k, c->full_cols, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, out,
                            apply, c->counters, 0, c->grid);
         // lists too long for the collection groups (none in practice): the one-thread
         // kernel from the retry queue; as the run's last LP launch it empties the queues
-        hipLaunchKernelGGL((lp.phase1 ? k_lp_full<9, false, true, false> : k_lp_full<9, false, false, false>),
+        hipLaunchKernelGGL((full_kernel<9, false>(lp.phase1)),
                            dim3(1), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys, c->ids, c->cell_start,
                            c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, out, apply, c->counters, kLpRetry,
                            c->q_retry, 1);
@@ -1940,16 +1963,68 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
             const bool stored = full_stored_costs(c, n);
             // the warm pass carries the crash code; plain and retry launches do not
             const bool w = mode == kLpWarm;
-            hipLaunchKernelGGL((lp.phase1 ? (stored ? (w ? k_lp_full<9, true, true, true> : k_lp_full<9, true, true, false>)
-                                                    : (w ? k_lp_full<9, false, true, true> : k_lp_full<9, false, true, false>))
-                                          : (stored ? (w ? k_lp_full<9, true, false, true> : k_lp_full<9, true, false, false>)
-                                                    : (w ? k_lp_full<9, false, false, true> : k_lp_full<9, false, false, false>))),
+            hipLaunchKernelGGL((stored ? (w ? full_warm_kernel<true>(lp.phase1) : full_kernel<9, true>(lp.phase1))
+                                         : (w ? full_warm_kernel<false>(lp.phase1) : full_kernel<9, false>(lp.phase1))),
                                dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
                                c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                                out, apply, c->counters, mode, c->q_retry, mode == last ? 1 : 0);
             VRM_HIP(hipGetLastError());
         }
     }
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
+}
+
+// Network outputs of the queued LPs as the warm pass sees them (test hook of the
+// fused inference): small LPs' 8 logits or complete LPs' 64 outputs, and the
+// particle of each row.
+namespace {
+__global__ void k_pred_out(const Queues* qs, int m, const float* __restrict__ pred, const int32_t* __restrict__ rec_i,
+                           const int32_t* __restrict__ perm, const int32_t* __restrict__ q_full, int max_rows,
+                           float* out, int32_t* particle)
+{
+    const int nq = m == 5 ? qs->n_small : qs->n_full;
+    const int rows = min(nq, max_rows);
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
+        for (int a = 0; a < kMlpOut; ++a)
+            out[(size_t)r * kMlpOut + a] = m == 5 ? (a < VRM_NSEG ? pred[(size_t)r * VRM_NSEG + a] : 0.0f)
+                                                  : pred[(size_t)r * kMlpOut + a];
+        particle[r] = m == 5 ? rec_i[r] : perm[q_full[r]];
+    }
+}
+__global__ void k_queues_done(Queues* qs)
+{
+    qs->last_small = qs->n_small;
+    qs->last_full = qs->n_full;
+    qs->n_small = 0;
+    qs->n_full = 0;
+    qs->n_retry = 0;
+    qs->blocks_done = 0;
+}
+}  // namespace
+
+int vrm_warm_predict_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchParams& lp, float* out,
+                         int32_t* particle, int max_rows)
+{
+    if (n <= 0) return VRM_OK;
+    const bool coop = n <= kNbhdCoopMaxN;
+    hipLaunchKernelGGL(coop ? k_small_nbhd_coop : k_small_nbhd, dim3(nbhd_blocks(n)), dim3(256), 0, c->stream, n,
+                       cl->n_dev, c->perm, c->xs, c->ys, c->ids, c->cell_start, c->diffused, c->grid, lp, c->srec,
+                       c->q_small, c->q_full, c->queues, (int32_t*)nullptr, (int32_t*)nullptr, 0);
+    VRM_HIP(hipGetLastError());
+    int r;
+    if (lp.m == 5) {
+        r = vrm_mlp_infer_small_run(c, n, &c->queues->n_small, c->srec, lp.sc, lp.q, c->pred);
+    } else {
+        hipLaunchKernelGGL(k_feat_full, dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->xs, c->ys, c->ids,
+                           c->cell_start, c->grid, c->q_full, c->queues, lp, c->feat);
+        VRM_HIP(hipGetLastError());
+        r = vrm_mlp_infer_run(c, c->feat, n, c->pred, &c->queues->n_full);
+    }
+    if (r) return r;
+    hipLaunchKernelGGL(k_pred_out, dim3(256), dim3(256), 0, c->stream, c->queues, lp.m, c->pred, c->srec.i, c->perm,
+                       c->q_full, max_rows, out, particle);
+    hipLaunchKernelGGL(k_queues_done, dim3(1), dim3(1), 0, c->stream, c->queues);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }

@@ -29,6 +29,7 @@ constexpr float kTolPiv = 1e-6f;                  // FP32 pivot tolerance (relat
 constexpr float kTolFeas = 1e-3f;                 // phase-I infeasibility (relative to the rhs)
 constexpr float kCertD = 1e-9f;                   // certified reduced-cost tolerance (relative)
 constexpr float kCertX = 1e-9f;                   // certified primal tolerance (absolute, fhat units)
+constexpr float kNnlsRes = 1e-5f;                 // NNLS: residual of a found support (relative to b)
 constexpr int kMaxRefine = 6;
 constexpr float kFastMargin = 1e-3f;              // FP32 reduced-cost margin of the fast certificate
 
@@ -123,9 +124,11 @@ __device__ __forceinline__ df rhs_df(int a, const LaunchParams& P)
 //   int active()     columns the simplex prices (a prefix of the k; k by default)
 //   kLds, load_lds(j, ...)  columns j < kLds are in LDS: load without the general path
 //   bool widen()     price every column from now on; false if that is already so
-// The simplex declares a phase finished only after widen() returned false, so
-// a store whose working set is the nearest columns (most optimal stencils use
-// only those) gives the same certified optimum as pricing all of them.
+// The simplex declares phase II optimal, or phase I infeasible, only after
+// widen() returned false (a feasible phase I goes on to phase II on the working
+// set), so a store whose working set is the nearest columns (most optimal
+// stencils use only those) gives the same certified optimum as pricing all of
+// them.
 // A store with kCoop spreads the columns over a group of lanes, one each
 // (own, x, y, c: this lane's column); every lane of the group runs this
 // simplex on the same, replicated state, and the loops over columns become
@@ -516,13 +519,22 @@ struct ThreadSimplex {
             prices(p2, y);
             const int e = price(cs, y, p2, it >= bland_after);
             if (e < 0) {
-                if (cs.widen()) continue;   // the working set is done: price every column
-                if (p2) return 0;
+                // a working set of columns (sifting) is widened to every column
+                // when it is done: at the end of phase II, or at the end of a
+                // phase I that found it infeasible; a feasible phase I goes on
+                // to phase II on the working set
+                if (p2) {
+                    if (cs.widen()) continue;
+                    return 0;
+                }
                 // end of phase I: feasible iff the artificial variables vanished
                 float art = 0.0f;
 #pragma unroll
                 for (int r = 0; r < M; ++r) art += bs[r] >= ART ? fabsf(xb[r]) : 0.0f;
-                if (art > kTolFeas * P_bt()) return 1;
+                if (art > kTolFeas * P_bt()) {
+                    if (cs.widen()) continue;
+                    return 1;
+                }
 #pragma unroll
                 for (int r = 0; r < M; ++r) {
                     float c = 0.0f;
@@ -898,15 +910,300 @@ struct ThreadSimplex {
 template <int M>
 constexpr int warm_cap() { return M == 5 ? 3 : 12; }
 
-// PH1: phase I only (the first feasible vertex, P.phase1) compiled in; the
-// canonical-only instantiation carries none of its code.
+// Non-negative least squares (Sec. 4.1's alternative: min_{f >= 0} |V f - b|^2,
+// Lawson and Hanson's active-set method) in FP32 to find the stencil's support:
+// free the column with the largest negative gradient w_j = v_j . (b - V f) (the
+// lowest index among equal ones, relative tolerance kTolD), solve the
+// unconstrained least squares on the free columns (Householder QR, at most M
+// of them), step back towards it and fix again the entries that reach zero while
+// it has a non-positive entry.  The support's exact values then come from the
+// double-float refinement of the basis it spans (the columns enter the
+// artificial basis by their largest pivot element); a support whose exact
+// values are not a non-negative solution of the moment conditions counts as
+// infeasible.  Returns 0 or 1 as solve_lp.
+// Columns of the least-squares problem in the paper's units: monomials of the
+// offset over h (the stored offsets are over 2^e = s h), right-hand side 2 at
+// the second-order rows.  The simplex may scale rows (it does not change the
+// solution set); least squares may not (row weights change the path).
+template <int M, class CS>
+__device__ __forceinline__ void nnls_column(const CS& cs, const LaunchParams& P, int j, float (&v)[M])
+{
+    float rx, ry, cc;
+    cs.get(j, rx, ry, cc);
+    mono<M>(rx * P.sc, ry * P.sc, v);
+}
+template <int M>
+__device__ __forceinline__ float nnls_rhs(int a) { return rhs_row<M>(a) ? 2.0f : 0.0f; }
+
+// Unconstrained least squares on the free columns set[0..p) (Householder QR);
+// false if a column is (numerically) dependent on the ones before it.
+template <int M, class CS>
+__device__ bool nnls_least_squares(const CS& cs, const LaunchParams& P, const int (&set)[M], int p, float (&z)[M])
+{
+    float Q[M][M], c[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) c[a] = nnls_rhs<M>(a);
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        float v[M];
+        if (t < p) {
+            nnls_column<M>(cs, P, set[t], v);
+        } else {
+#pragma unroll
+            for (int a = 0; a < M; ++a) v[a] = 0.0f;
+        }
+#pragma unroll
+        for (int a = 0; a < M; ++a) Q[a][t] = v[a];
+    }
+    float scale = 0.0f;
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+        for (int t = 0; t < M; ++t) scale = fmaxf(scale, fabsf(Q[a][t]));
+    bool ok = true;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        if (t >= p) continue;
+        float nrm = 0.0f;
+#pragma unroll
+        for (int a = 0; a < M; ++a) nrm = a >= t ? __builtin_fmaf(Q[a][t], Q[a][t], nrm) : nrm;
+        nrm = __builtin_sqrtf(nrm);
+        ok = ok && nrm > 1e-6f * scale;
+        const float alpha = Q[t][t] > 0.0f ? -nrm : nrm;
+        float v[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) v[a] = a < t ? 0.0f : Q[a][t];
+        v[t] -= alpha;
+        float vv = 0.0f;
+#pragma unroll
+        for (int a = 0; a < M; ++a) vv = __builtin_fmaf(v[a], v[a], vv);
+        const float inv = vv > 0.0f ? 2.0f / vv : 0.0f;
+#pragma unroll
+        for (int u = 0; u < M; ++u) {
+            if (u < t || u >= p) continue;
+            float sd = 0.0f;
+#pragma unroll
+            for (int a = 0; a < M; ++a) sd = __builtin_fmaf(v[a], Q[a][u], sd);
+            sd *= inv;
+#pragma unroll
+            for (int a = 0; a < M; ++a) Q[a][u] = __builtin_fmaf(-sd, v[a], Q[a][u]);
+        }
+        float sd = 0.0f;
+#pragma unroll
+        for (int a = 0; a < M; ++a) sd = __builtin_fmaf(v[a], c[a], sd);
+        sd *= inv;
+#pragma unroll
+        for (int a = 0; a < M; ++a) c[a] = __builtin_fmaf(-sd, v[a], c[a]);
+    }
+#pragma unroll
+    for (int t = M - 1; t >= 0; --t) {
+        float sd = c[t];
+#pragma unroll
+        for (int u = t + 1; u < M; ++u) sd = u < p ? __builtin_fmaf(-Q[t][u], z[u], sd) : sd;
+        z[t] = t < p ? sd / Q[t][t] : 0.0f;
+    }
+    return ok;
+}
+
+template <int M, class CS, class Store>
+__device__ int solve_nnls(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified,
+                          uint64_t& basis)
+{
+    const int k = cs.k;
+    int set[M];
+    float fz[M];
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        set[t] = 0;
+        fz[t] = 0.0f;
+    }
+    int p = 0;
+    uint64_t inP = 0;
+    uint64_t tabu = 0;   // freed columns whose least-squares value came out <= 0 (FP32 rounding)
+    basis = 0;
+    certified = 1;
+    fii = 0.0f;
+    // first pass: stop once the free columns reproduce b to FP32 accuracy; if
+    // the exact values on that support are not a solution (a column with a
+    // tiny share is still missing), go on until no gradient is positive
+    bool res_stop = true;
+    ThreadSimplex<M, CS> lp;
+    df x[M];
+    for (int pass = 0; pass < 2; ++pass) {
+        bool stopped_by_residual = false;
+        for (int outer = 0; outer < 3 * M + 8; ++outer) {
+            // residual of the current point and the column with the largest negative gradient
+            float r[M];
+#pragma unroll
+            for (int a = 0; a < M; ++a) r[a] = nnls_rhs<M>(a);
+#pragma unroll
+            for (int t = 0; t < M; ++t) {
+                if (t >= p) continue;
+                float v[M];
+                nnls_column<M>(cs, P, set[t], v);
+#pragma unroll
+                for (int a = 0; a < M; ++a) r[a] = __builtin_fmaf(-fz[t], v[a], r[a]);
+            }
+            float rmax = 0.0f;
+#pragma unroll
+            for (int a = 0; a < M; ++a) rmax = fmaxf(rmax, fabsf(r[a]));
+            if (res_stop && p > 0 && rmax <= 2.0f * kNnlsRes) {
+                stopped_by_residual = true;
+                break;
+            }
+            int best = -1;
+            float wbest = 0.0f;
+            for (int j = 0; j < k; ++j) {
+                if (((inP | cs.dead | tabu) >> j) & 1ull) continue;
+                float v[M];
+                nnls_column<M>(cs, P, j, v);
+                float w = 0.0f, sc = 0.0f;
+#pragma unroll
+                for (int a = 0; a < M; ++a) {
+                    w = __builtin_fmaf(v[a], r[a], w);
+                    sc = __builtin_fmaf(fabsf(v[a]), fabsf(r[a]), sc);
+                }
+                if (w > kTolD * sc && w > wbest) {
+                    best = j;
+                    wbest = w;
+                }
+            }
+            if (best < 0 || p == M) break;
+#pragma unroll
+            for (int t = 0; t < M; ++t)
+                if (t == p) {
+                    set[t] = best;
+                    fz[t] = 0.0f;
+                }
+            ++p;
+            ++piv;
+            inP |= 1ull << best;
+            for (int inner = 0; inner < M + 2 && p > 0; ++inner) {
+                float z[M];
+                if (!nnls_least_squares<M>(cs, P, set, p, z)) return 1;
+                if (inner == 0) {
+                    // in exact arithmetic the freed column's value is positive; if
+                    // rounding says otherwise it is fixed again and not freed until
+                    // another column has been
+                    float znew = 0.0f;
+#pragma unroll
+                    for (int t = 0; t < M; ++t) znew = t == p - 1 ? z[t] : znew;
+                    if (!(znew > 0.0f)) {
+                        --p;
+                        inP &= ~(1ull << best);
+                        tabu |= 1ull << best;
+                        break;
+                    }
+                    tabu = 0;
+                }
+                bool allpos = true;
+#pragma unroll
+                for (int t = 0; t < M; ++t) allpos = allpos && (t >= p || z[t] > 0.0f);
+                if (allpos) {
+#pragma unroll
+                    for (int t = 0; t < M; ++t) fz[t] = t < p ? z[t] : 0.0f;
+                    break;
+                }
+                // step from the current point towards z until the first entry
+                // reaches zero, and fix the entries at zero again (order kept)
+                float alpha = 1.0f;
+                int tmin = -1;
+#pragma unroll
+                for (int t = 0; t < M; ++t) {
+                    if (t < p && z[t] <= 0.0f) {
+                        const float a = fz[t] / (fz[t] - z[t]);
+                        if (tmin < 0 || a < alpha) {
+                            alpha = a;
+                            tmin = t;
+                        }
+                    }
+                }
+                alpha = fminf(alpha, 1.0f);
+                int q = 0;
+                int nset[M];
+                float nf[M];
+#pragma unroll
+                for (int t = 0; t < M; ++t) {
+                    nset[t] = 0;
+                    nf[t] = 0.0f;
+                }
+#pragma unroll
+                for (int t = 0; t < M; ++t) {
+                    if (t >= p) continue;
+                    const float v = __builtin_fmaf(alpha, z[t] - fz[t], fz[t]);
+                    if (t == tmin || v <= 1e-7f * P.bt_hi) {
+                        inP &= ~(1ull << set[t]);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < M; ++u)
+                            if (u == q) {
+                                nset[u] = set[t];
+                                nf[u] = v;
+                            }
+                        ++q;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < M; ++t) {
+                    set[t] = nset[t];
+                    fz[t] = nf[t];
+                }
+                p = q;
+            }
+        }
+        if (p == 0) return 1;
+        // exact values on the support: its columns enter the artificial basis
+        // (each where its pivot element is largest), then the double-float
+        // refinement of the basic solution
+        lp.bt_ = P.bt_hi;
+        lp.init(P);
+        lp.dead = cs.dead;
+        lp.cert_rounds = 0;
+        lp.cert_exact = 0;
+        int cp = 0;
+        lp.crash(cs, nullptr, cp, true, inP);
+        if (lp.accept_phase1(cs, P, x)) break;
+        if (!stopped_by_residual) return 1;
+        res_stop = false;
+    }
+    float sum = 0.0f, v[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const float t = x[r].hi + x[r].lo;
+        v[r] = (lp.bs[r] < lp.ART && t > 0.0f) ? t : 0.0f;
+        sum += v[r];
+    }
+    const float tiny = 9.313225746154785e-10f * sum;
+    sum = 0.0f;
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        v[r] = v[r] < tiny ? 0.0f : v[r];
+        sum += v[r];
+        if (v[r] != 0.0f) store(lp.bs[r], v[r]);
+    }
+    fii = -sum;
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+        if (lp.bs[r] < lp.ART) basis |= 1ull << lp.bs[r];
+    return 0;
+}
+
+// OBJ: 0 the canonical stencil; 1 phase I only (the first feasible vertex,
+// P.phase1 = 1); 2 non-negative least squares (P.phase1 = 2).  Each
+// instantiation carries only its own code.
 // WARM: the warm-pass code compiled in (a kernel that never runs a warm pass
 // leaves it out, and with it its registers).
-template <int M, bool PH1, bool WARM = true, class CS, class Store>
+template <int M, int OBJ, bool WARM = true, class CS, class Store>
 __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified,
                         bool warm_pass_arg, const float* logit, int& warm, uint64_t& basis, bool use_pref = false,
                         uint64_t pref = 0, int* stats = nullptr)
 {
+    if constexpr (OBJ == 2) {
+        warm = 0;
+        if (stats) stats[0] = stats[1] = 0;
+        return solve_nnls<M>(cs, P, store, fii, piv, certified, basis);
+    }
+    constexpr bool PH1 = OBJ == 1;
     const bool warm_pass = WARM && warm_pass_arg;
     ThreadSimplex<M, CS> lp;
     lp.bt_ = P.bt_hi;

@@ -79,8 +79,25 @@ def _oracle_run(orc, name, steps):
     return _REF[key]
 
 
+_NET = {}
+
+
+def _network(name):
+    """The warm-start network exactly as bench.py trains it for this workload."""
+    if name not in _NET:
+        import bench
+        _NET[name] = bench.train_network(name, 30, 6)
+        _say("network", _NET[name][1])
+    return _NET[name][0]
+
+
 def _gpu_run(vrm, name, wl, steps, warm_mode):
-    cloud, ctx = _context(vrm, name, wl, warm_mode)
+    if warm_mode == 1:
+        cloud, ctx = _context(vrm, name, wl, 0)
+        ctx.vrm_mlp_load(_network(name))
+        ctx.vrm_set_warm_start(1)
+    else:
+        cloud, ctx = _context(vrm, name, wl, warm_mode)
     vt = vrm.vortex_table(wl.vortices) if wl.vortices is not None else None
     P = vrm.params_of(wl)
     t = wl.t0
@@ -92,11 +109,13 @@ def _gpu_run(vrm, name, wl, steps, warm_mode):
 
 
 @pytest.mark.timeout(400)
-@pytest.mark.parametrize("warm_mode", [0, 2])
+@pytest.mark.parametrize("warm_mode", [0, 2, 1])
 @pytest.mark.parametrize("name,steps", [("lamb_oseen_h0.01_q2", 100), ("lamb_oseen_h0.01_q3", 100)])
 def test_full_size_run_matches_oracle(vrm, orc, name, steps, warm_mode):
     """Sec. 3.3-3.4 and 4: whole runs at h = 0.01 (insertion on), Gamma within 1e-5
-    relative L2 of the FP64 oracle, same particle count, circulation kept."""
+    relative L2 of the FP64 oracle, same particle count, circulation kept; plain
+    solver, previous-basis warm start, and the learned warm start with the network
+    bench.py trains (the exact solver certifies every stencil)."""
     wl = FULL[name]()
     _say("case", name, "steps", steps, "warm mode", warm_mode, "N0", wl.n)
     (x, y, g, ids), cnt = _gpu_run(vrm, name, wl, steps, warm_mode)
@@ -222,6 +241,86 @@ def test_moving_vortex_cloud_whole_step(vrm, orc):
     assert err_rest <= 2e-5
     g0 = np.abs(wl.gamma).astype(np.float64).sum()
     assert abs(g.sum() - wl.gamma.astype(np.float64).sum()) <= 1e-5 * g0
+
+
+def _small_by_segment(st):
+    """The oracle's small-neighbourhood fractions spread over the 8 segments (its
+    column list skips empty segments)."""
+    has = st.small >= 0
+    at = np.cumsum(has, axis=1) - 1
+    f = np.take_along_axis(st.f[:, :8], np.maximum(at, 0), axis=1)
+    return np.where(has, f, 0.0)
+
+
+@pytest.mark.timeout(600)
+def test_moving_vortex_cloud_stages_on_the_same_inputs(vrm, orc):
+    """One step of the 64-vortex cloud moving with the prescribed velocity (3.5 M
+    particles after insertion), stage by stage: the oracle takes each stage's input
+    from the GPU (its FP32 positions and circulations, the same particles and
+    diffused set) and computes that stage (Sec. 3.3-3.4: stencils at the stage's
+    positions, the scatter, the Shu-Osher combination).  On identical inputs the
+    stencil decisions must agree exactly: same status and support for every
+    particle, fractions within 1e-6, and the stage's Gamma within 1e-5 relative L2
+    (positions within 4 ulps: both sides move them with the GPU's velocity)."""
+    name = "vortices64_h0.005"
+    wl = FULL[name]()
+    _say("case", name, "stage by stage on the GPU's inputs, N0", wl.n)
+    cloud, ctx = _context(vrm, name, wl)
+    P = vrm.params_of(wl)
+    po = orc.params_of(wl)
+    vt = vrm.vortex_table(wl.vortices)
+    x, y, g, ids = cloud.numpy()
+    pre, _, _ = orc.diffused(g, ids, wl.h, wl.q, wl.c_diff)
+    pre_by_id = dict(zip(ids.tolist(), pre.tolist()))
+    ctx.vrm_insert_particles(cloud, P)
+    x0, y0, g0, ids0 = (a.copy() for a in cloud.numpy())
+    n = x0.size
+    mask = np.array([pre_by_id.get(int(i), 0) for i in ids0], np.uint8)
+    u = torch.zeros(cloud.capacity, device="cuda")
+    v = torch.zeros(cloud.capacity, device="cuda")
+    A, B, C = orc.RK3_A, orc.RK3_B, orc.RK3_C
+    for s_ in range(3):
+        xs_, ys_, gs_, ids_ = (a.copy() for a in cloud.numpy())
+        np.testing.assert_array_equal(ids_, ids0)
+        ctx.vrm_vortex_velocity(cloud, vt, wl.nu, wl.t0 + C[s_] * wl.dt, u, v)
+        # the GPU's stencils at this stage's positions, then the stage itself
+        st = vrm.Stencils.alloc(cloud.capacity, full=True)
+        ctx.vrm_solve_fractions(cloud, P, st)
+        S = {k: getattr(st, k)[:n].cpu().numpy() for k in ("small_idx", "small_f", "status", "full_k", "full_idx",
+                                                            "full_f")}
+        del st
+        ctx.vrm_rk_stage(cloud, P, s_, u, v)
+        torch.cuda.synchronize()
+        uu, vv = u[:n].cpu().numpy().astype(np.float64), v[:n].cpu().numpy().astype(np.float64)
+        xo, yo, go, _ = cloud.numpy()
+        ref = orc.stencils(xs_, ys_, ids_, mask, po)
+        np.testing.assert_array_equal(S["status"], ref.status)
+        small = ref.status == 0
+        fs = _small_by_segment(ref)
+        np.testing.assert_array_equal(S["small_idx"][small], ref.small[small])
+        np.testing.assert_array_equal(S["small_f"][small] != 0.0, fs[small] != 0.0)
+        worst = float(np.max(np.abs(S["small_f"][small] - fs[small]) / np.maximum(1.0, np.abs(fs[small])))) \
+            if small.any() else 0.0
+        full = np.flatnonzero(ref.status == 1)
+        for i in full:
+            k = S["full_k"][i]
+            gd = {int(c): float(f) for c, f in zip(S["full_idx"][i, :k], S["full_f"][i, :k]) if f != 0.0}
+            rd = {int(c): float(f) for c, f in zip(ref.cols[i, :ref.kcol[i]], ref.f[i, :ref.kcol[i]]) if f != 0.0}
+            assert gd.keys() == rd.keys(), i
+            worst = max(worst, max(abs(gd[c] - rd[c]) / max(1.0, abs(rd[c])) for c in rd))
+        dg = orc.apply(ref, gs_.astype(np.float64), po)
+        g_ref = A[s_] * g0 + B[s_] * (gs_ + wl.dt * dg)
+        x_ref = A[s_] * x0 + B[s_] * (xs_ + wl.dt * uu)
+        y_ref = A[s_] * y0 + B[s_] * (ys_ + wl.dt * vv)
+        err = np.linalg.norm(go - g_ref) / np.linalg.norm(g_ref)
+        ulp_x = np.spacing((np.abs(x_ref) + wl.h).astype(np.float32)).astype(np.float64)
+        ulp_y = np.spacing((np.abs(y_ref) + wl.h).astype(np.float32)).astype(np.float64)
+        dx = max(np.max(np.abs(xo - x_ref) / ulp_x), np.max(np.abs(yo - y_ref) / ulp_y))
+        _say("stage", s_, "N", n, "small", int(small.sum()), "complete", full.size, "infeasible",
+             int((ref.status == 2).sum()), "worst fraction diff", worst, "Gamma rel L2", err, "max |dx| ulps", dx)
+        assert worst <= 1e-6
+        assert err <= 1e-5
+        assert dx <= 4.0
 
 
 @pytest.mark.timeout(400)

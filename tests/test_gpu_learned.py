@@ -2,6 +2,8 @@
 network's forward pass and gradient against the FP64 reference (oracle.mlp),
 training on the solver's own stencils, and results identical to the plain
 solver with the warm start switched on."""
+import math
+
 import numpy as np
 import pytest
 
@@ -189,3 +191,72 @@ def test_warm_start_gives_the_plain_results(vrm, trained, q):
         # most 5-row LPs start from their optimal basis: fewer pivots in total, even
         # counting the crash pivots and the cold solves of the rejected predictions
         assert cb["pivots"] < ca["pivots"]
+
+
+def _host_features(x, y, ids, i, cols, h):
+    """The network's input row of particle i with columns `cols` (cloud indices in
+    slot order, -1 empty), from the positions: offsets / h formed as the method
+    forms them (FP32 difference, exact scaling by 2^-e with 2^e >= h, times
+    fl32(2^e / h)), rounded to BF16; slot masks; q - 2 at [96] (set by the caller)."""
+    e = math.ceil(math.log2(h))
+    if 2.0 ** e < h:
+        e += 1
+    s, sc = np.float32(2.0 ** -e), np.float32(2.0 ** e / h)
+    row = np.zeros(128, np.float32)
+    for j, c in enumerate(cols[:32]):
+        if c < 0:
+            continue
+        row[2 * j] = np.float32(np.float32(x[c] - x[i]) * s) * sc
+        row[2 * j + 1] = np.float32(np.float32(y[c] - y[i]) * s) * sc
+        row[64 + j] = 1.0
+    return row
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_fused_inference_matches_fp64_reference(vrm, orc, trained, q):
+    """The warm pass's network outputs as the fused kernels compute them (q = 2: the
+    input built from the small LPs' column records inside the inference kernel;
+    q = 3: the complete neighbourhood's nearest 32 columns by (d2, id), then the
+    inference kernel) against the FP64 reference network on input rows built on
+    the host from the same positions."""
+    from oracle import mlp
+    theta = trained[q][0]
+    wl = workloads.config_jittered(h=0.02, q=q, seed=2)
+    P = vrm.params_of(wl)
+    cloud = vrm.Cloud(wl.x, wl.y, wl.gamma, capacity=3 * wl.n)
+    ctx = vrm.Context(cloud.capacity)
+    ctx.vrm_mlp_load(theta)
+    ctx.vrm_set_warm_start(1)
+    ctx.vrm_insert_particles(cloud, P)
+    out = torch.zeros((cloud.capacity, 64), device="cuda")
+    part = torch.zeros(cloud.capacity, dtype=torch.int32, device="cuda")
+    rows = ctx.vrm_warm_predictions(cloud, P, out, part)
+    got = out[:rows].cpu().numpy()
+    pi = part[:rows].cpu().numpy()
+    x, y, g, ids = cloud.numpy()
+    mask = np.zeros(x.size, np.uint8)
+    mask[pi] = 1
+    X = np.zeros((rows, 128), np.float32)
+    if q == 2:
+        st = orc.stencils(x, y, ids, mask, orc.params_of(wl))
+        for r, i in enumerate(pi):
+            X[r] = _host_features(x, y, ids, i, st.small[i], wl.h)
+    else:
+        f32 = np.float32
+        lo2 = f32(0.25 * wl.h * wl.h * (1 - 2 ** -20))
+        hi2 = f32(wl.R_full ** 2 * wl.h * wl.h * (1 + 2 ** -20))
+        for r, i in enumerate(pi):
+            dx, dy = x - x[i], y - y[i]
+            d2 = dx * dx + dy * dy
+            m = (d2 >= lo2) & (d2 <= hi2)
+            m[i] = False
+            cand = np.flatnonzero(m)
+            cand = cand[np.lexsort((ids[cand], d2[cand]))][:48]
+            X[r] = _host_features(x, y, ids, i, cand, wl.h)
+            X[r, 96] = 1.0
+    ref, _ = mlp.forward(bf16_round(theta.cpu().numpy()), bf16_round(X))
+    cols = 8 if q == 2 else 64
+    err = np.abs(got[:, :cols] - ref[:, :cols]).max() / np.abs(ref[:, :cols]).max()
+    print("q", q, "rows", rows, "max rel err", err, flush=True)
+    assert rows > 1000
+    assert err <= 3e-2

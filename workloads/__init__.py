@@ -84,6 +84,25 @@ def lamb_oseen_omega(x, y, t, nu, gamma_total=1.0):
     return gamma_total / (math.pi * s) * np.exp(-(x * x + y * y) / s)
 
 
+def lamb_oseen_weak_error(x, y, g, t, nu, s=0.1):
+    """Weak error of a particle field against the Lamb-Oseen vorticity at time t
+    (Sec. 5.1): the largest |sum_i Gamma_i phi_c(x_i) - integral omega phi_c| over
+    Gaussian test functions phi_c(x) = exp(-|x - c|^2 / s^2) centred on a 9 x 9 grid of
+    c in [-0.4, 0.4]^2; the exact integral is s^2 / (s^2 + 4 nu t) exp(-|c|^2 / (s^2 + 4 nu t))
+    (unit total circulation).  FP64."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    g = np.asarray(g, np.float64)
+    a = 4.0 * nu * t
+    err = 0.0
+    for cx in np.linspace(-0.4, 0.4, 9):
+        for cy in np.linspace(-0.4, 0.4, 9):
+            num = (g * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / s ** 2)).sum()
+            ex = s * s / (a + s * s) * np.exp(-(cx * cx + cy * cy) / (a + s * s))
+            err = max(err, abs(num - ex))
+    return err
+
+
 def lamb_oseen_velocity(x, y, t, nu, gamma_total=1.0):
     """Lamb-Oseen velocity (counter-clockwise for positive circulation, Sec. 5)."""
     r2 = x * x + y * y
