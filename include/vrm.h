@@ -393,6 +393,23 @@ int vrm_timing(vrm_ctx* ctx, int enable);
 int vrm_timing_groups(vrm_ctx* ctx, uint32_t groups);
 int vrm_read_timing(vrm_ctx* ctx, double* ms_host, int64_t* launches_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the diffused-set selection
+ * of vrm_select_diffused (Sec. 3.5, eq. reduced_bound; the same ranking, bound,
+ * round-off band and result) without a context.  gamma_dev[n] (device FP32,
+ * caller-owned) in; mask_dev[n] (device uint8, caller-owned) out, 1 = diffused;
+ * nonfinite_dev (device int32, may be NULL) receives 2 if a circulation is NaN or
+ * infinite, else 0.  h, q (2 or 3), c_diff as in vrm_params.  Runs on the current
+ * device, enqueued on `stream` (a hipStream_t of that device; NULL = the null
+ * stream), without synchronising.  Its working state (histogram bins, threshold,
+ * flag: about 3 KB) lives in one fixed device array per GPU, kept until the
+ * process ends; the call allocates nothing and clears that state itself.  Every
+ * call on a GPU shares its array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be ordered by the caller.  n up to 2^26;
+ * VRM_E_ARG for larger n, NULL pointers or bad parameters. */
+int vrm_select_diffused_static(const float* gamma_dev, int32_t n, double h, int32_t q, double c_diff,
+                               uint8_t* mask_dev, int32_t* nonfinite_dev, void* stream);
+
 const char* vrm_last_error(void);
 const char* vrm_status_string(int code);
 

@@ -80,7 +80,7 @@ EXPORTS = ["vrm_create", "vrm_destroy", "vrm_select_diffused", "vrm_set_diffused
            "vrm_read_counters",
            "vrm_vortex_velocity", "vrm_biot_savart", "vrm_set_lp_objective", "vrm_timing", "vrm_timing_groups", "vrm_read_timing", "vrm_mlp_load", "vrm_mlp_read",
            "vrm_set_warm_start", "vrm_collect_training", "vrm_mlp_train_step", "vrm_mlp_infer", "vrm_gemm_bf16",
-           "vrm_warm_predictions", "vrm_last_error", "vrm_status_string"]
+           "vrm_select_diffused_static", "vrm_warm_predictions", "vrm_last_error", "vrm_status_string"]
 MLP_IN, MLP_OUT, MLP_PARAMS, MLP_SLOTS = 128, 64, 41280, 32
 TIMERS = ["select", "cells", "nbhd", "lp_small", "lp_full", "insert", "combine", "mlp", "full_cols"]
 
@@ -133,6 +133,8 @@ def lib():
         L.vrm_timing.argtypes = [vp, ctypes.c_int]
         L.vrm_timing_groups.argtypes = [vp, ctypes.c_uint32]
         L.vrm_read_timing.argtypes = [vp, vp, vp]
+        L.vrm_select_diffused_static.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                                 vp, vp, vp]
         L.vrm_last_error.restype = ctypes.c_char_p
         L.vrm_status_string.restype = ctypes.c_char_p
         L.vrm_status_string.argtypes = [ctypes.c_int]
@@ -380,6 +382,15 @@ class Context:
             uv = velocity(cloud, t + c * p.dt) if velocity is not None else None
             u, v = uv if uv is not None else (None, None)
             self.vrm_rk_stage(cloud, p, s, u, v)
+
+
+def vrm_select_diffused_static(gamma, n: int, h: float, q: int, c_diff: float, mask, nonfinite=None, stream=None):
+    """Sec. 3.5 selection without a context (allocates nothing): mask[:n] = 1 for the
+    diffused particles of gamma[:n]; on the current torch device and stream."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    _check(lib().vrm_select_diffused_static(_ptr(gamma), int(n), float(h), int(q), float(c_diff), _ptr(mask),
+                                            _ptr(nonfinite), ctypes.c_void_p(s.cuda_stream)))
 
 
 def vortex_table(v: dict, device="cuda"):

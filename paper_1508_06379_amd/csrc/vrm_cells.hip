@@ -8,7 +8,9 @@
 // the greedy result in (id, segment) order by rounds of the lexicographically
 // first independent set.
 #include <hip/hip_runtime.h>
+#include <cmath>
 #include <cstring>
+#include <mutex>
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "vrm_device.h"
@@ -885,4 +887,79 @@ size_t vrm_sort_tmp_bytes(int32_t cap)
     rocprim::radix_sort_pairs((void*)nullptr, bytes, (uint64_t*)nullptr, (uint64_t*)nullptr, (int32_t*)nullptr,
                               (int32_t*)nullptr, (size_t)cap, 0, 35, (hipStream_t)0);
     return bytes;
+}
+
+// ------------------------------------------------- allocation-free selection
+// vrm_select_diffused_static: the selection kernels above with their state
+// (histogram bins, threshold, the non-finite flag) in a fixed device array
+// instead of a context's memory, for callers that cannot allocate.
+namespace {
+struct StaticSelect {
+    SelectState sel;
+    GridState grid;
+};
+constexpr size_t kStaticScratchBytes = 4096;
+static_assert(sizeof(StaticSelect) <= kStaticScratchBytes, "static selection state exceeds its array");
+constexpr int32_t kStaticMaxN = 1 << 26;   // exact FP64 bin sums (k_sel_hist)
+constexpr int kStaticMaxDevices = 64;
+
+__global__ void k_static_reset(GridState* g) { g->bad = 0; }
+__global__ void k_static_report(const GridState* g, int32_t* out) { *out = g->bad; }
+}  // namespace
+
+// One copy per GPU, held until the process ends; in host code the name stands
+// for the symbol, never for the device address (that is static_scratch_ptr's).
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_static_mu;
+void* g_static_ptr[kStaticMaxDevices];
+
+// the device address of this GPU's copy of scratch (the current device's), looked
+// up once per device
+int static_scratch_ptr(int dev, void** out)
+{
+    if (dev < 0 || dev >= kStaticMaxDevices) return vrm_fail(VRM_E_ARG, "device %d outside [0, %d)", dev, kStaticMaxDevices);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        VRM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return vrm_fail(VRM_E_HIP, "hipGetSymbolAddress(scratch) gave no address");
+        g_static_ptr[dev] = p;
+    }
+    *out = g_static_ptr[dev];
+    return VRM_OK;
+}
+}  // namespace
+
+extern "C" int vrm_select_diffused_static(const float* gamma_dev, int32_t n, double h, int32_t q, double c_diff,
+                                          uint8_t* mask_dev, int32_t* nonfinite_dev, void* stream)
+{
+    if (!gamma_dev || !mask_dev) return vrm_fail(VRM_E_ARG, "gamma and mask are required");
+    if (n < 0 || n > kStaticMaxN) return vrm_fail(VRM_E_ARG, "n = %d outside [0, 2^26] (the largest selection this entry point takes)", n);
+    if (!(h > 0.0) || !std::isfinite(h)) return vrm_fail(VRM_E_ARG, "h must be positive and finite");
+    if (q != 2 && q != 3) return vrm_fail(VRM_E_ARG, "q must be 2 or 3 (got %d)", q);
+    if (!(c_diff >= 0.0) || !std::isfinite(c_diff)) return vrm_fail(VRM_E_ARG, "c_diff must be >= 0");
+    int dev = 0;
+    VRM_HIP(hipGetDevice(&dev));
+    void* ptr = nullptr;
+    if (int r = static_scratch_ptr(dev, &ptr)) return r;
+    StaticSelect* st = static_cast<StaticSelect*>(ptr);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double factor = c_diff * std::pow(h, q + 1);
+    hipLaunchKernelGGL(k_static_reset, dim3(1), dim3(1), 0, s, &st->grid);
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, &st->sel, (vrm_counters*)nullptr, &st->grid);
+    const int nb = min(2048, blocks_for(n));
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        if (n > 0)
+            hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, s, gamma_dev, (const int32_t*)nullptr, n, &st->sel,
+                               shift, &st->grid);
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, &st->sel, shift, factor);
+    }
+    if (n > 0)
+        hipLaunchKernelGGL(k_sel_mask, dim3(blocks_for(n)), dim3(256), 0, s, gamma_dev, n, &st->sel, mask_dev,
+                           (uint8_t*)nullptr, (vrm_counters*)nullptr);
+    if (nonfinite_dev) hipLaunchKernelGGL(k_static_report, dim3(1), dim3(1), 0, s, &st->grid, nonfinite_dev);
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
 }
