@@ -116,12 +116,13 @@ typedef struct {
     int32_t n_diffused;       /* size of the diffused set of the step */
     int32_t n_candidates;     /* insertion candidates of the last insertion */
     int32_t n_inserted;       /* particles appended by the last insertion */
-    int32_t n_small;          /* LPs solved on the small neighbourhood (cumulative) */
-    int32_t n_full;           /* LPs solved on the complete neighbourhood (cumulative) */
-    int32_t n_infeasible;     /* particles without a stencil (cumulative) */
-    int32_t n_uncertified;    /* LPs whose optimality could not be certified (cumulative) */
-    int32_t n_truncated;      /* complete neighbourhoods cut to VRM_KMAX (cumulative) */
+    int64_t n_small;          /* LPs solved on the small neighbourhood (cumulative) */
+    int64_t n_full;           /* LPs solved on the complete neighbourhood (cumulative) */
+    int64_t n_infeasible;     /* particles without a stencil (cumulative) */
+    int64_t n_uncertified;    /* LPs whose optimality could not be certified (cumulative) */
+    int64_t n_truncated;      /* complete neighbourhoods cut to VRM_KMAX (cumulative) */
     int32_t n_grid_clamped;   /* cell grids that hit their size limit (cumulative) */
+    int32_t reserved0;
     int64_t pivots;           /* simplex pivots (cumulative) */
     int64_t redistributions;  /* stencils applied by vrm_rk_stage (cumulative) */
     int32_t capacity_needed;  /* set when an insertion failed for capacity */

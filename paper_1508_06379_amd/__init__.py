@@ -62,9 +62,9 @@ class vrm_stencils(ctypes.Structure):
 
 class vrm_counters(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_diffused", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
-                ("n_inserted", ctypes.c_int32), ("n_small", ctypes.c_int32), ("n_full", ctypes.c_int32),
-                ("n_infeasible", ctypes.c_int32), ("n_uncertified", ctypes.c_int32),
-                ("n_truncated", ctypes.c_int32), ("n_grid_clamped", ctypes.c_int32),
+                ("n_inserted", ctypes.c_int32), ("n_small", ctypes.c_int64), ("n_full", ctypes.c_int64),
+                ("n_infeasible", ctypes.c_int64), ("n_uncertified", ctypes.c_int64),
+                ("n_truncated", ctypes.c_int64), ("n_grid_clamped", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("pivots", ctypes.c_int64), ("redistributions", ctypes.c_int64),
                 ("capacity_needed", ctypes.c_int32), ("mis_rounds", ctypes.c_int32), ("full_cols", ctypes.c_int64),
                 ("warm_hit", ctypes.c_int64), ("warm_phase2", ctypes.c_int64), ("warm_cold", ctypes.c_int64),

@@ -281,6 +281,7 @@ int vrm_destroy(vrm_ctx* c)
     if (c->t_dev) (void)hipFree(c->t_dev);
     if (c->prev) (void)hipFree(c->prev);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->pmask) (void)hipFree(c->pmask);
     if (c->feat) (void)hipFree(c->feat);
     if (c->u_tmp) (void)hipFree(c->u_tmp);
     if (c->pred) (void)hipFree(c->pred);
@@ -767,6 +768,8 @@ int vrm_set_warm_start(vrm_ctx* c, int enable)
             VRM_HIP(hipMalloc(&p, sizeof(int32_t) * (size_t)c->capacity * 9 + 64));
             c->prev = (int32_t*)p;
             VRM_HIP(hipMemsetAsync(c->prev, 0xff, sizeof(int32_t) * (size_t)c->capacity * 9, c->stream));
+            VRM_HIP(hipMalloc(&p, sizeof(uint64_t) * (size_t)c->capacity + 64));
+            c->pmask = (uint64_t*)p;
         }
         c->warm = 2;
         return VRM_OK;

@@ -361,6 +361,7 @@ struct StencilOut {
     int32_t* prev;       // basis (column ids) of each particle's last stencil, [id][kPrevIds]: recorded if non-NULL
     int prev_cap;        // rows of prev: particles with larger ids keep no basis (they start cold)
     int use_prev;        // warm start from prev instead of pred
+    const uint64_t* pmask;   // previous basis as a column mask per complete-neighbourhood queue item (size-binned path)
     const int32_t* cloud_id;   // ids by cloud index
 };
 
@@ -402,6 +403,12 @@ __device__ __forceinline__ void count_add(int* p, bool v)
 {
     uint64_t m = __ballot(v);
     if (m && lane_id() == __ffsll((unsigned long long)m) - 1) atomicAdd(p, __popcll(m));
+}
+__device__ __forceinline__ void count_add(int64_t* p, bool v)
+{
+    uint64_t m = __ballot(v);
+    if (m && lane_id() == __ffsll((unsigned long long)m) - 1)
+        atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__popcll(m));
 }
 
 // Tie-break of the canonical cost: 2^-10 rank(id); for the removal LP (q = 1)
@@ -1151,11 +1158,16 @@ constexpr int kRecRow = VRM_KMAX;
 // nearest if there are more).  No sort, no rescans; a list longer than
 // kMemCap (a density the method never produces) goes to the retry queue and
 // is solved by the one-thread kernel, which collects on its own.
+// Warm starts take their inputs here as well: with prev, the columns whose
+// ids form the particle's previous basis (a mask per LP, pmask); with feat,
+// the network's input row (the offsets over h of the kMlpSlots nearest
+// columns, their mask and q), written by the group's lanes 16 bytes each.
 constexpr int kCollL = 16;
 constexpr int kMemCap = 96;
 constexpr int kCollBlock = 256;
 constexpr int kCollGroups = kCollBlock / kCollL;
 constexpr int kMemPerLane = kMemCap / kCollL;
+static_assert(kMlpIn == 8 * kCollL, "a feature row is written 8 elements per lane of a group");
 
 __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __restrict__ xs,
                                                              const float* __restrict__ ys,
@@ -1163,9 +1175,13 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
                                                              const int32_t* __restrict__ cell_start,
                                                              const GridState* gs, const int32_t* __restrict__ q_full,
                                                              Queues* qs, LaunchParams P, int32_t* rec, int32_t* kcol,
-                                                             int32_t* khist, int32_t* q_retry, vrm_counters* cnt)
+                                                             int32_t* khist, int32_t* q_retry, vrm_counters* cnt,
+                                                             const int32_t* __restrict__ prev, int prev_cap,
+                                                             uint64_t* pmask, uint16_t* feat)
 {
     __shared__ float s_d2[kCollGroups][kMemCap];
+    __shared__ float s_fx[kCollGroups][kMlpSlots];
+    __shared__ float s_fy[kCollGroups][kMlpSlots];
     __shared__ int s_id[kCollGroups][kMemCap];
     __shared__ int s_u[kCollGroups][kMemCap];
     __shared__ int s_pos[kCollGroups][kMemCap];
@@ -1262,6 +1278,69 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
                 const bool kept = s_pos[grp][o] < VRM_KMAX;
 #pragma unroll
                 for (int q = 0; q < kMemPerLane; ++q) rk[q] += (kept && id < mi[q]) ? 1 : 0;
+            }
+        }
+        if (pmask) {
+            // the previous basis as a column mask: members whose id is one of its ids
+            uint64_t m = 0;
+            const int own = live ? ids[t] : -1;
+            if (live && !over && (unsigned)own < (unsigned)prev_cap) {
+                int pv[kPrevIds];
+#pragma unroll
+                for (int a = 0; a < kPrevIds; ++a) pv[a] = prev[(size_t)own * kPrevIds + a];
+#pragma unroll
+                for (int q = 0; q < kMemPerLane; ++q) {
+                    bool in = false;
+#pragma unroll
+                    for (int a = 0; a < kPrevIds; ++a) in = in || pv[a] == mi[q];
+                    if (sub + kCollL * q < nm && pos[q] < VRM_KMAX && in) m |= 1ull << pos[q];
+                }
+            }
+            uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+#pragma unroll
+            for (int o = 1; o < kCollL; o <<= 1) {
+                lo |= __shfl_xor(lo, o, 64);
+                hi |= __shfl_xor(hi, o, 64);
+            }
+            if (live && !over && sub == 0) pmask[r] = ((uint64_t)hi << 32) | lo;
+        }
+        if (feat) {
+            // offsets over h of the kMlpSlots nearest columns (the slot order of the record)
+#pragma unroll
+            for (int q = 0; q < kMemPerLane; ++q) {
+                const int e = sub + kCollL * q;
+                if (live && e < nm && pos[q] < kMlpSlots) {
+                    const int u = s_u[grp][e];
+                    s_fx[grp][pos[q]] = ((xs[u] - xi) * P.scale2e) * P.sc;
+                    s_fy[grp][pos[q]] = ((ys[u] - yi) * P.scale2e) * P.sc;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (live && !over) {
+                // elements 8 sub .. 8 sub + 7 of the row: offset pairs, masks, q, zero padding
+                uint16_t v[8];
+#pragma unroll
+                for (int w = 0; w < 8; ++w) {
+                    const int e = 8 * sub + w;
+                    uint16_t b = 0;
+                    if (e < 2 * kMlpSlots) {
+                        const int j = e >> 1;
+                        if (j < k) b = f2bf((e & 1) ? s_fy[grp][j] : s_fx[grp][j]);
+                    } else if (e < 3 * kMlpSlots) {
+                        b = (e - 2 * kMlpSlots) < k ? 0x3f80 : 0;
+                    } else if (e == 3 * kMlpSlots) {
+                        b = P.q == 3 ? 0x3f80 : 0;
+                    }
+                    v[w] = b;
+                }
+                uint4 pk;
+                pk.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+                pk.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+                pk.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+                pk.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+                *reinterpret_cast<uint4*>(feat + (size_t)r * kMlpIn + 8 * sub) = pk;
             }
         }
         if (live && !over) {
@@ -1361,6 +1440,7 @@ struct SiftCols {
         kw = k;
         return true;
     }
+    __device__ __forceinline__ void restart() const { kw = k < W ? k : W; }
     __device__ __forceinline__ void exact_xy(int j, df& X, df& Y) const
     {
         const int u = (int)((unsigned)row[j] >> 6);
@@ -1404,12 +1484,16 @@ struct SiftCols {
     }
 };
 
-template <int M, int W, int OBJ>
+// WM: 0 cold; 1 crash from the network's logits (out.pred, one row per queue
+// item); 2 crash from the previous basis (out.pmask), recording the new one.
+// A warm attempt that is given up (its crash basis rejected, or more phase-II
+// pivots than the cap) is solved cold in place.
+template <int M, int W, int OBJ, int WM>
 __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_lp_sift(
     const int32_t* __restrict__ perm, const float* __restrict__ xs, const float* __restrict__ ys,
-    const int32_t* __restrict__ order, const int32_t* __restrict__ kcol, const int32_t* __restrict__ rec,
-    const int32_t* __restrict__ q_full, Queues* qs, const float* __restrict__ gamma, float* acc, LaunchParams P,
-    StencilOut out, int apply, vrm_counters* cnt, int last_launch, const GridState* gs)
+    const int32_t* __restrict__ ids, const int32_t* __restrict__ order, const int32_t* __restrict__ kcol,
+    const int32_t* __restrict__ rec, const int32_t* __restrict__ q_full, Queues* qs, const float* __restrict__ gamma,
+    float* acc, LaunchParams P, StencilOut out, int apply, vrm_counters* cnt, int last_launch, const GridState* gs)
 {
     __shared__ float s_x[W * kFullBlock];
     __shared__ float s_y[W * kFullBlock];
@@ -1423,7 +1507,7 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
     for (int it = 0; it < loops; ++it) {
         const int p = blockIdx.x * blockDim.x + tid + it * stride;
         const bool live = p < nitems;
-        int st = 1, piv = 0, certified = 1, k = 0;
+        int st = 1, piv = 0, certified = 1, k = 0, warm = 0;
         int cstat[2] = {0, 0};
         if (live) {
             const int r = order[p];
@@ -1469,21 +1553,34 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
                 }
                 ++nz;
             };
-            int warm = 0;
             uint64_t basis = 0;
-            st = solve_lp<M, OBJ, false>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false, 0ull,
-                                         cstat);
+            if constexpr (WM == 0) {
+                st = solve_lp<M, OBJ, false>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false,
+                                             0ull, cstat);
+            } else {
+                const float* logit = WM == 1 ? out.pred + (size_t)r * kMlpOut : nullptr;
+                const uint64_t pref = WM == 2 ? out.pmask[r] : 0ull;
+                // a prediction that is given up is followed by the cold solve in place
+                st = solve_lp<M, OBJ, true, true>(cs, P, store, fii, piv, certified, true, logit, warm, basis,
+                                                  WM == 2, pref, cstat);
+            }
+            if constexpr (WM == 2) {
+                const int own = ids[t];
+                auto col_id = [&](int j) { return ids[(unsigned)row[j] >> 6]; };
+                if (st == 0 && (unsigned)own < (unsigned)out.prev_cap) record_basis(out.prev, own, basis, col_id);
+            }
             if (st == 0) {
                 if (apply) acc_add(acc, i, fii, g_i, dsc);
                 if (out.full_k) {
                     out.full_k[i] = nz;
                     out.fii[i] = fii;
-                    out.status[i] = VRM_ST_FULL;
+                    out.status[i] = (warm == 1 || warm == 2) ? VRM_ST_WARM : VRM_ST_FULL;
                 }
             } else if (out.status) {
                 out.status[i] = VRM_ST_INFEASIBLE;
             }
         }
+        if constexpr (WM != 0) count_warm(cnt, live, warm);
         const bool ok = live && st == 0;
         if (piv) atomicAdd((unsigned long long*)&cnt->pivots, (unsigned long long)piv);
         if (ok) atomicAdd((unsigned long long*)&cnt->full_cols, (unsigned long long)k);
@@ -1824,13 +1921,6 @@ auto full_kernel(int obj) -> decltype(&k_lp_full<M, SC, 0, false>)
 {
     return by_objective(obj, k_lp_full<M, SC, 0, false>, k_lp_full<M, SC, 1, false>, k_lp_full<M, SC, 2, false>);
 }
-// warm passes exist for the simplex objectives only (the setters keep warm
-// starts and the least-squares objective apart)
-template <bool SC>
-auto full_warm_kernel(int obj) -> decltype(&k_lp_full<9, SC, 0, true>)
-{
-    return obj == 1 ? k_lp_full<9, SC, 1, true> : k_lp_full<9, SC, 0, true>;
-}
 
 }  // namespace
 
@@ -1883,18 +1973,10 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         out.prev_cap = c->capacity;
         out.use_prev = 1;
     }
-    if (net) {
-        // network inputs of the queued LPs, then the forward pass (row count read on the device)
+    if (net && lp.m == 5) {
+        // network inputs of the queued small LPs and the forward pass, fused (row count read on the device)
         ScopedTimer tm(c, VRM_T_MLP);
-        int r;
-        if (lp.m == 5) {
-            r = vrm_mlp_infer_small_run(c, n, &c->queues->n_small, c->srec, lp.sc, lp.q, c->pred);
-        } else {
-            hipLaunchKernelGGL(k_feat_full, dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->xs, c->ys, c->ids,
-                               c->cell_start, c->grid, c->q_full, c->queues, lp, c->feat);
-            VRM_HIP(hipGetLastError());
-            r = vrm_mlp_infer_run(c, c->feat, n, c->pred, &c->queues->n_full);
-        }
+        int r = vrm_mlp_infer_small_run(c, n, &c->queues->n_small, c->srec, lp.sc, lp.q, c->pred);
         if (r) return r;
         out.pred = c->pred;
     }
@@ -1932,44 +2014,53 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
                            dim3(min(lp_grid_full(c, n), 64)), dim3(kFullBlock), 0, c->stream, c->perm,
                            c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                            o2, apply, c->counters, kLpPlain, c->q_retry, 1);
-    } else if (!warm && !feat_out) {
-        // size-binned working-set path: column lists, counting sort by k, LPs
+    } else if (!feat_out) {
+        // size-binned working-set path: column lists (with the warm start's inputs),
+        // counting sort by k, the network's forward pass if it predicts, LPs
+        const int wm = net ? 1 : (warm ? 2 : 0);
         {
             ScopedTimer tm(c, VRM_T_FULL_COLS);
             hipLaunchKernelGGL(k_full_collect, dim3(min((n + kCollGroups - 1) / kCollGroups, 4096)), dim3(kCollBlock), 0,
                                c->stream, c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, lp,
-                               c->full_cols, c->full_k, c->khist, c->q_retry, c->counters);
+                               c->full_cols, c->full_k, c->khist, c->q_retry, c->counters,
+                               wm == 2 ? c->prev : nullptr, c->capacity, wm == 2 ? c->pmask : nullptr,
+                               wm == 1 ? c->feat : nullptr);
             hipLaunchKernelGGL(k_full_bin_starts, dim3(1), dim3(64), 0, c->stream, c->khist);
             hipLaunchKernelGGL(k_full_bin_scatter, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->full_k,
                                c->queues, c->khist, c->full_order);
             VRM_HIP(hipGetLastError());
         }
+        if (wm == 1) {
+            ScopedTimer tm(c, VRM_T_MLP);
+            int r = vrm_mlp_infer_run(c, c->feat, n, c->pred, &c->queues->n_full);
+            if (r) return r;
+            out.pred = c->pred;
+        }
+        if (wm == 2) out.pmask = c->pmask;
         ScopedTimer tm(c, VRM_T_LP_FULL);
-        hipLaunchKernelGGL((by_objective(lp.phase1, k_lp_sift<9, kSiftW, 0>, k_lp_sift<9, kSiftW, 1>, k_lp_sift<9, kSiftW, 2>)),
-                           dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
-                           c->full_order, c->full_k, c->full_cols, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, out,
-                           apply, c->counters, 0, c->grid);
+        const int obj = lp.phase1;
+        auto sift = wm == 0 ? by_objective(obj, k_lp_sift<9, kSiftW, 0, 0>, k_lp_sift<9, kSiftW, 1, 0>,
+                                           k_lp_sift<9, kSiftW, 2, 0>)
+                  : wm == 1 ? (obj == 1 ? k_lp_sift<9, kSiftW, 1, 1> : k_lp_sift<9, kSiftW, 0, 1>)
+                            : (obj == 1 ? k_lp_sift<9, kSiftW, 1, 2> : k_lp_sift<9, kSiftW, 0, 2>);
+        hipLaunchKernelGGL(sift, dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
+                           c->ids, c->full_order, c->full_k, c->full_cols, c->q_full, c->queues, cl->gamma_dev, c->acc,
+                           lp, out, apply, c->counters, 0, c->grid);
         // lists too long for the collection groups (none in practice): the one-thread
-        // kernel from the retry queue; as the run's last LP launch it empties the queues
-        hipLaunchKernelGGL((full_kernel<9, false>(lp.phase1)),
-                           dim3(1), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys, c->ids, c->cell_start,
-                           c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, out, apply, c->counters, kLpRetry,
-                           c->q_retry, 1);
+        // kernel from the retry queue, cold; as the run's last LP launch it empties the queues
+        hipLaunchKernelGGL((full_kernel<9, false>(lp.phase1)), dim3(1), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
+                           c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, out,
+                           apply, c->counters, kLpRetry, c->q_retry, 1);
         VRM_HIP(hipGetLastError());
     } else {
+        // training collection: the one-thread kernel records features and labels
         ScopedTimer tm(c, VRM_T_LP_FULL);
-        const int last = warm ? kLpRetry : kLpPlain;
-        for (int mode = first; mode <= last; ++mode) {
-            const bool stored = full_stored_costs(c, n);
-            // the warm pass carries the crash code; plain and retry launches do not
-            const bool w = mode == kLpWarm;
-            hipLaunchKernelGGL((stored ? (w ? full_warm_kernel<true>(lp.phase1) : full_kernel<9, true>(lp.phase1))
-                                         : (w ? full_warm_kernel<false>(lp.phase1) : full_kernel<9, false>(lp.phase1))),
-                               dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
-                               c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
-                               out, apply, c->counters, mode, c->q_retry, mode == last ? 1 : 0);
-            VRM_HIP(hipGetLastError());
-        }
+        const bool stored = full_stored_costs(c, n);
+        hipLaunchKernelGGL((stored ? full_kernel<9, true>(lp.phase1) : full_kernel<9, false>(lp.phase1)),
+                           dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys, c->ids,
+                           c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp, out, apply,
+                           c->counters, kLpPlain, c->q_retry, 1);
+        VRM_HIP(hipGetLastError());
     }
     VRM_HIP(hipGetLastError());
     return VRM_OK;

@@ -1193,7 +1193,10 @@ __device__ int solve_nnls(const CS& cs, const LaunchParams& P, Store store, floa
 // instantiation carries only its own code.
 // WARM: the warm-pass code compiled in (a kernel that never runs a warm pass
 // leaves it out, and with it its registers).
-template <int M, int OBJ, bool WARM = true, class CS, class Store>
+// INPLACE (warm passes): a prediction that is given up (warm = 3) is followed by
+// the cold solve in the same call instead of returning 4; the store's
+// restart() resets what the warm attempt changed in it (a widened working set).
+template <int M, int OBJ, bool WARM = true, bool INPLACE = false, class CS, class Store>
 __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified,
                         bool warm_pass_arg, const float* logit, int& warm, uint64_t& basis, bool use_pref = false,
                         uint64_t pref = 0, int* stats = nullptr)
@@ -1220,27 +1223,38 @@ __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float&
     // pivot cap applies (a cold retry of these long LPs would redo the work)
     const bool finish = M == 9 && warm_pass && !use_pref;
     bool guided = false;
+    bool cold = !warm_pass;
     if constexpr (WARM) if (warm_pass) {
         if (!lp.crash(cs, logit, piv, use_pref, pref)) {
             if (!finish) {
                 warm = 3;
-                return 4;
+                if constexpr (!INPLACE) return 4;
+                cold = true;
+            } else {
+                lp.init(P);
+                lp.guided(cs, logit, piv);
+                guided = true;
             }
+        }
+        if (!cold) {
+            const int p1 = piv;
+            st = guided ? lp.run(cs, piv, 1) : lp.run(cs, piv, 2, finish ? -1 : warm_cap<M>());
+            if (st == 2 && !finish) {
+                warm = 3;
+                if constexpr (!INPLACE) return 4;
+                cold = true;
+            } else {
+                warm = (!guided && piv == p1) ? 1 : 2;
+            }
+        }
+        if constexpr (INPLACE) if (cold) {
             lp.init(P);
-            lp.guided(cs, logit, piv);
-            guided = true;
+            cs.restart();
         }
-        const int p1 = piv;
-        st = guided ? lp.run(cs, piv, 1) : lp.run(cs, piv, 2, finish ? -1 : warm_cap<M>());
-        if (st == 2 && !finish) {
-            warm = 3;
-            return 4;
-        }
-        warm = (!guided && piv == p1) ? 1 : 2;
     }
     df x[M];
     bool accepted = false;   // phase I only: the first feasible vertex, exact to the refinement
-    if (!warm_pass) {
+    if (cold) {
         if constexpr (PH1)
             st = lp.run(cs, piv, 1, -1, &P, x, &accepted);
         else

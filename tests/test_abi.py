@@ -65,7 +65,7 @@ int main(void) {
   printf("VRM_E_NONFINITE %d\\n", VRM_E_NONFINITE);
   printf("VRM_ST_WARM %d\\n", VRM_ST_WARM);
   P(vrm_cloud, capacity) P(vrm_stencils, full_f_dev)
-  P(vrm_counters, pivots) P(vrm_counters, redistributions) P(vrm_counters, mis_rounds) P(vrm_counters, full_cols)
+  P(vrm_counters, n_small) P(vrm_counters, n_truncated) P(vrm_counters, n_grid_clamped) P(vrm_counters, pivots) P(vrm_counters, redistributions) P(vrm_counters, mis_rounds) P(vrm_counters, full_cols)
   P(vrm_counters, graph_replays) P(vrm_counters, cert_exact) P(vrm_tuning, infer_blocks) P(vrm_tuning, lp_small_lanes) P(vrm_tuning, lp_small_coop)
   return 0;
 }
@@ -84,6 +84,9 @@ int main(void) {
     assert int(out["VRM_ST_WARM"]) == vrm.ST_WARM
     assert int(out["vrm_cloud.capacity"]) == vrm.vrm_cloud.capacity.offset
     assert int(out["vrm_stencils.full_f_dev"]) == vrm.vrm_stencils.full_f_dev.offset
+    assert int(out["vrm_counters.n_small"]) == vrm.vrm_counters.n_small.offset
+    assert int(out["vrm_counters.n_truncated"]) == vrm.vrm_counters.n_truncated.offset
+    assert int(out["vrm_counters.n_grid_clamped"]) == vrm.vrm_counters.n_grid_clamped.offset
     assert int(out["vrm_counters.pivots"]) == vrm.vrm_counters.pivots.offset
     assert int(out["vrm_counters.redistributions"]) == vrm.vrm_counters.redistributions.offset
     assert int(out["vrm_counters.mis_rounds"]) == vrm.vrm_counters.mis_rounds.offset
