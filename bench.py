@@ -144,6 +144,9 @@ TRAINING = {
     "vortices64_h0.005": dict(kind="vortices", h=0.02, q=2),
     "vortices256_h0.004_q3": dict(kind="vortices_dense", h=0.02, q=3),
 }
+# rows taken from each training cloud (about 10 M solves for the 16 M-particle cloud's network)
+ROWS_PER_SNAPSHOT = {"vortices256_h0.004_q3": 1 << 18}
+TRAIN_SNAPSHOTS = {"vortices256_h0.004_q3": 100}
 
 
 def train_network(name, seeds, epochs):
@@ -155,7 +158,7 @@ def train_network(name, seeds, epochs):
     spec = TRAINING[name]
     t0 = time.perf_counter()
     X, Y = L.collect(lambda s: workloads.training_snapshot(1000 + s, h=spec["h"], q=spec["q"], kind=spec["kind"]),
-                     range(seeds))
+                     range(seeds), max_rows_per_cloud=ROWS_PER_SNAPSHOT.get(name, 65536))
     t1 = time.perf_counter()
     ctx = vrm.Context(64)
     # 9-row bases learn better with a light fraction term and a higher rate
@@ -386,7 +389,7 @@ def main():
                          "feasible vertex (phase I only), non-negative least squares; both = plain + learned, "
                          "all = the five on the same workload")
     ap.add_argument("--roofline-steps", type=int, default=5)
-    ap.add_argument("--train-snapshots", type=int, default=30)
+    ap.add_argument("--train-snapshots", type=int, default=0, help="training clouds (0: the workload's default)")
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--no-removal", action="store_true", help="skip the particle-removal measurement")
     ap.add_argument("--removal-only", action="store_true",
@@ -424,7 +427,8 @@ def main():
         runs["nnls"] = run_gpu(wl, args.steps, args.warmup, tuning=tuning, lp_objective=2, **kw)
         log(f"nnls: {runs['nnls']['elapsed']:.3f} s")
     if args.solver in ("all", "both", "learned"):
-        theta, train_info = train_network(args.workload, args.train_snapshots, args.epochs)
+        theta, train_info = train_network(args.workload, args.train_snapshots or TRAIN_SNAPSHOTS.get(args.workload, 30),
+                                          args.epochs)
         log(f"network: {train_info}")
         runs["learned"] = run_gpu(wl, args.steps, args.warmup, theta=theta, tuning=tuning, **kw)
         log(f"learned: {runs['learned']['elapsed']:.3f} s")

@@ -282,6 +282,7 @@ int vrm_destroy(vrm_ctx* c)
     if (c->prev) (void)hipFree(c->prev);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->pmask) (void)hipFree(c->pmask);
+    if (c->lkey) (void)hipFree(c->lkey);
     if (c->feat) (void)hipFree(c->feat);
     if (c->u_tmp) (void)hipFree(c->u_tmp);
     if (c->pred) (void)hipFree(c->pred);
@@ -768,6 +769,9 @@ int vrm_set_warm_start(vrm_ctx* c, int enable)
             VRM_HIP(hipMalloc(&p, sizeof(int32_t) * (size_t)c->capacity * 9 + 64));
             c->prev = (int32_t*)p;
             VRM_HIP(hipMemsetAsync(c->prev, 0xff, sizeof(int32_t) * (size_t)c->capacity * 9, c->stream));
+        }
+        if (!c->pmask) {
+            void* p = nullptr;
             VRM_HIP(hipMalloc(&p, sizeof(uint64_t) * (size_t)c->capacity + 64));
             c->pmask = (uint64_t*)p;
         }
@@ -782,6 +786,16 @@ int vrm_set_warm_start(vrm_ctx* c, int enable)
             c->feat = (uint16_t*)p;
             VRM_HIP(hipMalloc(&p, sizeof(float) * (size_t)c->capacity * vrm::kMlpOut + 64));
             c->pred = (float*)p;
+        }
+        if (!c->pmask) {
+            void* p = nullptr;
+            VRM_HIP(hipMalloc(&p, sizeof(uint64_t) * (size_t)c->capacity + 64));
+            c->pmask = (uint64_t*)p;
+        }
+        if (!c->lkey) {
+            void* p = nullptr;
+            VRM_HIP(hipMalloc(&p, sizeof(int32_t) * (size_t)c->capacity + 64));
+            c->lkey = (int32_t*)p;
         }
     }
     c->warm = enable ? 1 : 0;

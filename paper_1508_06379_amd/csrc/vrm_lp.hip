@@ -1169,6 +1169,7 @@ constexpr int kCollGroups = kCollBlock / kCollL;
 constexpr int kMemPerLane = kMemCap / kCollL;
 static_assert(kMlpIn == 8 * kCollL, "a feature row is written 8 elements per lane of a group");
 
+template <int WM>
 __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __restrict__ xs,
                                                              const float* __restrict__ ys,
                                                              const int32_t* __restrict__ ids,
@@ -1180,8 +1181,6 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
                                                              uint64_t* pmask, uint16_t* feat)
 {
     __shared__ float s_d2[kCollGroups][kMemCap];
-    __shared__ float s_fx[kCollGroups][kMlpSlots];
-    __shared__ float s_fy[kCollGroups][kMlpSlots];
     __shared__ int s_id[kCollGroups][kMemCap];
     __shared__ int s_u[kCollGroups][kMemCap];
     __shared__ int s_pos[kCollGroups][kMemCap];
@@ -1280,7 +1279,7 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
                 for (int q = 0; q < kMemPerLane; ++q) rk[q] += (kept && id < mi[q]) ? 1 : 0;
             }
         }
-        if (pmask) {
+        if constexpr (WM == 2) {
             // the previous basis as a column mask: members whose id is one of its ids
             uint64_t m = 0;
             const int own = live ? ids[t] : -1;
@@ -1304,15 +1303,18 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
             }
             if (live && !over && sub == 0) pmask[r] = ((uint64_t)hi << 32) | lo;
         }
-        if (feat) {
-            // offsets over h of the kMlpSlots nearest columns (the slot order of the record)
+        if constexpr (WM == 1) {
+            // offsets over h of the kMlpSlots nearest columns (the slot order of the record),
+            // staged in the group's distance and id lists, which are no longer read
+            float* s_fx = s_d2[grp];
+            float* s_fy = reinterpret_cast<float*>(s_id[grp]);
 #pragma unroll
             for (int q = 0; q < kMemPerLane; ++q) {
                 const int e = sub + kCollL * q;
                 if (live && e < nm && pos[q] < kMlpSlots) {
                     const int u = s_u[grp][e];
-                    s_fx[grp][pos[q]] = ((xs[u] - xi) * P.scale2e) * P.sc;
-                    s_fy[grp][pos[q]] = ((ys[u] - yi) * P.scale2e) * P.sc;
+                    s_fx[pos[q]] = ((xs[u] - xi) * P.scale2e) * P.sc;
+                    s_fy[pos[q]] = ((ys[u] - yi) * P.scale2e) * P.sc;
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1327,7 +1329,7 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
                     uint16_t b = 0;
                     if (e < 2 * kMlpSlots) {
                         const int j = e >> 1;
-                        if (j < k) b = f2bf((e & 1) ? s_fy[grp][j] : s_fx[grp][j]);
+                        if (j < k) b = f2bf((e & 1) ? s_fy[j] : s_fx[j]);
                     } else if (e < 3 * kMlpSlots) {
                         b = (e - 2 * kMlpSlots) < k ? 0x3f80 : 0;
                     } else if (e == 3 * kMlpSlots) {
@@ -1353,7 +1355,8 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
             }
             if (sub == 0) {
                 kcol[r] = k;
-                atomicAdd(&s_hist[k], 1);
+                // (with a network, the LPs are binned by its confidence instead, after inference)
+                if (WM != 1) atomicAdd(&s_hist[k], 1);
             }
         }
         if (over && sub == 0) kcol[r] = -1;
@@ -1484,10 +1487,69 @@ struct SiftCols {
     }
 };
 
-// WM: 0 cold; 1 crash from the network's logits (out.pred, one row per queue
-// item); 2 crash from the previous basis (out.pmask), recording the new one.
-// A warm attempt that is given up (its crash basis rejected, or more phase-II
-// pivots than the cap) is solved cold in place.
+// The network's predicted basis of each complete LP: the m columns of largest
+// logit among its first min(k, kMlpSlots) (lowest slot among equal logits), as
+// a column mask for the crash; and its bin for the counting sort: the
+// network's doubt, -4 sum log sigmoid over those m logits (0 when it is sure
+// of all m), so that the lanes of a wave take LPs of similar difficulty (their
+// number of repair pivots, not k, is what varies).
+__global__ __launch_bounds__(256) void k_top_mask(const float* __restrict__ pred, const int32_t* __restrict__ kcol,
+                                                  const Queues* qs, int m, uint64_t* pmask, int32_t* key,
+                                                  int32_t* khist)
+{
+    __shared__ int s_hist[kKBins];
+    for (int b = threadIdx.x; b < kKBins; b += blockDim.x) s_hist[b] = 0;
+    __syncthreads();
+    const int nitems = qs->n_full;
+    const int loops = (nitems + gridDim.x * blockDim.x - 1) / (gridDim.x * blockDim.x);
+    for (int it = 0; it < loops; ++it) {
+        const int r = blockIdx.x * blockDim.x + threadIdx.x + it * gridDim.x * blockDim.x;
+        const int k = r < nitems ? kcol[r] : -1;   // -1: a list left for the one-thread kernel
+        if (k < 0) {
+            if (r < nitems) key[r] = -1;
+            continue;
+        }
+        const int kk = min(k, kMlpSlots);
+        float v[kMlpSlots];
+        const float4* row = reinterpret_cast<const float4*>(pred + (size_t)r * kMlpOut);
+#pragma unroll
+        for (int a = 0; a < kMlpSlots / 4; ++a) {
+            const float4 q = row[a];
+            v[4 * a] = q.x;
+            v[4 * a + 1] = q.y;
+            v[4 * a + 2] = q.z;
+            v[4 * a + 3] = q.w;
+        }
+        uint64_t mask = 0;
+        float doubt = 0.0f;
+        for (int t = 0; t < m && t < kk; ++t) {
+            int best = -1;
+            float bv = 0.0f;
+#pragma unroll
+            for (int j = 0; j < kMlpSlots; ++j) {
+                const bool ok = j < kk && !((mask >> j) & 1ull) && (best < 0 || v[j] > bv);
+                best = ok ? j : best;
+                bv = ok ? v[j] : bv;
+            }
+            mask |= 1ull << best;
+            // -log sigmoid(bv) = log(1 + exp(-bv))
+            doubt += bv > 20.0f ? 0.0f : (bv < -20.0f ? -bv : __logf(1.0f + __expf(-bv)));
+        }
+        pmask[r] = mask;
+        const int b = (int)fminf(4.0f * doubt, (float)(kKBins - 1));
+        key[r] = b;
+        atomicAdd(&s_hist[b], 1);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kKBins; b += blockDim.x)
+        if (s_hist[b]) atomicAdd(&khist[b], s_hist[b]);
+}
+
+// WM: 0 cold; 1 crash from the network's prediction (out.pmask: its top-m
+// columns per queue item), finished whatever it takes; 2 crash from the
+// previous basis (out.pmask), at most warm_cap pivots, recording the new one.
+// A crash basis that is not feasible is repaired by the composite phase I; a
+// warm attempt that fails is solved cold in place.
 template <int M, int W, int OBJ, int WM>
 __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_lp_sift(
     const int32_t* __restrict__ perm, const float* __restrict__ xs, const float* __restrict__ ys,
@@ -1558,11 +1620,10 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
                 st = solve_lp<M, OBJ, false>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false,
                                              0ull, cstat);
             } else {
-                const float* logit = WM == 1 ? out.pred + (size_t)r * kMlpOut : nullptr;
-                const uint64_t pref = WM == 2 ? out.pmask[r] : 0ull;
+                const uint64_t pref = out.pmask[r];
                 // a prediction that is given up is followed by the cold solve in place
-                st = solve_lp<M, OBJ, true, true>(cs, P, store, fii, piv, certified, true, logit, warm, basis,
-                                                  WM == 2, pref, cstat);
+                st = solve_lp<M, OBJ, true, true>(cs, P, store, fii, piv, certified, true, nullptr, warm, basis,
+                                                  true, pref, cstat, WM == 2);
             }
             if constexpr (WM == 2) {
                 const int own = ids[t];
@@ -2020,23 +2081,32 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         const int wm = net ? 1 : (warm ? 2 : 0);
         {
             ScopedTimer tm(c, VRM_T_FULL_COLS);
-            hipLaunchKernelGGL(k_full_collect, dim3(min((n + kCollGroups - 1) / kCollGroups, 4096)), dim3(kCollBlock), 0,
+            auto collect = wm == 1 ? k_full_collect<1> : wm == 2 ? k_full_collect<2> : k_full_collect<0>;
+            hipLaunchKernelGGL(collect, dim3(min((n + kCollGroups - 1) / kCollGroups, 4096)), dim3(kCollBlock), 0,
                                c->stream, c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, lp,
                                c->full_cols, c->full_k, c->khist, c->q_retry, c->counters,
                                wm == 2 ? c->prev : nullptr, c->capacity, wm == 2 ? c->pmask : nullptr,
                                wm == 1 ? c->feat : nullptr);
-            hipLaunchKernelGGL(k_full_bin_starts, dim3(1), dim3(64), 0, c->stream, c->khist);
-            hipLaunchKernelGGL(k_full_bin_scatter, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->full_k,
-                               c->queues, c->khist, c->full_order);
+            if (wm != 1) {
+                hipLaunchKernelGGL(k_full_bin_starts, dim3(1), dim3(64), 0, c->stream, c->khist);
+                hipLaunchKernelGGL(k_full_bin_scatter, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->full_k,
+                                   c->queues, c->khist, c->full_order);
+            }
             VRM_HIP(hipGetLastError());
         }
         if (wm == 1) {
+            // the forward pass, the predicted bases, and the LPs sorted by the network's doubt
             ScopedTimer tm(c, VRM_T_MLP);
             int r = vrm_mlp_infer_run(c, c->feat, n, c->pred, &c->queues->n_full);
             if (r) return r;
-            out.pred = c->pred;
+            hipLaunchKernelGGL(k_top_mask, dim3(min((n + 255) / 256, 4096)), dim3(256), 0, c->stream, c->pred,
+                               c->full_k, c->queues, lp.m, c->pmask, c->lkey, c->khist);
+            hipLaunchKernelGGL(k_full_bin_starts, dim3(1), dim3(64), 0, c->stream, c->khist);
+            hipLaunchKernelGGL(k_full_bin_scatter, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->lkey,
+                               c->queues, c->khist, c->full_order);
+            VRM_HIP(hipGetLastError());
         }
-        if (wm == 2) out.pmask = c->pmask;
+        if (wm) out.pmask = c->pmask;
         ScopedTimer tm(c, VRM_T_LP_FULL);
         const int obj = lp.phase1;
         auto sift = wm == 0 ? by_objective(obj, k_lp_sift<9, kSiftW, 0, 0>, k_lp_sift<9, kSiftW, 1, 0>,
