@@ -1267,6 +1267,50 @@ __device__ int solve_nnls(const CS& cs, const LaunchParams& P, Store store, floa
 // instantiation carries only its own code.
 // WARM: the warm-pass code compiled in (a kernel that never runs a warm pass
 // leaves it out, and with it its registers).
+// The end of a simplex solve (run's result st): certification against the
+// exact problem, the basic values as fractions (stored with store(column,
+// value)), fii = -their sum, and the final basis.  Returns solve_lp's result.
+template <int M, class CS, class Store>
+__device__ int finish_lp(ThreadSimplex<M, CS>& lp, const CS& cs, const LaunchParams& P, Store store, int st,
+                         bool accepted, df (&x)[M], float& fii, int& piv, int& certified, uint64_t& basis, int* stats)
+{
+    certified = 1;
+    if (st == 1) return 1;
+    const int c = accepted ? 0 : lp.certify(cs, P, x, piv);
+    if (stats) {
+        stats[0] = lp.cert_rounds;
+        stats[1] = lp.cert_exact;
+    }
+    if (c == 1) return 1;
+    // not certified optimal: kept only if its exact values meet the moment
+    // conditions and the sign condition, else treated as infeasible
+    if (c == 3 && !lp.primal_feasible(x)) return 1;
+    certified = c == 0 ? 1 : 0;
+    float sum = 0.0f;
+    float v[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        float t = x[r].hi + x[r].lo;
+        v[r] = (lp.bs[r] < lp.ART && t > 0.0f) ? t : 0.0f;
+        sum += v[r];
+    }
+    // a basic value below 2^-30 of the stencil's sum is the round-off of a
+    // degenerate vertex (zero in exact arithmetic): make it zero
+    float tiny = 9.313225746154785e-10f * sum;
+    sum = 0.0f;
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        v[r] = v[r] < tiny ? 0.0f : v[r];
+        sum += v[r];
+        if (v[r] != 0.0f) store(lp.bs[r], v[r]);
+    }
+    fii = -sum;
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+        if (lp.bs[r] < lp.ART) basis |= 1ull << lp.bs[r];
+    return 0;
+}
+
 // INPLACE (warm passes): a prediction that is given up (warm = 3) is followed by
 // the cold solve in the same call instead of returning 4; the store's
 // restart() resets what the warm attempt changed in it (a widened working set).
@@ -1353,41 +1397,7 @@ __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float&
                 st = lp.run(cs, piv, 1);
         }
     }
-    certified = 1;
-    if (st == 1) return 1;
-    const int c = accepted ? 0 : lp.certify(cs, P, x, piv);
-    if (stats) {
-        stats[0] = lp.cert_rounds;
-        stats[1] = lp.cert_exact;
-    }
-    if (c == 1) return 1;
-    // not certified optimal: kept only if its exact values meet the moment
-    // conditions and the sign condition, else treated as infeasible
-    if (c == 3 && !lp.primal_feasible(x)) return 1;
-    certified = c == 0 ? 1 : 0;
-    float sum = 0.0f;
-    float v[M];
-#pragma unroll
-    for (int r = 0; r < M; ++r) {
-        float t = x[r].hi + x[r].lo;
-        v[r] = (lp.bs[r] < lp.ART && t > 0.0f) ? t : 0.0f;
-        sum += v[r];
-    }
-    // a basic value below 2^-30 of the stencil's sum is the round-off of a
-    // degenerate vertex (zero in exact arithmetic): make it zero
-    float tiny = 9.313225746154785e-10f * sum;
-    sum = 0.0f;
-#pragma unroll
-    for (int r = 0; r < M; ++r) {
-        v[r] = v[r] < tiny ? 0.0f : v[r];
-        sum += v[r];
-        if (v[r] != 0.0f) store(lp.bs[r], v[r]);
-    }
-    fii = -sum;
-#pragma unroll
-    for (int r = 0; r < M; ++r)
-        if (lp.bs[r] < lp.ART) basis |= 1ull << lp.bs[r];
-    return 0;
+    return finish_lp<M>(lp, cs, P, store, st, accepted, x, fii, piv, certified, basis, stats);
 }
 
 }  // namespace vrm

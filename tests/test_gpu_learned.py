@@ -111,9 +111,11 @@ def trained(vrm):
     import paper_1508_06379_amd.learned as L
     out = {}
     for q in (2, 3):
-        X, Y = L.collect(lambda s: workloads.training_snapshot(1000 + s, h=0.02, q=q), range(6))
+        # q = 3: 9 of ~29 columns, a much harder target: more clouds and epochs
+        X, Y = L.collect(lambda s: workloads.training_snapshot(1000 + s, h=0.02, q=q), range(6 if q == 2 else 60))
         ctx = vrm.Context(64)
-        hist = L.train(ctx, X, Y, epochs=4, batch=1024, lr=2e-3, seed=q)
+        hist = L.train(ctx, X, Y, epochs=4 if q == 2 else 10, batch=1024 if q == 2 else 4096,
+                       lr=2e-3 if q == 2 else 3e-3, frac_weight=1.0 if q == 2 else 0.1, seed=q)
         acc = L.basis_accuracy(ctx, X, Y, q)
         theta = torch.zeros(vrm.MLP_PARAMS, device="cuda")
         ctx.vrm_mlp_read(theta)
@@ -126,9 +128,9 @@ def trained(vrm):
 def test_training_learns_the_basis(vrm, trained, q):
     theta, hist, acc = trained[q]
     assert hist[-1] < 0.7 * hist[0]
-    # q = 2: 5 of <= 8 columns; q = 3: 9 of ~29 columns (much harder; this small
-    # test-time training set only starts to learn it)
-    assert acc >= (0.5 if q == 2 else 0.005)
+    # q = 2: 5 of <= 8 columns; q = 3: 9 of ~29 columns, whose exact set an MLP of
+    # this size predicts for a few per cent of the LPs at any training size tried
+    assert acc >= (0.5 if q == 2 else 0.03)
 
 
 def _stencil_dicts(vrm, ctx, cloud, P):
@@ -190,6 +192,10 @@ def test_warm_start_gives_the_plain_results(vrm, trained, q):
     if q == 2:
         # most 5-row LPs start from their optimal basis
         assert cb["warm_hit"] > 0.5 * cb["n_small"]
+    else:
+        # the predicted columns, repaired by the composite phase I, save pivots
+        # (counting the crash pivots)
+        assert cb["pivots"] < 0.95 * ca["pivots"]
 
 
 def _host_features(x, y, ids, i, cols, h):
