@@ -228,6 +228,8 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
     A(full_k, cap);
     A(full_order, cap);
     A(khist, 2 * (VRM_KMAX + 1));
+    A(lkey, cap);
+    A(pivhist, cap);
 #undef A
     if (r == VRM_OK) {
         c->sort_tmp_bytes = std::max(vrm_sort_tmp_bytes(capacity), vrm_remove_tmp_bytes(capacity));
@@ -250,6 +252,7 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
         if (e == hipSuccess) e = hipMemsetAsync(c->sel, 0, sizeof(vrm::SelectState), c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->grid, 0, sizeof(vrm::GridState), c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->khist, 0, 2 * (VRM_KMAX + 1) * sizeof(int32_t), c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->pivhist, 0xff, cap, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) r = vrm_hip_check(e, "initialisation");
     }
@@ -272,7 +275,7 @@ int vrm_destroy(vrm_ctx* c)
                     c->perm, c->xs, c->ys, c->ids, c->diffused, c->acc, c->x0, c->y0, c->g0, c->q_small, c->q_full, c->q_retry,
                     c->srec.i, c->srec.rank, c->srec.pj, c->srec.off, c->cx, c->cy, c->ckey, c->cstate, c->ccell, c->crank, c->cstart, c->cperm,
                     c->akey, c->aidx, c->tmp_f, c->tmp_i, c->tmp_u8, c->verify_buf, c->sort_tmp, c->full_cols,
-                    c->full_k, c->full_order, c->khist};
+                    c->full_k, c->full_order, c->khist, c->lkey, c->pivhist};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->q_host) (void)hipHostFree(c->q_host);
@@ -282,7 +285,6 @@ int vrm_destroy(vrm_ctx* c)
     if (c->prev) (void)hipFree(c->prev);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->pmask) (void)hipFree(c->pmask);
-    if (c->lkey) (void)hipFree(c->lkey);
     if (c->feat) (void)hipFree(c->feat);
     if (c->u_tmp) (void)hipFree(c->u_tmp);
     if (c->pred) (void)hipFree(c->pred);
@@ -791,11 +793,6 @@ int vrm_set_warm_start(vrm_ctx* c, int enable)
             void* p = nullptr;
             VRM_HIP(hipMalloc(&p, sizeof(uint64_t) * (size_t)c->capacity + 64));
             c->pmask = (uint64_t*)p;
-        }
-        if (!c->lkey) {
-            void* p = nullptr;
-            VRM_HIP(hipMalloc(&p, sizeof(int32_t) * (size_t)c->capacity + 64));
-            c->lkey = (int32_t*)p;
         }
     }
     c->warm = enable ? 1 : 0;

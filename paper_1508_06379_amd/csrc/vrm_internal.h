@@ -235,7 +235,8 @@ struct vrm_ctx {
     double* t_dev;               // step start time read by the graph's velocity kernels
     int32_t* prev;               // [cap][9] basis (column ids) of each particle's last stencil, by id
     uint64_t* pmask;             // [cap] crash basis (previous or predicted) as a column mask per complete LP
-    int32_t* lkey;               // [cap] bin of each complete LP by the network's doubt (learned warm start)
+    int32_t* lkey;               // [cap] bin of each complete LP for the counting sort (pivot history or doubt)
+    uint8_t* pivhist;            // [cap] by particle id: pivots of its last complete LP (255: none yet)
     vrm_tuning tuning;           // launch shapes in force (defaults filled in)
     hipStream_t cap_stream;      // stream the graph is captured on (the context's may be the null stream)
     // warm-start network (allocated on first use)

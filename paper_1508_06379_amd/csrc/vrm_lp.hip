@@ -362,6 +362,7 @@ struct StencilOut {
     int prev_cap;        // rows of prev: particles with larger ids keep no basis (they start cold)
     int use_prev;        // warm start from prev instead of pred
     const uint64_t* pmask;   // previous basis as a column mask per complete-neighbourhood queue item (size-binned path)
+    uint8_t* pivhist;        // by particle id (< prev_cap): pivots of its last cold complete LP
     const int32_t* cloud_id;   // ids by cloud index
 };
 
@@ -1178,7 +1179,8 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
                                                              Queues* qs, LaunchParams P, int32_t* rec, int32_t* kcol,
                                                              int32_t* khist, int32_t* q_retry, vrm_counters* cnt,
                                                              const int32_t* __restrict__ prev, int prev_cap,
-                                                             uint64_t* pmask, uint16_t* feat)
+                                                             uint64_t* pmask, uint16_t* feat,
+                                                             const uint8_t* __restrict__ pivhist, int32_t* key)
 {
     __shared__ float s_d2[kCollGroups][kMemCap];
     __shared__ int s_id[kCollGroups][kMemCap];
@@ -1355,11 +1357,24 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
             }
             if (sub == 0) {
                 kcol[r] = k;
-                // (with a network, the LPs are binned by its confidence instead, after inference)
-                if (WM != 1) atomicAdd(&s_hist[k], 1);
+                // the bin of the counting sort: the particle's pivots in its last
+                // complete LP when known (cold or network-started solves), else k
+                if constexpr (WM != 2) {
+                    const int own = ids[t];
+                    const int h = (unsigned)own < (unsigned)prev_cap ? pivhist[own] : 255;
+                    const int b = h == 255 ? k : min(h, kKBins - 1);
+                    key[r] = b;
+                    atomicAdd(&s_hist[b], 1);
+                } else if constexpr (WM == 2) {
+                    key[r] = k;
+                    atomicAdd(&s_hist[k], 1);
+                }
             }
         }
-        if (over && sub == 0) kcol[r] = -1;
+        if (over && sub == 0) {
+            kcol[r] = -1;
+            key[r] = -1;   // not binned: the one-thread kernel solves it
+        }
         // lists too long for the group: the one-thread kernel solves them from the retry queue
         const int pr = wave_append(&qs->n_retry, over && sub == 0);
         if (over && sub == 0) q_retry[pr] = t;
@@ -1489,26 +1504,14 @@ struct SiftCols {
 
 // The network's predicted basis of each complete LP: the m columns of largest
 // logit among its first min(k, kMlpSlots) (lowest slot among equal logits), as
-// a column mask for the crash; and its bin for the counting sort: the
-// network's doubt, -4 sum log sigmoid over those m logits (0 when it is sure
-// of all m), so that the lanes of a wave take LPs of similar difficulty (their
-// number of repair pivots, not k, is what varies).
+// a column mask for the crash.
 __global__ __launch_bounds__(256) void k_top_mask(const float* __restrict__ pred, const int32_t* __restrict__ kcol,
-                                                  const Queues* qs, int m, uint64_t* pmask, int32_t* key,
-                                                  int32_t* khist)
+                                                  const Queues* qs, int m, uint64_t* pmask)
 {
-    __shared__ int s_hist[kKBins];
-    for (int b = threadIdx.x; b < kKBins; b += blockDim.x) s_hist[b] = 0;
-    __syncthreads();
     const int nitems = qs->n_full;
-    const int loops = (nitems + gridDim.x * blockDim.x - 1) / (gridDim.x * blockDim.x);
-    for (int it = 0; it < loops; ++it) {
-        const int r = blockIdx.x * blockDim.x + threadIdx.x + it * gridDim.x * blockDim.x;
-        const int k = r < nitems ? kcol[r] : -1;   // -1: a list left for the one-thread kernel
-        if (k < 0) {
-            if (r < nitems) key[r] = -1;
-            continue;
-        }
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nitems; r += gridDim.x * blockDim.x) {
+        const int k = kcol[r];   // -1: a list left for the one-thread kernel
+        if (k < 0) continue;
         const int kk = min(k, kMlpSlots);
         float v[kMlpSlots];
         const float4* row = reinterpret_cast<const float4*>(pred + (size_t)r * kMlpOut);
@@ -1521,7 +1524,6 @@ __global__ __launch_bounds__(256) void k_top_mask(const float* __restrict__ pred
             v[4 * a + 3] = q.w;
         }
         uint64_t mask = 0;
-        float doubt = 0.0f;
         for (int t = 0; t < m && t < kk; ++t) {
             int best = -1;
             float bv = 0.0f;
@@ -1532,17 +1534,9 @@ __global__ __launch_bounds__(256) void k_top_mask(const float* __restrict__ pred
                 bv = ok ? v[j] : bv;
             }
             mask |= 1ull << best;
-            // -log sigmoid(bv) = log(1 + exp(-bv))
-            doubt += bv > 20.0f ? 0.0f : (bv < -20.0f ? -bv : __logf(1.0f + __expf(-bv)));
         }
         pmask[r] = mask;
-        const int b = (int)fminf(4.0f * doubt, (float)(kKBins - 1));
-        key[r] = b;
-        atomicAdd(&s_hist[b], 1);
     }
-    __syncthreads();
-    for (int b = threadIdx.x; b < kKBins; b += blockDim.x)
-        if (s_hist[b]) atomicAdd(&khist[b], s_hist[b]);
 }
 
 // WM: 0 cold; 1 crash from the network's prediction (out.pmask: its top-m
@@ -1629,6 +1623,11 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
                 const int own = ids[t];
                 auto col_id = [&](int j) { return ids[(unsigned)row[j] >> 6]; };
                 if (st == 0 && (unsigned)own < (unsigned)out.prev_cap) record_basis(out.prev, own, basis, col_id);
+            }
+            if constexpr (WM != 2) {
+                // this LP's pivots, the bin of the particle's next complete LP
+                const int own = ids[t];
+                if (out.pivhist && (unsigned)own < (unsigned)out.prev_cap) out.pivhist[own] = (uint8_t)min(piv, 254);
             }
             if (st == 0) {
                 if (apply) acc_add(acc, i, fii, g_i, dsc);
@@ -2086,27 +2085,24 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
                                c->stream, c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, lp,
                                c->full_cols, c->full_k, c->khist, c->q_retry, c->counters,
                                wm == 2 ? c->prev : nullptr, c->capacity, wm == 2 ? c->pmask : nullptr,
-                               wm == 1 ? c->feat : nullptr);
-            if (wm != 1) {
-                hipLaunchKernelGGL(k_full_bin_starts, dim3(1), dim3(64), 0, c->stream, c->khist);
-                hipLaunchKernelGGL(k_full_bin_scatter, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->full_k,
-                                   c->queues, c->khist, c->full_order);
-            }
-            VRM_HIP(hipGetLastError());
-        }
-        if (wm == 1) {
-            // the forward pass, the predicted bases, and the LPs sorted by the network's doubt
-            ScopedTimer tm(c, VRM_T_MLP);
-            int r = vrm_mlp_infer_run(c, c->feat, n, c->pred, &c->queues->n_full);
-            if (r) return r;
-            hipLaunchKernelGGL(k_top_mask, dim3(min((n + 255) / 256, 4096)), dim3(256), 0, c->stream, c->pred,
-                               c->full_k, c->queues, lp.m, c->pmask, c->lkey, c->khist);
+                               wm == 1 ? c->feat : nullptr, c->pivhist, c->lkey);
             hipLaunchKernelGGL(k_full_bin_starts, dim3(1), dim3(64), 0, c->stream, c->khist);
             hipLaunchKernelGGL(k_full_bin_scatter, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->lkey,
                                c->queues, c->khist, c->full_order);
             VRM_HIP(hipGetLastError());
         }
+        if (wm == 1) {
+            // the forward pass and the predicted bases
+            ScopedTimer tm(c, VRM_T_MLP);
+            int r = vrm_mlp_infer_run(c, c->feat, n, c->pred, &c->queues->n_full);
+            if (r) return r;
+            hipLaunchKernelGGL(k_top_mask, dim3(min((n + 255) / 256, 4096)), dim3(256), 0, c->stream, c->pred,
+                               c->full_k, c->queues, lp.m, c->pmask);
+            VRM_HIP(hipGetLastError());
+        }
         if (wm) out.pmask = c->pmask;
+        out.pivhist = c->pivhist;
+        out.prev_cap = c->capacity;
         ScopedTimer tm(c, VRM_T_LP_FULL);
         const int obj = lp.phase1;
         auto sift = wm == 0 ? by_objective(obj, k_lp_sift<9, kSiftW, 0, 0>, k_lp_sift<9, kSiftW, 1, 0>,
