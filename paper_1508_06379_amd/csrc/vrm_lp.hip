@@ -1243,14 +1243,19 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const bool over = live && count > kMemCap;
         const int nm = over ? 0 : count;
+        // members per lane that any group of the wave has (wave-uniform, so the
+        // unused ones of the kMemPerLane are skipped by a scalar branch)
+        int nqw = 0;
+#pragma unroll
+        for (int q = 0; q < kMemPerLane; ++q) nqw += __ballot(nm > kCollL * q) ? 1 : 0;
         // this lane's members: e = sub + kCollL q
         float md[kMemPerLane];
         int mi[kMemPerLane], pos[kMemPerLane], rk[kMemPerLane];
 #pragma unroll
         for (int q = 0; q < kMemPerLane; ++q) {
             const int e = sub + kCollL * q;
-            md[q] = e < nm ? s_d2[grp][e] : 0.0f;
-            mi[q] = e < nm ? s_id[grp][e] : 0;
+            md[q] = q < nqw && e < nm ? s_d2[grp][e] : 0.0f;
+            mi[q] = q < nqw && e < nm ? s_id[grp][e] : 0;
             pos[q] = 0;
             rk[q] = 0;
         }
@@ -1259,8 +1264,10 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
             const int id = s_id[grp][o];
 #pragma unroll
             for (int q = 0; q < kMemPerLane; ++q) {
-                pos[q] += (d < md[q] || (d == md[q] && id < mi[q])) ? 1 : 0;
-                rk[q] += id < mi[q] ? 1 : 0;
+                if (q < nqw) {
+                    pos[q] += (d < md[q] || (d == md[q] && id < mi[q])) ? 1 : 0;
+                    rk[q] += id < mi[q] ? 1 : 0;
+                }
             }
         }
         const int k = min(nm, VRM_KMAX);
