@@ -32,7 +32,8 @@ constexpr float kCertD = 1e-9f;                   // certified reduced-cost tole
 constexpr float kCertX = 1e-9f;                   // certified primal tolerance (absolute, fhat units)
 constexpr float kNnlsRes = 1e-5f;                 // NNLS: residual of a found support (relative to b)
 constexpr int kMaxRefine = 6;
-constexpr float kFastMargin = 1e-3f;              // FP32 reduced-cost margin of the fast certificate
+constexpr float kFastMargin = 64.0f;              // fast certificate: FP32 reduced costs clear zero by this many
+                                                  // times their error bound (first correction + 2^-23) x scale
 
 // Rows of a column: the monomials r^alpha, 1 <= |alpha| <= q (M = 5, 9), or
 // for the identity operator of particle removal (M = 3) 1, x, y.
@@ -699,7 +700,11 @@ struct ThreadSimplex {
 
     // Basic solution of the current basis for the exact right-hand side, refined
     // with double-float residuals; returns |first correction| / |x| (how far
-    // B^-1 is from the exact inverse).
+    // B^-1 is from the exact inverse).  One refinement step multiplies the
+    // error by about that ratio (the error of x0 = B^-1 b is B^-1's error, and
+    // the step leaves (I - B^-1 B) times it), so a first correction below
+    // 2^-20 of x leaves x accurate to about 2^-40 of x, far below the 1e-9
+    // of the certified decisions: no second residual is formed to confirm it.
     __device__ float refine_primal(const CS& cs, const LaunchParams& P, df (&x)[M]) const
     {
 #pragma unroll
@@ -724,7 +729,7 @@ struct ThreadSimplex {
                 xmax = fmaxf(xmax, fabsf(x[r].hi));
             }
             if (it == 0) first_corr = dmax / fmaxf(xmax, 1e-30f);
-            if (dmax <= 9.313225746154785e-10f * xmax) break;
+            if (dmax <= 9.313225746154785e-10f * xmax || (it == 0 && first_corr <= 9.5367431640625e-07f)) break;
         }
         return first_corr;
     }
@@ -761,10 +766,12 @@ struct ThreadSimplex {
             for (int r = 0; r < M; ++r)
                 if (bs[r] >= ART && fabsf(x[r].hi + x[r].lo) > kCertX) return 1;
             // Fast certificate: when B^-1 is accurate (the first correction is
-            // tiny) and every FP32 reduced cost clears zero by a margin far above
-            // its rounding error, the basis is optimal without the double-float
-            // dual check.
+            // tiny) and every FP32 reduced cost clears zero by 64 times its error
+            // bound, the basis is optimal without the double-float dual check.
             if (first_corr <= 1e-5f) {
+                // |d - d_exact| <= (error of B^-1 + FP32 rounding) x sc; the error of
+                // B^-1 is about the first correction
+                const float margin = kFastMargin * (first_corr + 1.1920929e-07f);
                 bool primal_ok = true;
 #pragma unroll
                 for (int r = 0; r < M; ++r)
@@ -779,7 +786,7 @@ struct ThreadSimplex {
                         mono<M>(cs.x, cs.y, v);
                         float d, sc;
                         reduced(v, cs.c, yf, true, d, sc);
-                        dual_ok = cs.all(((excl >> cs.own) & 1ull) || !(d < kFastMargin * sc));
+                        dual_ok = cs.all(((excl >> cs.own) & 1ull) || !(d < margin * sc));
                     } else if constexpr (CS::KC > 0) {
 #pragma unroll
                         for (int j = 0; j < CS::KC; ++j) {
@@ -790,7 +797,7 @@ struct ThreadSimplex {
                             mono<M>(rx, ry, v);
                             float d, sc;
                             reduced(v, c, yf, true, d, sc);
-                            dual_ok = dual_ok && !(d < kFastMargin * sc);
+                            dual_ok = dual_ok && !(d < margin * sc);
                         }
                     } else {
                         auto column = [&](int j, bool in, float rx, float ry, uint32_t aux) {
@@ -799,7 +806,7 @@ struct ThreadSimplex {
                             mono<M>(rx, ry, v);
                             float d, sc;
                             reduced(v, c, yf, true, d, sc);
-                            dual_ok = dual_ok && (!in || ((excl >> j) & 1ull) || !(d < kFastMargin * sc));
+                            dual_ok = dual_ok && (!in || ((excl >> j) & 1ull) || !(d < margin * sc));
                         };
                         const int k1 = min(k, CS::kLds);
                         for (int j0 = 0; j0 < k1; j0 += 4) {
