@@ -230,6 +230,8 @@ int vrm_create(vrm_ctx** out, int device, void* stream, int32_t capacity)
     A(khist, 2 * (VRM_KMAX + 1));
     A(lkey, cap);
     A(pivhist, cap);
+    A(q_defer, cap);
+    A(pmask, cap);
 #undef A
     if (r == VRM_OK) {
         c->sort_tmp_bytes = std::max(vrm_sort_tmp_bytes(capacity), vrm_remove_tmp_bytes(capacity));
@@ -275,7 +277,7 @@ int vrm_destroy(vrm_ctx* c)
                     c->perm, c->xs, c->ys, c->ids, c->diffused, c->acc, c->x0, c->y0, c->g0, c->q_small, c->q_full, c->q_retry,
                     c->srec.i, c->srec.rank, c->srec.pj, c->srec.off, c->cx, c->cy, c->ckey, c->cstate, c->ccell, c->crank, c->cstart, c->cperm,
                     c->akey, c->aidx, c->tmp_f, c->tmp_i, c->tmp_u8, c->verify_buf, c->sort_tmp, c->full_cols,
-                    c->full_k, c->full_order, c->khist, c->lkey, c->pivhist};
+                    c->full_k, c->full_order, c->khist, c->lkey, c->pivhist, c->q_defer, c->pmask};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->q_host) (void)hipHostFree(c->q_host);
@@ -284,7 +286,6 @@ int vrm_destroy(vrm_ctx* c)
     if (c->t_dev) (void)hipFree(c->t_dev);
     if (c->prev) (void)hipFree(c->prev);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->pmask) (void)hipFree(c->pmask);
     if (c->feat) (void)hipFree(c->feat);
     if (c->u_tmp) (void)hipFree(c->u_tmp);
     if (c->pred) (void)hipFree(c->pred);
@@ -772,11 +773,6 @@ int vrm_set_warm_start(vrm_ctx* c, int enable)
             c->prev = (int32_t*)p;
             VRM_HIP(hipMemsetAsync(c->prev, 0xff, sizeof(int32_t) * (size_t)c->capacity * 9, c->stream));
         }
-        if (!c->pmask) {
-            void* p = nullptr;
-            VRM_HIP(hipMalloc(&p, sizeof(uint64_t) * (size_t)c->capacity + 64));
-            c->pmask = (uint64_t*)p;
-        }
         c->warm = 2;
         return VRM_OK;
     }
@@ -788,11 +784,6 @@ int vrm_set_warm_start(vrm_ctx* c, int enable)
             c->feat = (uint16_t*)p;
             VRM_HIP(hipMalloc(&p, sizeof(float) * (size_t)c->capacity * vrm::kMlpOut + 64));
             c->pred = (float*)p;
-        }
-        if (!c->pmask) {
-            void* p = nullptr;
-            VRM_HIP(hipMalloc(&p, sizeof(uint64_t) * (size_t)c->capacity + 64));
-            c->pmask = (uint64_t*)p;
         }
     }
     c->warm = enable ? 1 : 0;

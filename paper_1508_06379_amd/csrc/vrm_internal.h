@@ -81,7 +81,7 @@ struct Queues {
     int32_t n_removed;     // particle removal: particles removed by the last call
     int32_t n_rm_uncertified;   // ... of which optimality was not certified
     int32_t nonfinite;     // copy of GridState::bad taken when the record is published
-    int32_t pad;
+    int32_t n_defer;       // complete LPs whose certification was deferred to a second launch
 };
 
 // Queue record published to pinned, coherent host memory: the kernel writes q,
@@ -236,6 +236,7 @@ struct vrm_ctx {
     int32_t* prev;               // [cap][9] basis (column ids) of each particle's last stencil, by id
     uint64_t* pmask;             // [cap] crash basis (previous or predicted) as a column mask per complete LP
     int32_t* lkey;               // [cap] bin of each complete LP for the counting sort (pivot history or doubt)
+    int32_t* q_defer;            // [cap] queue items of the complete LPs whose certification was deferred
     uint8_t* pivhist;            // [cap] by particle id: pivots of its last complete LP (255: none yet)
     vrm_tuning tuning;           // launch shapes in force (defaults filled in)
     hipStream_t cap_stream;      // stream the graph is captured on (the context's may be the null stream)

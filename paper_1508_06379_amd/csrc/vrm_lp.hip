@@ -361,7 +361,7 @@ struct StencilOut {
     int32_t* prev;       // basis (column ids) of each particle's last stencil, [id][kPrevIds]: recorded if non-NULL
     int prev_cap;        // rows of prev: particles with larger ids keep no basis (they start cold)
     int use_prev;        // warm start from prev instead of pred
-    const uint64_t* pmask;   // previous basis as a column mask per complete-neighbourhood queue item (size-binned path)
+    uint64_t* pmask;         // crash basis as a column mask per complete-neighbourhood queue item (size-binned path)
     uint8_t* pivhist;        // by particle id (< prev_cap): pivots of its last cold complete LP
     const int32_t* cloud_id;   // ids by cloud index
 };
@@ -1131,6 +1131,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
             qs->n_small = 0;
             qs->n_full = 0;
             qs->n_retry = 0;
+            qs->n_defer = 0;
             qs->blocks_done = 0;
         }
     }
@@ -1548,32 +1549,40 @@ __global__ __launch_bounds__(256) void k_top_mask(const float* __restrict__ pred
 
 // WM: 0 cold; 1 crash from the network's prediction (out.pmask: its top-m
 // columns per queue item), finished whatever it takes; 2 crash from the
-// previous basis (out.pmask), at most warm_cap pivots, recording the new one.
-// A crash basis that is not feasible is repaired by the composite phase I; a
-// warm attempt that fails is solved cold in place.
+// previous basis (out.pmask), at most warm_cap pivots, recording the new one;
+// 3 the deferred certifications of a cold launch (the items of `list`, their
+// bases in out.pmask).  A crash basis that is not feasible is repaired by the
+// composite phase I; a warm attempt that fails is solved cold in place.  The
+// cold canonical launch (WM 0, OBJ 0) defers the LPs whose fast certificate
+// fails to a WM 3 launch: the double-float dual check of a few per cent of
+// the LPs would otherwise hold up most waves (a wave runs it when any of its
+// 64 lanes needs it).
 template <int M, int W, int OBJ, int WM>
 __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_lp_sift(
     const int32_t* __restrict__ perm, const float* __restrict__ xs, const float* __restrict__ ys,
     const int32_t* __restrict__ ids, const int32_t* __restrict__ order, const int32_t* __restrict__ kcol,
     const int32_t* __restrict__ rec, const int32_t* __restrict__ q_full, Queues* qs, const float* __restrict__ gamma,
-    float* acc, LaunchParams P, StencilOut out, int apply, vrm_counters* cnt, int last_launch, const GridState* gs)
+    float* acc, LaunchParams P, StencilOut out, int apply, vrm_counters* cnt, int last_launch, const GridState* gs,
+    int32_t* q_defer)
 {
+    constexpr bool kDefer = WM == 0 && OBJ == 0;
     __shared__ float s_x[W * kFullBlock];
     __shared__ float s_y[W * kFullBlock];
     __shared__ float s_c[W * kFullBlock];
     cnt = counter_stripe(cnt);
     const int tid = threadIdx.x;
-    const int nitems = qs->n_full - qs->n_retry;   // the binned ones
+    // the binned items, or the deferred ones
+    const int nitems = WM == 3 ? qs->n_defer : qs->n_full - qs->n_retry;
     const int stride = gridDim.x * blockDim.x;
     const int loops = (nitems + stride - 1) / stride;
     const double dsc = P.det && apply ? det_scale(gs->gmax_bits) : 0.0;
     for (int it = 0; it < loops; ++it) {
         const int p = blockIdx.x * blockDim.x + tid + it * stride;
         const bool live = p < nitems;
-        int st = 1, piv = 0, certified = 1, k = 0, warm = 0;
+        int st = 1, piv = 0, certified = 1, k = 0, warm = 0, r = 0;
         int cstat[2] = {0, 0};
         if (live) {
-            const int r = order[p];
+            r = WM == 3 ? q_defer[p] : order[p];
             const int t = q_full[r];
             const int i = perm[t];
             k = kcol[r];
@@ -1619,19 +1628,21 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
             uint64_t basis = 0;
             if constexpr (WM == 0) {
                 st = solve_lp<M, OBJ, false>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false,
-                                             0ull, cstat);
+                                             0ull, cstat, true, kDefer);
+                if (kDefer && st == 5) out.pmask[r] = basis;
             } else {
                 const uint64_t pref = out.pmask[r];
                 // a prediction that is given up is followed by the cold solve in place
                 st = solve_lp<M, OBJ, true, true>(cs, P, store, fii, piv, certified, true, nullptr, warm, basis,
-                                                  true, pref, cstat, WM == 2);
+                                                  true, pref, cstat, WM != 1);
+                if (WM == 3) warm = 0;
             }
             if constexpr (WM == 2) {
                 const int own = ids[t];
                 auto col_id = [&](int j) { return ids[(unsigned)row[j] >> 6]; };
                 if (st == 0 && (unsigned)own < (unsigned)out.prev_cap) record_basis(out.prev, own, basis, col_id);
             }
-            if constexpr (WM != 2) {
+            if constexpr (WM < 2) {
                 // this LP's pivots, the bin of the particle's next complete LP
                 const int own = ids[t];
                 if (out.pivhist && (unsigned)own < (unsigned)out.prev_cap) out.pivhist[own] = (uint8_t)min(piv, 254);
@@ -1643,11 +1654,15 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
                     out.fii[i] = fii;
                     out.status[i] = (warm == 1 || warm == 2) ? VRM_ST_WARM : VRM_ST_FULL;
                 }
-            } else if (out.status) {
+            } else if (out.status && st != 5) {
                 out.status[i] = VRM_ST_INFEASIBLE;
             }
         }
-        if constexpr (WM != 0) count_warm(cnt, live, warm);
+        if constexpr (kDefer) {
+            const int dpos = wave_append(&qs->n_defer, live && st == 5);
+            if (live && st == 5) q_defer[dpos] = r;
+        }
+        if constexpr (WM == 1 || WM == 2) count_warm(cnt, live, warm);
         const bool ok = live && st == 0;
         if (piv) atomicAdd((unsigned long long*)&cnt->pivots, (unsigned long long)piv);
         if (ok) atomicAdd((unsigned long long*)&cnt->full_cols, (unsigned long long)k);
@@ -1681,6 +1696,7 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
             qs->n_small = 0;
             qs->n_full = 0;
             qs->n_retry = 0;
+            qs->n_defer = 0;
             qs->blocks_done = 0;
         }
     }
@@ -2107,7 +2123,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
                                c->full_k, c->queues, lp.m, c->pmask);
             VRM_HIP(hipGetLastError());
         }
-        if (wm) out.pmask = c->pmask;
+        out.pmask = c->pmask;
         out.pivhist = c->pivhist;
         out.prev_cap = c->capacity;
         ScopedTimer tm(c, VRM_T_LP_FULL);
@@ -2118,7 +2134,13 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
                             : (obj == 1 ? k_lp_sift<9, kSiftW, 1, 2> : k_lp_sift<9, kSiftW, 0, 2>);
         hipLaunchKernelGGL(sift, dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
                            c->ids, c->full_order, c->full_k, c->full_cols, c->q_full, c->queues, cl->gamma_dev, c->acc,
-                           lp, out, apply, c->counters, 0, c->grid);
+                           lp, out, apply, c->counters, 0, c->grid, c->q_defer);
+        if (wm == 0 && obj == 0) {
+            // the certifications the cold launch deferred, from their bases (count read on the device)
+            hipLaunchKernelGGL((k_lp_sift<9, kSiftW, 0, 3>), dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream,
+                               c->perm, c->xs, c->ys, c->ids, c->full_order, c->full_k, c->full_cols, c->q_full,
+                               c->queues, cl->gamma_dev, c->acc, lp, out, apply, c->counters, 0, c->grid, c->q_defer);
+        }
         // lists too long for the collection groups (none in practice): the one-thread
         // kernel from the retry queue, cold; as the run's last LP launch it empties the queues
         hipLaunchKernelGGL((full_kernel<9, false>(lp.phase1)), dim3(1), dim3(kFullBlock), 0, c->stream, c->perm, c->xs,
@@ -2163,6 +2185,7 @@ __global__ void k_queues_done(Queues* qs)
     qs->n_small = 0;
     qs->n_full = 0;
     qs->n_retry = 0;
+    qs->n_defer = 0;
     qs->blocks_done = 0;
 }
 }  // namespace

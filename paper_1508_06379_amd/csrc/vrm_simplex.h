@@ -750,9 +750,11 @@ struct ThreadSimplex {
     }
 
     // Certify against the exact problem, repairing the basis if needed.
-    // 0 optimal, 1 infeasible, 3 not certified.  x receives the basic values
+    // 0 optimal, 1 infeasible, 3 not certified; with `defer`, 5 when the first
+    // round's fast certificate does not settle it (the basis is left as it is
+    // for a later call without `defer`).  x receives the basic values
     // of the final basis (refined for it, also after a last repair pivot).
-    __device__ int certify(const CS& cs, const LaunchParams& P, df (&x)[M], int& piv)
+    __device__ int certify(const CS& cs, const LaunchParams& P, df (&x)[M], int& piv, bool defer = false)
     {
         const int k = cs.k;
         for (int round = 0; round < P.max_cert; ++round) {
@@ -829,6 +831,7 @@ struct ThreadSimplex {
                     if (dual_ok) return 0;
                 }
             }
+            if (defer && round == 0) return 5;
             cert_exact = 1;
             float yf[M];
             prices(true, yf);
@@ -976,7 +979,9 @@ struct ThreadSimplex {
 
 // Solve, certify and extract the fractions: f (k entries, written through
 // store(j, value) for the non-zero ones) and fii = -sum f.
-// Returns 0 ok, 1 infeasible, 4 left for a cold solve (warm pass);
+// Returns 0 ok, 1 infeasible, 4 left for a cold solve (warm pass), 5 the
+// certification deferred (`defer`: the fast certificate did not settle the
+// optimum; nothing is stored and `basis` holds the basic columns);
 // *certified = 0 if optimality could not be shown.
 // Warm pass (warm_pass): the simplex starts from the crash basis of the
 // prediction (logits of the first 32 columns, or the column set pref with
@@ -1279,16 +1284,24 @@ __device__ int solve_nnls(const CS& cs, const LaunchParams& P, Store store, floa
 // value)), fii = -their sum, and the final basis.  Returns solve_lp's result.
 template <int M, class CS, class Store>
 __device__ int finish_lp(ThreadSimplex<M, CS>& lp, const CS& cs, const LaunchParams& P, Store store, int st,
-                         bool accepted, df (&x)[M], float& fii, int& piv, int& certified, uint64_t& basis, int* stats)
+                         bool accepted, df (&x)[M], float& fii, int& piv, int& certified, uint64_t& basis, int* stats,
+                         bool defer = false)
 {
     certified = 1;
     if (st == 1) return 1;
-    const int c = accepted ? 0 : lp.certify(cs, P, x, piv);
+    const int c = accepted ? 0 : lp.certify(cs, P, x, piv, defer);
     if (stats) {
         stats[0] = lp.cert_rounds;
         stats[1] = lp.cert_exact;
     }
     if (c == 1) return 1;
+    if (c == 5) {
+        // deferred: the caller keeps the basis's columns for the later certification
+#pragma unroll
+        for (int r = 0; r < M; ++r)
+            if (lp.bs[r] < lp.ART) basis |= 1ull << lp.bs[r];
+        return 5;
+    }
     // not certified optimal: kept only if its exact values meet the moment
     // conditions and the sign condition, else treated as infeasible
     if (c == 3 && !lp.primal_feasible(x)) return 1;
@@ -1324,7 +1337,7 @@ __device__ int finish_lp(ThreadSimplex<M, CS>& lp, const CS& cs, const LaunchPar
 template <int M, int OBJ, bool WARM = true, bool INPLACE = false, class CS, class Store>
 __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float& fii, int& piv, int& certified,
                         bool warm_pass_arg, const float* logit, int& warm, uint64_t& basis, bool use_pref = false,
-                        uint64_t pref = 0, int* stats = nullptr, bool capped = true)
+                        uint64_t pref = 0, int* stats = nullptr, bool capped = true, bool defer = false)
 {
     if constexpr (OBJ == 2) {
         warm = 0;
@@ -1404,7 +1417,7 @@ __device__ int solve_lp(const CS& cs, const LaunchParams& P, Store store, float&
                 st = lp.run(cs, piv, 1);
         }
     }
-    return finish_lp<M>(lp, cs, P, store, st, accepted, x, fii, piv, certified, basis, stats);
+    return finish_lp<M>(lp, cs, P, store, st, accepted, x, fii, piv, certified, basis, stats, defer);
 }
 
 }  // namespace vrm
