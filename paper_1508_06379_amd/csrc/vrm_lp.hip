@@ -1550,13 +1550,14 @@ __global__ __launch_bounds__(256) void k_top_mask(const float* __restrict__ pred
 // WM: 0 cold; 1 crash from the network's prediction (out.pmask: its top-m
 // columns per queue item), finished whatever it takes; 2 crash from the
 // previous basis (out.pmask), at most warm_cap pivots, recording the new one;
-// 3 the deferred certifications of a cold launch (the items of `list`, their
-// bases in out.pmask).  A crash basis that is not feasible is repaired by the
-// composite phase I; a warm attempt that fails is solved cold in place.  The
-// cold canonical launch (WM 0, OBJ 0) defers the LPs whose fast certificate
-// fails to a WM 3 launch: the double-float dual check of a few per cent of
-// the LPs would otherwise hold up most waves (a wave runs it when any of its
-// 64 lanes needs it).
+// 3 the certifications deferred by the launch before (the items in q_defer,
+// their bases in out.pmask), recording the basis when out.prev is set.  A
+// crash basis that is not feasible is repaired by the composite phase I; a
+// warm attempt that fails is solved cold in place.  The canonical launches
+// (OBJ 0, WM 0 to 2) defer the LPs whose fast certificate fails to a WM 3
+// launch: the double-float dual check of a few per cent of the LPs would
+// otherwise hold up most waves (a wave runs it when any of its 64 lanes
+// needs it).
 template <int M, int W, int OBJ, int WM>
 __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_lp_sift(
     const int32_t* __restrict__ perm, const float* __restrict__ xs, const float* __restrict__ ys,
@@ -1565,7 +1566,7 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
     float* acc, LaunchParams P, StencilOut out, int apply, vrm_counters* cnt, int last_launch, const GridState* gs,
     int32_t* q_defer)
 {
-    constexpr bool kDefer = WM == 0 && OBJ == 0;
+    constexpr bool kDefer = WM != 3 && OBJ == 0;
     __shared__ float s_x[W * kFullBlock];
     __shared__ float s_y[W * kFullBlock];
     __shared__ float s_c[W * kFullBlock];
@@ -1579,10 +1580,17 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
     for (int it = 0; it < loops; ++it) {
         const int p = blockIdx.x * blockDim.x + tid + it * stride;
         const bool live = p < nitems;
-        int st = 1, piv = 0, certified = 1, k = 0, warm = 0, r = 0;
+        int st = 1, piv = 0, certified = 1, k = 0, warm = 0, r = 0, was_warm = 0;
         int cstat[2] = {0, 0};
         if (live) {
-            r = WM == 3 ? q_defer[p] : order[p];
+            if constexpr (WM == 3) {
+                // top bit: the deferring launch had settled the LP from its warm start
+                const int e = q_defer[p];
+                r = e & 0x7fffffff;
+                was_warm = (unsigned)e >> 31;
+            } else {
+                r = order[p];
+            }
             const int t = q_full[r];
             const int i = perm[t];
             k = kcol[r];
@@ -1629,15 +1637,15 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
             if constexpr (WM == 0) {
                 st = solve_lp<M, OBJ, false>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false,
                                              0ull, cstat, true, kDefer);
-                if (kDefer && st == 5) out.pmask[r] = basis;
             } else {
                 const uint64_t pref = out.pmask[r];
                 // a prediction that is given up is followed by the cold solve in place
                 st = solve_lp<M, OBJ, true, true>(cs, P, store, fii, piv, certified, true, nullptr, warm, basis,
-                                                  true, pref, cstat, WM != 1);
-                if (WM == 3) warm = 0;
+                                                  true, pref, cstat, WM != 1, kDefer);
+                if (WM == 3) warm = was_warm;
             }
-            if constexpr (WM == 2) {
+            if (kDefer && st == 5) out.pmask[r] = basis;
+            if (WM == 2 || (WM == 3 && out.prev)) {
                 const int own = ids[t];
                 auto col_id = [&](int j) { return ids[(unsigned)row[j] >> 6]; };
                 if (st == 0 && (unsigned)own < (unsigned)out.prev_cap) record_basis(out.prev, own, basis, col_id);
@@ -1660,7 +1668,7 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
         }
         if constexpr (kDefer) {
             const int dpos = wave_append(&qs->n_defer, live && st == 5);
-            if (live && st == 5) q_defer[dpos] = r;
+            if (live && st == 5) q_defer[dpos] = r | ((warm == 1 || warm == 2) ? (int)0x80000000u : 0);
         }
         if constexpr (WM == 1 || WM == 2) count_warm(cnt, live, warm);
         const bool ok = live && st == 0;
@@ -2135,7 +2143,7 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         hipLaunchKernelGGL(sift, dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
                            c->ids, c->full_order, c->full_k, c->full_cols, c->q_full, c->queues, cl->gamma_dev, c->acc,
                            lp, out, apply, c->counters, 0, c->grid, c->q_defer);
-        if (wm == 0 && obj == 0) {
+        if (obj == 0) {
             // the certifications the cold launch deferred, from their bases (count read on the device)
             hipLaunchKernelGGL((k_lp_sift<9, kSiftW, 0, 3>), dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream,
                                c->perm, c->xs, c->ys, c->ids, c->full_order, c->full_k, c->full_cols, c->q_full,
