@@ -1169,6 +1169,11 @@ constexpr int kMemCap = 96;
 constexpr int kCollBlock = 256;
 constexpr int kCollGroups = kCollBlock / kCollL;
 constexpr int kMemPerLane = kMemCap / kCollL;
+// LDS row stride of a group's lists: a multiple of four (16-byte reads of four
+// members) whose remainder mod 32 banks puts the four groups of a wave in
+// different banks when they read the same member index
+constexpr int kMemStride = kMemCap + 4;
+static_assert(kMemCap % 4 == 0 && kMemStride % 4 == 0, "lists are read four members at a time");
 static_assert(kMlpIn == 8 * kCollL, "a feature row is written 8 elements per lane of a group");
 
 template <int WM>
@@ -1183,10 +1188,10 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
                                                              uint64_t* pmask, uint16_t* feat,
                                                              const uint8_t* __restrict__ pivhist, int32_t* key)
 {
-    __shared__ float s_d2[kCollGroups][kMemCap];
-    __shared__ int s_id[kCollGroups][kMemCap];
-    __shared__ int s_u[kCollGroups][kMemCap];
-    __shared__ int s_pos[kCollGroups][kMemCap];
+    __shared__ __attribute__((aligned(16))) float s_d2[kCollGroups][kMemStride];
+    __shared__ __attribute__((aligned(16))) int s_id[kCollGroups][kMemStride];
+    __shared__ int s_u[kCollGroups][kMemStride];
+    __shared__ int s_pos[kCollGroups][kMemStride];
     __shared__ int s_hist[kKBins];
     cnt = counter_stripe(cnt);
     const int tid = threadIdx.x, sub = tid & (kCollL - 1), grp = tid / kCollL;
@@ -1238,12 +1243,19 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
                 count += __popc(m);
             }
         }
+        const bool over = live && count > kMemCap;
+        const int nm = over ? 0 : count;
+        // up to three sentinels after the list (never nearer, never a lower id),
+        // so the rank loop reads whole groups of four
+        const int nm4 = (nm + 3) & ~3;
+        if (nm + sub < nm4) {
+            s_d2[grp][nm + sub] = __builtin_inff();
+            s_id[grp][nm + sub] = 0x7fffffff;
+        }
         // the group's appends are read by its other lanes
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const bool over = live && count > kMemCap;
-        const int nm = over ? 0 : count;
         // members per lane that any group of the wave has (wave-uniform, so the
         // unused ones of the kMemPerLane are skipped by a scalar branch)
         int nqw = 0;
@@ -1260,14 +1272,19 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
             pos[q] = 0;
             rk[q] = 0;
         }
-        for (int o = 0; o < nm; ++o) {
-            const float d = s_d2[grp][o];
-            const int id = s_id[grp][o];
+        for (int o = 0; o < nm4; o += 4) {
+            const float4 d4 = *reinterpret_cast<const float4*>(&s_d2[grp][o]);
+            const int4 i4 = *reinterpret_cast<const int4*>(&s_id[grp][o]);
+            const float dd[4] = {d4.x, d4.y, d4.z, d4.w};
+            const int ii[4] = {i4.x, i4.y, i4.z, i4.w};
 #pragma unroll
             for (int q = 0; q < kMemPerLane; ++q) {
                 if (q < nqw) {
-                    pos[q] += (d < md[q] || (d == md[q] && id < mi[q])) ? 1 : 0;
-                    rk[q] += id < mi[q] ? 1 : 0;
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        pos[q] += (dd[w] < md[q] || (dd[w] == md[q] && ii[w] < mi[q])) ? 1 : 0;
+                        rk[q] += ii[w] < mi[q] ? 1 : 0;
+                    }
                 }
             }
         }
