@@ -125,6 +125,8 @@ __device__ __forceinline__ df rhs_df(int a, const LaunchParams& P)
 //   float cost_of<Q>(float rx, float ry, uint32_t aux)      its FP32 cost (order Q)
 //   int active()     columns the simplex prices (a prefix of the k; k by default)
 //   kLds, load_lds(j, ...)  columns j < kLds are in LDS: load without the general path
+//                  (kLds a multiple of four; load_lds(j) reads inside the store's
+//                  LDS for every j below min(k, kLds) rounded up to four)
 //   bool widen()     price every column from now on; false if that is already so
 // The simplex declares phase II optimal, or phase I infeasible, only after
 // widen() returned false (a feasible phase I goes on to phase II on the working
@@ -393,9 +395,11 @@ struct ThreadSimplex {
     // The same for the nine rows of q = 3 by Horner's scheme on the cubic
     // y . v(x, y) = x (y0 + y3 Y + x (y2 + y6 Y + y5 x)) + Y (y1 + Y (y4 + y7 x + y8 Y))
     // (9 operations instead of 7 monomials and 9 products), and its scale from
-    // |y| and |x|, |Y| (the |monomials| are the monomials of |x|, |Y|).
+    // |y| and |x|, |Y| (the |monomials| are the monomials of |x|, |Y|).  p2f is
+    // 1 in phase II, 0 in phase I: fma(p2f, c, -p) rounds as (p2 ? c : 0) - p
+    // for a finite cost.
     __device__ __forceinline__ static void reduced_horner(float x, float Y, float c, const float (&y)[M],
-                                                          const float (&ya)[M], bool p2, float& d, float& sc)
+                                                          const float (&ya)[M], float p2f, float& d, float& sc)
     {
         static_assert(M == 9, "cubic rows");
         const float a = __builtin_fmaf(x, y[5], __builtin_fmaf(Y, y[6], y[2]));
@@ -409,9 +413,8 @@ struct ThreadSimplex {
         const float ae = __builtin_fmaf(ay, ya[8], __builtin_fmaf(ax, ya[7], ya[4]));
         const float ag = __builtin_fmaf(ay, ae, ya[1]);
         const float ap = __builtin_fmaf(ax, ab, ay * ag);
-        const float cc = p2 ? c : 0.0f;
-        d = cc - p;
-        sc = fabsf(cc) + ap;
+        d = __builtin_fmaf(p2f, c, -p);
+        sc = __builtin_fmaf(p2f, fabsf(c), ap);
     }
 
     // Entering column: the most negative relative reduced cost d / sc (sc:
@@ -461,47 +464,57 @@ struct ThreadSimplex {
                 if (consider(j, d, sc)) break;
             }
         } else {
-            // Branch-free, four columns per iteration (their reads issued
-            // together); Bland's rule keeps the first qualifying column,
-            // the first of the most negative d / sc.
+            // Four columns per iteration (their reads issued together), with
+            // selects rather than branches.  A qualifying column has a negative
+            // key (d < -kTolD sc), so with best starting at 0 "no column yet"
+            // needs no test of its own; Bland's rule (the first qualifying
+            // column) gives every column the key -1, which only the first
+            // one beats.
             const int k = cs.active();
             float ya[M];
 #pragma unroll
             for (int a = 0; a < M; ++a) ya[a] = fabsf(y[a]);
+            const float p2f = p2 ? 1.0f : 0.0f;
+            // the columns past the k are excluded with the others
+            const uint64_t out = k < 64 ? excl | (~0ull << k) : excl;
             auto column = [&](int j, bool in, float rx, float ry, uint32_t aux) {
                 const float c = cs.template cost_of<kQ>(rx, ry, aux);
                 float d, sc;
                 if constexpr (M == 9) {
-                    reduced_horner(rx, ry, c, y, ya, p2, d, sc);
+                    reduced_horner(rx, ry, c, y, ya, p2f, d, sc);
                 } else {
                     float v[M];
                     mono<M>(rx, ry, v);
                     reduced(v, c, y, p2, d, sc);
                 }
-                const bool ok = in && !((excl >> j) & 1ull) && d < -kTolD * sc;
-                const float key = d * __builtin_amdgcn_rcpf(sc);
-                if (ok && (e < 0 || (!bland && key < best))) {
+                const float key = bland ? -1.0f : d * __builtin_amdgcn_rcpf(sc);
+                if (in && d < -kTolD * sc && key < best) {
                     e = j;
                     best = key;
                 }
             };
-            // the columns a store keeps in LDS (all, or its working set), then the rest
+            // the columns a store keeps in LDS (all, or its working set): whole
+            // groups of four, read without clamping (the rows past the k
+            // columns hold stale values, which `out` excludes); then the rest
+            static_assert(CS::kLds % 4 == 0, "a store's LDS rows come in groups of four");
             const int k1 = min(k, CS::kLds);
             for (int j0 = 0; j0 < k1; j0 += 4) {
                 float rx[4], ry[4];
                 uint32_t aux[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) cs.load_lds(min(j0 + u, k1 - 1), rx[u], ry[u], aux[u]);
+                for (int u = 0; u < 4; ++u) cs.load_lds(j0 + u, rx[u], ry[u], aux[u]);
+                const uint32_t ex4 = (uint32_t)(out >> j0);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) column(j0 + u, j0 + u < k1, rx[u], ry[u], aux[u]);
+                for (int u = 0; u < 4; ++u) column(j0 + u, !(ex4 & (1u << u)), rx[u], ry[u], aux[u]);
             }
             for (int j0 = k1; j0 < k; j0 += 4) {
                 float rx[4], ry[4];
                 uint32_t aux[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) cs.load(min(j0 + u, k - 1), rx[u], ry[u], aux[u]);
+                const uint32_t ex4 = (uint32_t)(out >> j0);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) column(j0 + u, j0 + u < k, rx[u], ry[u], aux[u]);
+                for (int u = 0; u < 4; ++u) column(j0 + u, !(ex4 & (1u << u)), rx[u], ry[u], aux[u]);
             }
         }
         return e;
