@@ -1169,9 +1169,11 @@ constexpr int kMemCap = 96;
 constexpr int kCollBlock = 256;
 constexpr int kCollGroups = kCollBlock / kCollL;
 constexpr int kMemPerLane = kMemCap / kCollL;
-// LDS row stride of a group's lists: a multiple of four (16-byte reads of four
-// members) whose remainder mod 32 banks puts the four groups of a wave in
-// different banks when they read the same member index
+// A member is one 64-bit key, the bits of its d2 (a non-negative float, whose
+// bits order as the values do) over its id, so one unsigned comparison orders
+// (d2, id).  LDS row stride of a group's keys: a multiple of four (16-byte
+// reads of two keys) whose remainder mod 32 banks (as 32-bit words) puts the
+// four groups of a wave in different banks when they read the same member.
 constexpr int kMemStride = kMemCap + 4;
 static_assert(kMemCap % 4 == 0 && kMemStride % 4 == 0, "lists are read four members at a time");
 static_assert(kMlpIn == 8 * kCollL, "a feature row is written 8 elements per lane of a group");
@@ -1188,8 +1190,7 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
                                                              uint64_t* pmask, uint16_t* feat,
                                                              const uint8_t* __restrict__ pivhist, int32_t* key)
 {
-    __shared__ __attribute__((aligned(16))) float s_d2[kCollGroups][kMemStride];
-    __shared__ __attribute__((aligned(16))) int s_id[kCollGroups][kMemStride];
+    __shared__ __attribute__((aligned(16))) uint64_t s_key[kCollGroups][kMemStride];
     __shared__ int s_u[kCollGroups][kMemStride];
     __shared__ int s_pos[kCollGroups][kMemStride];
     __shared__ int s_hist[kKBins];
@@ -1235,8 +1236,7 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
                 if (mem) {
                     const int at = count + __popc(m & ((1u << sub) - 1u));
                     if (at < kMemCap) {
-                        s_d2[grp][at] = d2;
-                        s_id[grp][at] = ids[u];
+                        s_key[grp][at] = member_key(d2, ids[u]);
                         s_u[grp][at] = u;
                     }
                 }
@@ -1249,8 +1249,7 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
         // so the rank loop reads whole groups of four
         const int nm4 = (nm + 3) & ~3;
         if (nm + sub < nm4) {
-            s_d2[grp][nm + sub] = __builtin_inff();
-            s_id[grp][nm + sub] = 0x7fffffff;
+            s_key[grp][nm + sub] = member_key(__builtin_inff(), 0x7fffffff);
         }
         // the group's appends are read by its other lanes
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1262,28 +1261,27 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
 #pragma unroll
         for (int q = 0; q < kMemPerLane; ++q) nqw += __ballot(nm > kCollL * q) ? 1 : 0;
         // this lane's members: e = sub + kCollL q
-        float md[kMemPerLane];
+        uint64_t mk[kMemPerLane];
         int mi[kMemPerLane], pos[kMemPerLane], rk[kMemPerLane];
 #pragma unroll
         for (int q = 0; q < kMemPerLane; ++q) {
             const int e = sub + kCollL * q;
-            md[q] = q < nqw && e < nm ? s_d2[grp][e] : 0.0f;
-            mi[q] = q < nqw && e < nm ? s_id[grp][e] : 0;
+            mk[q] = q < nqw && e < nm ? s_key[grp][e] : 0ull;
+            mi[q] = (int)(uint32_t)mk[q];
             pos[q] = 0;
             rk[q] = 0;
         }
         for (int o = 0; o < nm4; o += 4) {
-            const float4 d4 = *reinterpret_cast<const float4*>(&s_d2[grp][o]);
-            const int4 i4 = *reinterpret_cast<const int4*>(&s_id[grp][o]);
-            const float dd[4] = {d4.x, d4.y, d4.z, d4.w};
-            const int ii[4] = {i4.x, i4.y, i4.z, i4.w};
+            const ulonglong2 ka = *reinterpret_cast<const ulonglong2*>(&s_key[grp][o]);
+            const ulonglong2 kb = *reinterpret_cast<const ulonglong2*>(&s_key[grp][o + 2]);
+            const uint64_t kk[4] = {ka.x, ka.y, kb.x, kb.y};
 #pragma unroll
             for (int q = 0; q < kMemPerLane; ++q) {
                 if (q < nqw) {
 #pragma unroll
                     for (int w = 0; w < 4; ++w) {
-                        pos[q] += (dd[w] < md[q] || (dd[w] == md[q] && ii[w] < mi[q])) ? 1 : 0;
-                        rk[q] += ii[w] < mi[q] ? 1 : 0;
+                        pos[q] += kk[w] < mk[q] ? 1 : 0;
+                        rk[q] += (uint32_t)kk[w] < (uint32_t)mi[q] ? 1 : 0;
                     }
                 }
             }
@@ -1300,7 +1298,7 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
 #pragma unroll
             for (int q = 0; q < kMemPerLane; ++q) rk[q] = 0;
             for (int o = 0; o < nm; ++o) {
-                const int id = s_id[grp][o];
+                const int id = (int)(uint32_t)s_key[grp][o];
                 const bool kept = s_pos[grp][o] < VRM_KMAX;
 #pragma unroll
                 for (int q = 0; q < kMemPerLane; ++q) rk[q] += (kept && id < mi[q]) ? 1 : 0;
@@ -1332,9 +1330,9 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
         }
         if constexpr (WM == 1) {
             // offsets over h of the kMlpSlots nearest columns (the slot order of the record),
-            // staged in the group's distance and id lists, which are no longer read
-            float* s_fx = s_d2[grp];
-            float* s_fy = reinterpret_cast<float*>(s_id[grp]);
+            // staged in the group's key list, which is no longer read
+            float* s_fx = reinterpret_cast<float*>(s_key[grp]);
+            float* s_fy = s_fx + kMemStride;
 #pragma unroll
             for (int q = 0; q < kMemPerLane; ++q) {
                 const int e = sub + kCollL * q;
