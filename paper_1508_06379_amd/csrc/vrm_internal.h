@@ -103,6 +103,18 @@ struct SmallRec {
     float* off;      // [32][cap] exact scaled offset of segment s: planes 4s..4s+3 = X.hi, X.lo, Y.hi, Y.lo
 };
 
+// Column records of the queued complete LPs, as the network's inference reads them.
+struct FullRec {
+    const int32_t* rec;      // [item][row] (slot << 6) | id rank per column, nearest first
+    int32_t row;             // record row stride
+    const int32_t* kcol;     // [item] column count; -1: the list is left for the one-thread kernel
+    const int32_t* q_full;   // [item] sorted-cloud index of the particle
+    const float* xs;         // sorted positions
+    const float* ys;
+    float scale2e, sc;       // ((x_j - x_i) scale2e) sc is column j's offset over h
+    int q;
+};
+
 // Reduced-operator selection state (device side).
 struct SelectState {
     double norm1, bound, prefix;
@@ -319,6 +331,7 @@ int vrm_mlp_forward(vrm_ctx* c, const uint16_t* X, int rows, float* Y, const int
 int vrm_mlp_read_weights(vrm_ctx* c, float* w_dev);
 int vrm_mlp_infer_run(vrm_ctx* c, const uint16_t* X, int rows, float* Y, const int* rows_dev);
 // warm-start logits (8 per queued small LP) with the network input built from the positions
+int vrm_mlp_infer_full_run(vrm_ctx* c, int rows, const int* rows_dev, const vrm::FullRec& fr, float* L);
 int vrm_mlp_infer_small_run(vrm_ctx* c, int rows, const int* rows_dev, const vrm::SmallRec& rec, float sc, int q,
                             float* L);
 int vrm_mlp_train(vrm_ctx* c, const uint16_t* X, const float* T, int rows, float lr, float wd, float wf,

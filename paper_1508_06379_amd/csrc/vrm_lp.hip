@@ -1160,10 +1160,9 @@ constexpr int kRecRow = VRM_KMAX;
 // nearest if there are more).  No sort, no rescans; a list longer than
 // kMemCap (a density the method never produces) goes to the retry queue and
 // is solved by the one-thread kernel, which collects on its own.
-// Warm starts take their inputs here as well: with prev, the columns whose
-// ids form the particle's previous basis (a mask per LP, pmask); with feat,
-// the network's input row (the offsets over h of the kMlpSlots nearest
-// columns, their mask and q), written by the group's lanes 16 bytes each.
+// The previous-basis warm start (WM 2) takes its input here as well: the
+// columns whose ids form the particle's previous basis, as a mask per LP
+// (pmask).  The network's inputs are read from the records by its inference.
 constexpr int kCollL = 16;
 constexpr int kMemCap = 96;
 constexpr int kCollBlock = 256;
@@ -1176,7 +1175,6 @@ constexpr int kMemPerLane = kMemCap / kCollL;
 // four groups of a wave in different banks when they read the same member.
 constexpr int kMemStride = kMemCap + 4;
 static_assert(kMemCap % 4 == 0 && kMemStride % 4 == 0, "lists are read four members at a time");
-static_assert(kMlpIn == 8 * kCollL, "a feature row is written 8 elements per lane of a group");
 
 template <int WM>
 __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __restrict__ xs,
@@ -1187,9 +1185,10 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
                                                              Queues* qs, LaunchParams P, int32_t* rec, int32_t* kcol,
                                                              int32_t* khist, int32_t* q_retry, vrm_counters* cnt,
                                                              const int32_t* __restrict__ prev, int prev_cap,
-                                                             uint64_t* pmask, uint16_t* feat,
-                                                             const uint8_t* __restrict__ pivhist, int32_t* key)
+                                                             uint64_t* pmask, const uint8_t* __restrict__ pivhist,
+                                                             int32_t* key)
 {
+    static_assert(WM == 0 || WM == 2, "cold or previous-basis column lists");
     __shared__ __attribute__((aligned(16))) uint64_t s_key[kCollGroups][kMemStride];
     __shared__ int s_u[kCollGroups][kMemStride];
     __shared__ int s_pos[kCollGroups][kMemStride];
@@ -1328,48 +1327,6 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
             }
             if (live && !over && sub == 0) pmask[r] = ((uint64_t)hi << 32) | lo;
         }
-        if constexpr (WM == 1) {
-            // offsets over h of the kMlpSlots nearest columns (the slot order of the record),
-            // staged in the group's key list, which is no longer read
-            float* s_fx = reinterpret_cast<float*>(s_key[grp]);
-            float* s_fy = s_fx + kMemStride;
-#pragma unroll
-            for (int q = 0; q < kMemPerLane; ++q) {
-                const int e = sub + kCollL * q;
-                if (live && e < nm && pos[q] < kMlpSlots) {
-                    const int u = s_u[grp][e];
-                    s_fx[pos[q]] = ((xs[u] - xi) * P.scale2e) * P.sc;
-                    s_fy[pos[q]] = ((ys[u] - yi) * P.scale2e) * P.sc;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (live && !over) {
-                // elements 8 sub .. 8 sub + 7 of the row: offset pairs, masks, q, zero padding
-                uint16_t v[8];
-#pragma unroll
-                for (int w = 0; w < 8; ++w) {
-                    const int e = 8 * sub + w;
-                    uint16_t b = 0;
-                    if (e < 2 * kMlpSlots) {
-                        const int j = e >> 1;
-                        if (j < k) b = f2bf((e & 1) ? s_fy[j] : s_fx[j]);
-                    } else if (e < 3 * kMlpSlots) {
-                        b = (e - 2 * kMlpSlots) < k ? 0x3f80 : 0;
-                    } else if (e == 3 * kMlpSlots) {
-                        b = P.q == 3 ? 0x3f80 : 0;
-                    }
-                    v[w] = b;
-                }
-                uint4 pk;
-                pk.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
-                pk.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
-                pk.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
-                pk.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
-                *reinterpret_cast<uint4*>(feat + (size_t)r * kMlpIn + 8 * sub) = pk;
-            }
-        }
         if (live && !over) {
             int32_t* row = rec + (size_t)r * kRecRow;
 #pragma unroll
@@ -1382,13 +1339,13 @@ __global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __rest
                 kcol[r] = k;
                 // the bin of the counting sort: the particle's pivots in its last
                 // complete LP when known (cold or network-started solves), else k
-                if constexpr (WM != 2) {
+                if constexpr (WM == 0) {
                     const int own = ids[t];
                     const int h = (unsigned)own < (unsigned)prev_cap ? pivhist[own] : 255;
                     const int b = h == 255 ? k : min(h, kKBins - 1);
                     key[r] = b;
                     atomicAdd(&s_hist[b], 1);
-                } else if constexpr (WM == 2) {
+                } else {
                     key[r] = k;
                     atomicAdd(&s_hist[k], 1);
                 }
@@ -1526,8 +1483,8 @@ struct SiftCols {
 };
 
 // The network's predicted basis of each complete LP: the m columns of largest
-// logit among its first min(k, kMlpSlots) (lowest slot among equal logits), as
-// a column mask for the crash.
+// logit (L[item][kMlpSlots]) among its first min(k, kMlpSlots) (lowest slot
+// among equal logits), as a column mask for the crash.
 __global__ __launch_bounds__(256) void k_top_mask(const float* __restrict__ pred, const int32_t* __restrict__ kcol,
                                                   const Queues* qs, int m, uint64_t* pmask)
 {
@@ -1537,7 +1494,7 @@ __global__ __launch_bounds__(256) void k_top_mask(const float* __restrict__ pred
         if (k < 0) continue;
         const int kk = min(k, kMlpSlots);
         float v[kMlpSlots];
-        const float4* row = reinterpret_cast<const float4*>(pred + (size_t)r * kMlpOut);
+        const float4* row = reinterpret_cast<const float4*>(pred + (size_t)r * kMlpSlots);
 #pragma unroll
         for (int a = 0; a < kMlpSlots / 4; ++a) {
             const float4 q = row[a];
@@ -2121,26 +2078,27 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
                            c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, cl->gamma_dev, c->acc, lp,
                            o2, apply, c->counters, kLpPlain, c->q_retry, 1);
     } else if (!feat_out) {
-        // size-binned working-set path: column lists (with the warm start's inputs),
-        // counting sort by k, the network's forward pass if it predicts, LPs
+        // size-binned working-set path: column lists (with the previous basis),
+        // counting sort, the network's inference from the lists if it predicts, LPs
         const int wm = net ? 1 : (warm ? 2 : 0);
         {
             ScopedTimer tm(c, VRM_T_FULL_COLS);
-            auto collect = wm == 1 ? k_full_collect<1> : wm == 2 ? k_full_collect<2> : k_full_collect<0>;
+            auto collect = wm == 2 ? k_full_collect<2> : k_full_collect<0>;
             hipLaunchKernelGGL(collect, dim3(min((n + kCollGroups - 1) / kCollGroups, 4096)), dim3(kCollBlock), 0,
                                c->stream, c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, lp,
                                c->full_cols, c->full_k, c->khist, c->q_retry, c->counters,
-                               wm == 2 ? c->prev : nullptr, c->capacity, wm == 2 ? c->pmask : nullptr,
-                               wm == 1 ? c->feat : nullptr, c->pivhist, c->lkey);
+                               wm == 2 ? c->prev : nullptr, c->capacity, wm == 2 ? c->pmask : nullptr, c->pivhist,
+                               c->lkey);
             hipLaunchKernelGGL(k_full_bin_starts, dim3(1), dim3(64), 0, c->stream, c->khist);
             hipLaunchKernelGGL(k_full_bin_scatter, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->lkey,
                                c->queues, c->khist, c->full_order);
             VRM_HIP(hipGetLastError());
         }
         if (wm == 1) {
-            // the forward pass and the predicted bases
+            // the predicted bases, from the column lists (row count read on the device)
             ScopedTimer tm(c, VRM_T_MLP);
-            int r = vrm_mlp_infer_run(c, c->feat, n, c->pred, &c->queues->n_full);
+            const FullRec fr{c->full_cols, kRecRow, c->full_k, c->q_full, c->xs, c->ys, lp.scale2e, lp.sc, lp.q};
+            int r = vrm_mlp_infer_full_run(c, n, &c->queues->n_full, fr, c->pred);
             if (r) return r;
             hipLaunchKernelGGL(k_top_mask, dim3(min((n + 255) / 256, 4096)), dim3(256), 0, c->stream, c->pred,
                                c->full_k, c->queues, lp.m, c->pmask);

@@ -368,6 +368,88 @@ __global__ __launch_bounds__(256) void k_mlp_infer_small(const int* rows_dev, Sm
     }
 }
 
+// Inference for the queued complete LPs from their column records: the input
+// row is built in LDS from the record (slot j < 32 of the nearest-first list:
+// offset / h and mask; q - 2), four threads per row, and only the 32 basis
+// logits are computed and written: L[item][kMlpSlots].  (Choosing the m
+// largest here, at this kernel's occupancy, costs more than a separate pass.)
+__global__ __launch_bounds__(256) void k_mlp_infer_full(const int* rows_dev, FullRec fr,
+                                                        const uint16_t* __restrict__ wt, const float* __restrict__ w,
+                                                        float* __restrict__ Lout)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t Ta[FR * FKP];
+    __shared__ __attribute__((aligned(16))) uint16_t Tb[FR * FKP];
+    constexpr int LS = kMlpSlots + 1;   // row stride of the logits (staged in Tb)
+    static_assert(FR * LS * sizeof(float) <= sizeof(Tb), "the logits fit in the second tile");
+    const int rows = *rows_dev;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int rr = tid >> 2, part = tid & 3;   // this thread's row of the tile, its quarter of the slots
+    for (int r0 = blockIdx.x * FR; r0 < rows; r0 += gridDim.x * FR) {
+        const int r = r0 + rr;
+        const int k = r < rows ? fr.kcol[r] : -1;
+        {
+            float xi = 0.0f, yi = 0.0f;
+            if (k > 0) {
+                const int t = fr.q_full[r];
+                xi = fr.xs[t];
+                yi = fr.ys[t];
+            }
+            const int32_t* rrow = fr.rec + (size_t)r * fr.row;
+            uint32_t off[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int j = 8 * part + i;
+                uint32_t pr = 0;
+                if (j < k) {
+                    const int u = (int)((unsigned)rrow[j] >> 6);
+                    pr = (uint32_t)to_bf16(((fr.xs[u] - xi) * fr.scale2e) * fr.sc) |
+                         ((uint32_t)to_bf16(((fr.ys[u] - yi) * fr.scale2e) * fr.sc) << 16);
+                }
+                off[i] = pr;
+            }
+            uint16_t* row = Ta + rr * FKP;
+            // elements 16 part .. 16 part + 15: the offset pairs of slots 8 part .. 8 part + 7
+            *reinterpret_cast<uint4*>(row + 16 * part) = uint4{off[0], off[1], off[2], off[3]};
+            *reinterpret_cast<uint4*>(row + 16 * part + 8) = uint4{off[4], off[5], off[6], off[7]};
+            // their masks, then q - 2 (element 3 kMlpSlots) and zero padding
+            uint32_t mk[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = 8 * part + 2 * i;
+                mk[i] = (j < k ? 0x3f80u : 0u) | ((j + 1 < k ? 0x3f80u : 0u) << 16);
+            }
+            *reinterpret_cast<uint4*>(row + 2 * kMlpSlots + 8 * part) = uint4{mk[0], mk[1], mk[2], mk[3]};
+            *reinterpret_cast<uint4*>(row + 3 * kMlpSlots + 8 * part) =
+                uint4{part == 0 && fr.q == 3 ? 0x3f80u : 0u, 0u, 0u, 0u};
+        }
+        __syncthreads();
+        mlp_hidden(Ta, Tb, wt, w, tid);
+        // the logits: waves 0 and 1 compute columns [16 wv, 16 wv + 16) of the 64 rows
+        float* L = reinterpret_cast<float*>(Tb);
+        if (wv < 2) {
+            f32x4 acc[4];
+            mlp_out16(Ta, wt, wv * 16, lane, acc);
+            const int n = wv * 16 + (lane & 15);
+            const float b = w[kOffB3 + n];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) L[(i * 16 + (lane >> 4) * 4 + v) * LS + n] = acc[i][v] + b;
+        }
+        __syncthreads();
+        if (r < rows) {
+            float4* dst = reinterpret_cast<float4*>(Lout + (size_t)r * kMlpSlots + 8 * part);
+            // LS is odd: the row start is not 16-byte aligned in LDS, so the values are read one by one
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = L[rr * LS + 8 * part + i];
+            dst[0] = float4{v[0], v[1], v[2], v[3]};
+            dst[1] = float4{v[4], v[5], v[6], v[7]};
+        }
+        __syncthreads();
+    }
+}
+
 template <int EPI>
 int gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk,
          long sbn, float* C, long ldc, const float* bias, uint16_t* Cbf, const float* Zaux, int splitk,
@@ -493,6 +575,17 @@ int vrm_mlp_infer_small_run(vrm_ctx* c, int rows, const int* rows_dev, const Sma
     int tiles = (rows + FR - 1) / FR;
     int grid = tiles < c->tuning.infer_blocks ? tiles : c->tuning.infer_blocks;
     hipLaunchKernelGGL(k_mlp_infer_small, dim3(grid), dim3(256), 0, c->stream, rows_dev, rec, sc, q, m->wt, m->w, L);
+    VRM_HIP(hipGetLastError());
+    return VRM_OK;
+}
+
+int vrm_mlp_infer_full_run(vrm_ctx* c, int rows, const int* rows_dev, const FullRec& fr, float* L)
+{
+    if (rows <= 0) return VRM_OK;
+    MlpState* m = c->mlp;
+    int tiles = (rows + FR - 1) / FR;
+    int grid = tiles < c->tuning.infer_blocks ? tiles : c->tuning.infer_blocks;
+    hipLaunchKernelGGL(k_mlp_infer_full, dim3(grid), dim3(256), 0, c->stream, rows_dev, fr, m->wt, m->w, L);
     VRM_HIP(hipGetLastError());
     return VRM_OK;
 }
