@@ -248,7 +248,7 @@ struct vrm_ctx {
     int32_t* prev;               // [cap][9] basis (column ids) of each particle's last stencil, by id
     uint64_t* pmask;             // [cap] crash basis (previous or predicted) as a column mask per complete LP
     int32_t* lkey;               // [cap] bin of each complete LP for the counting sort (pivot history or doubt)
-    int32_t* q_defer;            // [cap] queue items of the complete LPs whose certification was deferred (top bit: warm)
+    int32_t* q_defer;            // [cap] queue items the LP launch deferred (bit 31: settled warm; bit 30: solve cold)
     uint8_t* pivhist;            // [cap] by particle id: pivots of its last complete LP (255: none yet)
     vrm_tuning tuning;           // launch shapes in force (defaults filled in)
     hipStream_t cap_stream;      // stream the graph is captured on (the context's may be the null stream)

@@ -1522,8 +1522,10 @@ __global__ __launch_bounds__(256) void k_top_mask(const float* __restrict__ pred
 // WM: 0 cold; 1 crash from the network's prediction (out.pmask: its top-m
 // columns per queue item), finished whatever it takes; 2 crash from the
 // previous basis (out.pmask), at most warm_cap pivots, recording the new one;
-// 3 the certifications deferred by the launch before (the items in q_defer,
-// their bases in out.pmask), recording the basis when out.prev is set.  A
+// 3 the LPs the launch before deferred (the items in q_defer, queue indices
+// below the 2^26 capacity limit with two flag bits): certified from their
+// bases in out.pmask, or solved cold where a warm attempt ended infeasible;
+// the basis is recorded when out.prev is set.  A
 // crash basis that is not feasible is repaired by the composite phase I; a
 // warm attempt that fails is solved cold in place.  The canonical launches
 // (OBJ 0, WM 0 to 2) defer the LPs whose fast certificate fails to a WM 3
@@ -1552,14 +1554,16 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
     for (int it = 0; it < loops; ++it) {
         const int p = blockIdx.x * blockDim.x + tid + it * stride;
         const bool live = p < nitems;
-        int st = 1, piv = 0, certified = 1, k = 0, warm = 0, r = 0, was_warm = 0;
+        int st = 1, piv = 0, certified = 1, k = 0, warm = 0, r = 0, was_warm = 0, cold = 0;
         int cstat[2] = {0, 0};
         if (live) {
             if constexpr (WM == 3) {
-                // top bit: the deferring launch had settled the LP from its warm start
+                // bit 31: the deferring launch had settled the LP from its warm start;
+                // bit 30: its warm attempt ended infeasible, solve it cold
                 const int e = q_defer[p];
-                r = e & 0x7fffffff;
-                was_warm = (unsigned)e >> 31;
+                r = e & 0x3fffffff;
+                was_warm = ((unsigned)e >> 31) & 1;
+                cold = ((unsigned)e >> 30) & 1;
             } else {
                 r = order[p];
             }
@@ -1610,11 +1614,16 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
                 st = solve_lp<M, OBJ, false>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false,
                                              0ull, cstat, true, kDefer);
             } else {
-                const uint64_t pref = out.pmask[r];
+                const uint64_t pref = cold ? 0ull : out.pmask[r];
                 // a prediction that is given up is followed by the cold solve in place
-                st = solve_lp<M, OBJ, true, true>(cs, P, store, fii, piv, certified, true, nullptr, warm, basis,
-                                                  true, pref, cstat, WM != 1, kDefer);
-                if (WM == 3) warm = was_warm;
+                st = solve_lp<M, OBJ, true, true>(cs, P, store, fii, piv, certified, !cold, nullptr, warm, basis,
+                                                  !cold, pref, cstat, WM != 1, kDefer);
+                if (WM == 3) warm = cold ? 0 : was_warm;
+                // A warm attempt that ends infeasible is not final: its FP32 phase I may
+                // stop on a vertex whose basic artificial is within the FP32 tolerance
+                // but not zero in exact arithmetic, which the certification rejects.
+                // The deferred launch solves it cold, as the plain solver does.
+                if (kDefer && st == 1 && (warm == 1 || warm == 2)) st = 7;
             }
             if (kDefer && st == 5) out.pmask[r] = basis;
             if (WM == 2 || (WM == 3 && out.prev)) {
@@ -1634,13 +1643,16 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
                     out.fii[i] = fii;
                     out.status[i] = (warm == 1 || warm == 2) ? VRM_ST_WARM : VRM_ST_FULL;
                 }
-            } else if (out.status && st != 5) {
+            } else if (out.status && st != 5 && st != 7) {
                 out.status[i] = VRM_ST_INFEASIBLE;
             }
         }
         if constexpr (kDefer) {
-            const int dpos = wave_append(&qs->n_defer, live && st == 5);
-            if (live && st == 5) q_defer[dpos] = r | ((warm == 1 || warm == 2) ? (int)0x80000000u : 0);
+            const bool later = live && (st == 5 || st == 7);
+            const int dpos = wave_append(&qs->n_defer, later);
+            if (later)
+                q_defer[dpos] = r | ((warm == 1 || warm == 2) && st == 5 ? (int)0x80000000u : 0) |
+                                (st == 7 ? 0x40000000 : 0);
         }
         if constexpr (WM == 1 || WM == 2) count_warm(cnt, live, warm);
         const bool ok = live && st == 0;
