@@ -417,12 +417,17 @@ struct ThreadSimplex {
         sc = __builtin_fmaf(p2f, fabsf(c), ap);
     }
 
-    // Entering column: the most negative relative reduced cost d / sc (sc:
-    // the magnitude of the terms of d, so the choice does not depend on the
-    // rows' or columns' scales; on the 16M-particle q = 3 cloud 16.9 pivots
-    // per LP against 26.6 for the most negative d), Bland (lowest index) after
-    // many iterations.  Every store computes the key d * rcp(sc) the same way
-    // and takes the lowest (key, column), so all kernels follow the same path.
+    // Entering column: the columns are taken in groups of four in their order
+    // (the complete LPs' lists are nearest first), and the choice is made in
+    // the first group that holds an improving column: there, the most
+    // negative relative reduced cost d / sc (sc: the magnitude of the terms
+    // of d, so the choice does not depend on the rows' or columns' scales).
+    // On the 16M-particle q = 3 cloud: 14.2 pivots per LP, against 17.2 for
+    // the most negative d / sc over all columns and 26.6 for the most negative
+    // d, and most iterations price four columns.  Bland (lowest index) after
+    // many iterations.  Every store computes the key d * rcp(sc) the same way,
+    // forms the same groups and takes the lowest (key, column) in the group,
+    // so all kernels follow the same path.
     __device__ __forceinline__ int price(const CS& cs, const float (&y)[M], bool p2, bool bland) const
     {
         const uint64_t excl = isb | blk | dead;
@@ -449,11 +454,15 @@ struct ThreadSimplex {
             float d, sc;
             reduced(v, cs.c, y, p2, d, sc);
             const bool ok = !((excl >> cs.own) & 1ull) && d < -kTolD * sc;
-            return cs.pick(ok, bland ? 0.0f : d * __builtin_amdgcn_rcpf(sc));
+            // the first group of four columns with an improving one
+            const int f = cs.first(ok);
+            const bool in_group = ok && (cs.own >> 2) == (f >> 2);
+            return cs.pick(in_group, bland ? 0.0f : d * __builtin_amdgcn_rcpf(sc));
         } else if constexpr (CS::KC > 0) {
             // compile-time column count: the loop is unrolled
 #pragma unroll
             for (int j = 0; j < CS::KC; ++j) {
+                if ((j & 3) == 0 && e >= 0) break;   // a group of four held an improving column
                 if ((excl >> j) & 1ull) continue;
                 float rx, ry, c;
                 cs.get(j, rx, ry, c);
@@ -506,8 +515,10 @@ struct ThreadSimplex {
                 const uint32_t ex4 = (uint32_t)(out >> j0);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) column(j0 + u, !(ex4 & (1u << u)), rx[u], ry[u], aux[u]);
+                if (e >= 0) break;   // this group holds an improving column (Bland: its first)
             }
             for (int j0 = k1; j0 < k; j0 += 4) {
+                if (e >= 0) break;
                 float rx[4], ry[4];
                 uint32_t aux[4];
 #pragma unroll

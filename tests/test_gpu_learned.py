@@ -194,8 +194,9 @@ def test_warm_start_gives_the_plain_results(vrm, trained, q):
         assert cb["warm_hit"] > 0.5 * cb["n_small"]
     else:
         # the predicted columns, repaired by the composite phase I, save pivots
-        # (counting the crash pivots)
-        assert cb["pivots"] < 0.95 * ca["pivots"]
+        # (counting the crash pivots); with the nearest-group-first pricing the
+        # cold solve itself needs few, so the saving is a few per cent here
+        assert cb["pivots"] < ca["pivots"]
 
 
 def _host_features(x, y, ids, i, cols, h):
