@@ -154,6 +154,10 @@ struct ThreadSimplex {
     uint64_t dead;    // columns that do not exist
     int cert_rounds;  // certification rounds taken
     int cert_exact;   // 1 once the double-float dual check ran
+    // smallest relative reduced cost d / sc (as d * rcp(sc)) of the last pricing
+    // pass that priced every existing non-basic column, none of them blocked,
+    // and found none to enter; -inf when the last pass was not such a pass
+    mutable float cert_key;
 
     static constexpr int ART = 64;
 
@@ -169,6 +173,7 @@ struct ThreadSimplex {
         }
         isb = 0;
         blk = 0;
+        cert_key = -__builtin_inff();
     }
 
     __device__ __forceinline__ void prices(bool phase2, float (&y)[M]) const
@@ -486,6 +491,7 @@ struct ThreadSimplex {
             const float p2f = p2 ? 1.0f : 0.0f;
             // the columns past the k are excluded with the others
             const uint64_t out = k < 64 ? excl | (~0ull << k) : excl;
+            float mk = __builtin_inff();   // smallest key of the priced columns
             auto column = [&](int j, bool in, float rx, float ry, uint32_t aux) {
                 const float c = cs.template cost_of<kQ>(rx, ry, aux);
                 float d, sc;
@@ -496,7 +502,9 @@ struct ThreadSimplex {
                     mono<M>(rx, ry, v);
                     reduced(v, c, y, p2, d, sc);
                 }
-                const float key = bland ? -1.0f : d * __builtin_amdgcn_rcpf(sc);
+                const float kraw = d * __builtin_amdgcn_rcpf(sc);
+                const float key = bland ? -1.0f : kraw;
+                mk = fminf(mk, in ? kraw : __builtin_inff());
                 if (in && d < -kTolD * sc && key < best) {
                     e = j;
                     best = key;
@@ -527,6 +535,9 @@ struct ThreadSimplex {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) column(j0 + u, !(ex4 & (1u << u)), rx[u], ry[u], aux[u]);
             }
+            // a pass over every column (the whole list, nothing blocked) that found
+            // none to enter leaves its smallest key to the fast certificate
+            cert_key = (e < 0 && blk == 0 && k == cs.k) ? mk : -__builtin_inff();
         }
         return e;
     }
@@ -825,6 +836,11 @@ struct ThreadSimplex {
                             reduced(v, c, yf, true, d, sc);
                             dual_ok = dual_ok && !(d < margin * sc);
                         }
+                    } else if (round == 0 && cert_key >= margin * 1.00000095367431640625f) {
+                        // the last pricing pass of the simplex priced every column with
+                        // these prices (no pivot since) and its smallest d * rcp(sc)
+                        // clears the margin by more than the reciprocal's error
+                        dual_ok = true;
                     } else {
                         auto column = [&](int j, bool in, float rx, float ry, uint32_t aux) {
                             const float c = cs.template cost_of<kQ>(rx, ry, aux);
