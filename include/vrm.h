@@ -356,9 +356,9 @@ int vrm_mlp_train_step(vrm_ctx* ctx, const uint16_t* x_dev, const float* y_dev, 
                        float weight_decay, float frac_weight, double* loss_dev, float* grad_dev);
 /* Test hook of the learned warm start: the network outputs the warm pass would use
  * for the LPs queued at the current positions and diffused set (small LPs for
- * q = 2: their 8 logits in columns 0..7, zeros after; complete LPs for q = 3: all
- * 64 outputs), computed by the same fused kernels (input rows built on the device
- * from the LPs' columns).  out_dev[max_rows][64] FP32, particle_dev[max_rows]: the
+ * q = 2: their 8 logits in columns 0..7, zeros after; complete LPs for q = 3: the
+ * 32 basis logits in columns 0..31, zeros after), computed by the kernels of the
+ * LP path (input rows built on the device from the LPs' column lists).  out_dev[max_rows][64] FP32, particle_dev[max_rows]: the
  * cloud index of each row's particle; *rows_host = rows written.  Needs
  * vrm_set_warm_start(ctx, 1).  Synchronises. */
 int vrm_warm_predictions(vrm_ctx* ctx, const vrm_cloud* cloud, const vrm_params* p, float* out_dev,

@@ -1916,37 +1916,6 @@ __global__ void k_rm_reset(Queues* q)
 }
 __global__ void k_rm_reset_undecided(Queues* q) { q->n_undecided = 0; }
 
-// feature rows of the queued complete-neighbourhood LPs (warm start)
-__global__ __launch_bounds__(kFullBlock) void k_feat_full(const float* __restrict__ xs, const float* __restrict__ ys,
-                                                          const int32_t* __restrict__ ids,
-                                                          const int32_t* __restrict__ cell_start, const GridState* gs,
-                                                          const int32_t* __restrict__ q_full, const Queues* qs,
-                                                          LaunchParams P, uint16_t* feat)
-{
-    __shared__ int s_u[VRM_KMAX * kFullBlock];
-    __shared__ float s_d2[VRM_KMAX * kFullBlock];
-    __shared__ int s_id[VRM_KMAX * kFullBlock];
-    const int tid = threadIdx.x;
-    const int nitems = qs->n_full;
-    const int stride = gridDim.x * blockDim.x;
-    const GridState g = *gs;
-    for (int item = blockIdx.x * blockDim.x + tid; item < nitems; item += stride) {
-        int t = q_full[item];
-        const float xi = xs[t], yi = ys[t];
-        bool tr;
-        int k = collect_full(t, xi, yi, g, cell_start, xs, ys, ids, P, s_u + tid, s_d2 + tid, s_id + tid, tr);
-        uint16_t* row = feat + (size_t)item * kMlpIn;
-        feature_zero(row);
-        for (int j = 0; j < k && j < kMlpSlots; ++j) {
-            int u = s_u[j * kFullBlock + tid];
-            df X, Y;
-            exact_offset(xi, yi, xs[u], ys[u], P.scale2e, X, Y);
-            feature_slot(row, j, X.hi * P.sc, Y.hi * P.sc);
-        }
-        feature_q(row, P.q);
-    }
-}
-
 __global__ void k_status_init(int n, const uint8_t* __restrict__ diffused, StencilOut out)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2165,9 +2134,10 @@ __global__ void k_pred_out(const Queues* qs, int m, const float* __restrict__ pr
     const int nq = m == 5 ? qs->n_small : qs->n_full;
     const int rows = min(nq, max_rows);
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
+        // small LPs: the logits of their 8 columns; complete LPs: the 32 basis logits
         for (int a = 0; a < kMlpOut; ++a)
             out[(size_t)r * kMlpOut + a] = m == 5 ? (a < VRM_NSEG ? pred[(size_t)r * VRM_NSEG + a] : 0.0f)
-                                                  : pred[(size_t)r * kMlpOut + a];
+                                                  : (a < kMlpSlots ? pred[(size_t)r * kMlpSlots + a] : 0.0f);
         particle[r] = m == 5 ? rec_i[r] : perm[q_full[r]];
     }
 }
@@ -2196,10 +2166,16 @@ int vrm_warm_predict_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const Launc
     if (lp.m == 5) {
         r = vrm_mlp_infer_small_run(c, n, &c->queues->n_small, c->srec, lp.sc, lp.q, c->pred);
     } else {
-        hipLaunchKernelGGL(k_feat_full, dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->xs, c->ys, c->ids,
-                           c->cell_start, c->grid, c->q_full, c->queues, lp, c->feat);
+        // the LP path's own kernels: the column lists (their histogram cleared
+        // again by the bin starts), then the inference from the lists
+        hipLaunchKernelGGL(k_full_collect<0>, dim3(min((n + kCollGroups - 1) / kCollGroups, 4096)), dim3(kCollBlock),
+                           0, c->stream, c->xs, c->ys, c->ids, c->cell_start, c->grid, c->q_full, c->queues, lp,
+                           c->full_cols, c->full_k, c->khist, c->q_retry, c->counters, nullptr, c->capacity, nullptr,
+                           c->pivhist, c->lkey);
+        hipLaunchKernelGGL(k_full_bin_starts, dim3(1), dim3(64), 0, c->stream, c->khist);
         VRM_HIP(hipGetLastError());
-        r = vrm_mlp_infer_run(c, c->feat, n, c->pred, &c->queues->n_full);
+        const FullRec fr{c->full_cols, kRecRow, c->full_k, c->q_full, c->xs, c->ys, lp.scale2e, lp.sc, lp.q};
+        r = vrm_mlp_infer_full_run(c, n, &c->queues->n_full, fr, c->pred);
     }
     if (r) return r;
     hipLaunchKernelGGL(k_pred_out, dim3(256), dim3(256), 0, c->stream, c->queues, lp.m, c->pred, c->srec.i, c->perm,
