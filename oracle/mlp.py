@@ -5,7 +5,9 @@ written from the definitions (a 3-layer perceptron with GELU activations in
 their tanh form, 0.5 z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))),
 BCE-with-logits on 32 basis indicators, squared error on 32 fractions, both
 masked by the input's slot mask and averaged over rows).  Used to check the
-GPU's BF16 matrix-core forward and backward passes.
+GPU's BF16 matrix-core forward and backward passes, and its optimiser step
+(AdamW: Kingma and Ba's bias-corrected moments with Loshchilov and Hutter's
+decoupled weight decay).
 """
 import math
 
@@ -81,3 +83,17 @@ def init_params(seed=0):
     for name, shape in SHAPES:
         d[name] = rng.normal(0.0, math.sqrt(2.0 / shape[0]), shape) if len(shape) == 2 else np.zeros(shape)
     return pack(d)
+
+
+def adamw_step(w, g, m, v, t, lr, wd, b1=0.9, b2=0.999, eps=1e-8):
+    """Step t (from 1) of AdamW: the moments m <- b1 m + (1 - b1) g and
+    v <- b2 v + (1 - b2) g^2, their bias corrections m / (1 - b1^t) and
+    v / (1 - b2^t), and w <- w - lr (m_hat / (sqrt(v_hat) + eps) + wd w), the
+    weight decay applied to the parameter directly rather than through the
+    gradient.  Returns the new (w, m, v)."""
+    w, g, m, v = (np.asarray(a, np.float64) for a in (w, g, m, v))
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return w - lr * (mh / (np.sqrt(vh) + eps) + wd * w), m, v

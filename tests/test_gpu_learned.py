@@ -106,6 +106,39 @@ def test_gradient_matches_fp64_reference(vrm):
         o += n
 
 
+def test_adamw_step_matches_fp64_reference(vrm):
+    """Two optimiser steps of vrm_mlp_train_step (learning rate and weight decay on)
+    against the oracle's FP64 AdamW applied to the gradients the library returned
+    for each step: the FP32 parameters agree to their rounding, which a missing
+    bias correction or weight decay term would exceed many times over."""
+    from oracle import mlp
+    import paper_1508_06379_amd.learned as L
+    rng = np.random.default_rng(7)
+    theta = L.init_params(9)
+    X, T = _features(rng, 2048)
+    ctx = vrm.Context(64)
+    ctx.vrm_mlp_load(torch.as_tensor(theta, device="cuda"))
+    w0 = torch.zeros(vrm.MLP_PARAMS, device="cuda")
+    ctx.vrm_mlp_read(w0)
+    w_ref = w0.cpu().numpy().astype(np.float64)
+    m = np.zeros_like(w_ref)
+    v = np.zeros_like(w_ref)
+    lr, wd = 1e-3, 1e-2
+    Xd, Td = bf16(torch.as_tensor(X, device="cuda")), torch.as_tensor(T, device="cuda")
+    for t in (1, 2):
+        grad = torch.zeros(vrm.MLP_PARAMS, device="cuda")
+        ctx.vrm_mlp_train_step(Xd, Td, 2048, lr, wd, 0.5, None, grad)
+        w_ref, m, v = mlp.adamw_step(w_ref, grad.cpu().numpy().astype(np.float64), m, v, t, lr, wd)
+    w1 = torch.zeros(vrm.MLP_PARAMS, device="cuda")
+    ctx.vrm_mlp_read(w1)
+    w_gpu = w1.cpu().numpy().astype(np.float64)
+    dev = np.abs(w_gpu - w_ref)
+    moved = np.abs(w_gpu - w0.cpu().numpy()).max()
+    print("adamw max deviation", dev.max(), "largest move", moved, flush=True)
+    assert moved > 1e-3   # two steps of size ~lr moved the parameters
+    assert (dev <= 2e-7 * np.abs(w_ref) + 1e-5 * lr).all()
+
+
 @pytest.fixture(scope="module")
 def trained(vrm):
     import paper_1508_06379_amd.learned as L

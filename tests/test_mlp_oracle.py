@@ -1,5 +1,6 @@
 """Pins of the FP64 reference network: its gradient against central finite
-differences of its own loss, and GELU against its definition."""
+differences of its own loss, GELU against its definition, and the AdamW step
+against the closed forms of its first steps."""
 import math
 
 import numpy as np
@@ -62,3 +63,28 @@ def test_masked_slots_do_not_contribute():
     T2[:, mlp.SLOTS + 25:] += 3.0
     l2, _ = mlp.loss_and_grad(theta, X, T2)
     assert l1 == l2
+
+
+def test_adamw_first_steps_closed_form():
+    """Step 1 of Adam moves every parameter by lr * g / (|g| + eps): the bias
+    corrections turn the first moments back into g and g^2.  With a constant
+    gradient every later step does the same.  The decoupled weight decay adds
+    lr * wd * w, whatever the gradient (also where it is zero)."""
+    rng = np.random.default_rng(5)
+    w = rng.normal(0, 1, 50)
+    g = rng.normal(0, 1e-2, 50)
+    g[:5] = 0.0
+    lr, wd, eps = 1e-3, 0.01, 1e-8
+    m = v = np.zeros(50)
+    w1, m, v = mlp.adamw_step(w, g, m, v, 1, lr, wd, eps=eps)
+    np.testing.assert_allclose(w1, w - lr * (g / (np.abs(g) + eps) + wd * w), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-14, atol=0)
+    w2, m, v = mlp.adamw_step(w1, g, m, v, 2, lr, wd, eps=eps)
+    np.testing.assert_allclose(w2, w1 - lr * (g / (np.abs(g) + eps) + wd * w1), rtol=0, atol=1e-15)
+    # a sign flip of the gradient: m_hat = (0.09 g - 0.1 g) / 0.19, v_hat = g^2 (both steps' |g| equal)
+    with np.errstate(divide="ignore", invalid="ignore"):   # the zero gradients, eps = 0
+        w3, _, _ = mlp.adamw_step(w1, -g, 0.1 * g, 0.001 * g * g, 2, lr, 0.0, eps=0.0)
+    mh = (0.9 * 0.1 * g - 0.1 * g) / (1 - 0.81)
+    nz = g != 0
+    np.testing.assert_allclose(w3[nz], w1[nz] - lr * mh[nz] / np.abs(g[nz]), rtol=1e-12)
