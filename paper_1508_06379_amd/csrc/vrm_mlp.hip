@@ -48,6 +48,61 @@ __device__ __forceinline__ float gelu_grad(float z)
 
 constexpr int TM = 64, TN = 64, TK = 32, KPAD = 8;
 
+// One 64 x 32 operand tile into LDS as T[i][kk] (i: row of A or column of B, kk
+// the k offset), from P(i, k) = P[i * si + k * sk], zeros outside i < ni,
+// k < ke.  An operand contiguous in k or in i is read eight elements (16
+// bytes) per thread: a run inside the bounds and 16-byte aligned by one
+// vector load, else element by element.  Any other layout: one element per load.
+__device__ __forceinline__ void stage_tile(uint16_t (*T)[TK + KPAD], const uint16_t* __restrict__ P, long si, long sk,
+                                           int i0, int ni, int k0, int ke, int tid)
+{
+    if (sk == 1) {
+        // thread: row tid / 4, k run 8 (tid % 4)
+        const int r = tid >> 2, kk = (tid & 3) * 8;
+        const int i = i0 + r, k = k0 + kk;
+        const uint16_t* src = P + (long)i * si + k;
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (i < ni && k + 7 < ke && ((uintptr_t)src & 15) == 0) {
+            v = *reinterpret_cast<const uint4*>(src);
+        } else if (i < ni) {
+            uint16_t e[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) e[u] = k + u < ke ? src[u] : (uint16_t)0;
+            v = uint4{e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16), e[4] | ((uint32_t)e[5] << 16),
+                      e[6] | ((uint32_t)e[7] << 16)};
+        }
+        *reinterpret_cast<uint4*>(&T[r][kk]) = v;
+    } else if (si == 1) {
+        // thread: k offset tid / 8, rows 8 (tid % 8) .. + 7
+        const int kk = tid >> 3, r0 = (tid & 7) * 8;
+        const int i = i0 + r0, k = k0 + kk;
+        const uint16_t* src = P + (long)k * sk + i;
+        uint16_t e[8];
+        if (k < ke && i + 7 < ni && ((uintptr_t)src & 15) == 0) {
+            const uint4 v = *reinterpret_cast<const uint4*>(src);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                e[2 * u] = (uint16_t)w[u];
+                e[2 * u + 1] = (uint16_t)(w[u] >> 16);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) e[u] = (k < ke && i + u < ni) ? src[u] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) T[r0 + u][kk] = e[u];
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = tid + e * 256;
+            const int r = idx >> 5, kk = idx & 31;
+            const int i = i0 + r, k = k0 + kk;
+            T[r][kk] = (i < ni && k < ke) ? P[(long)i * si + (long)k * sk] : (uint16_t)0;
+        }
+    }
+}
+
 // C(m, n) = epi(sum_k A(m, k) B(k, n));  A(m, k) = A[m * sam + k * sak], B(k, n) = B[k * sbk + n * sbn].
 // Tile 64 x 64 per block of 4 waves (each 32 x 32 = 2 x 2 MFMA blocks); K in steps of 32.
 // gridDim.z > 1 splits K; the partial sums are added atomically (EPI_ACC only).
@@ -71,16 +126,9 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = kb; k0 < ke; k0 += TK) {
-        // stage A (64 x 32) and B (32 x 64): 8 elements per thread each
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            int idx = tid + e * 256;
-            int r = idx >> 5, kk = idx & 31;
-            int m = m0 + r, k = k0 + kk;
-            As[r][kk] = (m < M && k < ke) ? A[(long)m * sam + (long)k * sak] : (uint16_t)0;
-            int n = n0 + (idx >> 5), kb2 = k0 + (idx & 31);
-            Bs[idx >> 5][idx & 31] = (n < N && kb2 < ke) ? B[(long)kb2 * sbk + (long)n * sbn] : (uint16_t)0;
-        }
+        // stage A (64 x 32) and B (32 x 64, stored [n][k]): 8 elements per thread each
+        stage_tile(As, A, sam, sak, m0, M, k0, ke, tid);
+        stage_tile(Bs, B, sbn, sbk, n0, N, k0, ke, tid);
         __syncthreads();
         const int row = lane & 15, kq = (lane >> 4) * 8;
 #pragma unroll
