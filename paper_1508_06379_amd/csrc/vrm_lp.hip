@@ -1158,13 +1158,13 @@ constexpr int kRecRow = VRM_KMAX;
 // lane places its members at once: position = number of members with a
 // smaller (d2, id), id rank = number with a smaller id (among the VRM_KMAX
 // nearest if there are more).  No sort, no rescans; a list longer than
-// kMemCap (a density the method never produces) goes to the retry queue and
+// kMemCap (rare: an LP keeps at most VRM_KMAX = 48 columns) goes to the retry queue and
 // is solved by the one-thread kernel, which collects on its own.
 // The previous-basis warm start (WM 2) takes its input here as well: the
 // columns whose ids form the particle's previous basis, as a mask per LP
 // (pmask).  The network's inputs are read from the records by its inference.
 constexpr int kCollL = 16;
-constexpr int kMemCap = 96;
+constexpr int kMemCap = 64;
 constexpr int kCollBlock = 256;
 constexpr int kCollGroups = kCollBlock / kCollL;
 constexpr int kMemPerLane = kMemCap / kCollL;
