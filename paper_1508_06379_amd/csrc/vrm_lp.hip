@@ -1176,8 +1176,10 @@ constexpr int kMemPerLane = kMemCap / kCollL;
 constexpr int kMemStride = kMemCap + 4;
 static_assert(kMemCap % 4 == 0 && kMemStride % 4 == 0, "lists are read four members at a time");
 
+// Eight waves per SIMD (64 VGPRs; the LDS of 17.6 KB per block allows nine):
+// the scan waits on its loads, and more resident waves hide that.
 template <int WM>
-__global__ __launch_bounds__(kCollBlock) void k_full_collect(const float* __restrict__ xs,
+__global__ __launch_bounds__(kCollBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_full_collect(const float* __restrict__ xs,
                                                              const float* __restrict__ ys,
                                                              const int32_t* __restrict__ ids,
                                                              const int32_t* __restrict__ cell_start,
