@@ -265,7 +265,9 @@ __global__ __launch_bounds__(256) void k_transpose_w(const uint16_t* __restrict_
 // Fused inference: each block runs all three layers on tiles of 64 rows; the
 // activations stay in LDS and the (L2-resident) transposed weights are read
 // from memory as MFMA B operands.  Persistent: blocks loop over tiles; the row
-// count may be read on the device.
+// count may be read on the device.  The inference kernels ask for three waves per SIMD
+// (at most 168 VGPRs, no spills): one more wave than the default allocation
+// gives hides more of the epilogue's and the loads' latency.
 constexpr int FR = 64;               // rows per tile
 constexpr int FKP = kMlpHid + 8;     // padded LDS row (bank spread)
 
@@ -332,7 +334,7 @@ __device__ __forceinline__ void mlp_out16(const uint16_t* Ta, const uint16_t* __
     }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_infer(int rows, const int* rows_dev, const uint16_t* __restrict__ X,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_infer(int rows, const int* rows_dev, const uint16_t* __restrict__ X,
                                                    const uint16_t* __restrict__ wt, const float* __restrict__ w,
                                                    float* __restrict__ Y)
 {
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int rows, const int* rows_dev
 // built in LDS from their column records (slot s = segment s: exact offset /
 // h and mask; q - 2), and only the logits of the eight columns written:
 // L[item][8].
-__global__ __launch_bounds__(256) void k_mlp_infer_small(const int* rows_dev, SmallRec rec, float sc, int q,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_infer_small(const int* rows_dev, SmallRec rec, float sc, int q,
                                                          const uint16_t* __restrict__ wt, const float* __restrict__ w,
                                                          float* __restrict__ L)
 {
@@ -421,7 +423,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer_small(const int* rows_dev, Sm
 // offset / h and mask; q - 2), four threads per row, and only the 32 basis
 // logits are computed and written: L[item][kMlpSlots].  (Choosing the m
 // largest here, at this kernel's occupancy, costs more than a separate pass.)
-__global__ __launch_bounds__(256) void k_mlp_infer_full(const int* rows_dev, FullRec fr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_infer_full(const int* rows_dev, FullRec fr,
                                                         const uint16_t* __restrict__ wt, const float* __restrict__ w,
                                                         float* __restrict__ Lout)
 {
