@@ -132,13 +132,36 @@ __global__ __launch_bounds__(256) void k_count(const float* __restrict__ x, cons
                                                int32_t* cell_of, int32_t* rank)
 {
     if (n_dev) n = *n_dev;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < n;
     GridState g = *gs;
-    if (g.bad & kBadPos) return;   // a non-finite position: no cell indices
-    int c = cell_index(g, x[i], y[i]);
-    cell_of[i] = c;
-    rank[i] = atomicAdd(&start[c], 1);
+    if (g.bad & kBadPos) return;   // a non-finite position: no cell indices (the same for every thread)
+    const int c = live ? cell_index(g, x[i], y[i]) : -1;
+    if (live) cell_of[i] = c;
+    // The rank only has to be unique within the cell.  The cloud is kept in cell
+    // order, so the lanes of a wave share few cells: in up to eight rounds, the
+    // lanes in the cell of the first lane still waiting take consecutive ranks
+    // from one atomic; lanes left after that (an unsorted cloud) add alone.
+    const int lane = lane_id();
+    bool todo = live;
+    int r = 0;
+    for (int round = 0; round < 8; ++round) {
+        const uint64_t act = __ballot(todo);
+        if (!act) break;
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const int lc = __shfl(c, leader, 64);
+        const bool mine = todo && c == lc;
+        const uint64_t same = __ballot(mine);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&start[lc], __popcll(same));
+        base = __shfl(base, leader, 64);
+        if (mine) {
+            r = base + __popcll(same & ((1ull << lane) - 1ull));
+            todo = false;
+        }
+    }
+    if (todo) r = atomicAdd(&start[c], 1);
+    if (live) rank[i] = r;
 }
 
 // ----- three-kernel exclusive scan over start[0..ncells), total in start[ncells]
