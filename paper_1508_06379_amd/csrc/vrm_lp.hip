@@ -1148,6 +1148,7 @@ __global__ __launch_bounds__(kFullBlock) void k_lp_full(const int32_t* __restric
 // canonical cost grows like |r|^4), pricing the others from HBM only once the
 // working set is exhausted -- the optimum is certified over all k columns.
 constexpr int kSiftW = 24;
+constexpr int kDeferMinN = 1 << 20;   // particles from which a cold LP launch defers certifications
 constexpr int kKBins = VRM_KMAX + 1;
 // a record row: (slot << 6) | id rank per column, nearest first
 constexpr int kRecRow = VRM_KMAX;
@@ -1540,9 +1541,11 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
     const int32_t* __restrict__ ids, const int32_t* __restrict__ order, const int32_t* __restrict__ kcol,
     const int32_t* __restrict__ rec, const int32_t* __restrict__ q_full, Queues* qs, const float* __restrict__ gamma,
     float* acc, LaunchParams P, StencilOut out, int apply, vrm_counters* cnt, int last_launch, const GridState* gs,
-    int32_t* q_defer)
+    int32_t* q_defer, int defer_cold)
 {
-    constexpr bool kDefer = WM != 3 && OBJ == 0;
+    // deferral: always for the warm launches (their cold re-solves run there),
+    // for the cold one only when the host asks (large clouds)
+    const bool defers = WM != 3 && OBJ == 0 && (WM != 0 || defer_cold);
     __shared__ float s_x[W * kFullBlock];
     __shared__ float s_y[W * kFullBlock];
     __shared__ float s_c[W * kFullBlock];
@@ -1614,20 +1617,20 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
             uint64_t basis = 0;
             if constexpr (WM == 0) {
                 st = solve_lp<M, OBJ, false>(cs, P, store, fii, piv, certified, false, nullptr, warm, basis, false,
-                                             0ull, cstat, true, kDefer);
+                                             0ull, cstat, true, defers);
             } else {
                 const uint64_t pref = cold ? 0ull : out.pmask[r];
                 // a prediction that is given up is followed by the cold solve in place
                 st = solve_lp<M, OBJ, true, true>(cs, P, store, fii, piv, certified, !cold, nullptr, warm, basis,
-                                                  !cold, pref, cstat, WM != 1, kDefer);
+                                                  !cold, pref, cstat, WM != 1, defers);
                 if (WM == 3) warm = cold ? 0 : was_warm;
                 // A warm attempt that ends infeasible is not final: its FP32 phase I may
                 // stop on a vertex whose basic artificial is within the FP32 tolerance
                 // but not zero in exact arithmetic, which the certification rejects.
                 // The deferred launch solves it cold, as the plain solver does.
-                if (kDefer && st == 1 && (warm == 1 || warm == 2)) st = 7;
+                if (defers && st == 1 && (warm == 1 || warm == 2)) st = 7;
             }
-            if (kDefer && st == 5) out.pmask[r] = basis;
+            if (defers && st == 5) out.pmask[r] = basis;
             if (WM == 2 || (WM == 3 && out.prev)) {
                 const int own = ids[t];
                 auto col_id = [&](int j) { return ids[(unsigned)row[j] >> 6]; };
@@ -1649,7 +1652,7 @@ __global__ __launch_bounds__(kFullBlock) __attribute__((amdgpu_waves_per_eu(2)))
                 out.status[i] = VRM_ST_INFEASIBLE;
             }
         }
-        if constexpr (kDefer) {
+        if (defers) {
             const bool later = live && (st == 5 || st == 7);
             const int dpos = wave_append(&qs->n_defer, later);
             if (later)
@@ -2092,18 +2095,24 @@ int vrm_stencil_run(vrm_ctx* c, const vrm_cloud* cl, int32_t n, const LaunchPara
         out.prev_cap = c->capacity;
         ScopedTimer tm(c, VRM_T_LP_FULL);
         const int obj = lp.phase1;
+        // A cold launch defers its exact certifications to a second launch only on
+        // large clouds: there a wave would otherwise wait on the few lanes that
+        // need them; on small ones every launch is one latency-bound wave per
+        // SIMD, and a second launch adds its whole chain.
+        const int defer_cold = n >= kDeferMinN ? 1 : 0;
         auto sift = wm == 0 ? by_objective(obj, k_lp_sift<9, kSiftW, 0, 0>, k_lp_sift<9, kSiftW, 1, 0>,
                                            k_lp_sift<9, kSiftW, 2, 0>)
                   : wm == 1 ? (obj == 1 ? k_lp_sift<9, kSiftW, 1, 1> : k_lp_sift<9, kSiftW, 0, 1>)
                             : (obj == 1 ? k_lp_sift<9, kSiftW, 1, 2> : k_lp_sift<9, kSiftW, 0, 2>);
         hipLaunchKernelGGL(sift, dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream, c->perm, c->xs, c->ys,
                            c->ids, c->full_order, c->full_k, c->full_cols, c->q_full, c->queues, cl->gamma_dev, c->acc,
-                           lp, out, apply, c->counters, 0, c->grid, c->q_defer);
-        if (obj == 0) {
-            // the certifications the cold launch deferred, from their bases (count read on the device)
+                           lp, out, apply, c->counters, 0, c->grid, c->q_defer, defer_cold);
+        if (obj == 0 && (wm != 0 || defer_cold)) {
+            // what the launch deferred, from the bases (count read on the device)
             hipLaunchKernelGGL((k_lp_sift<9, kSiftW, 0, 3>), dim3(lp_grid_full(c, n)), dim3(kFullBlock), 0, c->stream,
                                c->perm, c->xs, c->ys, c->ids, c->full_order, c->full_k, c->full_cols, c->q_full,
-                               c->queues, cl->gamma_dev, c->acc, lp, out, apply, c->counters, 0, c->grid, c->q_defer);
+                               c->queues, cl->gamma_dev, c->acc, lp, out, apply, c->counters, 0, c->grid, c->q_defer,
+                               0);
         }
         // lists too long for the collection groups (none in practice): the one-thread
         // kernel from the retry queue, cold; as the run's last LP launch it empties the queues
