@@ -259,7 +259,7 @@ typedef struct vrm_tuning {
     int32_t lp_full_blocks;      /* most workgroups (64 threads) of the complete-LP launches; default 2048 */
     int32_t full_stored_cost_n;  /* clouds with N up to this keep complete-LP costs in LDS; default 200000;
                                     -1: never */
-    int32_t infer_blocks;        /* most workgroups (256 threads) of the network's inference; default 512 */
+    int32_t infer_blocks;        /* most workgroups (256 threads) of the network's inference; default 768 */
     int32_t lp_small_lanes;      /* small LPs per wave of the small-LP launch (1, 2, 4, ..., 64); default 64 */
     int32_t lp_small_coop;       /* 1: the plain and phase-I small-LP passes give each LP eight lanes, one
                                     column each (shorter chains for latency-bound launches); 0 (default):

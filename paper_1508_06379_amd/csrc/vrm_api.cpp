@@ -580,7 +580,7 @@ int vrm_set_tuning(vrm_ctx* c, const vrm_tuning* t)
     d.lp_small_blocks = 2048;
     d.lp_full_blocks = 2048;
     d.full_stored_cost_n = 200000;
-    d.infer_blocks = 512;
+    d.infer_blocks = 768;   // the persistent inference grid: three resident blocks on each of 256 CUs
     d.lp_small_lanes = 64;
     if (t) {
         const int ln = t->lp_small_lanes;

@@ -22,26 +22,25 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
-    return (uint16_t)(u >> 16);
-}
+// FP32 to BF16, round to nearest even (the conversion instruction of gfx950)
+__device__ __forceinline__ uint16_t to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // GELU in its tanh form: z sigma(2u) with u = sqrt(2/pi) (z + 0.044715 z^3)
 // (0.5 z (1 + tanh u)); one exponential and one reciprocal
-__device__ __forceinline__ float gelu(float z)
+constexpr float kGeluK1 = -2.302208198144325f;    // -2 log2(e) sqrt(2/pi)
+constexpr float kGeluK2 = -0.1029432395800235f;   // kGeluK1 * 0.044715
+__device__ __forceinline__ float gelu_sigma(float z, float z2)
 {
-    const float u = z * (0.7978845608028654f + 0.0356774081363001f * z * z);
-    return z * __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));
+    // exp(-2u) = 2^(z (K1 + K2 z^2)): the factor -2 log2(e) folded into the constants
+    const float a = z * __builtin_fmaf(z2, kGeluK2, kGeluK1);
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(a));   // (1 + tanh u) / 2
 }
+__device__ __forceinline__ float gelu(float z) { return z * gelu_sigma(z, z * z); }
 __device__ __forceinline__ float gelu_grad(float z)
 {
     const float z2 = z * z;
-    const float u = z * (0.7978845608028654f + 0.0356774081363001f * z2);
-    const float s = __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));   // (1 + tanh u) / 2
+    const float s = gelu_sigma(z, z2);
     const float du = 0.7978845608028654f + 0.1070322244089003f * z2;
     return s + 2.0f * z * s * (1.0f - s) * du;
 }
